@@ -1,0 +1,58 @@
+"""Stencil inputs: grids with a fixed Dirichlet ring, and weight boxes.
+
+Grid convention (full extents include the ring): a 2D grid has shape
+``(ny, nx)`` and a 3D grid ``(nz, ny, nx)``, x fastest.  The ring of width
+``r`` (the stencil radius) is never updated; configurations set it to zero.
+
+Weights are a dense ``(2r+1)^d`` box indexed ``[dz][dy][dx]`` (2D: ``[dy][dx]``)
+with offsets ``-r..r``; an entry of zero marks an unused point.  Eq. 2 of the
+paper names the 2D 5-point weights N (j+1), S (j-1), C, W (i-1), E (i+1) with
+i along x and j along y, i.e. ``w[1+1][1]`` is N, ``w[1][1+1]`` is E.
+"""
+import numpy as np
+
+STENCIL_KINDS = ("2d5pt", "2d9pt", "3d7pt")
+
+
+def stencil_weights(kind, dtype=np.float64):
+    """Weight box of the benchmark stencils.
+
+    2d5pt: centre and four neighbours 0.2 each (Eq. 2 with C=N=S=W=E=0.2).
+    2d9pt: the radius-1 box, uniform 1/9 (tab:domain "2d9pt", order 1, 18 FLOPs).
+    3d7pt: centre 0.4, six face neighbours 0.1 (tab:domain "3d7pt", 14 FLOPs).
+    """
+    if kind == "2d5pt":
+        w = np.zeros((3, 3))
+        w[1, 1] = 0.2
+        w[0, 1] = w[2, 1] = w[1, 0] = w[1, 2] = 0.2
+    elif kind == "2d9pt":
+        w = np.full((3, 3), 1.0 / 9.0)
+    elif kind == "3d7pt":
+        w = np.zeros((3, 3, 3))
+        w[1, 1, 1] = 0.4
+        w[0, 1, 1] = w[2, 1, 1] = 0.1
+        w[1, 0, 1] = w[1, 2, 1] = 0.1
+        w[1, 1, 0] = w[1, 1, 2] = 0.1
+    else:
+        raise ValueError(f"unknown stencil kind {kind!r}")
+    return w.astype(dtype)
+
+
+def interior_slices(ndim, r=1):
+    return tuple(slice(r, -r) for _ in range(ndim))
+
+
+def stencil_grid(shape, seed=0, dtype=np.float64, r=1, ring_value=0.0):
+    """Grid of full extents ``shape`` whose interior is U[0,1) from ``seed``.
+
+    The interior values are drawn in float64 in row-major order and then
+    rounded to ``dtype``; the ring holds ``ring_value``.
+    """
+    shape = tuple(int(s) for s in shape)
+    if any(s < 2 * r + 1 for s in shape):
+        raise ValueError("every extent must exceed the ring on both sides")
+    rng = np.random.default_rng(seed)
+    g = np.full(shape, ring_value, dtype=np.float64)
+    inner = tuple(s - 2 * r for s in shape)
+    g[interior_slices(len(shape), r)] = rng.random(inner)
+    return g.astype(dtype)
