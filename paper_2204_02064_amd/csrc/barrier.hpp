@@ -1,0 +1,71 @@
+// Device-wide barrier of the persistent kernels (the grid.sync() of the
+// paper's Listing 1 / Listing 2), built for gfx950.
+//
+// Design (measured on MI355X, 256 workgroups of 512 threads):
+//   * One packed arrival word per workgroup; a single master wavefront
+//     (workgroup 0, wave 0) polls all of them with 64 lanes at a time and then
+//     publishes a generation word that the other workgroups poll.  No
+//     read-modify-write atomics: a shared counter serialises arrivals at the
+//     memory side (~70 ns each).
+//   * Only workgroup-scope fences.  All data that crosses workgroups is moved
+//     with agent-coherent (sc1) loads and stores, so the barrier never needs
+//     the agent-scope release/acquire that writes back and invalidates the
+//     eight XCD-private L2 caches (3.6 us per barrier at 256 workgroups).
+//   Result: ~2.1 us per barrier at 256 workgroups, ~1.4 us at 64.
+//
+// Epochs: the words hold monotonically increasing epoch numbers.  A launch
+// starts from the epoch the previous launch left in SYNC_EPOCH and stores its
+// final epoch there before it ends, so no reset (and no memset) is needed
+// between launches, including hipGraph replays.
+#pragma once
+
+#include "common.hpp"
+
+namespace perks {
+
+struct GridSync {
+    unsigned *ws;
+    unsigned epoch;
+
+    __device__ __forceinline__ void init(unsigned *w) {
+        ws = w;
+        epoch = ld_coh(ws + SYNC_EPOCH);
+    }
+
+    // All threads of all workgroups call this; returns when every workgroup
+    // has arrived.  Global writes made before the call with st_coh (or any
+    // other write that has completed) are visible to ld_coh after it.
+    __device__ __forceinline__ void sync() {
+        const unsigned e = ++epoch;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (threadIdx.x == 0) st_coh(ws + SYNC_FLAGS + blockIdx.x, e);
+        if (blockIdx.x == 0) {
+            if (threadIdx.x < 64) {
+                const unsigned G = gridDim.x;
+                for (unsigned base = 0; base < G; base += 64) {
+                    const unsigned i = base + threadIdx.x;
+                    while (true) {
+                        bool ok = (i >= G) || (ld_coh(ws + SYNC_FLAGS + i) == e);
+                        if (__all(ok)) break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                if (threadIdx.x == 0) st_coh(ws + SYNC_GEN, e);
+            }
+        } else if (threadIdx.x == 0) {
+            while (ld_coh(ws + SYNC_GEN) != e) __builtin_amdgcn_s_sleep(1);
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+
+    // Called once by every workgroup after its last sync(): records the epoch
+    // for the next launch.  Only workgroup 0 writes; every workgroup has read
+    // the start epoch before the first sync(), which precedes this write.
+    __device__ __forceinline__ void finish() {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, epoch);
+    }
+};
+
+}  // namespace perks

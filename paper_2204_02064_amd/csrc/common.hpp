@@ -1,0 +1,148 @@
+// Shared host/device helpers of libperks: error reporting, scratch memory,
+// coherent loads/stores for data that crosses workgroups, DPP lane shifts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/perks.h"
+
+namespace perks {
+
+// ---------------------------------------------------------------------------
+// Error reporting: a thread-local detail string behind perks_last_error().
+int set_error(int code, const char *fmt, ...);
+const char *last_error();
+
+#define PERKS_HIP_TRY(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::perks::set_error(PERKS_E_HIP, "%s failed: %s (%s:%d)", #expr,       \
+                                      hipGetErrorString(e_), __FILE__, __LINE__);        \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch memory, one growable buffer per (device, slot).
+// Growing frees the old buffer (which synchronises the device).
+enum ScratchSlot {
+    SLOT_SYNC = 0,      // barrier words (kept zero-initialised)
+    SLOT_FACES,         // stencil halo faces
+    SLOT_PINGPONG,      // per-step baseline's second grid
+    SLOT_CG_VEC,        // CG work vectors
+    SLOT_CG_PART,       // CG partition table / partial sums
+    SLOT_COUNT
+};
+// Returns a device pointer of at least `bytes`, or nullptr (error already set).
+void *scratch(int slot, size_t bytes);
+
+// Barrier workspace layout (32-bit words).  Flags are packed: one word per
+// workgroup, written by that workgroup only.
+constexpr int SYNC_GEN = 0;           // generation word released by the master
+constexpr int SYNC_EPOCH = 64;        // epoch carried from one launch to the next
+constexpr int SYNC_AUX = 128;         // small device-side results (CG scalars, ...)
+constexpr int SYNC_FLAGS = 1024;      // flags[wg]
+constexpr int SYNC_MAX_WGS = 8192;
+constexpr size_t SYNC_BYTES = (SYNC_FLAGS + SYNC_MAX_WGS) * 4 + 4096;
+
+struct DeviceFacts {
+    int device = -1;
+    int cus = 0;
+    int lds_per_cu = 0;
+    int regs_per_cu = 0;
+    int l2 = 0;
+    size_t hbm = 0;
+    char arch[64] = {0};
+};
+int device_facts(DeviceFacts *out);
+
+// Cooperative launch of a persistent kernel taking one by-value parameter
+// struct; maps a too-large grid to PERKS_E_NOTCORESIDENT.
+int launch_coop(const void *fn, int wgs, int threads, void *params, hipStream_t st);
+
+}  // namespace perks
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+#define PERKS_AGENT __HIP_MEMORY_SCOPE_AGENT
+
+namespace perks {
+
+// Loads and stores of data produced or consumed by another workgroup.  They
+// are relaxed agent-scope atomics: the compiler emits them with the sc1 cache
+// policy, which keeps them coherent across the eight XCD-private L2 caches
+// without a device-wide cache write-back or invalidate.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, PERKS_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, PERKS_AGENT);
+}
+
+// Lane shifts across the 64-lane wavefront with DPP wave_shr:1 / wave_shl:1.
+// shr: lane l receives lane l-1's value; lane 0 receives `fill` (lane 0's).
+// shl: lane l receives lane l+1's value; lane 63 receives `fill` (lane 63's).
+// With bound_ctrl off, a lane whose source is outside the wave keeps the
+// "old" operand, which is how the halo value enters the edge lane.
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float src, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(src),
+                                                      CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double src, double fill) {
+    long long s = __double_as_longlong(src), f = __double_as_longlong(fill);
+    int lo = __builtin_amdgcn_update_dpp((int)f, (int)s, CTRL, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(s >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ T from_west(T v, T fill) { return dpp_move<DPP_WAVE_SHR1>(v, fill); }
+template <typename T>
+__device__ __forceinline__ T from_east(T v, T fill) { return dpp_move<DPP_WAVE_SHL1>(v, fill); }
+
+// a*b+c (one rounding) in the three-address VOP3 form.  The compiler's own
+// FMA is the two-address v_fmac whose result must stay in the accumulator's
+// register; when a new grid value must replace its old value in place (the
+// register cache), the untied form lets the result take the old value's
+// register instead of costing a copy per cell and a second register set.
+__device__ __forceinline__ double fma_untied(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ float fma_untied(float a, float b, float c) {
+    float r;
+    asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Hides a uniform pointer's value from the optimiser for one use site.  The
+// step loops re-derive their face-buffer addresses from laundered bases every
+// step; otherwise loop-invariant code motion keeps dozens of per-lane 64-bit
+// addresses alive across the whole time loop, in the same registers that
+// should hold the cached domain.
+template <typename T>
+__device__ __forceinline__ T *opaque(T *p) {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
+}
+
+// Keeps the compiler from moving memory operations across this point.  LDS
+// operations of one wavefront complete in program order, so a wave that
+// writes LDS and then reads it needs no hardware barrier.
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+}  // namespace perks

@@ -1,0 +1,583 @@
+// 2D radius-1 Jacobi stencils (Eq. 2 and the 2d9pt box of tab:domain) on
+// gfx950: the shared tile arithmetic, the persistent kernel and the
+// per-step-launch baseline kernel.
+//
+// Tiling.  The interior (x in [1,nx-2], y in [1,ny-2]) is cut into wave tiles
+// of 64 columns x R rows.  Lane l of the wavefront owns column x0+l and keeps
+// the tile's R cells of that column in registers ("each thread computes a
+// vertical run of cells", Sec. 4.2.1): north/south neighbours are in the
+// lane's own registers, west/east neighbours arrive through DPP lane shifts,
+// and the tile's outer neighbours (halo) come from face buffers.
+//
+// Face buffers hold tile edges in global coordinates, double-buffered by step
+// parity:  rowbuf[par][slot][x]  (slot 2ty+1 = top edge row of tile row ty,
+// 2ty+2 = its bottom edge row, 0 and 2*nty+1 = the fixed ring rows) and
+// colbuf[par][slot][y] (the same for tile columns; edge columns are stored
+// transposed so that they are written and read contiguously, Sec. 4.2.2).
+// Tile (tx,ty) reads its north halo row from slot 2ty, south from 2ty+3, west
+// column from slot 2tx, east from 2tx+3.  Corner cells needed by the 9-point
+// box are the end entries of those rows/columns.
+#pragma once
+
+#include "barrier.hpp"
+#include "common.hpp"
+
+namespace perks {
+
+template <typename T>
+struct Weights2D {
+    T w[9];  // [dy+1][dx+1]
+};
+
+// Rolling state of one old row at this lane: value and its west/east values.
+template <typename T>
+struct RowVal {
+    T c, w, e;
+};
+
+// Updates rows 0..nrows-1 of u in place (one Jacobi step for one lane strip).
+//   u[0..nrows-1] old values on entry, new values on exit.
+//   above         old row above row 0 with its west/east values; on exit the
+//                 old value of row nrows-1 (so chunks can be chained).
+//   below         old row below row nrows-1 (south halo or next chunk's row).
+//   lw, le        LDS: west / east halo column, entry j <-> row j-1 (j=0..nrows+1).
+// FULL means nrows == RC; otherwise the last row's south neighbour is picked
+// with a wave-uniform select (never a register-array index that depends on a
+// run-time value, which would move the array to scratch memory).
+// Terms are summed in ascending (dy, dx) order, one multiply then FMAs; the
+// per-step baseline uses this same function, so both paths round identically.
+// Returns the new value of row nrows-1 (the tile's bottom edge when the strip
+// ends the tile), taken from the computed values rather than from u.
+template <typename T, int RC, bool BOX, bool FULL>
+__device__ __forceinline__ T compute_rows(T (&u)[RC], int nrows, RowVal<T> &above, T below, const T *lw,
+                                          const T *le, const Weights2D<T> &W) {
+    // acc carries the south-row terms of the row being computed; they are
+    // accumulated while the old south row is still live, so that each new
+    // value can take its old value's register (no second register set).
+    T acc;
+    if (BOX) {
+        acc = W.w[0] * above.w;
+        acc = __builtin_fma(W.w[1], above.c, acc);
+        acc = __builtin_fma(W.w[2], above.e, acc);
+    } else {
+        acc = W.w[1] * above.c;
+    }
+    T last = T(0);
+    T c = u[0];
+    T cw = from_west(c, lw[1]);
+    T ce = from_east(c, le[1]);
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        if (FULL || i < nrows) {
+            T n;
+            if (i + 1 < RC)
+                n = (FULL || i + 1 < nrows) ? u[i + 1] : below;
+            else
+                n = below;
+            acc = __builtin_fma(W.w[3], cw, acc);
+            acc = __builtin_fma(W.w[4], c, acc);
+            acc = __builtin_fma(W.w[5], ce, acc);
+            // south-row terms of row i+1 come from old row i: take them now, so
+            // old row i is dead before the new value of row i is complete
+            T nxt;
+            if (BOX) {
+                nxt = W.w[0] * cw;
+                nxt = __builtin_fma(W.w[1], c, nxt);
+                nxt = __builtin_fma(W.w[2], ce, nxt);
+            } else {
+                nxt = W.w[1] * c;
+            }
+            above.c = c;
+            above.w = cw;
+            above.e = ce;
+            T nw = n, ne = n;
+            if (BOX || (i + 1 < RC && (FULL || i + 1 < nrows))) {
+                nw = from_west(n, lw[i + 2]);
+                ne = from_east(n, le[i + 2]);
+            }
+            if (BOX) {
+                acc = __builtin_fma(W.w[6], nw, acc);
+                acc = __builtin_fma(W.w[7], n, acc);
+                acc = fma_untied(W.w[8], ne, acc);
+            } else {
+                acc = fma_untied(W.w[7], n, acc);
+            }
+            u[i] = acc;
+            if (FULL ? (i == RC - 1) : true) last = (FULL || i == nrows - 1) ? acc : last;
+            acc = nxt;
+            c = n;
+            cw = nw;
+            ce = ne;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+struct Tile2D {
+    int tx, ty, x0, y0, wx, hy;
+};
+
+template <typename T>
+struct Stencil2DParams {
+    T *grid;
+    T *src;            // baseline: read buffer
+    T *dst;            // baseline: write buffer
+    T *rowbuf;         // [2][2*nty+2][nx]
+    T *colbuf;         // [2][2*ntx+2][ny]
+    unsigned *sync;
+    long long steps;
+    int nx, ny;
+    int ntx, nty;
+    int R;             // tile height (rows per lane)
+    int last_w, last_h;
+    int ntiles;
+    int cached;        // number of tiles held in registers (tile id < cached)
+    Weights2D<T> W;
+};
+
+template <typename T>
+__device__ __forceinline__ Tile2D tile_of(const Stencil2DParams<T> &p, int t) {
+    Tile2D tl;
+    tl.tx = t % p.ntx;
+    tl.ty = t / p.ntx;
+    tl.x0 = 1 + 64 * tl.tx;
+    tl.y0 = 1 + p.R * tl.ty;
+    tl.wx = (tl.tx == p.ntx - 1) ? p.last_w : 64;
+    tl.hy = (tl.ty == p.nty - 1) ? p.last_h : p.R;
+    return tl;
+}
+
+template <typename T>
+__device__ __forceinline__ size_t rb_off(const Stencil2DParams<T> &p, int par, int slot) {
+    return ((size_t)par * (2 * p.nty + 2) + slot) * p.nx;
+}
+template <typename T>
+__device__ __forceinline__ size_t cb_off(const Stencil2DParams<T> &p, int par, int slot) {
+    return ((size_t)par * (2 * p.ntx + 2) + slot) * p.ny;
+}
+
+// Loads the halo of tile tl from parity `par` face buffers: north/south rows
+// into registers, west/east columns (rows y0-1..y0+hy) into this wave's LDS.
+template <typename T>
+__device__ __forceinline__ void load_halo(const Stencil2DParams<T> &p, const Tile2D &tl, int par,
+                                          int lane, T &hn, T &hs, T *lw, T *le) {
+    const int xl = min(tl.x0 + lane, p.nx - 1);
+    hn = ld_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty) + xl);
+    hs = ld_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty + 3) + xl);
+    const T *cw = p.colbuf + cb_off(p, par, 2 * tl.tx) + (tl.y0 - 1);
+    const T *ce = p.colbuf + cb_off(p, par, 2 * tl.tx + 3) + (tl.y0 - 1);
+    for (int j = lane; j < tl.hy + 2; j += 64) {
+        lw[j] = ld_coh(cw + j);
+        le[j] = ld_coh(ce + j);
+    }
+    compiler_fence();
+}
+
+// Publishes the edges of a tile strip into parity `par` face buffers.
+// Rows r0..r0+n-1 of the tile are in u[0..n-1].
+template <typename T, int RC, bool FULL>
+__device__ __forceinline__ void publish_rows(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
+                                             const T (&u)[RC], int r0, int n, T lastval) {
+    T *left = p.colbuf + cb_off(p, par, 2 * tl.tx + 1) + tl.y0 + r0;
+    T *right = p.colbuf + cb_off(p, par, 2 * tl.tx + 2) + tl.y0 + r0;
+    const bool in = lane < tl.wx;
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        if (FULL || i < n) {
+            if (lane == 0) st_coh(left + i, u[i]);
+            if (lane == tl.wx - 1) st_coh(right + i, u[i]);
+        }
+    }
+    if (in && r0 == 0) st_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty + 1) + tl.x0 + lane, u[0]);
+    if (in && r0 + n == tl.hy)
+        st_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty + 2) + tl.x0 + lane, lastval);
+}
+
+// Fixed ring entries of the face buffers, both parities (grid-stride loop
+// over all threads of the launch).
+template <typename T>
+__device__ void init_ring_faces(const Stencil2DParams<T> &p, const T *g) {
+    const int nthreads = gridDim.x * blockDim.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nrs = 2 * p.nty + 2, ncs = 2 * p.ntx + 2;
+    for (int par = 0; par < 2; ++par) {
+        for (int x = tid; x < p.nx; x += nthreads) {
+            st_coh(p.rowbuf + rb_off(p, par, 0) + x, g[x]);
+            st_coh(p.rowbuf + rb_off(p, par, nrs - 1) + x, g[(size_t)(p.ny - 1) * p.nx + x]);
+        }
+        for (int y = tid; y < p.ny; y += nthreads) {
+            st_coh(p.colbuf + cb_off(p, par, 0) + y, g[(size_t)y * p.nx]);
+            st_coh(p.colbuf + cb_off(p, par, ncs - 1) + y, g[(size_t)y * p.nx + p.nx - 1]);
+        }
+        // ring columns inside every row slot, ring rows inside every column slot
+        for (int s = tid; s < nrs - 2; s += nthreads) {
+            const int ty = s / 2;
+            const int y = (s % 2 == 0) ? 1 + p.R * ty : 1 + p.R * ty + ((ty == p.nty - 1) ? p.last_h : p.R) - 1;
+            st_coh(p.rowbuf + rb_off(p, par, s + 1) + 0, g[(size_t)y * p.nx]);
+            st_coh(p.rowbuf + rb_off(p, par, s + 1) + p.nx - 1, g[(size_t)y * p.nx + p.nx - 1]);
+        }
+        for (int s = tid; s < ncs - 2; s += nthreads) {
+            const int tx = s / 2;
+            const int x = (s % 2 == 0) ? 1 + 64 * tx : 1 + 64 * tx + ((tx == p.ntx - 1) ? p.last_w : 64) - 1;
+            st_coh(p.colbuf + cb_off(p, par, s + 1) + 0, g[x]);
+            st_coh(p.colbuf + cb_off(p, par, s + 1) + p.ny - 1, g[(size_t)(p.ny - 1) * p.nx + x]);
+        }
+    }
+}
+
+// Edges of a tile straight from the grid into parity-0 face buffers.
+template <typename T>
+__device__ void publish_initial(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
+    const T *g = p.grid;
+    if (lane < tl.wx) {
+        st_coh(p.rowbuf + rb_off(p, 0, 2 * tl.ty + 1) + tl.x0 + lane, g[(size_t)tl.y0 * p.nx + tl.x0 + lane]);
+        st_coh(p.rowbuf + rb_off(p, 0, 2 * tl.ty + 2) + tl.x0 + lane,
+               g[(size_t)(tl.y0 + tl.hy - 1) * p.nx + tl.x0 + lane]);
+    }
+    for (int j = lane; j < tl.hy; j += 64) {
+        const size_t row = (size_t)(tl.y0 + j) * p.nx;
+        st_coh(p.colbuf + cb_off(p, 0, 2 * tl.tx + 1) + tl.y0 + j, g[row + tl.x0]);
+        st_coh(p.colbuf + cb_off(p, 0, 2 * tl.tx + 2) + tl.y0 + j, g[row + tl.x0 + tl.wx - 1]);
+    }
+}
+
+// One step of one tile whose cells live in registers v.
+template <typename T, int R, bool BOX>
+__device__ __forceinline__ void step_cached(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
+                                            T (&v)[R], T *lw, T *le) {
+    T hn, hs;
+    load_halo(p, tl, par, lane, hn, hs, lw, le);
+    if (tl.wx < 64 && lane >= tl.wx) {
+        // ghost lanes carry the east halo column so the DPP east shift of the
+        // last real lane picks it up
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = le[i + 1];
+        hn = le[0];
+        hs = le[tl.hy + 1];
+    }
+    RowVal<T> above;
+    above.c = hn;
+    above.w = from_west(hn, lw[0]);
+    above.e = from_east(hn, le[0]);
+    if (tl.hy == R) {
+        const T last = compute_rows<T, R, BOX, true>(v, R, above, hs, lw, le, p.W);
+        publish_rows<T, R, true>(p, tl, par ^ 1, lane, v, 0, R, last);
+    } else {
+        const T last = compute_rows<T, R, BOX, false>(v, tl.hy, above, hs, lw, le, p.W);
+        publish_rows<T, R, false>(p, tl, par ^ 1, lane, v, 0, tl.hy, last);
+    }
+}
+
+// One step of a tile that lives in the grid (the uncached part, Eq. 5's
+// D_uncache): streamed through registers CH rows at a time, updated in place.
+// In-place is safe because neighbours read this tile only through the face
+// buffers, and the rolling `above` state keeps the old value of the last row
+// of the previous chunk.
+template <typename T, int CH, bool BOX>
+__device__ __forceinline__ void step_streamed(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
+                                              T *lw, T *le) {
+    T hn, hs;
+    load_halo(p, tl, par, lane, hn, hs, lw, le);
+    const bool ghost = lane >= tl.wx;
+    const int xl = min(tl.x0 + lane, p.nx - 1);
+    if (ghost) {
+        hn = le[0];
+        hs = le[tl.hy + 1];
+    }
+    RowVal<T> above;
+    above.c = hn;
+    above.w = from_west(hn, lw[0]);
+    above.e = from_east(hn, le[0]);
+    T u[CH];
+    for (int c = 0; c < tl.hy; c += CH) {
+        const int n = min(CH, tl.hy - c);
+        T *row0 = p.grid + (size_t)(tl.y0 + c) * p.nx + xl;
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            u[i] = (i < n) ? (ghost ? le[c + i + 1] : row0[(size_t)i * p.nx]) : T(0);
+        T below = hs;
+        if (c + n < tl.hy) below = ghost ? le[c + n + 1] : row0[(size_t)n * p.nx];
+        const T last = (n == CH) ? compute_rows<T, CH, BOX, true>(u, CH, above, below, lw + c, le + c, p.W)
+                                 : compute_rows<T, CH, BOX, false>(u, n, above, below, lw + c, le + c, p.W);
+        if (!ghost) {
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (i < n) row0[(size_t)i * p.nx] = u[i];
+        }
+        if (n == CH)
+            publish_rows<T, CH, true>(p, tl, par ^ 1, lane, u, c, CH, last);
+        else
+            publish_rows<T, CH, false>(p, tl, par ^ 1, lane, u, c, n, last);
+    }
+}
+
+// The persistent kernel: one launch runs all steps.  Tiles t < p.cached are
+// kept in registers by wave t for the whole run; the remaining tiles are
+// assigned round-robin to all waves and streamed through the grid.
+template <typename T, int R, bool BOX, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void stencil2d_persistent(Stencil2DParams<T> p) {
+    __shared__ T lds[WAVES][2][R + 2];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = blockIdx.x * WAVES + wave;
+    const int nwaves = gridDim.x * WAVES;
+    T *lw = lds[wave][0];
+    T *le = lds[wave][1];
+    GridSync gs;
+    gs.init(p.sync);
+
+    init_ring_faces(p, p.grid);
+    for (int t = gw; t < p.ntiles; t += nwaves) publish_initial(p, tile_of(p, t), lane);
+    gs.sync();
+
+    const bool has_cached = gw < p.cached;
+    T v[R];
+    Tile2D ct{};
+    if (has_cached) {
+        ct = tile_of(p, gw);
+        const int xl = min(ct.x0 + lane, p.nx - 1);
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = (i < ct.hy) ? p.grid[(size_t)(ct.y0 + i) * p.nx + xl] : T(0);
+    }
+    const int first_streamed = p.cached + gw;
+    for (long long s = 0; s < p.steps; ++s) {
+        const int par = (int)(s & 1);
+        Stencil2DParams<T> q = p;
+        q.grid = opaque(q.grid);
+        q.rowbuf = opaque(q.rowbuf);
+        q.colbuf = opaque(q.colbuf);
+        if (has_cached) step_cached<T, R, BOX>(q, ct, par, lane, v, lw, le);
+        for (int t = first_streamed; t < p.ntiles; t += nwaves)
+            step_streamed<T, 8, BOX>(q, tile_of(p, t), par, lane, lw, le);
+        gs.sync();
+    }
+    if (has_cached && lane < ct.wx) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (i < ct.hy) p.grid[(size_t)(ct.y0 + i) * p.nx + ct.x0 + lane] = v[i];
+    }
+    gs.finish();
+}
+
+// The per-step-launch baseline: one wave per tile, one step per launch, read
+// `src`, write `dst` (ring cells are not written: both buffers hold the ring).
+template <typename T, int R, bool BOX, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void stencil2d_step(Stencil2DParams<T> p) {
+    __shared__ T lds[WAVES][2][R + 2];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = blockIdx.x * WAVES + wave;
+    if (t >= p.ntiles) return;
+    const Tile2D tl = tile_of(p, t);
+    T *lw = lds[wave][0];
+    T *le = lds[wave][1];
+    const T *src = p.src;
+    const int xl = min(tl.x0 + lane, p.nx - 1);
+    for (int j = lane; j < tl.hy + 2; j += 64) {
+        const size_t row = (size_t)(tl.y0 - 1 + j) * p.nx;
+        lw[j] = src[row + tl.x0 - 1];
+        le[j] = src[row + tl.x0 + tl.wx];
+    }
+    compiler_fence();
+    const bool ghost = lane >= tl.wx;
+    T u[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        u[i] = (i < tl.hy) ? (ghost ? le[i + 1] : src[(size_t)(tl.y0 + i) * p.nx + xl]) : T(0);
+    const T hs = ghost ? le[tl.hy + 1] : src[(size_t)(tl.y0 + tl.hy) * p.nx + xl];
+    T hn = ghost ? le[0] : src[(size_t)(tl.y0 - 1) * p.nx + xl];
+    RowVal<T> above;
+    above.c = hn;
+    above.w = from_west(hn, lw[0]);
+    above.e = from_east(hn, le[0]);
+    if (tl.hy == R)
+        compute_rows<T, R, BOX, true>(u, R, above, hs, lw, le, p.W);
+    else
+        compute_rows<T, R, BOX, false>(u, tl.hy, above, hs, lw, le, p.W);
+    if (!ghost) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (i < tl.hy) p.dst[(size_t)(tl.y0 + i) * p.nx + xl] = u[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host planning / launch (2D).
+constexpr int W2 = 8;       // wavefronts per workgroup of the persistent kernel
+constexpr int WB = 4;       // wavefronts per workgroup of the baseline kernel
+constexpr int RB = 16;      // tile depth of the baseline kernel
+
+template <typename T> struct RList;
+template <> struct RList<double> { static constexpr int v[4] = {8, 16, 32, 48}; };
+template <> struct RList<float> { static constexpr int v[5] = {8, 16, 32, 48, 64}; };
+
+template <typename T, int R, bool BOX>
+const void *persist2d_fn() { return reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2>); }
+
+template <typename T, bool BOX>
+const void *pick2d(int R) {
+    switch (R) {
+        case 8: return persist2d_fn<T, 8, BOX>();
+        case 16: return persist2d_fn<T, 16, BOX>();
+        case 32: return persist2d_fn<T, 32, BOX>();
+        case 48: return persist2d_fn<T, 48, BOX>();
+        default: break;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        switch (R) {
+            case 64: return persist2d_fn<T, 64, BOX>();
+            default: break;
+        }
+    }
+    return nullptr;
+}
+
+struct Plan2D {
+    int R = 0, wgs = 0, ntx = 0, nty = 0, last_w = 0, last_h = 0, ntiles = 0, cached = 0;
+    const void *fn = nullptr;
+};
+
+template <typename T>
+int plan2d(const perks_shape &s, bool box, const perks_tuning *tu, Plan2D *pl) {
+    DeviceFacts f;
+    int rc = device_facts(&f);
+    if (rc) return rc;
+    const int nxi = (int)s.nx - 2, nyi = (int)s.ny - 2;
+    pl->ntx = (nxi + 63) / 64;
+    pl->last_w = nxi - 64 * (pl->ntx - 1);
+    const int want_r = tu ? tu->rows_per_lane : 0;
+    const int wgs_per_cu = (tu && tu->wgs_per_cu > 0) ? tu->wgs_per_cu : 1;
+    if (tu && tu->waves_per_wg != 0 && tu->waves_per_wg != W2)
+        return set_error(PERKS_E_UNSUPPORTED, "2D persistent kernels use %d waves per workgroup", W2);
+    int chosen = 0;
+    for (int r : RList<T>::v) {
+        const void *fn = pick2d<T, false>(r);
+        if (!fn) continue;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, box ? pick2d<T, true>(r) : fn, W2 * 64, 0) !=
+                hipSuccess ||
+            occ < wgs_per_cu)
+            continue;
+        const long long cap = (long long)f.cus * wgs_per_cu * W2;
+        const long long nt = (long long)pl->ntx * ((nyi + r - 1) / r);
+        if (want_r) {
+            if (r == want_r) chosen = r;
+        } else if (nt <= cap) {
+            chosen = r;
+            break;
+        } else {
+            chosen = r;  // largest that runs; tiles beyond the capacity stream
+        }
+    }
+    if (!chosen)
+        return set_error(PERKS_E_UNSUPPORTED, "no 2D tile depth matches the request (rows_per_lane=%d)", want_r);
+    pl->R = chosen;
+    pl->nty = (nyi + chosen - 1) / chosen;
+    pl->last_h = nyi - chosen * (pl->nty - 1);
+    pl->ntiles = pl->ntx * pl->nty;
+    const long long cap_waves = (long long)f.cus * wgs_per_cu * W2;
+    long long cached = std::min<long long>(pl->ntiles, cap_waves);
+    if (tu && tu->max_cached_tiles < 0) cached = 0;
+    if (tu && tu->max_cached_tiles > 0) cached = std::min<long long>(cached, tu->max_cached_tiles);
+    pl->cached = (int)cached;
+    long long waves = std::min<long long>(pl->ntiles, cap_waves);
+    pl->wgs = (int)((waves + W2 - 1) / W2);
+    pl->fn = box ? pick2d<T, true>(chosen) : pick2d<T, false>(chosen);
+    return pl->fn ? PERKS_OK : set_error(PERKS_E_UNSUPPORTED, "no kernel for this tile depth");
+}
+
+template <typename T>
+void fill_weights(Weights2D<T> &W, const double *c) {
+    for (int i = 0; i < 9; ++i) W.w[i] = (T)c[i];
+}
+
+template <typename T>
+int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+          const perks_tuning *tu) {
+    Plan2D pl;
+    int rc = plan2d<T>(s, box, tu, &pl);
+    if (rc) return rc;
+    Stencil2DParams<T> p{};
+    p.grid = grid;
+    p.nx = (int)s.nx;
+    p.ny = (int)s.ny;
+    p.ntx = pl.ntx;
+    p.nty = pl.nty;
+    p.R = pl.R;
+    p.last_w = pl.last_w;
+    p.last_h = pl.last_h;
+    p.ntiles = pl.ntiles;
+    p.cached = pl.cached;
+    p.steps = steps;
+    fill_weights(p.W, coeffs);
+    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx, cb = (size_t)2 * (2 * pl.ntx + 2) * s.ny;
+    T *faces = (T *)scratch(SLOT_FACES, (rb + cb) * sizeof(T));
+    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!faces || !sync) return PERKS_E_NOMEM;
+    p.rowbuf = faces;
+    p.colbuf = faces + rb;
+    p.sync = sync;
+    return launch_coop(pl.fn, pl.wgs, W2 * 64, &p, st);
+}
+
+template <typename T, bool BOX>
+int baseline2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st) {
+    const size_t cells = (size_t)s.nx * s.ny;
+    T *other = (T *)scratch(SLOT_PINGPONG, cells * sizeof(T));
+    if (!other) return PERKS_E_NOMEM;
+    Stencil2DParams<T> p{};
+    p.nx = (int)s.nx;
+    p.ny = (int)s.ny;
+    const int nxi = p.nx - 2, nyi = p.ny - 2;
+    p.ntx = (nxi + 63) / 64;
+    p.last_w = nxi - 64 * (p.ntx - 1);
+    p.R = RB;
+    p.nty = (nyi + RB - 1) / RB;
+    p.last_h = nyi - RB * (p.nty - 1);
+    p.ntiles = p.ntx * p.nty;
+    fill_weights(p.W, coeffs);
+    // the second buffer needs the fixed ring; copy the whole grid once
+    PERKS_HIP_TRY(hipMemcpyAsync(other, grid, cells * sizeof(T), hipMemcpyDeviceToDevice, st));
+    const int wgs = (p.ntiles + WB - 1) / WB;
+    T *a = grid, *b = other;
+    for (int64_t k = 0; k < steps; ++k) {
+        p.src = a;
+        p.dst = b;
+        hipLaunchKernelGGL((stencil2d_step<T, RB, BOX, WB>), dim3(wgs), dim3(WB * 64), 0, st, p);
+        std::swap(a, b);
+    }
+    PERKS_HIP_TRY(hipGetLastError());
+    if (a != grid) PERKS_HIP_TRY(hipMemcpyAsync(grid, a, cells * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return PERKS_OK;
+}
+
+
+template <typename T>
+int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan) {
+    Plan2D pl;
+    int rc = plan2d<T>(shape, box, tune, &pl);
+    if (rc) return rc;
+    plan->wgs = pl.wgs;
+    plan->waves_per_wg = W2;
+    plan->rows_per_lane = pl.R;
+    plan->planes_per_lane = 1;
+    plan->tiles = pl.ntiles;
+    plan->cached_tiles = pl.cached;
+    plan->interior_cells = (shape.nx - 2) * (shape.ny - 2);
+    int64_t cc = 0, face = 0;
+    for (int t = 0; t < pl.ntiles; ++t) {
+        const int tx = t % pl.ntx, ty = t / pl.ntx;
+        const int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64, hy = ty == pl.nty - 1 ? pl.last_h : pl.R;
+        if (t < pl.cached) cc += wx * hy;
+        // per step: 2 edge rows + 2 edge columns written, the same plus corners read
+        face += 2 * (2 * wx + 2 * hy) + 4;
+    }
+    plan->cached_cells = cc;
+    plan->halo_bytes_per_step = face * (int64_t)sizeof(T);
+    plan->sync = 1;
+    return PERKS_OK;
+}
+
+}  // namespace perks

@@ -1,0 +1,10 @@
+// 2D stencil kernels and launchers instantiated for double.
+#include "stencil2d.hpp"
+#include "stencil_api.hpp"
+
+namespace perks {
+template int run2d<double>(double *, const double *, const perks_shape &, int64_t, bool, hipStream_t, const perks_tuning *);
+template int baseline2d<double, false>(double *, const double *, const perks_shape &, int64_t, hipStream_t);
+template int baseline2d<double, true>(double *, const double *, const perks_shape &, int64_t, hipStream_t);
+template int plan2d_query<double>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
+}  // namespace perks

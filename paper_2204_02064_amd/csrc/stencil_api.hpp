@@ -1,0 +1,25 @@
+// Entry points of the per-dtype stencil translation units (explicitly
+// instantiated in stencil{2d,3d}_{f32,f64}.hip so they compile in parallel).
+#pragma once
+
+#include "common.hpp"
+
+namespace perks {
+
+template <typename T>
+int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+          const perks_tuning *tu);
+template <typename T, bool BOX>
+int baseline2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st);
+template <typename T>
+int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan);
+
+template <typename T>
+int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st,
+          const perks_tuning *tu);
+template <typename T>
+int baseline3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st);
+template <typename T>
+int plan3d_query(const perks_shape &s, const perks_tuning *tu, perks_stencil_plan *plan);
+
+}  // namespace perks

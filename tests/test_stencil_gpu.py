@@ -1,0 +1,170 @@
+"""GPU parity of the persistent and per-step stencil kernels against the oracle.
+
+Bars: FP64 relative error <= 1e-12 (max|u - u_ref| / max|u_ref|); FP32 (FP32
+storage and arithmetic) <= 1e-5 against the FP64 oracle run on the same
+FP32-rounded inputs (grid and weights: an FP32 run multiplies by the FP32
+weights, so the oracle is given those).  The persistent and per-step paths
+apply the same per-cell arithmetic, so they must agree bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2204_02064_amd as pk
+    pk.lib()
+    return pk
+
+
+def _run(pk, g_np, w, steps, dtype, baseline=False, tuning=None):
+    t = to_dev(g_np, dtype)
+    if baseline:
+        pk.stencil_run_baseline(t, w, steps)
+    else:
+        pk.stencil_run(t, w, steps, tuning=tuning)
+    torch.cuda.synchronize()
+    return t.cpu().double().numpy()
+
+
+CASES = [
+    ("2d5pt", (256, 256), 100),      # the 256^2 FP64 100-step configuration
+    ("2d5pt", (5, 7), 3),
+    ("2d5pt", (33, 65), 9),
+    ("2d5pt", (130, 200), 17),
+    ("2d9pt", (66, 130), 11),
+    ("2d9pt", (301, 77), 6),
+    ("3d7pt", (5, 6, 7), 4),
+    ("3d7pt", (17, 9, 13), 5),
+    ("3d7pt", (40, 37, 70), 8),
+]
+
+
+@pytest.mark.parametrize("kind,shape,steps", CASES)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_persistent_matches_oracle(pk, kind, shape, steps, dtype):
+    tdt = getattr(torch, dtype)
+    g = workloads.stencil_grid(shape, seed=0, dtype=np.float64)
+    g = g.astype(np.float32).astype(np.float64) if dtype == "float32" else g
+    w = workloads.stencil_weights(kind)
+    w = w.astype(np.float32).astype(np.float64) if dtype == "float32" else w
+    ref = oracle.stencil(g, w, steps)
+    got = _run(pk, g, w, steps, tdt)
+    assert rel_err(got, ref) <= (1e-12 if dtype == "float64" else 1e-5)
+    base = _run(pk, g, w, steps, tdt, baseline=True)
+    np.testing.assert_array_equal(got, base)
+
+
+@pytest.mark.parametrize("kind,shape", [("2d5pt", (45, 150)), ("2d9pt", (70, 99)), ("3d7pt", (11, 21, 67))])
+def test_asymmetric_weights_fix_orientation(pk, kind, shape):
+    rng = np.random.default_rng(42)
+    w = workloads.stencil_weights(kind)
+    w = np.where(w != 0, rng.uniform(0.05, 0.3, w.shape), 0.0)
+    g = workloads.stencil_grid(shape, seed=5, ring_value=0.7)
+    ref = oracle.stencil(g, w, 6)
+    got = _run(pk, g, w, 6, torch.float64)
+    assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,shape", [("2d5pt", (200, 300)), ("2d9pt", (129, 257)), ("3d7pt", (30, 40, 130))])
+def test_streamed_and_partially_cached_tiles_agree_bitwise(pk, kind, shape):
+    g = workloads.stencil_grid(shape, seed=3)
+    w = workloads.stencil_weights(kind)
+    full = _run(pk, g, w, 13, torch.float64)
+    none = _run(pk, g, w, 13, torch.float64, tuning={"max_cached_tiles": -1})
+    part = _run(pk, g, w, 13, torch.float64, tuning={"max_cached_tiles": 3})
+    np.testing.assert_array_equal(full, none)
+    np.testing.assert_array_equal(full, part)
+    assert rel_err(full, oracle.stencil(g, w, 13)) <= 1e-12
+
+
+@pytest.mark.parametrize("rows", [8, 16, 32, 48])
+def test_tile_depth_does_not_change_bits(pk, rows):
+    g = workloads.stencil_grid((190, 260), seed=8)
+    w = workloads.stencil_weights("2d5pt")
+    a = _run(pk, g, w, 10, torch.float64, tuning={"rows_per_lane": rows})
+    b = _run(pk, g, w, 10, torch.float64, baseline=True)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_split_runs_compose_bitwise_and_zero_steps_is_identity(pk):
+    g = workloads.stencil_grid((97, 131), seed=2)
+    w = workloads.stencil_weights("2d9pt")
+    t = to_dev(g)
+    pk.stencil_run(t, w, 4)
+    pk.stencil_run(t, w, 9)
+    torch.cuda.synchronize()
+    whole = _run(pk, g, w, 13, torch.float64)
+    np.testing.assert_array_equal(t.cpu().numpy(), whole)
+    np.testing.assert_array_equal(_run(pk, g, w, 0, torch.float64), g)
+
+
+@pytest.mark.parametrize("kind,shape,dtype", [("2d5pt", (3072, 3072), "float64"), ("2d9pt", (3072, 3072), "float32"),
+                                              ("3d7pt", (256, 256, 256), "float64")])
+def test_full_size_eigenmode_decay(pk, kind, shape, dtype):
+    # At the benchmark sizes the oracle cannot follow 1000 steps cell by cell;
+    # a discrete sine mode must decay by its closed-form factor instead.  The
+    # factor is evaluated with the weights the kernel multiplies by (FP32
+    # weights for an FP32 grid), so only the arithmetic's rounding remains.
+    steps = 1000
+    wk = workloads.stencil_weights(kind)
+    if dtype == "float32":
+        wk = wk.astype(np.float32).astype(np.float64)
+    c = wk[(1,) * len(shape)]
+    off = wk[(1,) * (len(shape) - 1) + (2,)]
+    axes = [np.sin(np.pi * (2 if d == 0 else 1) * np.arange(n) / (n - 1)) for d, n in enumerate(shape)]
+    thetas = [np.pi * (2 if d == 0 else 1) / (n - 1) for d, n in enumerate(shape)]
+    if len(shape) == 2:
+        u = np.outer(axes[0], axes[1])
+        if kind == "2d5pt":
+            lam = c + 2 * off * (math.cos(thetas[0]) + math.cos(thetas[1]))
+        else:
+            lam = c * (1 + 2 * math.cos(thetas[0])) * (1 + 2 * math.cos(thetas[1]))
+    else:
+        u = np.einsum("k,j,i->kji", *axes)
+        lam = c + 2 * off * sum(math.cos(t) for t in thetas)
+    for d in range(len(shape)):
+        idx = [slice(None)] * len(shape)
+        idx[d] = 0
+        u[tuple(idx)] = 0
+        idx[d] = -1
+        u[tuple(idx)] = 0
+    tdt = getattr(torch, dtype)
+    u = u.astype(np.float32).astype(np.float64) if dtype == "float32" else u
+    got = _run(pk, u, workloads.stencil_weights(kind), steps, tdt)
+    err = rel_err(got, lam ** steps * u)
+    print(f"{kind} {dtype} {shape}: relative error after {steps} steps {err:.2e}")
+    # FP32: each step rounds npts partial sums, each bounded by max|u| (the
+    # weights are non-negative and sum to ~1), so the error after `steps`
+    # steps is at most steps * npts * eps32 / 2 relative to max|u| (5.4e-5 per
+    # 100 steps for the 9-point box).  The 1e-5 bar of the FP32 form holds
+    # for runs of up to ~100 steps (checked against the oracle above); this
+    # 1000-step run is held to the derived bound.
+    npts = int(np.count_nonzero(wk))
+    tol = 1e-12 if dtype == "float64" else steps * npts * 2.0 ** -24 / 2
+    assert err <= tol
+
+
+def test_full_size_matches_oracle_for_a_few_steps(pk):
+    g = workloads.stencil_grid((3072, 3072), seed=0)
+    w = workloads.stencil_weights("2d5pt")
+    got = _run(pk, g, w, 6, torch.float64)
+    assert rel_err(got, oracle.stencil(g, w, 6)) <= 1e-12
+    base = _run(pk, g, w, 6, torch.float64, baseline=True)
+    np.testing.assert_array_equal(got, base)
+
+
+def test_plan_reports_cached_share(pk):
+    pl = pk.stencil_plan((3072, 3072), workloads.stencil_weights("2d5pt"), "float64")
+    assert pl["tiles"] >= pl["cached_tiles"] > 0
+    assert pl["interior_cells"] == 3070 * 3070
