@@ -1,0 +1,146 @@
+"""GPU parity of the persistent and host-looped CG solvers against the oracle.
+
+Several iterates are correct when the rounding order differs, so parity is:
+the true relative residual ||b - A x|| / ||b|| (recomputed on the host from
+the returned x) meets tol, the returned x agrees with the oracle's solution
+within kappa * tol, and the iteration count is within max(2, 2%) of the
+oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2204_02064_amd as pk
+    pk.lib()
+    return pk
+
+
+def _dense_to_csr(A):
+    rowptr = [0]; cols = []; vals = []
+    for i in range(A.shape[0]):
+        nz = np.nonzero(A[i])[0]
+        cols.extend(nz.tolist()); vals.extend(A[i, nz].tolist())
+        rowptr.append(len(cols))
+    return np.array(rowptr, np.int32), np.array(cols, np.int32), np.array(vals)
+
+
+def _spd(n, kappa, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * np.geomspace(1.0, kappa, n)) @ Q.T
+    return 0.5 * (A + A.T)
+
+
+def _true_relres(rp, ci, v, b, x):
+    import scipy.sparse as sp
+    n = rp.size - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def _solve(pk, rp, ci, v, b, tol, maxit=5000, precond=None, baseline=False, x0=None):
+    A = pk.CsrMatrix(rp, ci, v)
+    bd = to_dev(b)
+    xd = to_dev(np.zeros_like(b) if x0 is None else x0)
+    fn = pk.cg_solve_baseline if baseline else pk.cg_solve
+    info = fn(A, bd, xd, tol=tol, maxit=maxit, precond=precond)
+    torch.cuda.synchronize()
+    return xd.cpu().numpy(), info
+
+
+def _iters_close(a, b):
+    return abs(a - b) <= max(2, math.ceil(0.02 * b))
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+@pytest.mark.parametrize("n,kappa,seed", [(8, 10.0, 1), (40, 50.0, 2), (64, 100.0, 3)])
+def test_tiny_spd_matches_direct_solve(pk, baseline, n, kappa, seed):
+    A = _spd(n, kappa, seed)
+    rp, ci, v = _dense_to_csr(A)
+    b = np.random.default_rng(seed).uniform(-1, 1, n)
+    x, info = _solve(pk, rp, ci, v, b, 1e-12, maxit=500, baseline=baseline)
+    assert info["status"] == "converged"
+    xs = oracle.chol_solve(A, b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-11
+    _, oinfo = oracle.cg(rp, ci, v, b, tol=1e-12, maxit=500)
+    assert _iters_close(info["iters"], oinfo["iters"])
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d", "random"])
+def test_matches_oracle(pk, baseline, precond, case):
+    if case == "poisson2d":
+        rp, ci, v = workloads.poisson_csr(90, 2)
+    elif case == "poisson3d":
+        rp, ci, v = workloads.poisson_csr(24, 3)
+    else:
+        rp, ci, v = workloads.random_spd_csr(30000, seed=1)
+    n = rp.size - 1
+    b = workloads.rhs_uniform(n, seed=0)
+    x, info = _solve(pk, rp, ci, v, b, 1e-10, precond=precond, baseline=baseline)
+    xo, oinfo = oracle.cg(rp, ci, v, b, tol=1e-10, maxit=5000, precond=precond)
+    assert info["status"] == "converged" and oinfo["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x) <= 1e-10
+    assert abs(info["relres_true"] - _true_relres(rp, ci, v, b, x)) <= 1e-12
+    assert _iters_close(info["iters"], oinfo["iters"]), (info["iters"], oinfo["iters"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_m_distinct_eigenvalues_take_m_steps(pk):
+    m, n = 4, 3000
+    eig = np.array([1.0 + 2.5 * (i % m) for i in range(n)])
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    b = np.random.default_rng(0).uniform(0.5, 1.5, n)
+    x, info = _solve(pk, rp, ci, eig, b, 1e-13)
+    assert info["iters"] == m
+    np.testing.assert_allclose(x, b / eig, rtol=1e-12)
+
+
+def test_edge_cases(pk):
+    rp, ci, v = workloads.poisson_csr(30, 2)
+    n = rp.size - 1
+    x, info = _solve(pk, rp, ci, v, np.zeros(n), 1e-10)
+    assert info["status"] == "converged" and info["iters"] == 0 and not x.any()
+    x, info = _solve(pk, rp, ci, v, np.ones(n), 1e-10, maxit=0)
+    assert info["status"] == "not_converged" and not x.any()
+    d = np.tile(np.array([1.0, -2.0, 3.0]), 700)
+    rpd = np.arange(d.size + 1, dtype=np.int32)
+    b = np.zeros(d.size); b[1] = 1.0
+    _, info = _solve(pk, rpd, rpd[:-1].copy(), d, b, 1e-10)
+    assert info["status"] == "breakdown"
+
+
+def test_warm_start_continues(pk):
+    rp, ci, v = workloads.poisson_csr(60, 2)
+    b = workloads.rhs_uniform(rp.size - 1, seed=4)
+    x1, i1 = _solve(pk, rp, ci, v, b, 1e-10, maxit=40)
+    assert i1["status"] == "not_converged" and i1["iters"] == 40
+    x2, i2 = _solve(pk, rp, ci, v, b, 1e-10, x0=x1)
+    assert i2["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x2) <= 1e-10
+
+
+def test_full_size_poisson_128(pk):
+    # the 128^3 benchmark system: n = 2,097,152, nnz = 14,581,760
+    rp, ci, v = workloads.poisson_csr(128, 3)
+    b = workloads.rhs_uniform(rp.size - 1, seed=0)
+    x, info = _solve(pk, rp, ci, v, b, 1e-10)
+    assert info["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x) <= 1e-10
+    # CG on this system needs at most the sqrt(kappa) bound: ~975 iterations
+    assert info["iters"] <= 1000
+    xb, ib = _solve(pk, rp, ci, v, b, 1e-10, baseline=True)
+    assert ib["status"] == "converged" and _iters_close(info["iters"], ib["iters"])
