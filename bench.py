@@ -64,6 +64,44 @@ def cpu_baseline(target_s=10.0):
             "sample": f"2d5pt 3072^2 FP64, {k} Jacobi steps ({dt:.1f} s), single thread"}
 
 
+def bench_cg(pk, torch, args):
+    """CG time-to-tolerance, persistent vs host-looped, FP64, x0 = 0."""
+    import numpy as np
+
+    import workloads
+    systems = [("poisson3d 128^3", lambda: workloads.poisson_csr(128, 3))]
+    if args.cg_random:
+        systems.append(("random SPD n=1M lognormal(12,1)", lambda: workloads.random_spd_csr(1 << 20, seed=0)))
+    out = []
+    for name, make in systems:
+        rp, ci, v = make()
+        n = rp.size - 1
+        A = pk.CsrMatrix(rp, ci, v)
+        b = torch.from_numpy(workloads.rhs_uniform(n, seed=0)).cuda()
+        for tol in (1e-10, 1e-8):
+            rec = {"system": name, "n": int(n), "nnz": int(ci.size), "tol": tol}
+            for label, fn in (("persistent", pk.cg_solve), ("baseline", pk.cg_solve_baseline)):
+                x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                fn(A, b, x, tol=tol, maxit=5000)               # warm-up (allocations, caches)
+                times = []
+                for _ in range(max(1, min(args.steps, 3))):
+                    x.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = fn(A, b, x, tol=tol, maxit=5000)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                t = float(np.median(times))
+                rec[label] = {"seconds": t, "iters": info["iters"], "us_per_iter": t / max(1, info["iters"]) * 1e6,
+                              "relres_true": info["relres_true"], "status": info["status"]}
+            rec["speedup"] = rec["baseline"]["seconds"] / rec["persistent"]["seconds"]
+            log(f"CG {name} tol {tol:.0e}: persistent {rec['persistent']['seconds']*1e3:.2f} ms "
+                f"({rec['persistent']['iters']} it, {rec['persistent']['us_per_iter']:.1f} us/it)  baseline "
+                f"{rec['baseline']['seconds']*1e3:.2f} ms ({rec['baseline']['iters']} it)  x{rec['speedup']:.2f}")
+            out.append(rec)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +110,8 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cases", default="all")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--cg-random", action="store_true", help="also the n=1M random SPD system")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the method and this "
@@ -182,6 +222,8 @@ def main():
         base_time = sum(r["baseline_ms"] for r in results) / 1e3
         out["baseline_value"] = sum(interior(c[1]) * STENCIL_STEPS for c in cases) / base_time / 1e9
         out["speedup_vs_per_step_launch"] = value / out["baseline_value"]
+    if not args.no_cg:
+        out["cg"] = bench_cg(pk, torch, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

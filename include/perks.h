@@ -61,7 +61,7 @@ typedef struct {
 typedef struct perks_tuning {
     int32_t waves_per_wg;     /* wavefronts per workgroup (1..16)                      */
     int32_t wgs_per_cu;       /* co-resident workgroups per CU used by the plan        */
-    int32_t rows_per_lane;    /* cells each lane keeps along y (tile depth)            */
+    int32_t rows_per_lane;    /* cells each lane keeps in registers along y            */
     int32_t planes_per_lane;  /* 3D: cells each lane keeps along z                     */
     int32_t sync;             /* 0 auto, 1 grid barrier, 2 neighbour flags             */
     int32_t max_cached_tiles; /* <0: none cached (all tiles stream through HBM);
@@ -80,8 +80,8 @@ typedef struct {
     int64_t cached_cells;     /* interior cells held on chip                          */
     int64_t interior_cells;
     int64_t halo_bytes_per_step;  /* face traffic written + read per step             */
-    int32_t sync;
-    int32_t reserved;
+    int32_t sync;             /* 1 grid barrier per step, 2 point-to-point halo words */
+    int32_t lds_rows_per_lane;/* rows of each cached tile held in LDS (PERKS_MIX)     */
 } perks_stencil_plan;
 
 /*

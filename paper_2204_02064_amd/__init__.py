@@ -45,7 +45,7 @@ class StencilPlan(ctypes.Structure):
                 ("tiles", ctypes.c_int64), ("cached_tiles", ctypes.c_int64),
                 ("cached_cells", ctypes.c_int64), ("interior_cells", ctypes.c_int64),
                 ("halo_bytes_per_step", ctypes.c_int64), ("sync", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lds_rows_per_lane", ctypes.c_int32)]
 
 
 class Csr(ctypes.Structure):

@@ -31,7 +31,8 @@ const char *last_error();
 // Growing frees the old buffer (which synchronises the device).
 enum ScratchSlot {
     SLOT_SYNC = 0,      // barrier words (kept zero-initialised)
-    SLOT_FACES,         // stencil halo faces
+    SLOT_FACES,         // stencil halo faces (raw values, barrier mode)
+    SLOT_FACES_LL,      // stencil halo faces (epoch-tagged words, point-to-point mode)
     SLOT_PINGPONG,      // per-step baseline's second grid
     SLOT_CG_VEC,        // CG work vectors
     SLOT_CG_PART,       // CG partition table / partial sums
@@ -43,7 +44,8 @@ void *scratch(int slot, size_t bytes);
 // Barrier workspace layout (32-bit words).  Flags are packed: one word per
 // workgroup, written by that workgroup only.
 constexpr int SYNC_GEN = 0;           // generation word released by the master
-constexpr int SYNC_EPOCH = 64;        // epoch carried from one launch to the next
+constexpr int SYNC_EPOCH = 64;        // barrier epoch carried from one launch to the next
+constexpr int SYNC_LL_EPOCH = 96;     // LL face epoch carried from one launch to the next
 constexpr int SYNC_AUX = 128;         // small device-side results (CG scalars, ...)
 constexpr int SYNC_FLAGS = 1024;      // flags[wg]
 constexpr int SYNC_MAX_WGS = 8192;

@@ -22,7 +22,19 @@
 #include "barrier.hpp"
 #include "common.hpp"
 
+#ifndef PERKS_SCHED_ROWS
+#define PERKS_SCHED_ROWS 4
+#endif
+
 namespace perks {
+
+// Rows of a cached tile that may live in LDS (the PERKS_MIX tier), per wave:
+// 8 waves x (28 x 64) doubles or (56 x 64) floats = 112 KiB, next to the halo
+// columns.
+template <typename T>
+struct LdsRows {
+    static constexpr int value = sizeof(T) == 8 ? 28 : 56;
+};
 
 template <typename T>
 struct Weights2D {
@@ -109,7 +121,9 @@ __device__ __forceinline__ T compute_rows(T (&u)[RC], int nrows, RowVal<T> &abov
             cw = nw;
             ce = ne;
         }
-        __builtin_amdgcn_sched_barrier(0);
+        // bound how far the scheduler may hoist loads and products across
+        // rows: every hoisted row costs registers the cache needs
+        if ((i % PERKS_SCHED_ROWS) == PERKS_SCHED_ROWS - 1) __builtin_amdgcn_sched_barrier(0);
     }
     return last;
 }
@@ -130,10 +144,13 @@ struct Stencil2DParams {
     long long steps;
     int nx, ny;
     int ntx, nty;
-    int R;             // tile height (rows per lane)
+    int R;             // tile height H (rows per lane): register rows + LDS rows
+    int RL;            // rows of a cached tile kept in LDS (rows RREG .. H-1)
     int last_w, last_h;
     int ntiles;
     int cached;        // number of tiles held in registers (tile id < cached)
+    unsigned epoch0;   // LL mode: epoch of the initial faces (state 0)
+    unsigned ering;    // LL mode: epoch of the fixed ring words of this launch
     Weights2D<T> W;
 };
 
@@ -243,17 +260,193 @@ __device__ void publish_initial(const Stencil2DParams<T> &p, const Tile2D &tl, i
     }
 }
 
-// One step of one tile whose cells live in registers v.
-template <typename T, int R, bool BOX>
-__device__ __forceinline__ void step_cached(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
-                                            T (&v)[R], T *lw, T *le) {
+// ---------------------------------------------------------------------------
+// Low-latency (LL) face exchange: point-to-point synchronisation instead of a
+// device-wide barrier.  Every face element is stored as 64-bit words that
+// carry 32 data bits and the epoch of the state they belong to (FP32: one
+// word, FP64: two).  Aligned 64-bit stores and loads are single-copy atomic,
+// so a reader that sees the expected epoch in a word also sees its data: the
+// reader polls the halo words themselves, and a step needs no barrier and no
+// separate flag round trip.  Ring entries carry an epoch reserved for this
+// launch (every launch takes a fresh range of epochs, so a word left by an
+// earlier launch, whose layout may differ, is never taken as current).  Neighbour
+// dependencies are symmetric (a tile only polls the tiles that also poll it),
+// so no tile can run two steps ahead of a reader and overwrite words of a
+// parity buffer that reader still needs.
+typedef unsigned long long llword;
+
+template <typename T>
+struct LLTraits {
+    static constexpr int WPE = sizeof(T) / 4;   // 64-bit words per element
+};
+
+template <typename T>
+__device__ __forceinline__ void ll_store(llword *w, T v, unsigned e) {
+    const llword tag = (llword)e << 32;
+    if constexpr (sizeof(T) == 4) {
+        st_coh(w, tag | __float_as_uint(v));
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        st_coh(w, tag | (unsigned)b);
+        st_coh(w + 1, tag | (unsigned)(b >> 32));
+    }
+}
+
+// Loads one element; clears ok when `need` and a word is neither of epoch e
+// nor a ring word of this launch (epoch er).
+template <typename T>
+__device__ __forceinline__ T ll_load(const llword *w, unsigned e, unsigned er, bool need, bool &ok) {
+    if constexpr (sizeof(T) == 4) {
+        const llword a = ld_coh(w);
+        const unsigned f = (unsigned)(a >> 32);
+        if (need && f != e && f != er) ok = false;
+        return __uint_as_float((unsigned)a);
+    } else {
+        const llword a = ld_coh(w), b = ld_coh(w + 1);
+        const unsigned fa = (unsigned)(a >> 32), fb = (unsigned)(b >> 32);
+        if (need && ((fa != e && fa != er) || (fb != e && fb != er))) ok = false;
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)b << 32) | (unsigned)a));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ llword *ll_row(const Stencil2DParams<T> &p, int par, int slot) {
+    return reinterpret_cast<llword *>(p.rowbuf) + rb_off(p, par, slot) * LLTraits<T>::WPE;
+}
+template <typename T>
+__device__ __forceinline__ llword *ll_col(const Stencil2DParams<T> &p, int par, int slot) {
+    return reinterpret_cast<llword *>(p.colbuf) + cb_off(p, par, slot) * LLTraits<T>::WPE;
+}
+
+// Polls the halo of tile tl (parity par, epoch e) until every word it needs
+// is current.  The 5-point star needs no corner: ghost lanes and the end
+// entries of the columns are then not waited for (a diagonal tile does not
+// depend on this one either).
+template <typename T, bool BOX>
+__device__ __forceinline__ void load_halo_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int par, unsigned e,
+                                             int lane, T &hn, T &hs, T *lw, T *le) {
+    constexpr int WPE = LLTraits<T>::WPE;
+    const int xl = min(tl.x0 + lane, p.nx - 1);
+    const bool need_row = lane < tl.wx || (BOX && lane == tl.wx);
+    const llword *rn = ll_row(p, par, 2 * tl.ty) + (size_t)xl * WPE;
+    const llword *rs = ll_row(p, par, 2 * tl.ty + 3) + (size_t)xl * WPE;
+    const llword *cw = ll_col(p, par, 2 * tl.tx) + (size_t)(tl.y0 - 1) * WPE;
+    const llword *ce = ll_col(p, par, 2 * tl.tx + 3) + (size_t)(tl.y0 - 1) * WPE;
+    const int jlo = BOX ? 0 : 1, jhi = BOX ? tl.hy + 2 : tl.hy + 1;
+    while (true) {
+        bool ok = true;
+        hn = ll_load<T>(rn, e, p.ering, need_row, ok);
+        hs = ll_load<T>(rs, e, p.ering, need_row, ok);
+        for (int j = lane; j < tl.hy + 2; j += 64) {
+            const bool need = j >= jlo && j < jhi;
+            lw[j] = ll_load<T>(cw + (size_t)j * WPE, e, p.ering, need, ok);
+            le[j] = ll_load<T>(ce + (size_t)j * WPE, e, p.ering, need, ok);
+        }
+        if (__all(ok)) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    compiler_fence();
+}
+
+// Edge rows of a strip go straight out; edge column values are gathered in
+// LDS (ow / oe, indexed by tile row) and stored coalesced by publish_cols_ll.
+template <typename T, int RC, bool FULL>
+__device__ __forceinline__ void publish_rows_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int par, unsigned e,
+                                                int lane, const T (&u)[RC], int r0, int n, T lastval, T *ow, T *oe) {
+    constexpr int WPE = LLTraits<T>::WPE;
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        if (FULL || i < n) {
+            if (lane == 0) ow[r0 + i] = u[i];
+            if (lane == tl.wx - 1) oe[r0 + i] = u[i];
+        }
+    }
+    if (lane < tl.wx) {
+        const size_t xo = (size_t)(tl.x0 + lane) * WPE;
+        if (r0 == 0) ll_store(ll_row(p, par, 2 * tl.ty + 1) + xo, u[0], e);
+        if (r0 + n == tl.hy) ll_store(ll_row(p, par, 2 * tl.ty + 2) + xo, lastval, e);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void publish_cols_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int par, unsigned e,
+                                                int lane, const T *ow, const T *oe) {
+    constexpr int WPE = LLTraits<T>::WPE;
+    compiler_fence();
+    llword *cl = ll_col(p, par, 2 * tl.tx + 1) + (size_t)tl.y0 * WPE;
+    llword *cr = ll_col(p, par, 2 * tl.tx + 2) + (size_t)tl.y0 * WPE;
+    for (int j = lane; j < tl.hy; j += 64) {
+        ll_store(cl + (size_t)j * WPE, ow[j], e);
+        ll_store(cr + (size_t)j * WPE, oe[j], e);
+    }
+    compiler_fence();
+}
+
+template <typename T>
+__device__ void init_ring_faces_ll(const Stencil2DParams<T> &p) {
+    constexpr int WPE = LLTraits<T>::WPE;
+    const T *g = p.grid;
+    const int nthreads = gridDim.x * blockDim.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nrs = 2 * p.nty + 2, ncs = 2 * p.ntx + 2;
+    for (int par = 0; par < 2; ++par) {
+        for (int x = tid; x < p.nx; x += nthreads) {
+            ll_store(ll_row(p, par, 0) + (size_t)x * WPE, g[x], p.ering);
+            ll_store(ll_row(p, par, nrs - 1) + (size_t)x * WPE, g[(size_t)(p.ny - 1) * p.nx + x], p.ering);
+        }
+        for (int y = tid; y < p.ny; y += nthreads) {
+            ll_store(ll_col(p, par, 0) + (size_t)y * WPE, g[(size_t)y * p.nx], p.ering);
+            ll_store(ll_col(p, par, ncs - 1) + (size_t)y * WPE, g[(size_t)y * p.nx + p.nx - 1], p.ering);
+        }
+        for (int s = tid; s < nrs - 2; s += nthreads) {
+            const int ty = s / 2;
+            const int y = (s % 2 == 0) ? 1 + p.R * ty : 1 + p.R * ty + ((ty == p.nty - 1) ? p.last_h : p.R) - 1;
+            ll_store(ll_row(p, par, s + 1), g[(size_t)y * p.nx], p.ering);
+            ll_store(ll_row(p, par, s + 1) + (size_t)(p.nx - 1) * WPE, g[(size_t)y * p.nx + p.nx - 1], p.ering);
+        }
+        for (int s = tid; s < ncs - 2; s += nthreads) {
+            const int tx = s / 2;
+            const int x = (s % 2 == 0) ? 1 + 64 * tx : 1 + 64 * tx + ((tx == p.ntx - 1) ? p.last_w : 64) - 1;
+            ll_store(ll_col(p, par, s + 1), g[x], p.ering);
+            ll_store(ll_col(p, par, s + 1) + (size_t)(p.ny - 1) * WPE, g[(size_t)(p.ny - 1) * p.nx + x], p.ering);
+        }
+    }
+}
+
+template <typename T>
+__device__ void publish_initial_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
+    constexpr int WPE = LLTraits<T>::WPE;
+    const T *g = p.grid;
+    const unsigned e = p.epoch0;
+    if (lane < tl.wx) {
+        const size_t xo = (size_t)(tl.x0 + lane) * WPE;
+        ll_store(ll_row(p, 0, 2 * tl.ty + 1) + xo, g[(size_t)tl.y0 * p.nx + tl.x0 + lane], e);
+        ll_store(ll_row(p, 0, 2 * tl.ty + 2) + xo, g[(size_t)(tl.y0 + tl.hy - 1) * p.nx + tl.x0 + lane], e);
+    }
+    for (int j = lane; j < tl.hy; j += 64) {
+        const size_t row = (size_t)(tl.y0 + j) * p.nx;
+        ll_store(ll_col(p, 0, 2 * tl.tx + 1) + (size_t)(tl.y0 + j) * WPE, g[row + tl.x0], e);
+        ll_store(ll_col(p, 0, 2 * tl.tx + 2) + (size_t)(tl.y0 + j) * WPE, g[row + tl.x0 + tl.wx - 1], e);
+    }
+}
+
+// One step of a cached tile: rows 0..RREG-1 live in registers v, rows
+// RREG..hy-1 (at most p.RL) in this wave's LDS rows lt[r][lane] (the
+// register + shared-memory cache of PERKS_MIX).  In LL mode the halo is
+// polled (epoch e_in) and the faces are tagged e_in + 1; otherwise the step is
+// bracketed by device-wide barriers.
+template <typename T, int RREG, bool BOX, bool LL>
+__device__ __forceinline__ void step_cached(const Stencil2DParams<T> &p, const Tile2D &tl, int par, unsigned e_in,
+                                            int lane, T (&v)[RREG], T *lt, T *lw, T *le, T *ow, T *oe) {
     T hn, hs;
-    load_halo(p, tl, par, lane, hn, hs, lw, le);
-    if (tl.wx < 64 && lane >= tl.wx) {
+    if constexpr (LL) load_halo_ll<T, BOX>(p, tl, par, e_in, lane, hn, hs, lw, le);
+    else load_halo(p, tl, par, lane, hn, hs, lw, le);
+    const bool ghost = lane >= tl.wx;
+    if (tl.wx < 64 && ghost) {
         // ghost lanes carry the east halo column so the DPP east shift of the
         // last real lane picks it up
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = le[i + 1];
+        for (int i = 0; i < RREG; ++i) v[i] = le[i + 1];
         hn = le[0];
         hs = le[tl.hy + 1];
     }
@@ -261,13 +454,45 @@ __device__ __forceinline__ void step_cached(const Stencil2DParams<T> &p, const T
     above.c = hn;
     above.w = from_west(hn, lw[0]);
     above.e = from_east(hn, le[0]);
-    if (tl.hy == R) {
-        const T last = compute_rows<T, R, BOX, true>(v, R, above, hs, lw, le, p.W);
-        publish_rows<T, R, true>(p, tl, par ^ 1, lane, v, 0, R, last);
+    const int nreg = min(RREG, tl.hy);
+    // old value of the row below the register rows
+    T below = hs;
+    if (tl.hy > RREG) below = ghost ? le[RREG + 1] : lt[lane];
+    const unsigned e_out = e_in + 1;
+    if (nreg == RREG) {
+        const T last = compute_rows<T, RREG, BOX, true>(v, RREG, above, below, lw, le, p.W);
+        if constexpr (LL) publish_rows_ll<T, RREG, true>(p, tl, par ^ 1, e_out, lane, v, 0, RREG, last, ow, oe);
+        else publish_rows<T, RREG, true>(p, tl, par ^ 1, lane, v, 0, RREG, last);
     } else {
-        const T last = compute_rows<T, R, BOX, false>(v, tl.hy, above, hs, lw, le, p.W);
-        publish_rows<T, R, false>(p, tl, par ^ 1, lane, v, 0, tl.hy, last);
+        const T last = compute_rows<T, RREG, BOX, false>(v, nreg, above, below, lw, le, p.W);
+        if constexpr (LL) publish_rows_ll<T, RREG, false>(p, tl, par ^ 1, e_out, lane, v, 0, nreg, last, ow, oe);
+        else publish_rows<T, RREG, false>(p, tl, par ^ 1, lane, v, 0, nreg, last);
     }
+    // LDS rows, 8 at a time, updated in place (the rolling `above` keeps the
+    // old last row of the previous chunk)
+    constexpr int CH = 8;
+    for (int c = RREG; c < tl.hy; c += CH) {
+        const int n = min(CH, tl.hy - c);
+        T *lr = lt + (c - RREG) * 64 + lane;
+        T u[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) u[i] = (i < n) ? (ghost ? le[c + i + 1] : lr[i * 64]) : T(0);
+        T bl = hs;
+        if (c + n < tl.hy) bl = ghost ? le[c + n + 1] : lr[n * 64];
+        const T last = (n == CH) ? compute_rows<T, CH, BOX, true>(u, CH, above, bl, lw + c, le + c, p.W)
+                                 : compute_rows<T, CH, BOX, false>(u, n, above, bl, lw + c, le + c, p.W);
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < n) lr[i * 64] = u[i];
+        if constexpr (LL) {
+            if (n == CH) publish_rows_ll<T, CH, true>(p, tl, par ^ 1, e_out, lane, u, c, CH, last, ow, oe);
+            else publish_rows_ll<T, CH, false>(p, tl, par ^ 1, e_out, lane, u, c, n, last, ow, oe);
+        } else {
+            if (n == CH) publish_rows<T, CH, true>(p, tl, par ^ 1, lane, u, c, CH, last);
+            else publish_rows<T, CH, false>(p, tl, par ^ 1, lane, u, c, n, last);
+        }
+    }
+    if constexpr (LL) publish_cols_ll(p, tl, par ^ 1, e_out, lane, ow, oe);
 }
 
 // One step of a tile that lives in the grid (the uncached part, Eq. 5's
@@ -275,11 +500,12 @@ __device__ __forceinline__ void step_cached(const Stencil2DParams<T> &p, const T
 // In-place is safe because neighbours read this tile only through the face
 // buffers, and the rolling `above` state keeps the old value of the last row
 // of the previous chunk.
-template <typename T, int CH, bool BOX>
-__device__ __forceinline__ void step_streamed(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
-                                              T *lw, T *le) {
+template <typename T, int CH, bool BOX, bool LL>
+__device__ __forceinline__ void step_streamed(const Stencil2DParams<T> &p, const Tile2D &tl, int par, unsigned e_in,
+                                              int lane, T *lw, T *le, T *ow, T *oe) {
     T hn, hs;
-    load_halo(p, tl, par, lane, hn, hs, lw, le);
+    if constexpr (LL) load_halo_ll<T, BOX>(p, tl, par, e_in, lane, hn, hs, lw, le);
+    else load_halo(p, tl, par, lane, hn, hs, lw, le);
     const bool ghost = lane >= tl.wx;
     const int xl = min(tl.x0 + lane, p.nx - 1);
     if (ghost) {
@@ -306,30 +532,52 @@ __device__ __forceinline__ void step_streamed(const Stencil2DParams<T> &p, const
             for (int i = 0; i < CH; ++i)
                 if (i < n) row0[(size_t)i * p.nx] = u[i];
         }
-        if (n == CH)
-            publish_rows<T, CH, true>(p, tl, par ^ 1, lane, u, c, CH, last);
-        else
-            publish_rows<T, CH, false>(p, tl, par ^ 1, lane, u, c, n, last);
+        if constexpr (LL) {
+            if (n == CH) publish_rows_ll<T, CH, true>(p, tl, par ^ 1, e_in + 1, lane, u, c, CH, last, ow, oe);
+            else publish_rows_ll<T, CH, false>(p, tl, par ^ 1, e_in + 1, lane, u, c, n, last, ow, oe);
+        } else {
+            if (n == CH) publish_rows<T, CH, true>(p, tl, par ^ 1, lane, u, c, CH, last);
+            else publish_rows<T, CH, false>(p, tl, par ^ 1, lane, u, c, n, last);
+        }
     }
+    if constexpr (LL) publish_cols_ll(p, tl, par ^ 1, e_in + 1, lane, ow, oe);
 }
 
 // The persistent kernel: one launch runs all steps.  Tiles t < p.cached are
 // kept in registers by wave t for the whole run; the remaining tiles are
-// assigned round-robin to all waves and streamed through the grid.
-template <typename T, int R, bool BOX, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void stencil2d_persistent(Stencil2DParams<T> p) {
-    __shared__ T lds[WAVES][2][R + 2];
+// assigned round-robin to all waves and streamed through the grid.  LL selects
+// point-to-point halo synchronisation; otherwise every step ends with a
+// device-wide barrier.
+template <typename T, int R, bool BOX, int WAVES, bool LL>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void stencil2d_persistent(
+    Stencil2DParams<T> p) {
+    constexpr int HMAX = R + LdsRows<T>::value;
+    __shared__ T lds[WAVES][4][HMAX + 2];
+    __shared__ T ltile[WAVES][LdsRows<T>::value * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * WAVES + wave;
     const int nwaves = gridDim.x * WAVES;
     T *lw = lds[wave][0];
     T *le = lds[wave][1];
+    T *ow = lds[wave][2];
+    T *oe = lds[wave][3];
+    T *lt = ltile[wave];
     GridSync gs;
     gs.init(p.sync);
-
-    init_ring_faces(p, p.grid);
-    for (int t = gw; t < p.ntiles; t += nwaves) publish_initial(p, tile_of(p, t), lane);
+    if constexpr (LL) {
+        // this launch's epochs: ering (ring words), epoch0 .. epoch0+steps
+        // (states); all above the last epoch of the previous launch and above
+        // 0, the epoch of freshly zeroed words
+        const unsigned base = ld_coh(p.sync + SYNC_LL_EPOCH);
+        p.ering = base + 1u;
+        p.epoch0 = base + 2u;
+        init_ring_faces_ll(p);
+        for (int t = gw; t < p.ntiles; t += nwaves) publish_initial_ll(p, tile_of(p, t), lane);
+    } else {
+        init_ring_faces(p, p.grid);
+        for (int t = gw; t < p.ntiles; t += nwaves) publish_initial(p, tile_of(p, t), lane);
+    }
     gs.sync();
 
     const bool has_cached = gw < p.cached;
@@ -340,23 +588,30 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
         const int xl = min(ct.x0 + lane, p.nx - 1);
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = (i < ct.hy) ? p.grid[(size_t)(ct.y0 + i) * p.nx + xl] : T(0);
+        for (int i = R; i < ct.hy; ++i) lt[(i - R) * 64 + lane] = p.grid[(size_t)(ct.y0 + i) * p.nx + xl];
     }
     const int first_streamed = p.cached + gw;
     for (long long s = 0; s < p.steps; ++s) {
         const int par = (int)(s & 1);
+        const unsigned e_in = p.epoch0 + (unsigned)s;
         Stencil2DParams<T> q = p;
         q.grid = opaque(q.grid);
         q.rowbuf = opaque(q.rowbuf);
         q.colbuf = opaque(q.colbuf);
-        if (has_cached) step_cached<T, R, BOX>(q, ct, par, lane, v, lw, le);
+        if (has_cached) step_cached<T, R, BOX, LL>(q, ct, par, e_in, lane, v, lt, lw, le, ow, oe);
         for (int t = first_streamed; t < p.ntiles; t += nwaves)
-            step_streamed<T, 8, BOX>(q, tile_of(p, t), par, lane, lw, le);
-        gs.sync();
+            step_streamed<T, 8, BOX, LL>(q, tile_of(p, t), par, e_in, lane, lw, le, ow, oe);
+        if constexpr (!LL) gs.sync();
     }
     if (has_cached && lane < ct.wx) {
 #pragma unroll
         for (int i = 0; i < R; ++i)
             if (i < ct.hy) p.grid[(size_t)(ct.y0 + i) * p.nx + ct.x0 + lane] = v[i];
+        for (int i = R; i < ct.hy; ++i) p.grid[(size_t)(ct.y0 + i) * p.nx + ct.x0 + lane] = lt[(i - R) * 64 + lane];
+    }
+    if constexpr (LL) {
+        // the next launch starts its epochs above every word written here
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(p.sync + SYNC_LL_EPOCH, p.epoch0 + (unsigned)p.steps);
     }
     gs.finish();
 }
@@ -414,20 +669,23 @@ template <> struct RList<double> { static constexpr int v[4] = {8, 16, 32, 48}; 
 template <> struct RList<float> { static constexpr int v[5] = {8, 16, 32, 48, 64}; };
 
 template <typename T, int R, bool BOX>
-const void *persist2d_fn() { return reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2>); }
+const void *persist2d_fn(bool ll) {
+    return ll ? reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2, true>)
+              : reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2, false>);
+}
 
 template <typename T, bool BOX>
-const void *pick2d(int R) {
+const void *pick2d(int R, bool ll) {
     switch (R) {
-        case 8: return persist2d_fn<T, 8, BOX>();
-        case 16: return persist2d_fn<T, 16, BOX>();
-        case 32: return persist2d_fn<T, 32, BOX>();
-        case 48: return persist2d_fn<T, 48, BOX>();
+        case 8: return persist2d_fn<T, 8, BOX>(ll);
+        case 16: return persist2d_fn<T, 16, BOX>(ll);
+        case 32: return persist2d_fn<T, 32, BOX>(ll);
+        case 48: return persist2d_fn<T, 48, BOX>(ll);
         default: break;
     }
     if constexpr (std::is_same<T, float>::value) {
         switch (R) {
-            case 64: return persist2d_fn<T, 64, BOX>();
+            case 64: return persist2d_fn<T, 64, BOX>(ll);
             default: break;
         }
     }
@@ -435,7 +693,8 @@ const void *pick2d(int R) {
 }
 
 struct Plan2D {
-    int R = 0, wgs = 0, ntx = 0, nty = 0, last_w = 0, last_h = 0, ntiles = 0, cached = 0;
+    int R = 0, RL = 0, wgs = 0, ntx = 0, nty = 0, last_w = 0, last_h = 0, ntiles = 0, cached = 0;
+    bool ll = true;       // point-to-point halo synchronisation (else a grid barrier per step)
     const void *fn = nullptr;
 };
 
@@ -451,40 +710,49 @@ int plan2d(const perks_shape &s, bool box, const perks_tuning *tu, Plan2D *pl) {
     const int wgs_per_cu = (tu && tu->wgs_per_cu > 0) ? tu->wgs_per_cu : 1;
     if (tu && tu->waves_per_wg != 0 && tu->waves_per_wg != W2)
         return set_error(PERKS_E_UNSUPPORTED, "2D persistent kernels use %d waves per workgroup", W2);
-    int chosen = 0;
+    if (tu && (tu->sync < 0 || tu->sync > 2)) return set_error(PERKS_E_INVAL, "sync must be 0, 1 or 2");
+    pl->ll = !(tu && tu->sync == 1);
+    const long long cap = (long long)f.cus * wgs_per_cu * W2;   // co-resident waves = cacheable tiles
+    // smallest tile height H with every tile cached: the fewest rows of serial
+    // work per wave.  Register rows come from the instantiated depths; above the
+    // deepest one the tile continues in LDS (at most LdsRows rows); whatever is
+    // still left over streams through HBM.
+    const long long per_col = std::max<long long>(1, cap / pl->ntx);
+    const int h_min = (int)std::max<long long>(1, (nyi + per_col - 1) / per_col);
+    int chosen = 0, rl = 0, deepest = 0;
     for (int r : RList<T>::v) {
-        const void *fn = pick2d<T, false>(r);
+        const void *fn = box ? pick2d<T, true>(r, pl->ll) : pick2d<T, false>(r, pl->ll);
         if (!fn) continue;
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, box ? pick2d<T, true>(r) : fn, W2 * 64, 0) !=
-                hipSuccess ||
-            occ < wgs_per_cu)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, W2 * 64, 0) != hipSuccess || occ < wgs_per_cu)
             continue;
-        const long long cap = (long long)f.cus * wgs_per_cu * W2;
-        const long long nt = (long long)pl->ntx * ((nyi + r - 1) / r);
+        deepest = r;
         if (want_r) {
             if (r == want_r) chosen = r;
-        } else if (nt <= cap) {
+        } else if (!chosen && r >= h_min) {
             chosen = r;
-            break;
-        } else {
-            chosen = r;  // largest that runs; tiles beyond the capacity stream
         }
+    }
+    if (!chosen && !want_r && deepest) {
+        chosen = deepest;
+        const int lds_rows = (tu && tu->max_cached_tiles < 0) ? 0 : LdsRows<T>::value;
+        rl = std::min(h_min - deepest, lds_rows);
     }
     if (!chosen)
         return set_error(PERKS_E_UNSUPPORTED, "no 2D tile depth matches the request (rows_per_lane=%d)", want_r);
+    const int H = chosen + rl;
     pl->R = chosen;
-    pl->nty = (nyi + chosen - 1) / chosen;
-    pl->last_h = nyi - chosen * (pl->nty - 1);
+    pl->RL = rl;
+    pl->nty = (nyi + H - 1) / H;
+    pl->last_h = nyi - H * (pl->nty - 1);
     pl->ntiles = pl->ntx * pl->nty;
-    const long long cap_waves = (long long)f.cus * wgs_per_cu * W2;
-    long long cached = std::min<long long>(pl->ntiles, cap_waves);
+    long long cached = std::min<long long>(pl->ntiles, cap);
     if (tu && tu->max_cached_tiles < 0) cached = 0;
     if (tu && tu->max_cached_tiles > 0) cached = std::min<long long>(cached, tu->max_cached_tiles);
     pl->cached = (int)cached;
-    long long waves = std::min<long long>(pl->ntiles, cap_waves);
+    long long waves = std::min<long long>(pl->ntiles, cap);
     pl->wgs = (int)((waves + W2 - 1) / W2);
-    pl->fn = box ? pick2d<T, true>(chosen) : pick2d<T, false>(chosen);
+    pl->fn = box ? pick2d<T, true>(chosen, pl->ll) : pick2d<T, false>(chosen, pl->ll);
     return pl->fn ? PERKS_OK : set_error(PERKS_E_UNSUPPORTED, "no kernel for this tile depth");
 }
 
@@ -505,15 +773,20 @@ int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bo
     p.ny = (int)s.ny;
     p.ntx = pl.ntx;
     p.nty = pl.nty;
-    p.R = pl.R;
+    p.R = pl.R + pl.RL;
+    p.RL = pl.RL;
     p.last_w = pl.last_w;
     p.last_h = pl.last_h;
     p.ntiles = pl.ntiles;
     p.cached = pl.cached;
     p.steps = steps;
     fill_weights(p.W, coeffs);
-    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx, cb = (size_t)2 * (2 * pl.ntx + 2) * s.ny;
-    T *faces = (T *)scratch(SLOT_FACES, (rb + cb) * sizeof(T));
+    // LL words double the footprint of a face element (data + epoch)
+    const size_t mult = pl.ll ? 2 : 1;
+    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx * mult, cb = (size_t)2 * (2 * pl.ntx + 2) * s.ny * mult;
+    // LL words and raw values never share a buffer (a raw value read as an
+    // LL word could carry any epoch)
+    T *faces = (T *)scratch(pl.ll ? SLOT_FACES_LL : SLOT_FACES, (rb + cb) * sizeof(T));
     unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
     if (!faces || !sync) return PERKS_E_NOMEM;
     p.rowbuf = faces;
@@ -561,22 +834,23 @@ int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, p
     if (rc) return rc;
     plan->wgs = pl.wgs;
     plan->waves_per_wg = W2;
-    plan->rows_per_lane = pl.R;
+    plan->rows_per_lane = pl.R + pl.RL;
     plan->planes_per_lane = 1;
+    plan->lds_rows_per_lane = pl.RL;
     plan->tiles = pl.ntiles;
     plan->cached_tiles = pl.cached;
     plan->interior_cells = (shape.nx - 2) * (shape.ny - 2);
     int64_t cc = 0, face = 0;
     for (int t = 0; t < pl.ntiles; ++t) {
         const int tx = t % pl.ntx, ty = t / pl.ntx;
-        const int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64, hy = ty == pl.nty - 1 ? pl.last_h : pl.R;
+        const int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64, hy = ty == pl.nty - 1 ? pl.last_h : pl.R + pl.RL;
         if (t < pl.cached) cc += wx * hy;
         // per step: 2 edge rows + 2 edge columns written, the same plus corners read
         face += 2 * (2 * wx + 2 * hy) + 4;
     }
     plan->cached_cells = cc;
-    plan->halo_bytes_per_step = face * (int64_t)sizeof(T);
-    plan->sync = 1;
+    plan->halo_bytes_per_step = face * (int64_t)sizeof(T) * (pl.ll ? 2 : 1);
+    plan->sync = pl.ll ? 2 : 1;
     return PERKS_OK;
 }
 

@@ -88,6 +88,30 @@ def test_streamed_and_partially_cached_tiles_agree_bitwise(pk, kind, shape):
     assert rel_err(full, oracle.stencil(g, w, 13)) <= 1e-12
 
 
+@pytest.mark.parametrize("kind,shape", [("2d5pt", (150, 333)), ("2d9pt", (211, 100)), ("3d7pt", (19, 23, 90))])
+def test_grid_barrier_and_point_to_point_sync_agree_bitwise(pk, kind, shape):
+    # sync=1: a device-wide barrier after every step (the paper's grid.sync);
+    # sync=2: point-to-point halo words tagged with the step's epoch
+    g = workloads.stencil_grid(shape, seed=11)
+    w = workloads.stencil_weights(kind)
+    a = _run(pk, g, w, 21, torch.float64, tuning={"sync": 1})
+    b = _run(pk, g, w, 21, torch.float64, tuning={"sync": 2})
+    c = _run(pk, g, w, 21, torch.float64, tuning={"sync": 2, "max_cached_tiles": 5})
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+    assert rel_err(a, oracle.stencil(g, w, 21)) <= 1e-12
+
+
+def test_repeated_launches_reuse_epochs_safely(pk):
+    # consecutive persistent launches on different shapes share the face
+    # buffers; stale words must never be taken for current ones
+    w = workloads.stencil_weights("2d9pt")
+    for shape, steps in [((77, 300), 5), ((300, 77), 7), ((77, 300), 1), ((129, 129), 12)]:
+        g = workloads.stencil_grid(shape, seed=steps)
+        got = _run(pk, g, w, steps, torch.float64)
+        assert rel_err(got, oracle.stencil(g, w, steps)) <= 1e-12
+
+
 @pytest.mark.parametrize("rows", [8, 16, 32, 48])
 def test_tile_depth_does_not_change_bits(pk, rows):
     g = workloads.stencil_grid((190, 260), seed=8)
