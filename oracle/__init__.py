@@ -49,6 +49,10 @@ def _load():
     lib.oracle_cg.argtypes = [ctypes.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p,
                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _f64p]
     lib.oracle_cg.restype = ctypes.c_int
+    lib.oracle_cg_mixed.argtypes = [ctypes.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, _f64p, _f64p]
+    lib.oracle_cg_mixed.restype = ctypes.c_int
     lib.oracle_chol_solve.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p]
     lib.oracle_chol_solve.restype = ctypes.c_int
     _lib = lib
@@ -120,6 +124,36 @@ def cg(rowptr, colind, values, b, x0=None, tol=1e-10, maxit=5000, precond=None):
         raise ValueError("oracle_cg rejected its arguments")
     return x, {"iters": int(out[0]), "relres": float(out[1]), "relres_true": float(out[2]),
                "restarts": int(out[3]), "status": CG_STATUS[st]}
+
+
+MIXED_INNER_TOL = 1e-4   # default inner (FP32) relative reduction per outer step
+MIXED_MAX_OUTER = 30
+
+
+def cg_mixed(rowptr, colind, values, b, x0=None, tol=1e-8, maxit=5000, precond=None,
+             inner_tol=MIXED_INNER_TOL, max_outer=MIXED_MAX_OUTER):
+    """Mixed-precision CG: FP64 iterative refinement around an FP32 CG.
+
+    Returns ``(x, info)`` with ``info = {iters (total inner), relres_true,
+    outer, status, history}``; ``history[j]`` is the true relative residual
+    before outer step j.
+    """
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(colind, dtype=np.int32)
+    v, b = _f64(values), _f64(b)
+    n = rp.size - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    out = np.zeros(4)
+    hist = np.full(max_outer + 1, np.nan)
+    pc = {None: 0, "none": 0, "jacobi": 1}[precond]
+    st = _load().oracle_cg_mixed(n, _ptr(rp, _i32p), _ptr(ci, _i32p), _ptr(v), _ptr(b), _ptr(x),
+                                 float(tol), int(maxit), pc, float(inner_tol), int(max_outer),
+                                 _ptr(out), _ptr(hist))
+    if st < 0:
+        raise ValueError("oracle_cg_mixed rejected its arguments")
+    outer = int(out[3])
+    return x, {"iters": int(out[0]), "relres": float(out[1]), "relres_true": float(out[2]), "outer": outer,
+               "status": CG_STATUS[st], "history": hist[:outer + 1][~np.isnan(hist[:outer + 1])]}
 
 
 def chol_solve(A, b):

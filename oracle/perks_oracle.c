@@ -215,3 +215,140 @@ int oracle_chol_solve(int64_t n, const double *A, const double *b, double *x)
     free(L); free(yv);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed-precision conjugate gradient with FP64 iterative refinement.  The
+ * paper computes CG in one precision; this is the mixed-precision extension
+ * of its CG solver, so every choice below is a reading, not the paper's:
+ *
+ *   outer (FP64):  r = b - A x;  stop when ||r|| <= tol ||b||;
+ *                  solve A d = r approximately in FP32;  x = x + d.
+ *   inner (FP32):  CG on A32 d = r32 with A32 = float(A), r32 = float(s r)
+ *                  for a power-of-two s ~ 1/||r|| (exact scaling, keeps FP32
+ *                  far from under/overflow); vectors and SpMV / AXPY in
+ *                  FP32 arithmetic; dot products, alpha and beta in FP64
+ *                  (a product of two floats is exact in double); the
+ *                  inner loop stops when its recursive residual has fallen
+ *                  by inner_tol, or when the total iteration budget is spent.
+ *   stagnation:    an outer step that does not halve ||r|| ends the solve as
+ *                  not converged (FP32 cannot resolve the system), as does
+ *                  reaching max_outer outer steps.
+ *
+ * The Jacobi preconditioner, when asked for, is z = dinv32 * r in FP32 with
+ * dinv32 = float(1 / diag).
+ *
+ * out[0] : total inner iterations, out[1] : last outer ||r||/||b|| (this is
+ * the true FP64 residual), out[2] : same as out[1], out[3] : outer steps.
+ * hist   : if not NULL, hist[j] = ||r_j||/||b|| before outer step j
+ *          (max_outer + 1 entries).
+ * Returns 0 converged, 1 not converged, 2 breakdown, -1 bad arguments.     */
+
+/* pairwise FP64 sum of double(x_i) * double(y_i) for float vectors */
+static double dot32_rec(const float *x, const float *y, int64_t n)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s = s + (double)x[i] * (double)y[i];
+        return s;
+    }
+    int64_t h = n / 2;
+    return dot32_rec(x, y, h) + dot32_rec(x + h, y + h, n - h);
+}
+
+static double dot32(const float *x, const float *y, int64_t n)
+{
+    return n > 0 ? dot32_rec(x, y, n) : 0.0;
+}
+
+int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                    const double *b, double *x, double tol, int maxit, int precond,
+                    double inner_tol, int max_outer, double *out, double *hist)
+{
+    if (n < 0 || !rowptr || !b || !x || !out || maxit < 0 || !(tol >= 0.0) ||
+        !(inner_tol > 0.0) || max_outer < 1) return -1;
+    out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0;
+    if (n == 0) return 0;
+    const int64_t nnz = rowptr[n];
+    float *a32 = malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(float));
+    double *r = malloc((size_t)n * sizeof(double));
+    double *ax = malloc((size_t)n * sizeof(double));
+    float *rr = malloc((size_t)n * sizeof(float));
+    float *z = malloc((size_t)n * sizeof(float));
+    float *p = malloc((size_t)n * sizeof(float));
+    float *q = malloc((size_t)n * sizeof(float));
+    float *d = malloc((size_t)n * sizeof(float));
+    float *dinv = malloc((size_t)n * sizeof(float));
+    int status = 1, k = 0, outer = 0;
+    double rel = 0.0;
+    if (!a32 || !r || !ax || !rr || !z || !p || !q || !d || !dinv) { status = -1; goto done; }
+    for (int64_t e = 0; e < nnz; ++e) a32[e] = (float)val[e];
+    for (int64_t i = 0; i < n; ++i) {
+        double dd = 0.0;
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) if (colind[e] == i) dd = dd + val[e];
+        dinv[i] = (float)(1.0 / dd);
+    }
+    const double bnorm = sqrt(oracle_dot(b, b, n));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = 0;
+        goto done;
+    }
+    double prev = INFINITY;
+    for (;;) {
+        /* outer residual in FP64 */
+        oracle_spmv(n, rowptr, colind, val, x, ax);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - ax[i];
+        const double rn = sqrt(oracle_dot(r, r, n));
+        rel = rn / bnorm;
+        if (hist) hist[outer] = rel;
+        if (rn <= tol * bnorm) { status = 0; break; }
+        if (k >= maxit || outer >= max_outer || !(rn <= 0.5 * prev)) { status = 1; break; }
+        prev = rn;
+        /* inner FP32 CG on A d = s r, d0 = 0 */
+        const double s = ldexp(1.0, -ilogb(rn));
+        for (int64_t i = 0; i < n; ++i) {
+            rr[i] = (float)(r[i] * s);
+            z[i] = precond ? dinv[i] * rr[i] : rr[i];
+            p[i] = z[i];
+            d[i] = 0.0f;
+        }
+        double rho = dot32(rr, z, n);
+        double rr2 = dot32(rr, rr, n);
+        const double rr0 = rr2;
+        while (k < maxit && sqrt(rr2) > inner_tol * sqrt(rr0)) {
+            for (int64_t i = 0; i < n; ++i) {
+                float t = 0.0f;
+                for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) t = t + a32[e] * p[colind[e]];
+                q[i] = t;
+            }
+            const double pq = dot32(p, q, n);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
+            const float af = (float)(rho / pq);
+            for (int64_t i = 0; i < n; ++i) {
+                d[i] = d[i] + af * p[i];
+                rr[i] = rr[i] - af * q[i];
+                z[i] = precond ? dinv[i] * rr[i] : rr[i];
+            }
+            const double rho_new = dot32(rr, z, n);
+            rr2 = dot32(rr, rr, n);
+            ++k;
+            if (precond && !(rho_new > 0.0) && rr2 > 0.0) { status = 2; break; }
+            const float bf = (float)(rho_new / rho);
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + bf * p[i];
+            rho = rho_new;
+        }
+        /* x = x + d / s (exact rescaling by a power of two) */
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + (double)d[i] / s;
+        ++outer;
+        if (status == 2) {
+            oracle_spmv(n, rowptr, colind, val, x, ax);
+            for (int64_t i = 0; i < n; ++i) r[i] = b[i] - ax[i];
+            rel = sqrt(oracle_dot(r, r, n)) / bnorm;
+            break;
+        }
+    }
+done:
+    out[0] = k; out[1] = rel; out[2] = rel; out[3] = outer;
+    free(a32); free(r); free(ax); free(rr); free(z); free(p); free(q); free(d); free(dinv);
+    return status;
+}
