@@ -1,0 +1,33 @@
+"""Checks of the seeded input generators (no GPU)."""
+import numpy as np
+import pytest
+
+import workloads
+
+
+@pytest.mark.parametrize("side", [1, 2, 3, 17])
+def test_torch_poisson2d_equals_numpy(side):
+    torch = pytest.importorskip("torch")
+    rp, ci, v = workloads.poisson_csr(side, 2)
+    trp, tci, tv = workloads.poisson2d_csr_torch(side, device="cpu")
+    np.testing.assert_array_equal(trp.numpy(), rp)
+    np.testing.assert_array_equal(tci.numpy(), ci)
+    np.testing.assert_array_equal(tv.numpy(), v)
+
+
+def test_poisson_rows_are_sorted_and_symmetric():
+    rp, ci, v = workloads.poisson_csr(6, 3)
+    n = rp.size - 1
+    A = workloads.csr_to_dense(rp, ci, v, n)
+    np.testing.assert_array_equal(A, A.T)
+    for i in range(n):
+        row = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(row) > 0)
+
+
+def test_lognormal_sides_range_and_seed():
+    s = workloads.lognormal_sides(512, seed=0)
+    assert s.min() >= 64 and s.max() <= 1024
+    np.testing.assert_array_equal(s, workloads.lognormal_sides(512, seed=0))
+    # log-uniform: the median side is near sqrt(64 * 1024) = 256
+    assert 200 < np.median(s) < 330

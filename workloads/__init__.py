@@ -6,15 +6,16 @@ matrix-vector product, no Krylov step.  Both the CPU oracle and the GPU path
 receive the arrays produced here, so parity never depends on a random number
 generator being reimplemented twice.
 
-Every generator draws from ``numpy.random.default_rng(seed)`` (PCG64) in
-row-major order.
+Every random generator draws from ``numpy.random.default_rng(seed)``
+(PCG64) in row-major order.
 """
 from .stencil import (stencil_grid, stencil_weights, interior_slices, STENCIL_KINDS)
-from .sparse import (poisson_csr, random_spd_csr, rhs_uniform, rhs_normal,
+from .diffusion import grf_log_k, diffusion_csr, diffusion_problem
+from .sparse import (poisson_csr, poisson2d_csr_torch, random_spd_csr, rhs_uniform, rhs_normal,
                      csr_to_dense, lognormal_sides)
 
 __all__ = [
     "stencil_grid", "stencil_weights", "interior_slices", "STENCIL_KINDS",
-    "poisson_csr", "random_spd_csr", "rhs_uniform", "rhs_normal", "csr_to_dense",
-    "lognormal_sides",
+    "poisson_csr", "poisson2d_csr_torch", "random_spd_csr", "rhs_uniform", "rhs_normal", "csr_to_dense",
+    "lognormal_sides", "grf_log_k", "diffusion_csr", "diffusion_problem",
 ]

@@ -49,6 +49,28 @@ def poisson_csr(side, ndim):
     return rowptr.astype(np.int32), colind, values
 
 
+def poisson2d_csr_torch(side, device="cuda"):
+    """``poisson_csr(side, 2)`` built with torch on ``device`` (same arrays).
+
+    For large batches of inputs: building millions of rows on the host is
+    slow, on the device it takes milliseconds.  Returns (rowptr int32,
+    colind int32, values float64) tensors.
+    """
+    import torch
+    side = int(side)
+    n = side * side
+    idx = torch.arange(n, device=device, dtype=torch.int64)
+    ix, iy = idx % side, idx // side
+    # neighbour slots in ascending column order: -side, -1, 0, +1, +side
+    valid = torch.stack([iy > 0, ix > 0, torch.ones_like(ix, dtype=torch.bool), ix < side - 1, iy < side - 1], 1)
+    offs = torch.tensor([-side, -1, 0, 1, side], device=device, dtype=torch.int64)
+    cols = idx[:, None] + offs[None, :]
+    vals = torch.tensor([-1.0, -1.0, 4.0, -1.0, -1.0], device=device, dtype=torch.float64).expand(n, 5)
+    rowptr = torch.zeros(n + 1, device=device, dtype=torch.int64)
+    rowptr[1:] = torch.cumsum(valid.sum(1), 0)
+    return rowptr.to(torch.int32), cols[valid].to(torch.int32), vals[valid].contiguous()
+
+
 def random_spd_csr(n, seed=0, median=12.0, sigma=1.0, max_degree=200):
     """Random symmetric, strictly diagonally dominant (hence SPD) matrix.
 
