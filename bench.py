@@ -64,42 +64,180 @@ def cpu_baseline(target_s=10.0):
             "sample": f"2d5pt 3072^2 FP64, {k} Jacobi steps ({dt:.1f} s), single thread"}
 
 
-def bench_cg(pk, torch, args):
-    """CG time-to-tolerance, persistent vs host-looped, FP64, x0 = 0."""
+def _time(fn, torch, reps):
+    """Median wall time of fn() over reps runs (each bracketed by device syncs)."""
     import numpy as np
+    ts = []
+    out = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
 
+
+def bench_cg(pk, torch, args):
+    """CG time-to-tolerance, persistent vs host-looped, x0 = 0.
+
+    FP64 to 1e-10 and 1e-8, and mixed precision (FP64 refinement around FP32
+    CG) to 1e-8, on the 7-point Poisson 128^3 system; optionally the n=1M
+    random SPD system (Jacobi-preconditioned: unpreconditioned CG does not
+    reach 1e-8 on it within 5000 iterations).
+    """
     import workloads
-    systems = [("poisson3d 128^3", lambda: workloads.poisson_csr(128, 3))]
+    systems = [("poisson3d 128^3", lambda: workloads.poisson_csr(128, 3), None)]
     if args.cg_random:
-        systems.append(("random SPD n=1M lognormal(12,1)", lambda: workloads.random_spd_csr(1 << 20, seed=0)))
+        systems.append(("random SPD n=1M lognormal(12,1)", lambda: workloads.random_spd_csr(1 << 20, seed=0),
+                        "jacobi"))
     out = []
-    for name, make in systems:
+    reps = max(1, min(args.steps, 3))
+    for name, make, precond in systems:
         rp, ci, v = make()
         n = rp.size - 1
         A = pk.CsrMatrix(rp, ci, v)
         b = torch.from_numpy(workloads.rhs_uniform(n, seed=0)).cuda()
-        for tol in (1e-10, 1e-8):
-            rec = {"system": name, "n": int(n), "nnz": int(ci.size), "tol": tol}
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for tol, precision in ((1e-10, None), (1e-8, None), (1e-8, "mixed")):
+            rec = {"system": name, "n": int(n), "nnz": int(ci.size), "tol": tol, "precond": precond,
+                   "precision": precision or "f64"}
             for label, fn in (("persistent", pk.cg_solve), ("baseline", pk.cg_solve_baseline)):
-                x = torch.zeros(n, dtype=torch.float64, device="cuda")
-                fn(A, b, x, tol=tol, maxit=5000)               # warm-up (allocations, caches)
-                times = []
-                for _ in range(max(1, min(args.steps, 3))):
+                def run():
                     x.zero_()
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    info = fn(A, b, x, tol=tol, maxit=5000)
-                    torch.cuda.synchronize()
-                    times.append(time.perf_counter() - t0)
-                t = float(np.median(times))
+                    return fn(A, b, x, tol=tol, maxit=5000, precond=precond, precision=precision)
+                run()                                          # warm-up (allocations, caches)
+                t, info = _time(run, torch, reps)
                 rec[label] = {"seconds": t, "iters": info["iters"], "us_per_iter": t / max(1, info["iters"]) * 1e6,
-                              "relres_true": info["relres_true"], "status": info["status"]}
+                              "relres_true": info["relres_true"], "status": info["status"],
+                              "outer": info.get("outer")}
             rec["speedup"] = rec["baseline"]["seconds"] / rec["persistent"]["seconds"]
-            log(f"CG {name} tol {tol:.0e}: persistent {rec['persistent']['seconds']*1e3:.2f} ms "
+            log(f"CG {name} {rec['precision']} tol {tol:.0e}: persistent {rec['persistent']['seconds']*1e3:.2f} ms "
                 f"({rec['persistent']['iters']} it, {rec['persistent']['us_per_iter']:.1f} us/it)  baseline "
                 f"{rec['baseline']['seconds']*1e3:.2f} ms ({rec['baseline']['iters']} it)  x{rec['speedup']:.2f}")
             out.append(rec)
     return out
+
+
+def bench_batched(pk, torch, args):
+    """512 independent 2D 5-point Poisson systems, sides round(exp(U[ln 64, ln 1024])),
+    rhs N(0,1), mixed precision to 1e-8 each: one batched persistent launch vs the
+    same systems solved one after another by the single-system persistent solver
+    (and, with --batched-baseline, by the host-looped baseline)."""
+    import numpy as np
+
+    import workloads
+    count = args.batch_count
+    sides = workloads.lognormal_sides(count, seed=0)
+    As, bs, xs = [], [], []
+    cache = {}
+    for j, s in enumerate(sides):
+        s = int(s)
+        if s not in cache:
+            cache[s] = pk.CsrMatrix(*workloads.poisson2d_csr_torch(s, device="cuda"))
+        As.append(cache[s])
+        g = torch.Generator(device="cuda").manual_seed(j)
+        bs.append(torch.randn(s * s, generator=g, device="cuda", dtype=torch.float64))
+        xs.append(torch.zeros(s * s, device="cuda", dtype=torch.float64))
+    n_total = int(sum(int(s) ** 2 for s in sides))
+    nnz_total = int(sum(A.nnz for A in As))
+    tol, maxit = 1e-8, 20000
+    plan = pk.CgBatch(As, bs, xs, tol=tol, maxit=maxit, precision="mixed")
+
+    def run_batch():
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run()
+        infos = plan.results()
+        return time.perf_counter() - t0, infos
+
+    run_batch()
+    t_batch, infos = run_batch()
+    ok = sum(1 for i in infos if i["status"] == "converged")
+    worst = max(i["relres_true"] for i in infos)
+    rec = {"workload": f"{count} x 2D 5-point Poisson, sides log-uniform [64,1024] (seed 0), rhs N(0,1), "
+                       f"mixed precision to {tol:.0e}", "n_total": n_total, "nnz_total": nnz_total,
+           "batched_s": t_batch, "converged": ok, "worst_relres_true": worst,
+           "max_iters": max(i["iters"] for i in infos), "graph": plan.has_graph()}
+    # sequential single-system persistent solves of the same systems
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_ok = 0
+    for A, b, x in zip(As, bs, xs):
+        info = pk.cg_solve(A, b, x, tol=tol, maxit=maxit, precision="mixed")
+        seq_ok += info["status"] == "converged"
+    torch.cuda.synchronize()
+    rec["sequential_persistent_s"] = time.perf_counter() - t0
+    rec["speedup_vs_sequential"] = rec["sequential_persistent_s"] / t_batch
+    if args.batched_baseline:
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for A, b, x in zip(As, bs, xs):
+            pk.cg_solve_baseline(A, b, x, tol=tol, maxit=maxit, precision="mixed")
+        torch.cuda.synchronize()
+        rec["sequential_baseline_s"] = time.perf_counter() - t0
+        rec["speedup_vs_baseline"] = rec["sequential_baseline_s"] / t_batch
+    plan.close()
+    log(f"batched: {count} systems ({n_total/1e6:.1f}M unknowns) in {t_batch:.3f} s ({ok}/{count} converged, "
+        f"worst relres {worst:.2e}); sequential persistent {rec['sequential_persistent_s']:.3f} s "
+        f"(x{rec['speedup_vs_sequential']:.2f})"
+        + (f"; sequential baseline {rec['sequential_baseline_s']:.3f} s" if "sequential_baseline_s" in rec else ""))
+    return rec
+
+
+def bench_learned(pk, torch, args):
+    """Learned preconditioner: train on pairs harvested from the persistent PCG
+    on seeded 256^2 diffusion problems (log k a Gaussian random field, sigma 1,
+    correlation length 16 cells), then solve held-out problems at 256^2, 512^2
+    and 1024^2 to 1e-8 with FCG + network vs persistent Jacobi-PCG."""
+    import numpy as np
+
+    import workloads
+    from paper_2204_02064_amd import learned
+    n_train = args.nn_fields
+    t0 = time.perf_counter()
+    probs = [workloads.diffusion_problem_torch(256, seed=s) for s in range(n_train)]
+    X, T = learned.harvest_pairs(probs)
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    del probs
+    t0 = time.perf_counter()
+    params, losses = learned.train(X, T, epochs=args.nn_epochs, batch=16, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rec = {"train_fields": n_train, "pairs": int(X.shape[0]), "harvest_s": t_harvest, "train_s": t_train,
+           "epochs": args.nn_epochs, "loss_first": float(np.mean(losses[:20])),
+           "loss_last": float(np.mean(losses[-20:])), "eval": []}
+    del X, T
+    log(f"learned: {rec['pairs']} pairs from {n_train} fields in {t_harvest:.1f} s; trained {len(losses)} steps "
+        f"in {t_train:.1f} s, loss {rec['loss_first']:.3e} -> {rec['loss_last']:.3e}")
+    for n in (256, 512, 1024):
+        for s in range(10000, 10000 + args.nn_test):
+            rp, ci, v, lk, f = workloads.diffusion_problem_torch(n, seed=s)
+            A = pk.CsrMatrix(rp, ci, v)
+            x = torch.zeros_like(f)
+            e = {"n": n, "seed": s}
+            for label, fn in (("jacobi_pcg", lambda: pk.cg_solve(A, f, x, tol=1e-8, maxit=20000, precond="jacobi")),
+                              ("fcg_net", lambda: pk.fcg_solve(A, f, x, n, n, params=params, logk=lk, tol=1e-8,
+                                                               maxit=20000, stall=20))):
+                x.zero_()
+                fn()
+                t, info = _time(lambda: (x.zero_(), fn())[1], torch, 2)
+                e[label] = {"seconds": t, "iters": info["iters"], "status": info["status"],
+                            "relres_true": info["relres_true"], "fallbacks": info.get("fallbacks"),
+                            "switched_at": info.get("switched_at")}
+            e["speedup"] = e["jacobi_pcg"]["seconds"] / e["fcg_net"]["seconds"]
+            log(f"learned {n}^2 seed {s}: Jacobi-PCG {e['jacobi_pcg']['iters']} it {e['jacobi_pcg']['seconds']*1e3:.2f} ms"
+                f" | FCG+net {e['fcg_net']['iters']} it {e['fcg_net']['seconds']*1e3:.2f} ms "
+                f"(fallbacks {e['fcg_net']['fallbacks']}, switched {e['fcg_net']['switched_at']})  x{e['speedup']:.2f}")
+            rec["eval"].append(e)
+    return rec
 
 
 def main():
@@ -112,6 +250,14 @@ def main():
     ap.add_argument("--cases", default="all")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--cg-random", action="store_true", help="also the n=1M random SPD system")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision CG")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned preconditioner")
+    ap.add_argument("--nn-fields", type=int, default=200, help="training fields (256^2) for the network")
+    ap.add_argument("--nn-epochs", type=int, default=3)
+    ap.add_argument("--nn-test", type=int, default=2, help="held-out problems per size")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batched-baseline", action="store_true",
+                    help="also time the host-looped baseline on every batched system (slow)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the method and this "
@@ -188,16 +334,18 @@ def main():
             + f"  plan R={r['plan']['rows_per_lane']} cached {r['plan']['cached_tiles']}/{r['plan']['tiles']}")
 
     # dominant kernel (largest share of the timed region) -> roofline entry
-    dom = max(range(len(results)), key=lambda i: results[i]["persistent_ms"])
-    kind, shape, dt = cases[dom]
-    t_dom = results[dom]["persistent_ms"] / 1e3
-    flops = FLOPS_PER_CELL[kind] * interior(shape) * STENCIL_STEPS
-    achieved = flops / t_dom / 1e12
-    roofline = {"bound": "alu", "kernel": f"stencil{len(shape)}d_persistent {results[dom]['case']}",
-                "achieved": achieved, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS[dt], "traffic": None}
+    roofline = None
+    if results:
+        dom = max(range(len(results)), key=lambda i: results[i]["persistent_ms"])
+        kind, shape, dt = cases[dom]
+        t_dom = results[dom]["persistent_ms"] / 1e3
+        flops = FLOPS_PER_CELL[kind] * interior(shape) * STENCIL_STEPS
+        achieved = flops / t_dom / 1e12
+        roofline = {"bound": "alu", "kernel": f"stencil{len(shape)}d_persistent {results[dom]['case']}",
+                    "achieved": achieved, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_TFLOPS[dt], "traffic": None}
 
-    value = total_cells / total_time / 1e9
+    value = total_cells / total_time / 1e9 if total_time > 0 else None
     out = {
         "metric": "stencil GCells/s + CG s-to-1e-8 resid: persistent vs per-step launch, 1 GPU",
         "value": value,
@@ -218,12 +366,16 @@ def main():
         "roofline": roofline,
         "wall_s": wall,
     }
-    if not args.no_baseline:
+    if not args.no_baseline and results:
         base_time = sum(r["baseline_ms"] for r in results) / 1e3
         out["baseline_value"] = sum(interior(c[1]) * STENCIL_STEPS for c in cases) / base_time / 1e9
         out["speedup_vs_per_step_launch"] = value / out["baseline_value"]
     if not args.no_cg:
         out["cg"] = bench_cg(pk, torch, args)
+    if not args.no_batched:
+        out["batched_cg"] = bench_batched(pk, torch, args)
+    if not args.no_learned:
+        out["learned_preconditioner"] = bench_learned(pk, torch, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

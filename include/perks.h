@@ -140,34 +140,168 @@ typedef struct {
 
 enum { PERKS_PRECOND_NONE = 0, PERKS_PRECOND_JACOBI = 1 };
 
+/* Arithmetic of a CG solve.
+ *   PERKS_PREC_F64    FP64 throughout.
+ *   PERKS_PREC_MIXED  FP64 iterative refinement around an FP32 CG: each outer
+ *                     step forms r = b - A x in FP64 and, unless
+ *                     ||r|| <= tol ||b||, solves A d = r approximately with CG
+ *                     in FP32 (FP32 copy of A's values, FP32 vectors, SpMV and
+ *                     AXPYs; FP64 dot products, alpha and beta; the right-hand
+ *                     side scaled by an exact power of two near 1/||r||) until
+ *                     the inner recursive residual has fallen by
+ *                     PERKS_MIXED_INNER_TOL, then x += d.  An outer step that
+ *                     does not halve ||r||, or PERKS_MIXED_MAX_OUTER outer
+ *                     steps, end the solve as PERKS_NOT_CONVERGED.  The paper's
+ *                     CG runs in one precision; this mode is an extension. */
+enum { PERKS_PREC_F64 = 0, PERKS_PREC_MIXED = 1 };
+#define PERKS_MIXED_INNER_TOL 1e-4
+#define PERKS_MIXED_MAX_OUTER 30
+
 /*
  * perks_cg_solve -- conjugate gradient for SPD A (Sec. 2.2.2, Sec. 4.3).
  *
  * Hestenes-Stiefel CG as in the paper's CG algorithm, with its stopping test
- * read as: iterate while ||r||_2 > tol * ||b||_2 and iterations < maxit.  At
- * exit the true residual is recomputed; if it exceeds tol and iterations
- * remain, CG restarts from the current x.  The whole solve is one persistent
- * kernel launch per (re)start: SpMV, dot products (a fixed-order all-reduce
- * inside the kernel) and AXPYs are fused, the matrix slice of each workgroup is
- * cached on chip, and workgroups synchronise with a device-wide barrier.
- *   A       host struct describing device CSR arrays (FP64 only in this build).
- *   b       device, n doubles.      x  device, n doubles: initial guess in,
- *           solution out.
- *   precond PERKS_PRECOND_NONE or PERKS_PRECOND_JACOBI (z = D^{-1} r).
- *   out     host, filled on return (may be NULL).
+ * read as: iterate while ||r||_2 > tol * ||b||_2 and iterations < maxit.
+ * PERKS_PREC_F64: at exit the true residual is recomputed; if it exceeds tol
+ * and iterations remain, CG restarts from the current x.  The whole solve is
+ * one persistent kernel launch per (re)start: SpMV, dot products (a
+ * fixed-order all-reduce inside the kernel) and AXPYs are fused, the first
+ * part of each workgroup's slice of the matrix is cached in LDS, and
+ * workgroups synchronise with a device-wide barrier.
+ * PERKS_PREC_MIXED: the refinement loop above, all outer and inner steps in
+ * ONE persistent launch; the stopping test is on the true FP64 residual.
+ *   A         host struct describing device CSR arrays (values FP64).
+ *   b         device, n doubles.      x  device, n doubles: initial guess in,
+ *             solution out.
+ *   maxit     CG iterations allowed (mixed: inner iterations, all outer steps).
+ *   precond   PERKS_PRECOND_NONE or PERKS_PRECOND_JACOBI (z = D^{-1} r).
+ *   precision PERKS_PREC_F64 or PERKS_PREC_MIXED.
+ *   out       host, filled on return (may be NULL); `restarts` counts
+ *             restarts (F64) or outer refinement steps (MIXED).
  * Returns PERKS_OK, PERKS_NOT_CONVERGED, PERKS_BREAKDOWN or an error.
  */
 int perks_cg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
-                   int32_t precond, void *stream, perks_cg_result *out);
+                   int32_t precond, int32_t precision, void *stream, perks_cg_result *out);
+
+/* perks_cg_solve (FP64) that also records the iterate and its recursive
+ * residual after each iteration count listed in cap_iters (device, ncap
+ * ascending int32): cap_x[j][n] and cap_r[j][n] (device doubles) receive
+ * x_k and r_k for k = cap_iters[j]; entries not reached are left untouched.
+ * Used to harvest (residual, error) training pairs from the solver itself. */
+int perks_cg_solve_capture(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
+                           int32_t precond, const int32_t *cap_iters, int32_t ncap, double *cap_x,
+                           double *cap_r, void *stream, perks_cg_result *out);
 
 /* Same solve, host-looped: separate kernels per step (SpMV, dot products,
  * AXPYs) launched every iteration, scalars kept on the device, and the host
  * reading the residual norm back every `check_every` iterations (>= 1) to
  * decide convergence -- the multi-kernel structure the paper fuses (Sec. 3.1,
- * "Practicality of PERKS"). */
+ * "Practicality of PERKS").  MIXED: the host also runs the outer loop. */
 int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double tol,
-                            int32_t maxit, int32_t precond, int32_t check_every, void *stream,
-                            perks_cg_result *out);
+                            int32_t maxit, int32_t precond, int32_t precision,
+                            int32_t check_every, void *stream, perks_cg_result *out);
+
+/*
+ * Batched CG -- many independent SPD systems in ONE persistent launch.
+ *
+ * The paper solves one system per launch; batching is an extension of its
+ * CG.  Every problem is solved exactly as perks_cg_solve would solve it with
+ * the same arithmetic (`precision`, `precond`, tol, maxit apply to each
+ * problem), by a group of workgroups of the one launch: a problem predicted
+ * to cost more than two workgroups' fair share (predicted work: nnz * sqrt(n))
+ * gets a group of its own, synchronised by the group's own barrier; the
+ * other problems are solved by one workgroup each, packed onto the
+ * least-loaded workgroups.  A problem's result depends only on the problem
+ * and the size of its group, not on the other problems or their order.
+ *
+ * perks_cg_batch_create  validates, schedules and allocates (device memory
+ *                        owned by the plan; synchronous).  As[i], bs[i],
+ *                        xs[i] (count of each, host arrays of device
+ *                        pointers) stay bound to the plan: refill b or x
+ *                        between runs, do not free them before destroy.
+ * perks_cg_batch_run     enqueues the solve on `stream`: one kernel launch
+ *                        (a one-node HIP graph with the cooperative
+ *                        attribute when the runtime accepts one); no host
+ *                        synchronisation; x holds the solutions when the
+ *                        stream reaches that point.
+ * perks_cg_batch_results synchronises `stream` and fills outs[count] (host;
+ *                        may be NULL); returns PERKS_BREAKDOWN if any problem
+ *                        broke down, else PERKS_NOT_CONVERGED if any did not
+ *                        converge, else PERKS_OK.
+ * perks_cg_batch_graph   the plan's hipGraph_t (as void *) for use as a child
+ *                        graph in a caller's graph; PERKS_E_UNSUPPORTED when
+ *                        the plan has none.  Owned by the plan.
+ * perks_cg_batch_destroy synchronises the device and frees the plan.
+ * perks_cg_solve_batched create + run + results + destroy.
+ * Runs of one plan must not overlap in time (they share its barrier words).
+ */
+typedef struct perks_cg_batch perks_cg_batch;
+
+int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *const *xs, int32_t count,
+                          double tol, int32_t maxit, int32_t precond, int32_t precision,
+                          perks_cg_batch **plan);
+int perks_cg_batch_run(perks_cg_batch *plan, void *stream);
+int perks_cg_batch_results(perks_cg_batch *plan, perks_cg_result *outs, void *stream);
+int perks_cg_batch_graph(perks_cg_batch *plan, void **graph);
+int perks_cg_batch_destroy(perks_cg_batch *plan);
+int perks_cg_solve_batched(const perks_csr *As, const void *const *bs, void *const *xs, int32_t count,
+                           double tol, int32_t maxit, int32_t precond, int32_t precision, void *stream,
+                           perks_cg_result *outs);
+
+/*
+ * Learned preconditioner (an extension; the paper has no learned part).
+ *
+ * A six-layer 3x3 convolutional network, run in BF16 on the matrix cores
+ * with FP32 accumulation: input channels [r / rms(r), log k] on the N x N
+ * grid of unknowns, layers 2 -> 16 -> 16 -> 16 -> 16 -> 16 -> 1, zero 'same'
+ * padding, a bias per layer, ReLU after every layer but the last.  Weight
+ * W[o][i][1+dy][1+dx] multiplies input channel i at (y+dy, x+dx) for output
+ * channel o at (y, x).  Every layer's input and weights are rounded to BF16.
+ *
+ * params: PERKS_NN_PARAMS floats (device), layer l at l * PERKS_NN_LAYER_PARAMS:
+ *         W[16][16][3][3] then b[16], channels beyond a layer's real count
+ *         (2 inputs of layer 0, 1 output of layer 5) held at zero.
+ * x:      [B][H][W][2] floats (device): the two input channels per pixel.
+ */
+#define PERKS_NN_LAYERS 6
+#define PERKS_NN_LAYER_PARAMS (16 * 16 * 9 + 16)
+#define PERKS_NN_PARAMS (PERKS_NN_LAYERS * PERKS_NN_LAYER_PARAMS)
+
+/* out[B][H][W] (device floats) = the network applied to x. */
+int perks_nn_forward(const float *params, const float *x, int32_t B, int32_t H, int32_t W, float *out,
+                     void *stream);
+
+/* Mean squared error over all B*H*W outputs against target[B][H][W]
+ * (device floats) and its gradient w.r.t. params: grad (device,
+ * PERKS_NN_PARAMS floats, padded entries zero), *loss (host; may be NULL:
+ * then the call does not synchronise).  Requires H even and W <= 512. */
+int perks_nn_loss_grad(const float *params, const float *x, const float *target, int32_t B, int32_t H,
+                       int32_t W, float *grad, double *loss, void *stream);
+
+/* One Adam step with bias correction (step counts from 1) on the FP32
+ * master weights; m and v (device, PERKS_NN_PARAMS floats) start at zero. */
+int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void *stream);
+
+/*
+ * perks_fcg_solve -- flexible CG preconditioned by the network, one
+ * persistent launch.  FCG(1): p = z - (<z, q_old> / <p_old, q_old>) p_old,
+ * q = A p, alpha = <p, r> / <p, q>, with z = rms(r) * net([r / rms(r), log k])
+ * computed inside the kernel (16 x 16 tiles, all six layers per tile in LDS).
+ * Safeguards: z = D^{-1} r for an iteration where <z, r> <= 0 or z is not
+ * finite; after `stall` iterations without a new minimum of ||r|| the solve
+ * continues as Jacobi-preconditioned CG.  nn_params == NULL: Jacobi-PCG from
+ * the start (the judge the network is compared against).
+ *   A       FP64 CSR on an H x W grid of unknowns (row y * W + x), n = H * W.
+ *   logk    device, H * W doubles (the second network input).
+ *   out     iters, status, restarts = iterations that fell back to Jacobi,
+ *           reserved = iteration at which the solve switched to Jacobi-PCG
+ *           (-1: never), relres / relres_true as for perks_cg_solve.
+ * Returns PERKS_OK when the true relative residual meets tol.
+ */
+int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
+                    const float *nn_params, const double *logk, int32_t H, int32_t W, int32_t stall,
+                    void *stream, perks_cg_result *out);
 
 /* Device facts the planner uses (host struct, filled from the current device). */
 typedef struct {

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libperks.so")
 
 PERKS_F32, PERKS_F64 = 0, 1
 PRECOND = {None: 0, "none": 0, "jacobi": 1}
+PRECISION = {None: 0, "f64": 0, "float64": 0, "mixed": 1}
 STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
 
 
@@ -86,14 +87,34 @@ def lib():
     L.perks_strerror.argtypes = [ctypes.c_int]
     L.perks_last_error.restype = ctypes.c_char_p
     L.perks_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
-    if hasattr(L, "perks_cg_solve"):
-        L.perks_cg_solve.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, vp, ctypes.POINTER(CgResult)]
-        L.perks_cg_solve_baseline.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, i32, vp,
-                                              ctypes.POINTER(CgResult)]
+    L.perks_cg_solve.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, i32, vp, ctypes.POINTER(CgResult)]
+    L.perks_cg_solve_baseline.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, i32, i32, vp,
+                                          ctypes.POINTER(CgResult)]
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.perks_cg_batch_create.argtypes = [ctypes.POINTER(Csr), pp, pp, i32, f64, i32, i32, i32, pp]
+    L.perks_cg_batch_run.argtypes = [vp, vp]
+    L.perks_cg_batch_results.argtypes = [vp, ctypes.POINTER(CgResult), vp]
+    L.perks_cg_batch_graph.argtypes = [vp, pp]
+    L.perks_cg_batch_destroy.argtypes = [vp]
+    L.perks_cg_solve_batched.argtypes = [ctypes.POINTER(Csr), pp, pp, i32, f64, i32, i32, i32, vp,
+                                         ctypes.POINTER(CgResult)]
+    L.perks_cg_solve_capture.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, vp, i32, vp, vp, vp,
+                                         ctypes.POINTER(CgResult)]
+    L.perks_fcg_solve.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, vp, vp, i32, i32, i32, vp,
+                                  ctypes.POINTER(CgResult)]
+    for name in ("perks_cg_solve_capture", "perks_fcg_solve"):
+        getattr(L, name).restype = ctypes.c_int
+    L.perks_nn_forward.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+    L.perks_nn_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.perks_nn_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, vp]
+    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("perks_stencil_run", "perks_stencil_run_baseline", "perks_stencil_plan_query",
-                 "perks_device_query", "perks_cg_solve", "perks_cg_solve_baseline"):
-        if hasattr(L, name):
-            getattr(L, name).restype = ctypes.c_int
+                 "perks_device_query", "perks_cg_solve", "perks_cg_solve_baseline", "perks_cg_batch_create",
+                 "perks_cg_batch_run", "perks_cg_batch_results", "perks_cg_batch_graph", "perks_cg_batch_destroy",
+                 "perks_cg_solve_batched"):
+        getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -197,9 +218,14 @@ class CsrMatrix:
 
     def __init__(self, rowptr, colind, values, device="cuda"):
         import torch
-        self.rowptr = torch.as_tensor(np.asarray(rowptr, dtype=np.int32), device=device).contiguous()
-        self.colind = torch.as_tensor(np.asarray(colind, dtype=np.int32), device=device).contiguous()
-        self.values = torch.as_tensor(np.asarray(values, dtype=np.float64), device=device).contiguous()
+
+        def dev(a, npt, tt):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=device, dtype=tt).contiguous()
+            return torch.as_tensor(np.asarray(a, dtype=npt), device=device).contiguous()
+        self.rowptr = dev(rowptr, np.int32, torch.int32)
+        self.colind = dev(colind, np.int32, torch.int32)
+        self.values = dev(values, np.float64, torch.float64)
         self.n = self.rowptr.numel() - 1
         self.nnz = self.colind.numel()
 
@@ -208,31 +234,237 @@ class CsrMatrix:
                    PERKS_F64 if self.values.dtype.itemsize == 8 else PERKS_F32, 0)
 
 
-def _cg_result(r):
-    return {"iters": r.iters, "status": STATUS.get(r.status, str(r.status)), "restarts": r.restarts,
-            "wgs": r.wgs, "relres": r.relres, "relres_true": r.relres_true, "cached_nnz_frac": r.cached_nnz_frac}
+def _cg_result(r, precision):
+    d = {"iters": r.iters, "status": STATUS.get(r.status, str(r.status)), "wgs": r.wgs, "relres": r.relres,
+         "relres_true": r.relres_true, "cached_nnz_frac": r.cached_nnz_frac}
+    d["outer" if PRECISION[precision] == 1 else "restarts"] = r.restarts
+    return d
 
 
-def cg_solve(A, b, x, tol=1e-10, maxit=5000, precond=None, stream=None):
-    """Persistent-kernel CG: solves A x = b in place in ``x``; returns an info dict."""
-    L = lib()
-    if not hasattr(L, "perks_cg_solve"):
-        raise RuntimeError("this libperks.so has no CG entry points")
+def _check_vec(v, n, name):
+    import torch
+    if not v.is_cuda or not v.is_contiguous() or v.dtype != torch.float64 or v.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 device vector of length {n}")
+
+
+def cg_solve(A, b, x, tol=1e-10, maxit=5000, precond=None, precision=None, stream=None):
+    """Persistent-kernel CG: solves A x = b in place in ``x``; returns an info dict.
+
+    ``precision``: None / "f64" (FP64 throughout) or "mixed" (FP64 iterative
+    refinement around an FP32 CG, one launch).
+    """
+    _check_vec(b, A.n, "b")
+    _check_vec(x, A.n, "x")
     res = CgResult()
     st = A._struct()
-    rc = L.perks_cg_solve(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                          float(tol), int(maxit), PRECOND[precond], _stream_handle(stream), ctypes.byref(res))
+    rc = lib().perks_cg_solve(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                              float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
+                              _stream_handle(stream), ctypes.byref(res))
     _check(rc, allow_positive=True)
-    return _cg_result(res)
+    return _cg_result(res, precision)
 
 
-def cg_solve_baseline(A, b, x, tol=1e-10, maxit=5000, precond=None, check_every=1, stream=None):
+def cg_solve_baseline(A, b, x, tol=1e-10, maxit=5000, precond=None, precision=None, check_every=1, stream=None):
     """Host-looped multi-kernel CG (the baseline); same interface as cg_solve."""
-    L = lib()
+    _check_vec(b, A.n, "b")
+    _check_vec(x, A.n, "x")
     res = CgResult()
     st = A._struct()
-    rc = L.perks_cg_solve_baseline(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                   float(tol), int(maxit), PRECOND[precond], int(check_every),
-                                   _stream_handle(stream), ctypes.byref(res))
+    rc = lib().perks_cg_solve_baseline(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()),
+                                       ctypes.c_void_p(x.data_ptr()), float(tol), int(maxit), PRECOND[precond],
+                                       PRECISION[precision], int(check_every), _stream_handle(stream),
+                                       ctypes.byref(res))
     _check(rc, allow_positive=True)
-    return _cg_result(res)
+    return _cg_result(res, precision)
+
+
+def _batch_args(As, bs, xs):
+    m = len(As)
+    if len(bs) != m or len(xs) != m:
+        raise ValueError("As, bs and xs must have the same length")
+    for A, b, x in zip(As, bs, xs):
+        _check_vec(b, A.n, "b")
+        _check_vec(x, A.n, "x")
+    arr = (Csr * max(m, 1))(*[A._struct() for A in As])
+    bp = (ctypes.c_void_p * max(m, 1))(*[b.data_ptr() for b in bs])
+    xp = (ctypes.c_void_p * max(m, 1))(*[x.data_ptr() for x in xs])
+    return m, arr, bp, xp
+
+
+def cg_solve_batched(As, bs, xs, tol=1e-10, maxit=5000, precond=None, precision=None, stream=None):
+    """Solve every A_i x_i = b_i in ONE persistent launch; returns a list of info dicts."""
+    m, arr, bp, xp = _batch_args(As, bs, xs)
+    res = (CgResult * max(m, 1))()
+    rc = lib().perks_cg_solve_batched(arr, bp, xp, m, float(tol), int(maxit), PRECOND[precond],
+                                      PRECISION[precision], _stream_handle(stream), res)
+    _check(rc, allow_positive=True)
+    return [_cg_result(res[i], precision) for i in range(m)]
+
+
+class CgBatch:
+    """A batched CG plan: schedule and device memory made once, run many times.
+
+    ``run()`` enqueues one launch (a HIP graph node when available) on the
+    stream without synchronising; ``results()`` synchronises and returns the
+    per-problem info dicts.  The plan keeps references to the matrices and
+    vectors it was built from; refill ``bs`` / ``xs`` in place between runs.
+    """
+
+    def __init__(self, As, bs, xs, tol=1e-10, maxit=5000, precond=None, precision=None):
+        self._keep = (list(As), list(bs), list(xs))
+        self.count, arr, bp, xp = _batch_args(As, bs, xs)
+        self.precision = precision
+        self._h = ctypes.c_void_p()
+        rc = lib().perks_cg_batch_create(arr, bp, xp, self.count, float(tol), int(maxit), PRECOND[precond],
+                                         PRECISION[precision], ctypes.byref(self._h))
+        _check(rc)
+
+    def run(self, stream=None):
+        _check(lib().perks_cg_batch_run(self._h, _stream_handle(stream)))
+
+    def results(self, stream=None):
+        res = (CgResult * max(self.count, 1))()
+        rc = lib().perks_cg_batch_results(self._h, res, _stream_handle(stream))
+        _check(rc, allow_positive=True)
+        return [_cg_result(res[i], self.precision) for i in range(self.count)]
+
+    def has_graph(self):
+        g = ctypes.c_void_p()
+        return lib().perks_cg_batch_graph(self._h, ctypes.byref(g)) == 0
+
+    def close(self):
+        if self._h:
+            lib().perks_cg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner network (six 3x3 conv layers, BF16 on the matrix cores).
+NN_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 16), (16, 16), (16, 1)]
+NN_LAYER_PARAMS = 16 * 16 * 9 + 16
+NN_PARAMS = len(NN_LAYERS) * NN_LAYER_PARAMS
+
+
+def nn_pack_params(layers):
+    """[(W [co, ci, 3, 3], b [co]) per layer] -> padded float32 vector (host)."""
+    out = np.zeros(NN_PARAMS, dtype=np.float32)
+    for l, ((ci, co), (w, b)) in enumerate(zip(NN_LAYERS, layers)):
+        blk = np.zeros((16, 16, 3, 3), dtype=np.float32)
+        blk[:co, :ci] = np.asarray(w, dtype=np.float32).reshape(co, ci, 3, 3)
+        bias = np.zeros(16, dtype=np.float32)
+        bias[:co] = np.asarray(b, dtype=np.float32)
+        base = l * NN_LAYER_PARAMS
+        out[base:base + 16 * 16 * 9] = blk.ravel()
+        out[base + 16 * 16 * 9:base + NN_LAYER_PARAMS] = bias
+    return out
+
+
+def nn_unpack_params(vec):
+    """Inverse of nn_pack_params (real channels only), float32 arrays."""
+    vec = np.asarray(vec, dtype=np.float32)
+    layers = []
+    for l, (ci, co) in enumerate(NN_LAYERS):
+        base = l * NN_LAYER_PARAMS
+        blk = vec[base:base + 16 * 16 * 9].reshape(16, 16, 3, 3)
+        layers.append((blk[:co, :ci].copy(), vec[base + 16 * 16 * 9:base + 16 * 16 * 9 + co].copy()))
+    return layers
+
+
+def _check_f32(t, n, name):
+    import torch
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32 or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
+
+
+def nn_forward(params, x, out=None, stream=None):
+    """Network output [B, H, W] for x [B, H, W, 2] (float32 device tensors)."""
+    import torch
+    B, H, W, C = x.shape
+    if C != 2:
+        raise ValueError("x must be [B, H, W, 2]")
+    _check_f32(params, NN_PARAMS, "params")
+    _check_f32(x, B * H * W * 2, "x")
+    if out is None:
+        out = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+    _check_f32(out, B * H * W, "out")
+    _check(lib().perks_nn_forward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()), B, H, W,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def nn_loss_grad(params, x, target, grad=None, stream=None):
+    """(loss, grad): mean squared error of the network on (x, target) and its gradient."""
+    import torch
+    B, H, W, _ = x.shape
+    _check_f32(params, NN_PARAMS, "params")
+    _check_f32(x, B * H * W * 2, "x")
+    _check_f32(target, B * H * W, "target")
+    if grad is None:
+        grad = torch.empty(NN_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double()
+    _check(lib().perks_nn_loss_grad(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(target.data_ptr()), B, H, W, ctypes.c_void_p(grad.data_ptr()),
+                                    ctypes.byref(loss), _stream_handle(stream)))
+    return loss.value, grad
+
+
+def nn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _check_f32(t, NN_PARAMS, nm)
+    _check(lib().perks_nn_adam(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                               ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(step),
+                               float(lr), float(beta1), float(beta2), float(eps), _stream_handle(stream)))
+
+
+def cg_solve_capture(A, b, x, iters, tol=1e-10, maxit=5000, precond=None, stream=None):
+    """Persistent FP64 CG that also returns x_k and r_k after each k in ``iters``.
+
+    Returns (info, xcap [m, n], rcap [m, n]) with device tensors; rows for
+    iteration counts the solve did not reach hold NaN.
+    """
+    import torch
+    _check_vec(b, A.n, "b")
+    _check_vec(x, A.n, "x")
+    its = sorted(int(k) for k in iters)
+    m = len(its)
+    it_dev = torch.tensor(its if m else [0], dtype=torch.int32, device=b.device)
+    xcap = torch.full((max(m, 1), A.n), float("nan"), dtype=torch.float64, device=b.device)
+    rcap = torch.full((max(m, 1), A.n), float("nan"), dtype=torch.float64, device=b.device)
+    res = CgResult()
+    st = A._struct()
+    rc = lib().perks_cg_solve_capture(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                      float(tol), int(maxit), PRECOND[precond], ctypes.c_void_p(it_dev.data_ptr()), m,
+                                      ctypes.c_void_p(xcap.data_ptr()), ctypes.c_void_p(rcap.data_ptr()),
+                                      _stream_handle(stream), ctypes.byref(res))
+    _check(rc, allow_positive=True)
+    return _cg_result(res, None), xcap[:m], rcap[:m]
+
+
+def fcg_solve(A, b, x, H, W, params=None, logk=None, tol=1e-8, maxit=5000, stall=20, stream=None):
+    """Flexible CG preconditioned by the network (``params`` None: Jacobi-PCG),
+    one persistent launch.  Returns an info dict with ``fallbacks`` (iterations
+    that used the Jacobi step) and ``switched_at`` (iteration at which the solve
+    continued as Jacobi-PCG, or None)."""
+    _check_vec(b, A.n, "b")
+    _check_vec(x, A.n, "x")
+    if params is not None:
+        _check_f32(params, NN_PARAMS, "params")
+        _check_vec(logk.reshape(-1), A.n, "logk")
+    res = CgResult()
+    st = A._struct()
+    rc = lib().perks_fcg_solve(ctypes.byref(st), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                               float(tol), int(maxit),
+                               ctypes.c_void_p(params.data_ptr() if params is not None else 0),
+                               ctypes.c_void_p(logk.data_ptr() if params is not None else 0), int(H), int(W),
+                               int(stall), _stream_handle(stream), ctypes.byref(res))
+    _check(rc, allow_positive=True)
+    d = _cg_result(res, None)
+    d["fallbacks"] = d.pop("restarts")
+    d["switched_at"] = None if res.reserved < 0 else int(res.reserved)
+    return d

@@ -34,7 +34,12 @@ struct GridSync {
 
     // All threads of all workgroups call this; returns when every workgroup
     // has arrived.  Global writes made before the call with st_coh (or any
-    // other write that has completed) are visible to ld_coh after it.
+    // other write that has completed) are visible to ld_coh after it.  With
+    // acquire_caches, thread 0 also invalidates this CU's L1 and its XCD's L2
+    // (one agent-scope acquire per workgroup), after which ordinary cached
+    // loads see every st_coh store made before the barrier; that lets a
+    // workgroup gather data written by others through the caches.
+    template <bool acquire_caches = false>
     __device__ __forceinline__ void sync() {
         const unsigned e = ++epoch;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -56,6 +61,7 @@ struct GridSync {
         } else if (threadIdx.x == 0) {
             while (ld_coh(ws + SYNC_GEN) != e) __builtin_amdgcn_s_sleep(1);
         }
+        if (acquire_caches && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
@@ -65,6 +71,69 @@ struct GridSync {
     // the start epoch before the first sync(), which precedes this write.
     __device__ __forceinline__ void finish() {
         if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, epoch);
+    }
+};
+
+// Barrier over a group of `size` consecutive workgroups of the grid, the
+// member of rank r being workgroup first + r; the same master-gather scheme as
+// GridSync, with the group's own generation word.  A group of one workgroup
+// synchronises with __syncthreads() alone.  Epochs start from `epoch0`, which
+// every group of a launch shares (the launch's start epoch): a flag or
+// generation word left over from an earlier launch holds an epoch <= epoch0,
+// so it can never match.
+struct GroupSync {
+    unsigned *flags;   // flags of the group's workgroups, indexed by rank
+    unsigned *gen;     // the group's generation word
+    unsigned epoch;
+    int rank, size;
+
+    __device__ __forceinline__ void init(unsigned *ws, int first, int group, int r, int n, unsigned epoch0) {
+        flags = ws + SYNC_FLAGS + first;
+        gen = ws + SYNC_GROUP_GEN + group * SYNC_GROUP_STRIDE;
+        rank = r;
+        size = n;
+        epoch = epoch0;
+    }
+    // The whole grid as one group, epochs continuing from the last launch.
+    __device__ __forceinline__ void init_grid(unsigned *ws) {
+        flags = ws + SYNC_FLAGS;
+        gen = ws + SYNC_GEN;
+        rank = blockIdx.x;
+        size = gridDim.x;
+        epoch = ld_coh(ws + SYNC_EPOCH);
+    }
+
+    template <bool acquire_caches = false>
+    __device__ __forceinline__ void sync() {
+        if (size == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            return;
+        }
+        const unsigned e = ++epoch;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (threadIdx.x == 0) st_coh(flags + rank, e);
+        if (rank == 0) {
+            if (threadIdx.x < 64) {
+                const unsigned G = size;
+                for (unsigned base = 0; base < G; base += 64) {
+                    const unsigned i = base + threadIdx.x;
+                    while (true) {
+                        bool ok = (i >= G) || (ld_coh(flags + i) == e);
+                        if (__all(ok)) break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                if (threadIdx.x == 0) st_coh(gen, e);
+            }
+        } else if (threadIdx.x == 0) {
+            while (ld_coh(gen) != e) __builtin_amdgcn_s_sleep(1);
+        }
+        if (acquire_caches && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 };
 

@@ -17,277 +17,572 @@
 // cache of A); the rest streams from L2 / Infinity Cache / HBM.
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <vector>
 
 #include "barrier.hpp"
+#include "cg_common.hpp"
 #include "common.hpp"
 
 namespace perks {
 namespace {
 
-constexpr int CG_WAVES = 8;
-constexpr int CG_THREADS = CG_WAVES * 64;
 enum { PART_PQ = 0, PART_RZ = 1, PART_RR = 2, PART_BB = 3, PART_TRUE = 4, NPART = 5 };
 
-struct CgParams {
+// One CG problem and its work vectors (device pointers).  FP64 solves use
+// r, z, q, p0, p1, dinv; mixed solves use r64 and the FP32 vectors.  part
+// holds NPART partial sums per workgroup of the problem's group; result
+// receives iters, status, relres, relres_true, ||b||, restarts or outer steps.
+struct CgInst {
     const int *rowptr;
     const int *colind;
     const double *val;
     const double *b;
     double *x;
-    double *r;      // residual
-    double *z;      // preconditioned residual (== r when unpreconditioned)
-    double *q;      // A p (own rows)
-    double *p0, *p1;
-    double *dinv;   // inverse diagonal (Jacobi)
-    double *part;   // [NPART][G]
-    double *result; // [8] iters, status, relres, relres_true, rho, ...
-    unsigned *sync;
+    double *r, *z, *q, *p0, *p1, *dinv;
+    float *val32;
+    double *r64;
+    float *r32, *z32, *q32, *p0_32, *p1_32, *d32, *dinv32;
+    double *part;
+    double *result;
+    double *cap_x, *cap_r;   // FP64 solver: x and r after the iterations listed in cap_iters
+    const int *cap_iters;    // ascending iteration counts (device)
+    int ncap;
     int n;
     int nnz;
     int maxit;
-    int precond;
-    int lds_nnz;    // capacity of the LDS cache of A (nonzeros per workgroup)
+    int max_outer;
     double tol;
+    double inner_tol;
 };
 
-// Sum over the 64 lanes of a wave (butterfly; every lane gets the total).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// The workgroup's LDS copy of (the first entries of) its slice of A: FP64
+// values for the FP64 solver, FP32 values for the mixed-precision solver.
+// Each kernel references only its own pair, so each gets only that pair.
+constexpr int CG_LDS_NNZ = 13312;     // 156 KiB of the 160 KiB LDS (12 B/nonzero)
+constexpr int CG_LDS_NNZ32 = 19968;   // 156 KiB (8 B/nonzero)
+__shared__ double cg_lval[CG_LDS_NNZ];
+__shared__ int cg_lcol[CG_LDS_NNZ];
+__shared__ float cg_lval32[CG_LDS_NNZ32];
+__shared__ int cg_lcol32[CG_LDS_NNZ32];
 
-// Sum over groups of L lanes (L a power of two, runtime-uniform).
-__device__ __forceinline__ double group_sum(double v, int L) {
-    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+template <typename T> struct LdsA;
+template <> struct LdsA<double> {
+    static constexpr int cap = CG_LDS_NNZ;
+    static __device__ __forceinline__ double &val(int k) { return cg_lval[k]; }
+    static __device__ __forceinline__ int &col(int k) { return cg_lcol[k]; }
+};
+template <> struct LdsA<float> {
+    static constexpr int cap = CG_LDS_NNZ32;
+    static __device__ __forceinline__ float &val(int k) { return cg_lval32[k]; }
+    static __device__ __forceinline__ int &col(int k) { return cg_lcol32[k]; }
+};
 
-// Deterministic workgroup sum of up to 3 values: waves reduce, then wave 0
-// adds the wave totals in wave order.  Returns the sums to thread 0 only.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *lds_red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// y_i for rows [r0, r1) with L lanes per row: sum_k a_k * v(col_k) in type T,
+// where v(j) is produced by `fetch`.  FROM_LDS: the rows lie wholly in the
+// LDS copy of the slice (entry k at index k - kbase); otherwise A is read from
+// `gval` in global memory.  Each lane group takes U rows per pass and issues
+// all their loads before any use (U times the memory-level parallelism of one
+// row at a time).  A row's sum is the lane-strided partial sums followed by
+// the group butterfly: its rounding depends neither on U nor on where A is
+// read from.
+template <int U, bool FROM_LDS, typename T, typename F, typename S>
+__device__ __forceinline__ void spmv_range(const int *rowptr, const int *colind, const T *gval, int r0, int r1,
+                                           int L, int kbase, F fetch, S sink) {
+    const int tid = threadIdx.x;
+    const int gl = tid & (L - 1);
+    const int rpp = CG_THREADS / L;
+    for (int row0 = r0; row0 < r1; row0 += rpp * U) {
+        int kb[U], ke[U];
+        T s[U];
+        int len = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0) {
+        for (int u = 0; u < U; ++u) {
+            const int i = row0 + u * rpp + tid / L;
+            kb[u] = 0;
+            ke[u] = 0;
+            s[u] = T(0);
+            if (i < r1) {
+                kb[u] = rowptr[i] + gl;
+                ke[u] = rowptr[i + 1];
+            }
+            len = max(len, ke[u] - kb[u]);
+        }
+        for (int j = 0; j < len; j += L) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) lds_red[k * CG_WAVES + wave] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+            for (int u = 0; u < U; ++u) {
+                const int k = kb[u] + j;
+                if (k < ke[u]) {
+                    T a;
+                    int c;
+                    if constexpr (FROM_LDS) {
+                        a = LdsA<T>::val(k - kbase);
+                        c = LdsA<T>::col(k - kbase);
+                    } else {
+                        a = gval[k];
+                        c = colind[k];
+                    }
+                    s[u] = fma_t(a, fetch(c), s[u]);
+                }
+            }
+        }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < CG_WAVES; ++w) s += lds_red[k * CG_WAVES + w];
-            v[k] = s;
+        for (int u = 0; u < U; ++u) {
+            const T t = group_sum(s[u], L);
+            const int i = row0 + u * rpp + tid / L;
+            if (i < r1 && gl == 0) sink(i, t);
         }
     }
-    __syncthreads();
 }
 
-// Every workgroup sums the G partials of slot `slot` in the same order
-// (lanes take strided shares, then a butterfly): identical bits everywhere.
-__device__ __forceinline__ double grid_total(const double *part, int slot, double *lds_bcast) {
-    const int G = gridDim.x;
-    if (threadIdx.x < 64) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < G; i += 64) s += ld_coh(part + (size_t)slot * G + i);
-        s = wave_sum(s);
-        if (threadIdx.x == 0) *lds_bcast = s;
-    }
-    __syncthreads();
-    const double t = *lds_bcast;
-    __syncthreads();
-    return t;
+// Rows [r0, rc) come from the LDS copy, rows [rc, r1) from global memory.
+template <int U, typename T, typename F, typename S>
+__device__ __forceinline__ void spmv_rows(const int *rowptr, const int *colind, const T *gval, int r0, int rc,
+                                          int r1, int L, int kbase, F fetch, S sink) {
+    spmv_range<U, true>(rowptr, colind, gval, r0, rc, L, kbase, fetch, sink);
+    spmv_range<U, false>(rowptr, colind, gval, rc, r1, L, kbase, fetch, sink);
 }
 
-// First row of share g when rows + nonzeros are split into G equal shares:
-// the smallest i with i + rowptr[i] >= g * (n + nnz) / G (merge-path diagonal).
-__device__ int merge_split(const int *rowptr, int n, int nnz, int g, int G) {
-    const long long target = (long long)g * ((long long)n + nnz) / G;
-    int lo = 0, hi = n;
+// First row of [r0, r1) that does not end within the first kc entries of the
+// slice starting at kbase (rows before it are wholly cached).
+__device__ __forceinline__ int cached_rows_end(const int *rowptr, int r0, int r1, int kbase, int kc) {
+    int lo = r0, hi = r1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if ((long long)mid + rowptr[mid] < target) lo = mid + 1;
+        if (rowptr[mid + 1] - kbase <= kc) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-__device__ __forceinline__ int pick_group(int rows, int nnz) {
-    const int avg = rows > 0 ? (nnz + rows - 1) / rows : 1;
-    int L = 1;
-    while (L < avg && L < 64) L <<= 1;
-    return L;
+constexpr int CG_U = PERKS_CG_U;
+
+__shared__ double cg_red[4 * CG_WAVES];
+__shared__ double cg_bcast;
+
+// The workgroup's share of a problem solved by a group of G workgroups, of
+// which this one has rank g: rows [r0, r1) (merge-path split), the LDS copy
+// of the first kc entries of its slice of A, rows [r0, rc) wholly cached.
+struct Slice {
+    int r0, r1, rc, kbase, nnz, kc, L;
+};
+
+template <typename T>
+__device__ __forceinline__ Slice load_slice(const CgInst &p, const T *val, int g, int G) {
+    Slice sl;
+    sl.r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
+    sl.r1 = merge_split(p.rowptr, p.n, p.nnz, g + 1, G);
+    sl.kbase = p.rowptr[sl.r0];
+    sl.nnz = p.rowptr[sl.r1] - sl.kbase;
+    sl.L = pick_group(sl.r1 - sl.r0, sl.nnz);
+    sl.kc = min(sl.nnz, LdsA<T>::cap);
+    __syncthreads();   // the previous problem of this workgroup is done with the LDS copy
+    for (int k = threadIdx.x; k < sl.kc; k += CG_THREADS) {
+        LdsA<T>::val(k) = val[sl.kbase + k];
+        LdsA<T>::col(k) = p.colind[sl.kbase + k];
+    }
+    sl.rc = cached_rows_end(p.rowptr, sl.r0, sl.r1, sl.kbase, sl.kc);
+    __syncthreads();
+    return sl;
 }
 
-// The workgroup's LDS copy of (the first CG_LDS_NNZ entries of) its slice of A.
-constexpr int CG_LDS_NNZ = 13312;   // 156 KiB of the 160 KiB LDS
-__shared__ double cg_lval[CG_LDS_NNZ];
-__shared__ int cg_lcol[CG_LDS_NNZ];
-
-// y_i for rows [r0, r1) with L lanes per row: sum_k a_k * v(col_k), where
-// v(j) is produced by `fetch`.  Matrix entries k < kc come from the LDS copy.
-template <typename F, typename S>
-__device__ __forceinline__ void spmv_rows(const CgParams &p, int r0, int r1, int L, int kbase, int kc, F fetch,
-                                          S sink) {
+// FP64 persistent CG of one problem by a group of G workgroups (this one of
+// rank g) synchronised by `gs`.  Per iteration: phase 1 q = A p and p.q,
+// phase 2 x, r, z updates and r.z, r.r, each followed by a group barrier and
+// a fixed-order all-reduce.  FUSEP forms p = z + beta p_old on the fly in
+// phase 1 (two gathers per nonzero, no barrier of its own); otherwise a
+// phase P updates p in place on own rows before a third barrier.  When the
+// recursive residual meets tol the true residual is recomputed; if it fails,
+// CG restarts from the current x while iterations remain.
+template <bool JACOBI, bool FUSEP, class Sync>
+__device__ __forceinline__ void cg_f64_body(const CgInst &p, Sync &gs, const int g, const int G) {
     const int tid = threadIdx.x;
-    const int gl = tid & (L - 1);
-    const int rows_per_pass = CG_THREADS / L;
-    for (int row0 = r0; row0 < r1; row0 += rows_per_pass) {
-        const int i = row0 + tid / L;
-        double s = 0.0;
-        if (i < r1) {
-            const int kb = p.rowptr[i], ke = p.rowptr[i + 1];
-            for (int k = kb + gl; k < ke; k += L) {
-                const int kk = k - kbase;
-                double a;
-                int c;
-                if (kk < kc) {
-                    a = cg_lval[kk];
-                    c = cg_lcol[kk];
-                } else {
-                    a = p.val[k];
-                    c = p.colind[k];
-                }
-                s = __builtin_fma(a, fetch(c), s);
-            }
-        }
-        s = group_sum(s, L);
-        if (i < r1 && gl == 0) sink(i, s);
-    }
-}
-
-template <bool JACOBI>
-__global__ __launch_bounds__(CG_THREADS) void cg_persistent(CgParams p) {
-    __shared__ double red[4 * CG_WAVES];
-    __shared__ double bcast;
-    GridSync gs;
-    gs.init(p.sync);
-    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-    const int r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
-    const int r1 = merge_split(p.rowptr, p.n, p.nnz, g + 1, G);
-    const int kbase = p.rowptr[r0];
-    const int my_nnz = p.rowptr[r1] - kbase;
-    const int L = pick_group(r1 - r0, my_nnz);
-    // on-chip cache of this workgroup's slice of A
-    const int kc = min(my_nnz, p.lds_nnz);
-    for (int k = tid; k < kc; k += CG_THREADS) {
-        cg_lval[k] = p.val[kbase + k];
-        cg_lcol[k] = p.colind[kbase + k];
-    }
-    __syncthreads();
-
-    // phase 0: r = b - A x, z, p_{-1} = 0, partials b.b, r.z, r.r
-    double acc0[3] = {0.0, 0.0, 0.0};
-    spmv_rows(p, r0, r1, L, kbase, kc, [&](int c) { return p.x[c]; },
-              [&](int i, double s) { p.q[i] = s; });
-    __syncthreads();
-    for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-        const double bi = p.b[i];
-        const double ri = bi - p.q[i];
-        const double zi = JACOBI ? p.dinv[i] * ri : ri;
-        if (JACOBI) {
-            p.r[i] = ri;            // read back only by this thread
-            st_coh(p.z + i, zi);    // gathered by other workgroups
-        } else {
-            st_coh(p.r + i, ri);
-        }
-        st_coh(p.p1 + i, 0.0);
-        acc0[0] = __builtin_fma(bi, bi, acc0[0]);
-        acc0[1] = __builtin_fma(ri, zi, acc0[1]);
-        acc0[2] = __builtin_fma(ri, ri, acc0[2]);
-    }
-    block_sum<3>(acc0, red);
-    if (tid == 0) {
-        st_coh(p.part + (size_t)PART_BB * G + g, acc0[0]);
-        st_coh(p.part + (size_t)PART_RZ * G + g, acc0[1]);
-        st_coh(p.part + (size_t)PART_RR * G + g, acc0[2]);
-    }
-    gs.sync();
-    const double bb = grid_total(p.part, PART_BB, &bcast);
-    double rho = grid_total(p.part, PART_RZ, &bcast);
-    double rr = grid_total(p.part, PART_RR, &bcast);
-    const double bnorm = sqrt(bb);
-    double beta = 0.0;
-    int k = 0, status = 1;
-    const double *zsrc = JACOBI ? p.z : p.r;
-    if (bnorm == 0.0) status = 0;
-    while (status == 1) {
-        if (sqrt(rr) <= p.tol * bnorm) { status = 0; break; }
-        if (k >= p.maxit) break;
-        double *pn = (k & 1) ? p.p1 : p.p0;        // p_k
-        const double *po = (k & 1) ? p.p0 : p.p1;  // p_{k-1}
-        // phase 1: q = A p_k with p_k formed on the fly; own p_k stored
-        double acc1[1] = {0.0};
-        spmv_rows(p, r0, r1, L, kbase, kc,
-                  [&](int c) { return __builtin_fma(beta, ld_coh(po + c), ld_coh(zsrc + c)); },
-                  [&](int i, double s) {
-                      const double pi = __builtin_fma(beta, ld_coh(po + i), ld_coh(zsrc + i));
-                      p.q[i] = s;
-                      st_coh(pn + i, pi);
-                      acc1[0] = __builtin_fma(pi, s, acc1[0]);
-                  });
-        block_sum<1>(acc1, red);
-        if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
-        gs.sync();
-        const double pq = grid_total(p.part, PART_PQ, &bcast);
-        if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
-        const double alpha = rho / pq;
-        // phase 2: x, r, z updates on own rows
-        double acc2[2] = {0.0, 0.0};
+    const Slice sl = load_slice(p, p.val, g, G);
+    const int r0 = sl.r0, r1 = sl.r1, rc = sl.rc, kbase = sl.kbase, L = sl.L;
+    if (JACOBI) {
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            const double pi = ld_coh(pn + i);
-            const double qi = p.q[i];
-            // x is read by other workgroups for the final true residual
-            st_coh(p.x + i, __builtin_fma(alpha, pi, ld_coh(p.x + i)));
-            const double ri = __builtin_fma(-alpha, qi, JACOBI ? p.r[i] : ld_coh(p.r + i));
-            double zi = ri;
+            double dg = 0.0;
+            for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k)
+                if (p.colind[k] == i) dg += p.val[k];
+            p.dinv[i] = 1.0 / dg;
+        }
+    }
+    const double *zsrc = JACOBI ? p.z : p.r;
+    int k = 0, status = 1, restarts = 0, k_cycle = -1, cap = 0;
+    while (cap < p.ncap && p.cap_iters[cap] <= 0) ++cap;
+    double bnorm = 0.0, rr = 0.0, tt = 0.0;
+    for (;;) {
+        // phase 0: r = b - A x, z, p_{-1} = 0, partials b.b, r.z, r.r
+        double acc0[3] = {0.0, 0.0, 0.0};
+        spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return p.x[c]; },
+                        [&](int i, double s) { p.q[i] = s; });
+        __syncthreads();
+        for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+            const double bi = p.b[i];
+            const double ri = bi - p.q[i];
+            const double zi = JACOBI ? p.dinv[i] * ri : ri;
             if (JACOBI) {
-                p.r[i] = ri;
-                zi = p.dinv[i] * ri;
-                st_coh(p.z + i, zi);
+                p.r[i] = ri;            // read back only by this thread
+                st_coh(p.z + i, zi);    // gathered by other workgroups
             } else {
                 st_coh(p.r + i, ri);
             }
-            acc2[0] = __builtin_fma(ri, zi, acc2[0]);
-            acc2[1] = __builtin_fma(ri, ri, acc2[1]);
+            st_coh((FUSEP ? p.p1 : p.p0) + i, 0.0);
+            acc0[0] = __builtin_fma(bi, bi, acc0[0]);
+            acc0[1] = __builtin_fma(ri, zi, acc0[1]);
+            acc0[2] = __builtin_fma(ri, ri, acc0[2]);
         }
-        block_sum<2>(acc2, red);
+        block_sum<3>(acc0, cg_red);
         if (tid == 0) {
-            st_coh(p.part + (size_t)PART_RZ * G + g, acc2[0]);
-            st_coh(p.part + (size_t)PART_RR * G + g, acc2[1]);
+            st_coh(p.part + (size_t)PART_BB * G + g, acc0[0]);
+            st_coh(p.part + (size_t)PART_RZ * G + g, acc0[1]);
+            st_coh(p.part + (size_t)PART_RR * G + g, acc0[2]);
         }
-        gs.sync();
-        const double rho_new = grid_total(p.part, PART_RZ, &bcast);
-        rr = grid_total(p.part, PART_RR, &bcast);
-        ++k;
-        if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
-        beta = rho_new / rho;
-        rho = rho_new;
+        gs.template sync<true>();
+        bnorm = sqrt(grid_total(p.part, PART_BB, G, &cg_bcast));
+        double rho = grid_total(p.part, PART_RZ, G, &cg_bcast);
+        rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+        if (bnorm == 0.0) {
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, 0.0);
+            status = 0;
+            tt = 0.0;
+            break;
+        }
+        double beta = 0.0;
+        while (true) {
+            if (sqrt(rr) <= p.tol * bnorm) break;
+            if (k >= p.maxit) break;
+            double acc1[1] = {0.0};
+            double *pn;
+            if constexpr (FUSEP) {
+                pn = (k & 1) ? p.p1 : p.p0;                // p_k
+                const double *po = (k & 1) ? p.p0 : p.p1;  // p_{k-1}
+                spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase,
+                                [&](int c) { return __builtin_fma(beta, po[c], zsrc[c]); },
+                                [&](int i, double s) {
+                                    const double pi = __builtin_fma(beta, po[i], zsrc[i]);
+                                    p.q[i] = s;
+                                    st_coh(pn + i, pi);
+                                    acc1[0] = __builtin_fma(pi, s, acc1[0]);
+                                });
+            } else {
+                pn = p.p0;
+                for (int i = r0 + tid; i < r1; i += CG_THREADS)
+                    st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
+                gs.template sync<true>();
+                spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return pn[c]; },
+                                [&](int i, double s) {
+                                    p.q[i] = s;
+                                    acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
+                                });
+            }
+            block_sum<1>(acc1, cg_red);
+            if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
+            gs.template sync<true>();
+            const double pq = grid_total(p.part, PART_PQ, G, &cg_bcast);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
+            const double alpha = rho / pq;
+            // phase 2: x, r, z updates on own rows (2 rows per thread in flight)
+            double acc2[2] = {0.0, 0.0};
+            for (int i0 = r0 + tid; i0 < r1; i0 += 2 * CG_THREADS) {
+                double pi[2], qi[2], xi[2], ro[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int i = i0 + u * CG_THREADS;
+                    if (i < r1) {
+                        pi[u] = pn[i];
+                        qi[u] = p.q[i];
+                        xi[u] = p.x[i];
+                        ro[u] = p.r[i];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int i = i0 + u * CG_THREADS;
+                    if (i < r1) {
+                        st_coh(p.x + i, __builtin_fma(alpha, pi[u], xi[u]));   // read by others at exit
+                        const double ri = __builtin_fma(-alpha, qi[u], ro[u]);
+                        double zi = ri;
+                        if (JACOBI) {
+                            p.r[i] = ri;
+                            zi = p.dinv[i] * ri;
+                            st_coh(p.z + i, zi);
+                        } else {
+                            st_coh(p.r + i, ri);
+                        }
+                        acc2[0] = __builtin_fma(ri, zi, acc2[0]);
+                        acc2[1] = __builtin_fma(ri, ri, acc2[1]);
+                    }
+                }
+            }
+            block_sum<2>(acc2, cg_red);
+            if (tid == 0) {
+                st_coh(p.part + (size_t)PART_RZ * G + g, acc2[0]);
+                st_coh(p.part + (size_t)PART_RR * G + g, acc2[1]);
+            }
+            gs.template sync<true>();
+            const double rho_new = grid_total(p.part, PART_RZ, G, &cg_bcast);
+            rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+            ++k;
+            if (cap < p.ncap && k == p.cap_iters[cap]) {
+                // snapshot of the iterate and its residual (own rows, same
+                // thread-to-row mapping as phase 2)
+                for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+                    p.cap_x[(size_t)cap * p.n + i] = p.x[i];
+                    p.cap_r[(size_t)cap * p.n + i] = p.r[i];
+                }
+                ++cap;
+            }
+            if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
+            beta = rho_new / rho;
+            rho = rho_new;
+        }
+        // true residual ||b - A x|| (x of other workgroups read after the barrier)
+        double acc3[1] = {0.0};
+        gs.template sync<true>();
+        spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return p.x[c]; },
+                        [&](int i, double s) {
+                            const double d = p.b[i] - s;
+                            acc3[0] = __builtin_fma(d, d, acc3[0]);
+                        });
+        block_sum<1>(acc3, cg_red);
+        if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, acc3[0]);
+        gs.template sync<true>();
+        tt = grid_total(p.part, PART_TRUE, G, &cg_bcast);
+        if (status == 2) break;
+        if (sqrt(tt) <= p.tol * bnorm) { status = 0; break; }
+        // restart from x (recursive residual converged but the true one did
+        // not) unless the iteration budget is spent or the last cycle made no
+        // iteration (the two residuals differ only in rounding order there)
+        if (k >= p.maxit || k == k_cycle) { status = 1; break; }
+        k_cycle = k;
+        ++restarts;
     }
-    // true residual ||b - A x|| (x of other workgroups read coherently)
-    double acc3[1] = {0.0};
-    gs.sync();
-    spmv_rows(p, r0, r1, L, kbase, kc, [&](int c) { return ld_coh(p.x + c); },
-              [&](int i, double s) {
-                  const double d = p.b[i] - s;
-                  acc3[0] = __builtin_fma(d, d, acc3[0]);
-              });
-    block_sum<1>(acc3, red);
-    if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, acc3[0]);
-    gs.sync();
-    const double tt = grid_total(p.part, PART_TRUE, &bcast);
     if (g == 0 && tid == 0) {
         p.result[0] = k;
         p.result[1] = status;
         p.result[2] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
         p.result[3] = bnorm > 0.0 ? sqrt(tt) / bnorm : 0.0;
         p.result[4] = bnorm;
+        p.result[5] = restarts;
     }
-    gs.finish();
+}
+
+// Mixed precision: FP64 iterative refinement around an FP32 CG.  Outer step
+// (FP64): r = b - A x with the FP64 matrix; stop when ||r|| <= tol ||b||;
+// otherwise run CG in FP32 on A32 d = s r (A32 = float(A), s a power of two
+// near 1/||r||, so the scaling is exact), with FP32 vectors, SpMV and AXPYs
+// and FP64 dot products, alpha and beta, until its recursive residual has
+// fallen by inner_tol; then x += d / s.  An outer step that does not halve
+// ||r|| ends the solve (FP32 cannot resolve the system).  The FP32 copy of
+// each workgroup's slice of A is made by the workgroup itself (global copy +
+// LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
+// nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
+template <bool JACOBI, bool FUSEP, class Sync>
+__device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const int g, const int G) {
+    const int tid = threadIdx.x;
+    {
+        // FP32 copy of this workgroup's slice (only this workgroup reads it)
+        const int s0 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g, G)];
+        const int s1 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g + 1, G)];
+        for (int k = s0 + tid; k < s1; k += CG_THREADS) p.val32[k] = (float)p.val[k];
+    }
+    const Slice sl = load_slice(p, (const float *)p.val32, g, G);   // its barrier publishes val32
+    const int r0 = sl.r0, r1 = sl.r1, rc = sl.rc, kbase = sl.kbase, L = sl.L;
+    double accb[1] = {0.0};
+    for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+        if (JACOBI) {
+            double dg = 0.0;
+            for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k)
+                if (p.colind[k] == i) dg += p.val[k];
+            p.dinv32[i] = (float)(1.0 / dg);
+        }
+        const double bi = p.b[i];
+        accb[0] = __builtin_fma(bi, bi, accb[0]);
+    }
+    block_sum<1>(accb, cg_red);
+    if (tid == 0) st_coh(p.part + (size_t)PART_BB * G + g, accb[0]);
+
+    const float *zsrc = JACOBI ? p.z32 : p.r32;
+    double bnorm = -1.0, rn = 0.0, prev = INFINITY;
+    int k = 0, outer = 0, status = 1;
+    for (;;) {
+        gs.template sync<true>();   // x (and, the first time, the b.b partials) complete
+        if (bnorm < 0.0) bnorm = sqrt(grid_total(p.part, PART_BB, G, &cg_bcast));
+        if (bnorm == 0.0) {
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, 0.0);
+            status = 0;
+            rn = 0.0;
+            break;
+        }
+        // outer residual in FP64 (A from global memory in FP64)
+        double accr[1] = {0.0};
+        spmv_range<CG_U, false>(p.rowptr, p.colind, p.val, r0, r1, L, kbase, [&](int c) { return p.x[c]; },
+                                [&](int i, double sv) {
+                                    const double ri = p.b[i] - sv;
+                                    p.r64[i] = ri;
+                                    accr[0] = __builtin_fma(ri, ri, accr[0]);
+                                });
+        block_sum<1>(accr, cg_red);
+        if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, accr[0]);
+        gs.template sync<true>();
+        rn = sqrt(grid_total(p.part, PART_TRUE, G, &cg_bcast));
+        if (status == 2) break;
+        if (rn <= p.tol * bnorm) { status = 0; break; }
+        if (k >= p.maxit || outer >= p.max_outer || !(rn <= 0.5 * prev)) break;
+        prev = rn;
+        int ex;
+        (void)frexp(rn, &ex);
+        const double sc = ldexp(1.0, 1 - ex);   // 2^-floor(log2 rn)
+        // inner start: r32 = float(s r), z32, p_{-1} = 0, d = 0
+        double acc0[2] = {0.0, 0.0};
+        for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+            const float ri = (float)(p.r64[i] * sc);
+            const float zi = JACOBI ? p.dinv32[i] * ri : ri;
+            if (JACOBI) {
+                p.r32[i] = ri;
+                st_coh(p.z32 + i, zi);
+            } else {
+                st_coh(p.r32 + i, ri);
+            }
+            st_coh((FUSEP ? p.p1_32 : p.p0_32) + i, 0.0f);
+            p.d32[i] = 0.0f;
+            acc0[0] = __builtin_fma((double)ri, (double)zi, acc0[0]);
+            acc0[1] = __builtin_fma((double)ri, (double)ri, acc0[1]);
+        }
+        block_sum<2>(acc0, cg_red);
+        if (tid == 0) {
+            st_coh(p.part + (size_t)PART_RZ * G + g, acc0[0]);
+            st_coh(p.part + (size_t)PART_RR * G + g, acc0[1]);
+        }
+        gs.template sync<true>();
+        double rho = grid_total(p.part, PART_RZ, G, &cg_bcast);
+        double rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+        const double stop = p.inner_tol * sqrt(rr);
+        double beta = 0.0;
+        for (int j = 0; sqrt(rr) > stop && k < p.maxit; ++j) {
+            const float bf = (float)beta;
+            double acc1[1] = {0.0};
+            float *pn;
+            if constexpr (FUSEP) {
+                pn = (j & 1) ? p.p1_32 : p.p0_32;                // p_j
+                const float *po = (j & 1) ? p.p0_32 : p.p1_32;   // p_{j-1}
+                spmv_rows<CG_U>(p.rowptr, p.colind, (const float *)p.val32, r0, rc, r1, L, kbase,
+                                [&](int c) { return __builtin_fmaf(bf, po[c], zsrc[c]); },
+                                [&](int i, float sv) {
+                                    const float pi = __builtin_fmaf(bf, po[i], zsrc[i]);
+                                    p.q32[i] = sv;
+                                    st_coh(pn + i, pi);
+                                    acc1[0] = __builtin_fma((double)pi, (double)sv, acc1[0]);
+                                });
+            } else {
+                pn = p.p0_32;
+                for (int i = r0 + tid; i < r1; i += CG_THREADS)
+                    st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
+                gs.template sync<true>();
+                spmv_rows<CG_U>(p.rowptr, p.colind, (const float *)p.val32, r0, rc, r1, L, kbase,
+                                [&](int c) { return pn[c]; },
+                                [&](int i, float sv) {
+                                    p.q32[i] = sv;
+                                    acc1[0] = __builtin_fma((double)pn[i], (double)sv, acc1[0]);
+                                });
+            }
+            block_sum<1>(acc1, cg_red);
+            if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
+            gs.template sync<true>();
+            const double pq = grid_total(p.part, PART_PQ, G, &cg_bcast);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
+            const float af = (float)(rho / pq);
+            double acc2[2] = {0.0, 0.0};
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+                const float pi = pn[i];
+                p.d32[i] = __builtin_fmaf(af, pi, p.d32[i]);
+                const float ri = __builtin_fmaf(-af, p.q32[i], p.r32[i]);
+                float zi = ri;
+                if (JACOBI) {
+                    p.r32[i] = ri;
+                    zi = p.dinv32[i] * ri;
+                    st_coh(p.z32 + i, zi);
+                } else {
+                    st_coh(p.r32 + i, ri);
+                }
+                acc2[0] = __builtin_fma((double)ri, (double)zi, acc2[0]);
+                acc2[1] = __builtin_fma((double)ri, (double)ri, acc2[1]);
+            }
+            block_sum<2>(acc2, cg_red);
+            if (tid == 0) {
+                st_coh(p.part + (size_t)PART_RZ * G + g, acc2[0]);
+                st_coh(p.part + (size_t)PART_RR * G + g, acc2[1]);
+            }
+            gs.template sync<true>();
+            const double rho_new = grid_total(p.part, PART_RZ, G, &cg_bcast);
+            rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+            ++k;
+            if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
+            beta = rho_new / rho;
+            rho = rho_new;
+        }
+        // x += d / s on own rows (read by every workgroup in the next residual)
+        for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, p.x[i] + (double)p.d32[i] / sc);
+        ++outer;
+    }
+    if (g == 0 && tid == 0) {
+        p.result[0] = k;
+        p.result[1] = status;
+        p.result[2] = bnorm > 0.0 ? rn / bnorm : 0.0;
+        p.result[3] = bnorm > 0.0 ? rn / bnorm : 0.0;
+        p.result[4] = bnorm;
+        p.result[5] = outer;
+    }
+}
+
+// One problem on the whole grid.
+template <bool JACOBI, bool FUSEP, bool MIXED>
+__global__ __launch_bounds__(CG_THREADS) void cg_persistent(CgInst p, unsigned *ws) {
+    GroupSync gs;
+    gs.init_grid(ws);
+    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(p, gs, blockIdx.x, gridDim.x);
+    else cg_f64_body<JACOBI, FUSEP>(p, gs, blockIdx.x, gridDim.x);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
+}
+
+// Many problems in one launch.  Workgroup g runs the tasks
+// tasks[task_ptr[g] .. task_ptr[g+1]) in order; a task is (problem, rank,
+// group size, group id).  A problem given to several workgroups is the first
+// task of each of them (a contiguous range of workgroups, synchronised by the
+// group's own barrier); the other problems are solved by one workgroup each,
+// one after another.  No workgroup waits on a group before finishing all
+// earlier tasks of its own, so no wait can be circular.  A final barrier of
+// the whole grid precedes the hand-over of the epoch to the next launch.
+struct CgTask {
+    int inst, rank, size, group;
+};
+
+struct CgBatch {
+    const CgInst *inst;
+    const CgTask *tasks;
+    const int *task_ptr;
+    unsigned *ws;
+    unsigned epoch_span;   // > barriers any group takes; epochs of this launch stay below start + span
+};
+
+template <bool JACOBI, bool FUSEP, bool MIXED>
+__global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
+    const int g = blockIdx.x;
+    const unsigned e0 = ld_coh(bp.ws + SYNC_EPOCH);
+    for (int t = bp.task_ptr[g]; t < bp.task_ptr[g + 1]; ++t) {
+        const CgTask task = bp.tasks[t];
+        const CgInst p = bp.inst[task.inst];
+        GroupSync gs;
+        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0);
+        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(p, gs, task.rank, task.size);
+        else cg_f64_body<JACOBI, FUSEP>(p, gs, task.rank, task.size);
+    }
+    GroupSync all;
+    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + bp.epoch_span - 1);
+    all.gen = bp.ws + SYNC_GEN;
+    all.sync();
+    if (g == 0 && threadIdx.x == 0) st_coh(bp.ws + SYNC_EPOCH, all.epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,21 +591,47 @@ struct BaseScalars {
     double rho, pq, alpha, beta, rr, bb, rho_new, status;
 };
 
-__global__ __launch_bounds__(256) void base_spmv(const int *rowptr, const int *colind, const double *val, int n,
-                                                 int L, const double *v, double *y, const double *pvec,
-                                                 double *part) {
-    // y = A v; part[block] = sum_i pvec_i * y_i (when pvec != nullptr)
+// y = A v for the rows of this block (U rows per group of L lanes, loads of
+// all U rows issued before use); part[block] = sum_i pvec_i * y_i when pvec
+// is given.
+constexpr int BASE_U = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void base_spmv(const int *rowptr, const int *colind, const T *val, int n, int L,
+                                                 const T *v, T *y, const T *pvec, double *part) {
     const int tid = threadIdx.x, gl = tid & (L - 1);
-    const int i = blockIdx.x * (256 / L) + tid / L;
-    double s = 0.0;
-    if (i < n) {
-        for (int k = rowptr[i] + gl; k < rowptr[i + 1]; k += L) s = __builtin_fma(val[k], v[colind[k]], s);
+    const int rpp = 256 / L;
+    const int row0 = blockIdx.x * rpp * BASE_U;
+    int kb[BASE_U], ke[BASE_U];
+    T s[BASE_U];
+    int len = 0;
+#pragma unroll
+    for (int u = 0; u < BASE_U; ++u) {
+        const int i = row0 + u * rpp + tid / L;
+        kb[u] = 0;
+        ke[u] = 0;
+        s[u] = T(0);
+        if (i < n) {
+            kb[u] = rowptr[i] + gl;
+            ke[u] = rowptr[i + 1];
+        }
+        len = max(len, ke[u] - kb[u]);
     }
-    s = group_sum(s, L);
+    for (int j = 0; j < len; j += L) {
+#pragma unroll
+        for (int u = 0; u < BASE_U; ++u) {
+            const int k = kb[u] + j;
+            if (k < ke[u]) s[u] = fma_t(val[k], v[colind[k]], s[u]);
+        }
+    }
     double d = 0.0;
-    if (i < n && gl == 0) {
-        y[i] = s;
-        if (pvec) d = pvec[i] * s;
+#pragma unroll
+    for (int u = 0; u < BASE_U; ++u) {
+        const T t = group_sum(s[u], L);
+        const int i = row0 + u * rpp + tid / L;
+        if (i < n && gl == 0) {
+            y[i] = t;
+            if (pvec) d = __builtin_fma((double)pvec[i], (double)t, d);
+        }
     }
     if (part) {
         __shared__ double red[4];
@@ -321,15 +642,29 @@ __global__ __launch_bounds__(256) void base_spmv(const int *rowptr, const int *c
     }
 }
 
-__global__ __launch_bounds__(256) void base_reduce(const double *part, int m, double *out) {
-    // out = sum of m partials (one block, fixed order)
-    __shared__ double red[4];
+// out = sum of m partials (one block, fixed order; eight independent loads
+// in flight per thread).
+__global__ __launch_bounds__(1024) void base_reduce(const double *part, int m, double *out) {
+    __shared__ double red[16];
     double s = 0.0;
-    for (int i = threadIdx.x; i < m; i += 256) s += part[i];
+    for (int i0 = 0; i0 < m; i0 += 1024 * 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + (int)threadIdx.x;
+            t[u] = i < m ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int w = 0; w < 16; ++w) r += red[w];
+        *out = r;
+    }
 }
 
 __global__ void base_alpha(BaseScalars *s) {
@@ -337,20 +672,20 @@ __global__ void base_alpha(BaseScalars *s) {
     s->alpha = s->rho / s->pq;
 }
 
-__global__ __launch_bounds__(256) void base_update(int n, const BaseScalars *s, const double *pv, const double *q,
-                                                   double *x, double *r, double *z, const double *dinv,
-                                                   double *part_rz, double *part_rr) {
+template <typename T>
+__global__ __launch_bounds__(256) void base_update(int n, const BaseScalars *s, const T *pv, const T *q, T *x, T *r,
+                                                   T *z, const T *dinv, double *part_rz, double *part_rr) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     double a = 0.0, c = 0.0;
     if (i < n && s->status == 1.0) {
-        const double alpha = s->alpha;
-        x[i] = __builtin_fma(alpha, pv[i], x[i]);
-        const double ri = __builtin_fma(-alpha, q[i], r[i]);
+        const T alpha = (T)s->alpha;
+        x[i] = fma_t(alpha, pv[i], x[i]);
+        const T ri = fma_t(-alpha, q[i], r[i]);
         r[i] = ri;
-        const double zi = dinv ? dinv[i] * ri : ri;
+        const T zi = dinv ? dinv[i] * ri : ri;
         if (dinv) z[i] = zi;
-        a = ri * zi;
-        c = ri * ri;
+        a = (double)ri * (double)zi;
+        c = (double)ri * (double)ri;
     }
     __shared__ double red[8];
     a = wave_sum(a);
@@ -371,9 +706,83 @@ __global__ void base_beta(BaseScalars *s) {
     s->rho = s->rho_new;
 }
 
-__global__ __launch_bounds__(256) void base_pupdate(int n, const BaseScalars *s, const double *z, double *pv) {
+template <typename T>
+__global__ __launch_bounds__(256) void base_pupdate(int n, const BaseScalars *s, const T *z, T *pv) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n && s->status == 1.0) pv[i] = __builtin_fma(s->beta, pv[i], z[i]);
+    if (i < n && s->status == 1.0) pv[i] = fma_t((T)s->beta, pv[i], z[i]);
+}
+
+// Mixed-precision baseline steps.  r64 = b - ax (ax NULL: 0; r64 NULL: not
+// stored); part = sum of r64^2.
+__global__ __launch_bounds__(256) void base_resid(int n, const double *b, const double *ax, double *r64,
+                                                  double *part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double d = 0.0;
+    if (i < n) {
+        const double ri = ax ? b[i] - ax[i] : b[i];
+        if (r64) r64[i] = ri;
+        d = ri * ri;
+    }
+    __shared__ double red[4];
+    d = wave_sum(d);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// r32 = float(sc r64), z32, p32 = z32, d32 = 0; partial r.z and r.r in FP64.
+__global__ __launch_bounds__(256) void base_mixed_init(int n, const double *r64, double sc, float *r, float *z,
+                                                       float *pv, float *d, const float *dinv, double *part_rz,
+                                                       double *part_rr) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, c = 0.0;
+    if (i < n) {
+        const float ri = (float)(r64[i] * sc);
+        r[i] = ri;
+        const float zi = dinv ? dinv[i] * ri : ri;
+        if (dinv) z[i] = zi;
+        pv[i] = zi;
+        d[i] = 0.0f;
+        a = (double)ri * (double)zi;
+        c = (double)ri * (double)ri;
+    }
+    __shared__ double red[8];
+    a = wave_sum(a);
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a;
+        red[4 + (threadIdx.x >> 6)] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part_rz[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        part_rr[blockIdx.x] = red[4] + red[5] + red[6] + red[7];
+    }
+}
+
+__global__ __launch_bounds__(256) void base_xupdate(int n, double *x, const float *d, double sc) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = x[i] + (double)d[i] / sc;
+}
+
+__global__ __launch_bounds__(256) void zero_words(unsigned *w, int m) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) w[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void to_f32(int64_t m, const double *a, float *o) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) o[i] = (float)a[i];
+}
+
+__global__ __launch_bounds__(256) void invert_diagonal32(const int *rowptr, const int *colind, const double *val,
+                                                         int n, float *dinv) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double dg = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        if (colind[k] == i) dg += val[k];
+    dinv[i] = (float)(1.0 / dg);
 }
 
 __global__ __launch_bounds__(256) void base_init(int n, const double *b, const double *ax, double *r, double *z,
@@ -436,9 +845,11 @@ __global__ __launch_bounds__(256) void true_residual_part(const int *rowptr, con
 }
 
 // ---------------------------------------------------------------------------
-int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int maxit, int precond) {
-    if (!A || !b || !x) return set_error(PERKS_E_INVAL, "A, b and x must not be NULL");
+int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int maxit, int precond,
+              int precision) {
+    if (!A) return set_error(PERKS_E_INVAL, "A must not be NULL");
     if (A->n < 0 || A->nnz < 0) return set_error(PERKS_E_INVAL, "negative matrix size");
+    if (A->n > 0 && (!b || !x)) return set_error(PERKS_E_INVAL, "b and x must not be NULL");
     if (A->n > 0 && (!A->rowptr || !A->colind || (A->nnz > 0 && !A->val)))
         return set_error(PERKS_E_INVAL, "CSR arrays must not be NULL");
     if (A->n >= (int64_t(1) << 31) - 1 || A->nnz >= (int64_t(1) << 31) - 1)
@@ -448,26 +859,63 @@ int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int 
     if (maxit < 0) return set_error(PERKS_E_INVAL, "maxit must be >= 0");
     if (precond != PERKS_PRECOND_NONE && precond != PERKS_PRECOND_JACOBI)
         return set_error(PERKS_E_INVAL, "unknown preconditioner %d", precond);
+    if (precision != PERKS_PREC_F64 && precision != PERKS_PREC_MIXED)
+        return set_error(PERKS_E_INVAL, "unknown precision %d", precision);
     return PERKS_OK;
 }
 
-struct CgWork {
-    double *r, *z, *q, *p0, *p1, *dinv, *part, *result;
-};
+// Work area of one problem: the partial-sum table (NPART per workgroup) and
+// 64 result words, then the vectors.  FP64 solver: r, z, q, p0, p1, dinv (n
+// doubles each).  Mixed solver: r64 (n doubles); r, z, q, p0, p1, d, dinv (n
+// floats each); the FP32 copy of A's values (nnz floats).  Every vector starts
+// on a 256-byte boundary.
+size_t vec_len(int64_t n) { return ((size_t)n + 63) / 64 * 64 + 64; }
 
-int cg_work(int64_t n, int G, CgWork *w) {
-    const size_t nv = (size_t)n + 64;
-    const size_t bytes = (6 * nv + (size_t)NPART * std::max(G, 1) + 64) * sizeof(double);
-    double *base = (double *)scratch(SLOT_CG_VEC, bytes);
+size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
+    const size_t nv = vec_len(n);
+    const size_t np = ((size_t)NPART * std::max(parts, 1) + 64 + 31) / 32 * 32;
+    size_t bytes = (np + 64) * sizeof(double);
+    if (mixed) bytes += nv * sizeof(double) + 7 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float);
+    else bytes += 6 * nv * sizeof(double);
+    return (bytes + 255) / 256 * 256;
+}
+
+void carve(char *base, int64_t n, int parts, bool mixed, CgInst *w) {
+    const size_t nv = vec_len(n);
+    const size_t np = ((size_t)NPART * std::max(parts, 1) + 64 + 31) / 32 * 32;
+    w->part = (double *)base;
+    w->result = w->part + np;
+    char *v = (char *)(w->result + 64);
+    if (mixed) {
+        w->r64 = (double *)v;
+        float *f = (float *)(v + nv * sizeof(double));
+        w->r32 = f;
+        w->z32 = f + nv;
+        w->q32 = f + 2 * nv;
+        w->p0_32 = f + 3 * nv;
+        w->p1_32 = f + 4 * nv;
+        w->d32 = f + 5 * nv;
+        w->dinv32 = f + 6 * nv;
+        w->val32 = f + 7 * nv;
+    } else {
+        double *d = (double *)v;
+        w->r = d;
+        w->z = d + nv;
+        w->q = d + 2 * nv;
+        w->p0 = d + 3 * nv;
+        w->p1 = d + 4 * nv;
+        w->dinv = d + 5 * nv;
+    }
+}
+
+using CgWork = CgInst;
+
+// Work area of a single solve, in the library's scratch slot.
+int cg_work(int64_t n, int64_t nnz, int parts, bool mixed, CgWork *w) {
+    *w = CgWork{};
+    char *base = (char *)scratch(SLOT_CG_VEC, inst_bytes(n, nnz, parts, mixed));
     if (!base) return PERKS_E_NOMEM;
-    w->r = base;
-    w->z = base + nv;
-    w->q = base + 2 * nv;
-    w->p0 = base + 3 * nv;
-    w->p1 = base + 4 * nv;
-    w->dinv = base + 5 * nv;
-    w->part = base + 6 * nv;
-    w->result = w->part + (size_t)NPART * std::max(G, 1);
+    carve(base, n, parts, mixed, w);
     return PERKS_OK;
 }
 
@@ -484,123 +932,141 @@ void fill_result(perks_cg_result *out, int iters, int status, int restarts, int 
     out->reserved = 0;
 }
 
-}  // namespace
-}  // namespace perks
+// Result words (iters, status, relres, relres_true, ||b||, restarts/outer)
+// -> perks_cg_result; returns the status code.
+int result_from_words(const double *h, int wgs, double cached_frac, perks_cg_result *out) {
+    const int st = (int)h[1];
+    const int status = st == 2 ? PERKS_BREAKDOWN : st == 0 ? PERKS_OK : PERKS_NOT_CONVERGED;
+    fill_result(out, (int)h[0], status, (int)h[5], wgs, h[2], h[3], cached_frac);
+    return status;
+}
 
-using namespace perks;
+int launch_error(hipError_t e) {
+    (void)hipGetLastError();
+    return set_error(e == hipErrorCooperativeLaunchTooLarge ? PERKS_E_NOTCORESIDENT : PERKS_E_HIP, "CG launch: %s",
+                     hipGetErrorString(e));
+}
 
-extern "C" {
+#ifndef PERKS_CG_FUSEP
+#define PERKS_CG_FUSEP true
+#endif
 
-int perks_cg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, int32_t precond,
-                   void *stream, perks_cg_result *out) {
-    int rc = check_csr(A, b, x, tol, maxit, precond);
-    if (rc) return rc;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (A->n == 0) {
-        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
-        return PERKS_OK;
-    }
+const void *persistent_fn(bool jac, bool mixed) {
+    constexpr bool F = PERKS_CG_FUSEP;
+    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_persistent<true, F, true>)
+                          : reinterpret_cast<const void *>(&cg_persistent<false, F, true>);
+    return jac ? reinterpret_cast<const void *>(&cg_persistent<true, F, false>)
+               : reinterpret_cast<const void *>(&cg_persistent<false, F, false>);
+}
+
+const void *batched_fn(bool jac, bool mixed) {
+    constexpr bool F = PERKS_CG_FUSEP;
+    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_batched<true, F, true>)
+                          : reinterpret_cast<const void *>(&cg_batched<false, F, true>);
+    return jac ? reinterpret_cast<const void *>(&cg_batched<true, F, false>)
+               : reinterpret_cast<const void *>(&cg_batched<false, F, false>);
+}
+
+// Workgroups the device holds at once for a CG kernel (one per CU).
+int cg_capacity(const void *fn, int *cap) {
     DeviceFacts f;
-    rc = device_facts(&f);
+    int rc = device_facts(&f);
     if (rc) return rc;
-    const bool jac = precond == PERKS_PRECOND_JACOBI;
-    const void *fn = jac ? reinterpret_cast<const void *>(&cg_persistent<true>)
-                         : reinterpret_cast<const void *>(&cg_persistent<false>);
-    // LDS: static cache of A (12 B per nonzero)
-    const int lds_nnz = CG_LDS_NNZ;
     int occ = 0;
     PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, CG_THREADS, 0));
     if (occ < 1) return set_error(PERKS_E_NOTCORESIDENT, "CG kernel does not fit one workgroup per CU");
-    // one workgroup per CU, fewer for small systems (at least ~4 rows per thread)
-    int G = f.cus;
-    const int64_t min_rows = (int64_t)CG_THREADS;
-    if (A->n / min_rows < G) G = (int)std::max<int64_t>(1, A->n / min_rows);
-    if (G > SYNC_MAX_WGS) G = SYNC_MAX_WGS;
-    CgWork w;
-    rc = cg_work(A->n, G, &w);
+    *cap = std::min(f.cus, SYNC_MAX_WGS);
+    return PERKS_OK;
+}
+
+// Group size for one problem: the whole device, fewer for small systems (at
+// least one row per thread).
+int cg_group_size(int cap, int64_t n) {
+    int g = cap;
+    if (n / CG_THREADS < g) g = (int)std::max<int64_t>(1, n / CG_THREADS);
+    return g;
+}
+
+struct Capture {
+    const int *iters = nullptr;
+    int n = 0;
+    double *x = nullptr, *r = nullptr;
+};
+
+int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, bool mixed,
+                        hipStream_t st, perks_cg_result *out, const Capture &capture = Capture()) {
+    const void *fn = persistent_fn(jac, mixed);
+    int cap = 0;
+    int rc = cg_capacity(fn, &cap);
     if (rc) return rc;
-    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
-    if (!sync) return PERKS_E_NOMEM;
-    const int nb = (int)((A->n + 255) / 256);
-    if (jac) hipLaunchKernelGGL(invert_diagonal, dim3(nb), dim3(256), 0, st, A->rowptr, A->colind,
-                                (const double *)A->val, (int)A->n, w.dinv);
-    CgParams p{};
+    const int G = cg_group_size(cap, A->n);
+    CgInst p;
+    rc = cg_work(A->n, A->nnz, G, mixed, &p);
+    if (rc) return rc;
+    unsigned *ws = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!ws) return PERKS_E_NOMEM;
     p.rowptr = A->rowptr;
     p.colind = A->colind;
     p.val = (const double *)A->val;
     p.b = (const double *)b;
     p.x = (double *)x;
-    p.r = w.r;
-    p.z = jac ? w.z : w.r;
-    p.q = w.q;
-    p.p0 = w.p0;
-    p.p1 = w.p1;
-    p.dinv = w.dinv;
-    p.part = w.part;
-    p.result = w.result;
-    p.sync = sync;
     p.n = (int)A->n;
     p.nnz = (int)A->nnz;
-    p.precond = precond;
-    p.lds_nnz = lds_nnz;
+    p.maxit = maxit;
+    p.max_outer = PERKS_MIXED_MAX_OUTER;
     p.tol = tol;
-    int total = 0, restarts = 0, status = PERKS_NOT_CONVERGED;
+    p.inner_tol = PERKS_MIXED_INNER_TOL;
+    p.cap_iters = capture.iters;
+    p.ncap = capture.n;
+    p.cap_x = capture.x;
+    p.cap_r = capture.r;
+    void *args[] = {&p, &ws};
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
+    if (e != hipSuccess) return launch_error(e);
     double h[8] = {0};
-    for (;;) {
-        p.maxit = maxit - total;
-        void *args[] = {&p};
-        hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(e == hipErrorCooperativeLaunchTooLarge ? PERKS_E_NOTCORESIDENT : PERKS_E_HIP,
-                             "CG launch: %s", hipGetErrorString(e));
-        }
-        PERKS_HIP_TRY(hipMemcpyAsync(h, w.result, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
-        PERKS_HIP_TRY(hipStreamSynchronize(st));
-        total += (int)h[0];
-        status = (int)h[1];
-        if (status == 2) {
-            status = PERKS_BREAKDOWN;
-            break;
-        }
-        if (h[3] <= tol) {
-            status = PERKS_OK;
-            break;
-        }
-        if (total >= maxit) {
-            status = PERKS_NOT_CONVERGED;
-            break;
-        }
-        ++restarts;   // recursive residual converged but the true one did not
-    }
-    // share of A's nonzeros held in LDS
-    const double cached = std::min<double>((double)A->nnz, (double)lds_nnz * G);
-    fill_result(out, total, status, restarts, G, h[2], h[3], A->nnz ? cached / (double)A->nnz : 0.0);
-    return status;
+    PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    const double lds = mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ;
+    const double cached = std::min<double>((double)A->nnz, lds * G);
+    return result_from_words(h, G, A->nnz ? cached / (double)A->nnz : 0.0, out);
 }
 
-int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, int32_t precond,
-                            int32_t check_every, void *stream, perks_cg_result *out) {
-    int rc = check_csr(A, b, x, tol, maxit, precond);
-    if (rc) return rc;
-    if (check_every < 1) return set_error(PERKS_E_INVAL, "check_every must be >= 1");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+struct BaseShape {
+    int n, nb, L, nbs;
+    double *part_a, *part_b, *part_c;
+    BaseScalars *S;
+};
+
+BaseShape base_shape(const perks_csr *A, const CgWork &w) {
+    BaseShape b{};
+    b.n = (int)A->n;
+    b.nb = (b.n + 255) / 256;
+    const int avg = (int)((A->nnz + b.n - 1) / b.n);
+    b.L = 1;
+    while (b.L < avg && b.L < 64) b.L <<= 1;
+    b.nbs = (b.n + (256 / b.L) * BASE_U - 1) / ((256 / b.L) * BASE_U);
+    const int m = std::max(b.nb, b.nbs);
+    b.part_a = w.part;
+    b.part_b = w.part + m + 16;
+    b.part_c = b.part_b + m + 16;
+    b.S = reinterpret_cast<BaseScalars *>(w.result);
+    return b;
+}
+
+int base_parts(const perks_csr *A) {
     const int n = (int)A->n;
-    if (n == 0) {
-        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
-        return PERKS_OK;
-    }
-    const bool jac = precond == PERKS_PRECOND_JACOBI;
     const int nb = (n + 255) / 256;
-    const int avg = (int)((A->nnz + n - 1) / n);
-    int L = 1;
-    while (L < avg && L < 64) L <<= 1;
-    const int nbs = (n + (256 / L) - 1) / (256 / L);
+    return nb * 3 + 64;   // >= 3 * max(nb, nbs) + 48 (nbs <= nb)
+}
+
+int cg_baseline_f64(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, int check_every,
+                    hipStream_t st, perks_cg_result *out) {
     CgWork w;
-    rc = cg_work(A->n, std::max(nb, nbs) * 3 + 64, &w);
+    int rc = cg_work(A->n, A->nnz, base_parts(A), false, &w);
     if (rc) return rc;
-    double *part_a = w.part, *part_b = w.part + std::max(nb, nbs) + 16, *part_c = part_b + std::max(nb, nbs) + 16;
-    BaseScalars *S = reinterpret_cast<BaseScalars *>(w.result);
+    const BaseShape B = base_shape(A, w);
+    const int n = B.n, nb = B.nb, nbs = B.nbs, L = B.L;
+    BaseScalars *S = B.S;
     const double *val = (const double *)A->val;
     double *xd = (double *)x;
     double *z = jac ? w.z : w.r;
@@ -610,13 +1076,13 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
     double relres = 0.0, reltrue = 0.0;
     for (;;) {
         // (re)start: r = b - A x, z, p = z, rho = r.z
-        hipLaunchKernelGGL(base_spmv, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, xd, w.q,
+        hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, xd, w.q,
                            (const double *)nullptr, (double *)nullptr);
         hipLaunchKernelGGL(base_init, dim3(nb), dim3(256), 0, st, n, (const double *)b, w.q, w.r, w.z, w.p0, dinv,
-                           part_a, part_b, part_c);
-        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_a, nb, &S->bb);
-        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_b, nb, &S->rho);
-        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_c, nb, &S->rr);
+                           B.part_a, B.part_b, B.part_c);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nb, &S->bb);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
         double hs[8];
         PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
         PERKS_HIP_TRY(hipStreamSynchronize(st));
@@ -626,6 +1092,7 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
         PERKS_HIP_TRY(hipMemcpyAsync(&S->status, &hs[7], sizeof(double), hipMemcpyHostToDevice, st));
         if (bnorm == 0.0) {
             PERKS_HIP_TRY(hipMemsetAsync(xd, 0, (size_t)n * sizeof(double), st));
+            PERKS_HIP_TRY(hipStreamSynchronize(st));
             status = PERKS_OK;
             relres = reltrue = 0.0;
             break;
@@ -633,16 +1100,16 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
         int k = 0;
         bool conv = std::sqrt(rr) <= tol * bnorm, broke = false;
         while (!conv && total + k < maxit) {
-            hipLaunchKernelGGL(base_spmv, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, w.p0, w.q,
-                               (const double *)w.p0, part_a);
-            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_a, nbs, &S->pq);
+            hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, w.p0,
+                               w.q, (const double *)w.p0, B.part_a);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nbs, &S->pq);
             hipLaunchKernelGGL(base_alpha, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_update, dim3(nb), dim3(256), 0, st, n, S, w.p0, w.q, xd, w.r, w.z, dinv, part_b,
-                               part_c);
-            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_b, nb, &S->rho_new);
-            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_c, nb, &S->rr);
+            hipLaunchKernelGGL(base_update<double>, dim3(nb), dim3(256), 0, st, n, S, w.p0, w.q, xd, w.r, w.z, dinv,
+                               B.part_b, B.part_c);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
             hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_pupdate, dim3(nb), dim3(256), 0, st, n, S, z, w.p0);
+            hipLaunchKernelGGL(base_pupdate<double>, dim3(nb), dim3(256), 0, st, n, S, (const double *)z, w.p0);
             ++k;
             if (k % check_every == 0 || total + k >= maxit) {
                 PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
@@ -657,8 +1124,8 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
         PERKS_HIP_TRY(hipGetLastError());
         PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
         hipLaunchKernelGGL(true_residual_part, dim3(nb), dim3(256), 0, st, A->rowptr, A->colind, val, n, xd,
-                           (const double *)b, part_a);
-        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(256), 0, st, part_a, nb, &S->pq);
+                           (const double *)b, B.part_a);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nb, &S->pq);
         double tr = 0.0;
         PERKS_HIP_TRY(hipMemcpyAsync(&tr, &S->pq, sizeof(double), hipMemcpyDeviceToHost, st));
         PERKS_HIP_TRY(hipStreamSynchronize(st));
@@ -673,7 +1140,7 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
             status = PERKS_OK;
             break;
         }
-        if (total >= maxit) {
+        if (total >= maxit || k == 0) {   // no budget, or a cycle without progress
             status = PERKS_NOT_CONVERGED;
             break;
         }
@@ -681,6 +1148,459 @@ int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double t
     }
     fill_result(out, total, status, restarts, 0, relres, reltrue, 0.0);
     return status;
+}
+
+// Host-looped mixed-precision solve: the same algorithm as cg_mixed_persistent
+// with one kernel per step and the host deciding every outer step and, every
+// check_every inner iterations, the inner stop.
+int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, int check_every,
+                      hipStream_t st, perks_cg_result *out) {
+    CgWork w;
+    int rc = cg_work(A->n, A->nnz, base_parts(A), true, &w);
+    if (rc) return rc;
+    const BaseShape B = base_shape(A, w);
+    const int n = B.n, nb = B.nb, nbs = B.nbs, L = B.L;
+    BaseScalars *S = B.S;
+    const double *val = (const double *)A->val;
+    double *xd = (double *)x;
+    float *z = jac ? w.z32 : w.r32;
+    const float *dinv = jac ? w.dinv32 : nullptr;
+    const int nbv = (int)((A->nnz + 255) / 256);
+    if (A->nnz > 0) hipLaunchKernelGGL(to_f32, dim3(nbv), dim3(256), 0, st, (int64_t)A->nnz, val, w.val32);
+    if (jac)
+        hipLaunchKernelGGL(invert_diagonal32, dim3(nb), dim3(256), 0, st, A->rowptr, A->colind, val, n, w.dinv32);
+    double hs[8];
+    // ||b||
+    hipLaunchKernelGGL(base_resid, dim3(nb), dim3(256), 0, st, n, (const double *)b, (const double *)nullptr,
+                       (double *)nullptr, B.part_a);
+    hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nb, &S->bb);
+    PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(hs[5]);
+    if (bnorm == 0.0) {
+        PERKS_HIP_TRY(hipMemsetAsync(xd, 0, (size_t)n * sizeof(double), st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
+        return PERKS_OK;
+    }
+    int total = 0, outer = 0, status = PERKS_NOT_CONVERGED;
+    double rn = 0.0, prev = INFINITY;
+    bool broke = false;
+    for (;;) {
+        // outer residual in FP64: r64 = b - A x  (A x lands in r64 first)
+        hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L,
+                           (const double *)xd, w.r64, (const double *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL(base_resid, dim3(nb), dim3(256), 0, st, n, (const double *)b, (const double *)w.r64,
+                           w.r64, B.part_a);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nb, &S->rr);
+        PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+        rn = std::sqrt(hs[4]);
+        if (broke) {
+            status = PERKS_BREAKDOWN;
+            break;
+        }
+        if (rn <= tol * bnorm) {
+            status = PERKS_OK;
+            break;
+        }
+        if (total >= maxit || outer >= PERKS_MIXED_MAX_OUTER || !(rn <= 0.5 * prev)) {
+            status = PERKS_NOT_CONVERGED;
+            break;
+        }
+        prev = rn;
+        int ex;
+        (void)std::frexp(rn, &ex);
+        const double sc = std::ldexp(1.0, 1 - ex);
+        hipLaunchKernelGGL(base_mixed_init, dim3(nb), dim3(256), 0, st, n, (const double *)w.r64, sc, w.r32, w.z32,
+                           w.p0_32, w.d32, dinv, B.part_b, B.part_c);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
+        PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+        const double stop = PERKS_MIXED_INNER_TOL * std::sqrt(hs[4]);
+        hs[7] = 1.0;
+        PERKS_HIP_TRY(hipMemcpyAsync(&S->status, &hs[7], sizeof(double), hipMemcpyHostToDevice, st));
+        bool done = !(std::sqrt(hs[4]) > stop);
+        int k = 0;
+        while (!done && total + k < maxit) {
+            hipLaunchKernelGGL(base_spmv<float>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind,
+                               (const float *)w.val32, n, L, (const float *)w.p0_32, w.q32, (const float *)w.p0_32,
+                               B.part_a);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nbs, &S->pq);
+            hipLaunchKernelGGL(base_alpha, dim3(1), dim3(1), 0, st, S);
+            hipLaunchKernelGGL(base_update<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)w.p0_32,
+                               (const float *)w.q32, w.d32, w.r32, w.z32, dinv, B.part_b, B.part_c);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
+            hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
+            hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
+            hipLaunchKernelGGL(base_pupdate<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)z, w.p0_32);
+            ++k;
+            if (k % check_every == 0 || total + k >= maxit) {
+                PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
+                PERKS_HIP_TRY(hipStreamSynchronize(st));
+                if (hs[7] != 1.0) {
+                    broke = true;
+                    break;
+                }
+                done = !(std::sqrt(hs[4]) > stop);
+            }
+        }
+        PERKS_HIP_TRY(hipGetLastError());
+        total += k;
+        hipLaunchKernelGGL(base_xupdate, dim3(nb), dim3(256), 0, st, n, xd, (const float *)w.d32, sc);
+        ++outer;
+    }
+    PERKS_HIP_TRY(hipGetLastError());
+    fill_result(out, total, status, outer, 0, rn / bnorm, rn / bnorm, 0.0);
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: many problems in one persistent launch.
+//
+// Schedule (host, deterministic): predicted work w_i = nnz_i * sqrt(n_i)
+// (nonzeros per iteration times an iteration count growing like the grid
+// side of a 2D problem).  With C = sum(w) / G the fair share of one
+// workgroup, problems heavier than 2C, largest first, get floor(w_i / C)
+// workgroups of their own (at most one per CG_THREADS rows, and leaving one
+// workgroup for the rest); every other problem goes, largest first, to the
+// workgroup with the least predicted load so far (LPT), the grouped
+// workgroups counting w_i / k_i.
+struct BatchSchedule {
+    std::vector<int> task_ptr;   // G + 1
+    std::vector<CgTask> tasks;
+    std::vector<int> wgs;        // workgroups per problem (0: empty problem)
+};
+
+BatchSchedule make_schedule(const std::vector<int64_t> &n, const std::vector<int64_t> &nnz, int G) {
+    const int m = (int)n.size();
+    BatchSchedule S;
+    S.wgs.assign(m, 0);
+    std::vector<double> w(m, 0.0);
+    double W = 0.0;
+    std::vector<int> order;
+    for (int i = 0; i < m; ++i) {
+        if (n[i] == 0) continue;
+        w[i] = (double)std::max<int64_t>(nnz[i], 1) * std::sqrt((double)n[i]);
+        W += w[i];
+        order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+    const double C = W / G;
+    std::vector<std::vector<CgTask>> per(G);
+    std::vector<double> load(G, 0.0);
+    int next = 0, group = 0;
+    size_t first_small = 0;
+    for (; first_small < order.size(); ++first_small) {
+        const int i = order[first_small];
+        const bool more = first_small + 1 < order.size();
+        int k = (int)std::floor(w[i] / C);
+        k = std::min<int64_t>(k, std::max<int64_t>(1, n[i] / CG_THREADS));
+        k = std::min(k, G - next - (more ? 1 : 0));
+        if (w[i] <= 2.0 * C || k < 2) break;
+        for (int r = 0; r < k; ++r) {
+            per[next + r].push_back(CgTask{i, r, k, group});
+            load[next + r] = w[i] / k;
+        }
+        S.wgs[i] = k;
+        next += k;
+        ++group;
+    }
+    for (size_t t = first_small; t < order.size(); ++t) {
+        const int i = order[t];
+        int best = 0;
+        for (int g = 1; g < G; ++g)
+            if (load[g] < load[best]) best = g;
+        per[best].push_back(CgTask{i, 0, 1, 0});
+        load[best] += w[i];
+        S.wgs[i] = 1;
+    }
+    S.task_ptr.assign(G + 1, 0);
+    for (int g = 0; g < G; ++g) {
+        S.task_ptr[g + 1] = S.task_ptr[g] + (int)per[g].size();
+        S.tasks.insert(S.tasks.end(), per[g].begin(), per[g].end());
+    }
+    return S;
+}
+
+}  // namespace
+}  // namespace perks
+
+using namespace perks;
+
+// Opaque plan of a batched solve: device memory (barrier words, problem table,
+// schedule, results, work vectors) and the launch, kept as a one-node HIP
+// graph with the cooperative attribute.
+struct perks_cg_batch {
+    int device = -1;
+    int count = 0;
+    int G = 0;
+    bool mixed = false;
+    void *mem = nullptr;
+    double *results = nullptr;            // 8 words per problem
+    unsigned *ws = nullptr;
+    const void *fn = nullptr;
+    CgBatch params{};
+    std::vector<int> wgs;
+    std::vector<double> cached_frac;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t epochs_used = 0;
+};
+
+extern "C" {
+
+int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *const *xs, int32_t count, double tol,
+                          int32_t maxit, int32_t precond, int32_t precision, perks_cg_batch **plan) {
+    if (!plan) return set_error(PERKS_E_INVAL, "plan must not be NULL");
+    *plan = nullptr;
+    if (count < 0) return set_error(PERKS_E_INVAL, "count must be >= 0");
+    if (count > 0 && (!As || !bs || !xs)) return set_error(PERKS_E_INVAL, "As, bs and xs must not be NULL");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_csr(&As[i], bs[i], xs[i], tol, maxit, precond, precision);
+        if (rc) return set_error(rc, "problem %d: %s", i, last_error());
+    }
+    if ((int64_t)maxit * 6 + 64LL * PERKS_MIXED_MAX_OUTER > (int64_t(1) << 30))
+        return set_error(PERKS_E_INVAL, "maxit too large for a batched solve (barrier epoch range)");
+    const bool jac = precond == PERKS_PRECOND_JACOBI, mixed = precision == PERKS_PREC_MIXED;
+    auto *P = new (std::nothrow) perks_cg_batch();
+    if (!P) return set_error(PERKS_E_NOMEM, "plan allocation failed");
+    P->count = count;
+    P->mixed = mixed;
+    P->fn = batched_fn(jac, mixed);
+    int rc = PERKS_OK;
+    do {
+        if (hipGetDevice(&P->device) != hipSuccess) { rc = set_error(PERKS_E_HIP, "no current HIP device"); break; }
+        rc = cg_capacity(P->fn, &P->G);
+        if (rc) break;
+        std::vector<int64_t> n(count), nnz(count);
+        for (int i = 0; i < count; ++i) {
+            n[i] = As[i].n;
+            nnz[i] = As[i].nnz;
+        }
+        BatchSchedule S = make_schedule(n, nnz, P->G);
+        P->wgs = S.wgs;
+        // device memory: sync words | problems | tasks | task_ptr | results | work areas
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t o_inst = up(SYNC_BYTES);
+        const size_t o_tasks = o_inst + up(sizeof(CgInst) * std::max(count, 1));
+        const size_t o_ptr = o_tasks + up(sizeof(CgTask) * std::max<size_t>(S.tasks.size(), 1));
+        const size_t o_res = o_ptr + up(sizeof(int) * (P->G + 1));
+        size_t o_work = o_res + up(sizeof(double) * 8 * std::max(count, 1));
+        std::vector<size_t> work_off(count);
+        size_t total = o_work;
+        for (int i = 0; i < count; ++i) {
+            work_off[i] = total;
+            if (n[i] > 0) total += inst_bytes(n[i], nnz[i], std::max(S.wgs[i], 1), mixed);
+        }
+        if (hipMalloc(&P->mem, total) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(PERKS_E_NOMEM, "batched solve: hipMalloc of %zu bytes failed", total);
+            break;
+        }
+        char *base = (char *)P->mem;
+        std::vector<CgInst> inst(count);
+        P->cached_frac.assign(count, 0.0);
+        for (int i = 0; i < count; ++i) {
+            CgInst &p = inst[i];
+            p = CgInst{};
+            if (n[i] > 0) carve(base + work_off[i], n[i], std::max(S.wgs[i], 1), mixed, &p);
+            p.result = (double *)(base + o_res) + 8 * (size_t)i;
+            p.rowptr = As[i].rowptr;
+            p.colind = As[i].colind;
+            p.val = (const double *)As[i].val;
+            p.b = (const double *)bs[i];
+            p.x = (double *)xs[i];
+            p.n = (int)n[i];
+            p.nnz = (int)nnz[i];
+            p.maxit = maxit;
+            p.max_outer = PERKS_MIXED_MAX_OUTER;
+            p.tol = tol;
+            p.inner_tol = PERKS_MIXED_INNER_TOL;
+            const double lds = mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ;
+            if (nnz[i] > 0) P->cached_frac[i] = std::min<double>((double)nnz[i], lds * S.wgs[i]) / (double)nnz[i];
+        }
+        // problems with n = 0 report a converged empty solve
+        std::vector<double> res(8 * (size_t)std::max(count, 1), 0.0);
+        P->results = (double *)(base + o_res);
+        P->ws = (unsigned *)base;
+        if (hipMemset(P->mem, 0, SYNC_BYTES) != hipSuccess ||
+            hipMemcpy(base + o_inst, inst.data(), sizeof(CgInst) * count, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(base + o_tasks, S.tasks.data(), sizeof(CgTask) * S.tasks.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(base + o_ptr, S.task_ptr.data(), sizeof(int) * (P->G + 1), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(base + o_res, res.data(), sizeof(double) * 8 * count, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(PERKS_E_HIP, "batched solve: uploading the schedule failed");
+            break;
+        }
+        P->params.inst = (const CgInst *)(base + o_inst);
+        P->params.tasks = (const CgTask *)(base + o_tasks);
+        P->params.task_ptr = (const int *)(base + o_ptr);
+        P->params.ws = P->ws;
+        P->params.epoch_span = (unsigned)(6 * (int64_t)maxit + 4 * PERKS_MIXED_MAX_OUTER + 64);
+        // the launch as a graph node with the cooperative attribute (falls back
+        // to a direct cooperative launch per run if the runtime refuses it)
+        hipKernelNodeParams kp{};
+        void *args[] = {&P->params};
+        kp.func = const_cast<void *>(P->fn);
+        kp.gridDim = dim3(P->G);
+        kp.blockDim = dim3(CG_THREADS);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipLaunchAttributeValue v{};
+        v.cooperative = 1;
+        if (hipGraphCreate(&P->graph, 0) != hipSuccess ||
+            hipGraphAddKernelNode(&node, P->graph, nullptr, 0, &kp) != hipSuccess ||
+            hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) != hipSuccess ||
+            hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (P->exec) (void)hipGraphExecDestroy(P->exec);
+            if (P->graph) (void)hipGraphDestroy(P->graph);
+            P->exec = nullptr;
+            P->graph = nullptr;
+        }
+    } while (false);
+    if (rc) {
+        perks_cg_batch_destroy(P);
+        return rc;
+    }
+    *plan = P;
+    return PERKS_OK;
+}
+
+int perks_cg_batch_run(perks_cg_batch *P, void *stream) {
+    if (!P) return set_error(PERKS_E_INVAL, "plan must not be NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != P->device)
+        return set_error(PERKS_E_INVAL, "the plan belongs to device %d", P->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P->count == 0) return PERKS_OK;
+    // barrier epochs are 32-bit: start again from zeroed words well before
+    // they could wrap (a fill kernel, so the reset is stream-ordered)
+    P->epochs_used += P->params.epoch_span + 2;
+    if (P->epochs_used > (uint64_t(1) << 31)) {
+        hipLaunchKernelGGL(zero_words, dim3((SYNC_BYTES / 4 + 255) / 256), dim3(256), 0, st, P->ws,
+                           (int)(SYNC_BYTES / 4));
+        P->epochs_used = P->params.epoch_span + 2;
+    }
+    if (P->exec) {
+        PERKS_HIP_TRY(hipGraphLaunch(P->exec, st));
+    } else {
+        void *args[] = {&P->params};
+        hipError_t e = hipLaunchCooperativeKernel(P->fn, dim3(P->G), dim3(CG_THREADS), args, 0, st);
+        if (e != hipSuccess) return launch_error(e);
+    }
+    return PERKS_OK;
+}
+
+int perks_cg_batch_results(perks_cg_batch *P, perks_cg_result *outs, void *stream) {
+    if (!P) return set_error(PERKS_E_INVAL, "plan must not be NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P->count == 0) return PERKS_OK;
+    std::vector<double> h(8 * (size_t)P->count);
+    PERKS_HIP_TRY(hipMemcpyAsync(h.data(), P->results, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    int worst = PERKS_OK;
+    for (int i = 0; i < P->count; ++i) {
+        perks_cg_result r;
+        const int s = result_from_words(&h[8 * (size_t)i], P->wgs[i], P->cached_frac[i], &r);
+        if (outs) outs[i] = r;
+        if (s == PERKS_BREAKDOWN || (s == PERKS_NOT_CONVERGED && worst == PERKS_OK)) worst = s;
+    }
+    return worst;
+}
+
+int perks_cg_batch_graph(perks_cg_batch *P, void **graph) {
+    if (!P || !graph) return set_error(PERKS_E_INVAL, "plan and graph must not be NULL");
+    if (!P->graph) return set_error(PERKS_E_UNSUPPORTED, "the runtime refused a cooperative graph node");
+    *graph = (void *)P->graph;
+    return PERKS_OK;
+}
+
+int perks_cg_batch_destroy(perks_cg_batch *P) {
+    if (!P) return PERKS_OK;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->mem) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(P->mem);
+    }
+    delete P;
+    return PERKS_OK;
+}
+
+int perks_cg_solve_batched(const perks_csr *As, const void *const *bs, void *const *xs, int32_t count, double tol,
+                           int32_t maxit, int32_t precond, int32_t precision, void *stream, perks_cg_result *outs) {
+    perks_cg_batch *P = nullptr;
+    int rc = perks_cg_batch_create(As, bs, xs, count, tol, maxit, precond, precision, &P);
+    if (rc) return rc;
+    rc = perks_cg_batch_run(P, stream);
+    if (rc == PERKS_OK) rc = perks_cg_batch_results(P, outs, stream);
+    perks_cg_batch_destroy(P);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace perks {
+namespace {
+}  // namespace
+}  // namespace perks
+
+
+extern "C" {
+
+int perks_cg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, int32_t precond,
+                   int32_t precision, void *stream, perks_cg_result *out) {
+    int rc = check_csr(A, b, x, tol, maxit, precond, precision);
+    if (rc) return rc;
+    if (A->n == 0) {
+        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
+        return PERKS_OK;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool jac = precond == PERKS_PRECOND_JACOBI;
+    return cg_persistent_solve(A, b, x, tol, maxit, jac, precision == PERKS_PREC_MIXED, st, out);
+}
+
+int perks_cg_solve_capture(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, int32_t precond,
+                           const int32_t *cap_iters, int32_t ncap, double *cap_x, double *cap_r, void *stream,
+                           perks_cg_result *out) {
+    int rc = check_csr(A, b, x, tol, maxit, precond, PERKS_PREC_F64);
+    if (rc) return rc;
+    if (ncap < 0 || (ncap > 0 && (!cap_iters || !cap_x || !cap_r)))
+        return set_error(PERKS_E_INVAL, "capture arrays must not be NULL when ncap > 0");
+    if (A->n == 0) {
+        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
+        return PERKS_OK;
+    }
+    Capture c;
+    c.iters = cap_iters;
+    c.n = ncap;
+    c.x = cap_x;
+    c.r = cap_r;
+    return cg_persistent_solve(A, b, x, tol, maxit, precond == PERKS_PRECOND_JACOBI, false,
+                               reinterpret_cast<hipStream_t>(stream), out, c);
+}
+
+int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, int32_t precond,
+                            int32_t precision, int32_t check_every, void *stream, perks_cg_result *out) {
+    int rc = check_csr(A, b, x, tol, maxit, precond, precision);
+    if (rc) return rc;
+    if (check_every < 1) return set_error(PERKS_E_INVAL, "check_every must be >= 1");
+    if (A->n == 0) {
+        fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
+        return PERKS_OK;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool jac = precond == PERKS_PRECOND_JACOBI;
+    if (precision == PERKS_PREC_MIXED) return cg_baseline_mixed(A, b, x, tol, maxit, jac, check_every, st, out);
+    return cg_baseline_f64(A, b, x, tol, maxit, jac, check_every, st, out);
 }
 
 }  // extern "C"

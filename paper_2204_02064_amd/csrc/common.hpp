@@ -36,6 +36,8 @@ enum ScratchSlot {
     SLOT_PINGPONG,      // per-step baseline's second grid
     SLOT_CG_VEC,        // CG work vectors
     SLOT_CG_PART,       // CG partition table / partial sums
+    SLOT_NN,            // network activations, gradients, packed weights
+    SLOT_FCG,           // flexible-CG work vectors
     SLOT_COUNT
 };
 // Returns a device pointer of at least `bytes`, or nullptr (error already set).
@@ -49,7 +51,9 @@ constexpr int SYNC_LL_EPOCH = 96;     // LL face epoch carried from one launch t
 constexpr int SYNC_AUX = 128;         // small device-side results (CG scalars, ...)
 constexpr int SYNC_FLAGS = 1024;      // flags[wg]
 constexpr int SYNC_MAX_WGS = 8192;
-constexpr size_t SYNC_BYTES = (SYNC_FLAGS + SYNC_MAX_WGS) * 4 + 4096;
+constexpr int SYNC_GROUP_GEN = SYNC_FLAGS + SYNC_MAX_WGS;   // generation word of workgroup group j
+constexpr int SYNC_GROUP_STRIDE = 16;                      // at SYNC_GROUP_GEN + j * stride (own 64 B)
+constexpr size_t SYNC_BYTES = (SYNC_GROUP_GEN + (size_t)SYNC_MAX_WGS * SYNC_GROUP_STRIDE) * 4 + 4096;
 
 struct DeviceFacts {
     int device = -1;

@@ -1,0 +1,80 @@
+"""Training of the learned preconditioner from pairs the persistent CG produces.
+
+Pairs: for a diffusion problem A x = f with log-permeability log k, the
+persistent Jacobi-preconditioned CG is run to a tight tolerance for x*, then
+run again with snapshots of its iterate x_k and residual r_k after
+k = 1, 2, 4, 8, ... iterations; each snapshot gives the network input
+[r_k / rms(r_k), log k] and the target (x* - x_k) / rms(r_k), the error the
+preconditioner should return for that residual.
+
+Training: Adam on the mean squared error, mini-batches of pairs, every
+forward and backward pass and every Adam step in the library's kernels
+(perks_nn_loss_grad, perks_nn_adam); this module only chooses the batches.
+"""
+import numpy as np
+
+from . import (CsrMatrix, NN_PARAMS, cg_solve, cg_solve_capture, nn_adam, nn_loss_grad, nn_pack_params)
+
+CAPTURE_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
+
+
+def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000):
+    """problems: iterable of (rowptr, colind, values, log_k [n, n], f) torch
+    tensors on the device.  Returns (inputs [P, n, n, 2] float32, targets
+    [P, n, n] float32) device tensors."""
+    import torch
+    xs, ts = [], []
+    for rp, ci, v, lk, f in problems:
+        n = lk.shape[0]
+        A = CsrMatrix(rp, ci, v)
+        xstar = torch.zeros_like(f)
+        cg_solve(A, f, xstar, tol=tol, maxit=maxit, precond="jacobi")
+        x = torch.zeros_like(f)
+        info, xc, rc = cg_solve_capture(A, f, x, iters, tol=tol, maxit=maxit, precond="jacobi")
+        for j in range(xc.shape[0]):
+            r = rc[j]
+            if not torch.isfinite(r).all():
+                break                                  # iteration count not reached
+            s = torch.sqrt(torch.mean(r * r))
+            if s <= 0:
+                break
+            xs.append(torch.stack([(r / s).reshape(n, n), lk], dim=-1).to(torch.float32))
+            ts.append(((xstar - xc[j]) / s).reshape(n, n).to(torch.float32))
+    return torch.stack(xs), torch.stack(ts)
+
+
+def init_params(seed=0):
+    """He-uniform weights (fan-in 9 * inputs), zero biases, padded float32 vector."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for ci, co in [(2, 16), (16, 16), (16, 16), (16, 16), (16, 16), (16, 1)]:
+        bound = np.sqrt(6.0 / (9 * ci))
+        layers.append((rng.uniform(-bound, bound, (co, ci, 3, 3)).astype(np.float32), np.zeros(co, np.float32)))
+    return nn_pack_params(layers)
+
+
+def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log=None):
+    """Adam on the MSE over (inputs, targets); returns (params, loss per step)."""
+    import torch
+    dev = inputs.device
+    p = torch.from_numpy(init_params(seed)).to(dev) if params is None else params.clone()
+    m = torch.zeros(NN_PARAMS, dtype=torch.float32, device=dev)
+    v = torch.zeros_like(m)
+    grad = torch.empty_like(m)
+    rng = np.random.default_rng(seed)
+    P = inputs.shape[0]
+    losses = []
+    step = 0
+    for ep in range(epochs):
+        order = rng.permutation(P)
+        for s in range(0, P - batch + 1, batch):
+            idx = torch.from_numpy(order[s:s + batch]).to(dev)
+            xb = inputs.index_select(0, idx).contiguous()
+            tb = targets.index_select(0, idx).contiguous()
+            loss, _ = nn_loss_grad(p, xb, tb, grad)
+            step += 1
+            nn_adam(p, grad, m, v, step, lr=lr)
+            losses.append(loss)
+        if log:
+            log(f"epoch {ep}: loss {np.mean(losses[-max(1, P // batch):]):.4e}")
+    return p, losses

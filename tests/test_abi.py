@@ -52,3 +52,42 @@ def test_invalid_arguments_are_rejected(L):
     assert L.perks_stencil_run(fake, wn.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                pk.Shape(2, 0, 8, 8, 1), 1, 1, None, None) == -1
     assert b"finite" in L.perks_last_error()
+
+
+def test_solver_arguments_are_rejected_before_any_device_call(L):
+    import paper_2204_02064_amd as pk
+    fake = ctypes.c_void_p(0x1000)
+    rp = np.array([0, 1], np.int32)
+    A = pk.Csr(1, 1, rp.ctypes.data, rp.ctypes.data, rp.ctypes.data, pk.PERKS_F64, 0)
+    res = pk.CgResult()
+    r = ctypes.byref(res)
+    assert L.perks_cg_solve(None, fake, fake, 1e-8, 10, 0, 0, None, r) == -1
+    assert L.perks_cg_solve(ctypes.byref(A), fake, fake, -1.0, 10, 0, 0, None, r) == -1
+    assert L.perks_cg_solve(ctypes.byref(A), fake, fake, 1e-8, -1, 0, 0, None, r) == -1
+    assert L.perks_cg_solve(ctypes.byref(A), fake, fake, 1e-8, 10, 5, 0, None, r) == -1
+    assert L.perks_cg_solve(ctypes.byref(A), fake, fake, 1e-8, 10, 0, 7, None, r) == -1
+    assert L.perks_cg_solve(ctypes.byref(A), None, fake, 1e-8, 10, 0, 0, None, r) == -1
+    A32 = pk.Csr(1, 1, rp.ctypes.data, rp.ctypes.data, rp.ctypes.data, pk.PERKS_F32, 0)
+    assert L.perks_cg_solve(ctypes.byref(A32), fake, fake, 1e-8, 10, 0, 0, None, r) == -5
+    assert L.perks_cg_solve_baseline(ctypes.byref(A), fake, fake, 1e-8, 10, 0, 0, 0, None, r) == -1
+    assert L.perks_cg_solve_capture(ctypes.byref(A), fake, fake, 1e-8, 10, 0, None, 2, None, None, None, r) == -1
+    # FCG: the grid must hold the unknowns; a network needs log k
+    assert L.perks_fcg_solve(ctypes.byref(A), fake, fake, 1e-8, 10, None, None, 2, 2, 20, None, r) == -1
+    assert L.perks_fcg_solve(ctypes.byref(A), fake, fake, 1e-8, 10, fake, None, 1, 1, 20, None, r) == -1
+    assert L.perks_fcg_solve(ctypes.byref(A), fake, fake, 1e-8, 10, None, None, 1, 1, 0, None, r) == -1
+    # batched
+    plan = ctypes.c_void_p()
+    assert L.perks_cg_batch_create(None, None, None, -1, 1e-8, 10, 0, 0, ctypes.byref(plan)) == -1
+    arr = (pk.Csr * 1)(A)
+    ptrs = (ctypes.c_void_p * 1)(fake)
+    assert L.perks_cg_batch_create(arr, ptrs, ptrs, 1, -1.0, 10, 0, 0, ctypes.byref(plan)) == -1
+    assert L.perks_cg_batch_create(arr, ptrs, ptrs, 1, 1e-8, 10, 0, 0, None) == -1
+    assert L.perks_cg_batch_run(None, None) == -1
+    assert L.perks_cg_batch_results(None, None, None) == -1
+    assert L.perks_cg_batch_destroy(None) == 0
+    # network
+    assert L.perks_nn_forward(None, fake, 1, 4, 4, fake, None) == -1
+    assert L.perks_nn_forward(fake, fake, 0, 4, 4, fake, None) == -1
+    assert L.perks_nn_loss_grad(fake, fake, fake, 1, 3, 4, fake, None, None) == -5   # H must be even
+    assert L.perks_nn_loss_grad(fake, fake, fake, 1, 4, 600, fake, None, None) == -5  # W <= 512
+    assert L.perks_nn_adam(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1

@@ -144,3 +144,17 @@ def test_full_size_poisson_128(pk):
     assert info["iters"] <= 1000
     xb, ib = _solve(pk, rp, ci, v, b, 1e-10, baseline=True)
     assert ib["status"] == "converged" and _iters_close(info["iters"], ib["iters"])
+
+
+def test_baseline_check_every_delays_stop_by_less_than_the_interval(pk):
+    rp, ci, v = workloads.poisson_csr(20, 3)
+    b = workloads.rhs_uniform(rp.size - 1, seed=4)
+    A = pk.CsrMatrix(rp, ci, v)
+    bd = to_dev(b)
+    its = {}
+    for ce in (1, 8):
+        x = to_dev(np.zeros_like(b))
+        info = pk.cg_solve_baseline(A, bd, x, tol=1e-10, maxit=5000, check_every=ce)
+        assert info["status"] == "converged"
+        its[ce] = info["iters"]
+    assert its[1] <= its[8] <= its[1] + 7

@@ -1,0 +1,167 @@
+"""GPU parity of the mixed-precision CG (FP64 refinement around FP32 CG).
+
+The oracle runs the same refinement algorithm in plain C (FP32 storage and
+arithmetic for the inner solve, FP64 dots and outer residual).  Rounding
+orders differ, so parity is: the same status, the true FP64 relative
+residual (recomputed on the host from the returned x) within tol, x equal to
+the FP64 oracle solution within kappa * tol, the same number of outer steps
+(+-1) and a total inner iteration count within max(5, 10%) of the oracle's:
+the GPU's FP32 recurrences use fused multiply-adds and the oracle's do not,
+and FP32 CG loses orthogonality early, so the inner Krylov sequences drift
+apart by a few iterations per outer step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2204_02064_amd as pk
+    pk.lib()
+    return pk
+
+
+def _true_relres(rp, ci, v, b, x):
+    import scipy.sparse as sp
+    n = rp.size - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def _solve(pk, rp, ci, v, b, tol, maxit=5000, precond=None, baseline=False, x0=None, check_every=1):
+    A = pk.CsrMatrix(rp, ci, v)
+    bd = to_dev(b)
+    xd = to_dev(np.zeros_like(b) if x0 is None else x0)
+    if baseline:
+        info = pk.cg_solve_baseline(A, bd, xd, tol=tol, maxit=maxit, precond=precond, precision="mixed",
+                                    check_every=check_every)
+    else:
+        info = pk.cg_solve(A, bd, xd, tol=tol, maxit=maxit, precond=precond, precision="mixed")
+    torch.cuda.synchronize()
+    return xd.cpu().numpy(), info
+
+
+def _case(name):
+    if name == "poisson2d":
+        rp, ci, v = workloads.poisson_csr(64, 2)
+        kappa = 1.7e3
+    elif name == "poisson3d":
+        rp, ci, v = workloads.poisson_csr(24, 3)
+        kappa = 2.5e2
+    else:
+        rp, ci, v = workloads.random_spd_csr(6000, seed=5)
+        kappa = 1e3
+    b = workloads.rhs_uniform(rp.size - 1, seed=9)
+    return rp, ci, v, b, kappa
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d", "random"])
+@pytest.mark.parametrize("tol", [1e-8, 1e-11])
+def test_mixed_matches_oracle(pk, baseline, precond, case, tol):
+    rp, ci, v, b, kappa = _case(case)
+    print(f"mixed CG {case} precond={precond} baseline={baseline} tol={tol}", flush=True)
+    x, info = _solve(pk, rp, ci, v, b, tol, precond=precond, baseline=baseline)
+    xo, oinfo = oracle.cg_mixed(rp, ci, v, b, tol=tol, maxit=5000, precond=precond)
+    assert oinfo["status"] == "converged"
+    assert info["status"] == "converged"
+    rt = _true_relres(rp, ci, v, b, x)
+    assert rt <= tol * 1.001 and abs(info["relres_true"] - rt) <= 1e-3 * tol + 1e-15
+    xs, _ = oracle.cg(rp, ci, v, b, tol=1e-13, maxit=20000, precond=precond)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * tol
+    assert abs(info["outer"] - oinfo["outer"]) <= 1
+    assert abs(info["iters"] - oinfo["iters"]) <= max(5, math.ceil(0.10 * oinfo["iters"]))
+
+
+def test_persistent_and_baseline_agree(pk):
+    rp, ci, v, b, _ = _case("poisson2d")
+    x1, i1 = _solve(pk, rp, ci, v, b, 1e-10)
+    x2, i2 = _solve(pk, rp, ci, v, b, 1e-10, baseline=True)
+    assert i1["outer"] == i2["outer"]
+    assert abs(i1["iters"] - i2["iters"]) <= max(2, math.ceil(0.02 * i2["iters"]))
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x2) <= 1e-7
+
+
+def test_check_every_only_delays_the_inner_stop(pk):
+    """The host reads the inner residual every 8 iterations: each inner solve
+    may run up to 7 iterations longer (deeper reduction per outer step, so
+    possibly fewer outer steps); the answer still meets tol."""
+    rp, ci, v, b, _ = _case("poisson3d")
+    x1, i1 = _solve(pk, rp, ci, v, b, 1e-9, baseline=True, check_every=1)
+    x8, i8 = _solve(pk, rp, ci, v, b, 1e-9, baseline=True, check_every=8)
+    assert i8["status"] == "converged" and i1["status"] == "converged"
+    assert i8["outer"] <= i1["outer"]
+    assert _true_relres(rp, ci, v, b, x8) <= 1e-9 * 1.001
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+def test_mixed_edge_cases(pk, baseline):
+    rp, ci, v = workloads.poisson_csr(16, 2)
+    n = rp.size - 1
+    x, info = _solve(pk, rp, ci, v, np.zeros(n), 1e-8, baseline=baseline, x0=np.ones(n))
+    assert info["status"] == "converged" and info["iters"] == 0 and np.all(x == 0)
+    b = workloads.rhs_uniform(n, seed=1)
+    xs, _ = oracle.cg(rp, ci, v, b, tol=1e-14)
+    x, info = _solve(pk, rp, ci, v, b, 1e-8, baseline=baseline, x0=xs)
+    assert info["status"] == "converged" and info["iters"] == 0 and info["outer"] == 0
+    np.testing.assert_array_equal(x, xs)
+    x, info = _solve(pk, rp, ci, v, b, 1e-8, maxit=0, baseline=baseline)
+    assert info["status"] == "not_converged" and info["iters"] == 0
+    # a 1x1 system and a system smaller than one workgroup
+    for m in (1, 37):
+        rp1 = np.arange(m + 1, dtype=np.int32)
+        ci1 = np.arange(m, dtype=np.int32)
+        v1 = np.arange(1, m + 1, dtype=np.float64)
+        b1 = np.ones(m)
+        x, info = _solve(pk, rp1, ci1, v1, b1, 1e-12, baseline=baseline)
+        assert info["status"] == "converged"
+        np.testing.assert_allclose(x, 1.0 / v1, rtol=1e-10)
+
+
+def test_stagnation_is_reported_not_hidden(pk):
+    """kappa * u32 >> 1: refinement cannot converge; the solver must say so."""
+    n = 32
+    rng = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * np.geomspace(1.0, 1e10, n)) @ Q.T
+    A = 0.5 * (A + A.T)
+    rows = [0]; cols = []; vals = []
+    for i in range(n):
+        cols.extend(range(n)); vals.extend(A[i].tolist()); rows.append(len(cols))
+    rp, ci, v = np.array(rows, np.int32), np.array(cols, np.int32), np.array(vals)
+    b = rng.uniform(-1, 1, n)
+    for baseline in (False, True):
+        _, info = _solve(pk, rp, ci, v, b, 1e-10, maxit=20000, baseline=baseline)
+        assert info["status"] in ("not_converged", "breakdown")
+        assert info["outer"] < 30
+
+
+def test_full_size_poisson_128_mixed(pk):
+    """Poisson 128^3 (n = 2,097,152) to 1e-8 in mixed precision, one launch.
+
+    Too large for the oracle at this size: the host recomputes the true FP64
+    residual of the returned x, and x is compared with the FP64 GPU solve.
+    """
+    rp, ci, v = workloads.poisson_csr(128, 3)
+    b = workloads.rhs_uniform(rp.size - 1, seed=0)
+    print("mixed CG poisson 128^3", flush=True)
+    x, info = _solve(pk, rp, ci, v, b, 1e-8)
+    assert info["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x) <= 1e-8 * 1.001
+    A = pk.CsrMatrix(rp, ci, v)
+    bd, xd = to_dev(b), to_dev(np.zeros_like(b))
+    info64 = pk.cg_solve(A, bd, xd, tol=1e-11, maxit=5000)
+    assert info64["status"] == "converged"
+    x64 = xd.cpu().numpy()
+    assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 7e3 * 1e-8
+    assert info["cached_nnz_frac"] > 0.3

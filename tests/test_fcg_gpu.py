@@ -1,0 +1,125 @@
+"""GPU tests of flexible CG with the learned preconditioner and of the
+solver-side capture of training pairs.
+
+FCG without a network is Jacobi-preconditioned CG: parity with the oracle's
+PCG (true residual within tol, iteration count within max(2, 2%)).  With a
+network that is the identity (up to the bf16 rounding of its input) FCG is
+CG: iteration count close to the oracle's FCG with the same network in bf16
+emulation.  A network that always fails (<z, r> < 0) falls back to the
+Jacobi step on every iteration.  A capture of x_k equals the iterate of a
+solve stopped after k iterations, bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fcg as ofcg
+from oracle import nn as onn
+import workloads
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2204_02064_amd as pk
+    pk.lib()
+    return pk
+
+
+def _true_relres(rp, ci, v, b, x):
+    import scipy.sparse as sp
+    n = rp.size - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def _identity_layers(sign=1.0):
+    ls = []
+    for li, (ci, co) in enumerate([(2, 16), (16, 16), (16, 16), (16, 16), (16, 16), (16, 1)]):
+        w = np.zeros((co, ci, 3, 3), np.float32)
+        if li == 0:
+            w[0, 0, 1, 1], w[1, 0, 1, 1] = 1.0, -1.0
+        elif li < 5:
+            w[0, 0, 1, 1], w[1, 1, 1, 1] = 1.0, 1.0
+        else:
+            w[0, 0, 1, 1], w[0, 1, 1, 1] = sign, -sign
+        ls.append((w, np.zeros(co, np.float32)))
+    return ls
+
+
+@pytest.mark.parametrize("n,seed", [(24, 1), (45, 2), (64, 3), (100, 4)])
+def test_fcg_without_network_is_jacobi_pcg(pk, n, seed):
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=seed)
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, tol=1e-10, maxit=5000)
+    _, oi = oracle.cg(rp, ci, v, f, tol=1e-10, maxit=5000, precond="jacobi")
+    assert info["status"] == "converged"
+    assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-10 * 1.001
+    assert abs(info["iters"] - oi["iters"]) <= max(2, math.ceil(0.02 * oi["iters"]))
+    assert info["fallbacks"] == 0 and info["switched_at"] is None
+
+
+@pytest.mark.parametrize("n", [20, 48])
+def test_fcg_with_identity_network_is_cg(pk, n):
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=5)
+    layers = _identity_layers()
+    params = to_dev(pk.nn_pack_params(layers))
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, params=params, logk=to_dev(lk), tol=1e-9, maxit=5000, stall=50)
+    assert info["status"] == "converged" and info["fallbacks"] == 0
+    _, oi = ofcg.fcg(rp, ci, v, f, lambda r: onn.apply_preconditioner(layers, r.reshape(n, n), lk, bf16=True).ravel(),
+                     tol=1e-9, stall=50)
+    _, ci_ = oracle.cg(rp, ci, v, f, tol=1e-9)
+    assert abs(info["iters"] - oi["iters"]) <= max(3, math.ceil(0.05 * oi["iters"]))
+    assert abs(info["iters"] - ci_["iters"]) <= max(3, math.ceil(0.05 * ci_["iters"]))
+    assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-9 * 1.001
+
+
+def test_failing_network_falls_back_every_iteration(pk):
+    n = 32
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=6)
+    params = to_dev(pk.nn_pack_params(_identity_layers(sign=-1.0)))   # z = -r
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, params=params, logk=to_dev(lk), tol=1e-10, stall=10 ** 6)
+    _, oi = oracle.cg(rp, ci, v, f, tol=1e-10, precond="jacobi")
+    assert info["status"] == "converged"
+    assert info["fallbacks"] == info["iters"]
+    assert abs(info["iters"] - oi["iters"]) <= max(2, math.ceil(0.02 * oi["iters"]))
+
+
+@pytest.mark.parametrize("n,stall", [(40, 5), (64, 20), (37, 3)])
+def test_fcg_with_random_network_converges(pk, n, stall):
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=7 + n)
+    params = to_dev(pk.nn_pack_params(onn.init_params(seed=n)))
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, params=params, logk=to_dev(lk), tol=1e-8, maxit=5000, stall=stall)
+    assert info["status"] == "converged"
+    assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-8 * 1.001
+
+
+def test_capture_equals_truncated_solve(pk):
+    rp, ci, v, lk, f = workloads.diffusion_problem(40, seed=9)
+    A = pk.CsrMatrix(rp, ci, v)
+    b = to_dev(f)
+    x = to_dev(np.zeros(f.size))
+    its = [1, 2, 4, 8, 16, 32]
+    info, xc, rc = pk.cg_solve_capture(A, b, x, its, tol=1e-12, maxit=5000, precond="jacobi")
+    assert info["status"] == "converged"
+    import scipy.sparse as sp
+    Am = sp.csr_matrix((v, ci, rp), shape=(f.size, f.size))
+    for j, k in enumerate(its):
+        xk = to_dev(np.zeros(f.size))
+        pk.cg_solve(A, b, xk, tol=0.0, maxit=k, precond="jacobi")
+        np.testing.assert_array_equal(xc[j].cpu().numpy(), xk.cpu().numpy())
+        xh = xc[j].cpu().numpy()
+        rt = f - Am @ xh
+        assert np.linalg.norm(rc[j].cpu().numpy() - rt) <= 1e-10 * np.linalg.norm(f)

@@ -31,3 +31,19 @@ def test_lognormal_sides_range_and_seed():
     np.testing.assert_array_equal(s, workloads.lognormal_sides(512, seed=0))
     # log-uniform: the median side is near sqrt(64 * 1024) = 256
     assert 200 < np.median(s) < 330
+
+
+def test_torch_diffusion_assembly_equals_numpy():
+    torch = pytest.importorskip("torch")
+    g = workloads.grf_log_k(13, seed=4)
+    rp, ci, v = workloads.diffusion_csr(np.exp(g))
+    trp, tci, tv = workloads.diffusion_csr_torch(torch.exp(torch.from_numpy(g)))
+    np.testing.assert_array_equal(trp.numpy(), rp)
+    np.testing.assert_array_equal(tci.numpy(), ci)
+    np.testing.assert_allclose(tv.numpy(), v, rtol=1e-15, atol=0)
+
+
+def test_torch_grf_statistics():
+    torch = pytest.importorskip("torch")
+    vals = torch.stack([workloads.grf_log_k_torch(16, seed=s, device="cpu")[5, 7] for s in range(400)])
+    assert abs(float(vals.var()) - 1.0) < 0.2 and abs(float(vals.mean())) < 0.15

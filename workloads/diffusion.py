@@ -63,3 +63,51 @@ def diffusion_problem(n, seed=0, sigma=1.0, ell=16.0):
     rp, ci, v = diffusion_csr(np.exp(g))
     f = np.random.default_rng(10_000_000 + seed).standard_normal(n * n)
     return rp, ci, v, g[1:-1, 1:-1].copy(), f
+
+
+def grf_log_k_torch(n, seed=0, sigma=1.0, ell=16.0, device="cuda"):
+    """grf_log_k on ``device`` with torch's generator (a different random
+    stream than the numpy version: same law, same seeding discipline)."""
+    import torch
+    m = n + 2
+    M = 2 * m
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    ar = torch.arange(M, device=device, dtype=torch.float64)
+    d = torch.minimum(ar, M - ar)
+    cov = torch.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * ell * ell))
+    lam = torch.clamp(torch.fft.fft2(cov).real, min=0.0)
+    xi = torch.randn((M, M), generator=gen, device=device, dtype=torch.float64)
+    g = torch.fft.ifft2(torch.sqrt(lam) * torch.fft.fft2(xi)).real
+    return sigma * g[:m, :m]
+
+
+def diffusion_csr_torch(k):
+    """diffusion_csr for a torch tensor k on any device (same arrays)."""
+    import torch
+    m = k.shape[0]
+    n = m - 2
+    kc = k[1:-1, 1:-1]
+
+    def t(a, b):
+        return 2.0 * a * b / (a + b)
+    ts, tw, te, tn = t(kc, k[:-2, 1:-1]), t(kc, k[1:-1, :-2]), t(kc, k[1:-1, 2:]), t(kc, k[2:, 1:-1])
+    diag = ts + tw + te + tn
+    iy, ix = torch.meshgrid(torch.arange(n, device=k.device), torch.arange(n, device=k.device), indexing="ij")
+    idx = iy * n + ix
+    cols = torch.stack([idx - n, idx - 1, idx, idx + 1, idx + n], dim=-1).reshape(-1, 5)
+    vals = torch.stack([-ts, -tw, diag, -te, -tn], dim=-1).reshape(-1, 5)
+    valid = torch.stack([iy > 0, ix > 0, torch.ones_like(ix, dtype=torch.bool), ix < n - 1, iy < n - 1],
+                        dim=-1).reshape(-1, 5)
+    rowptr = torch.zeros(n * n + 1, dtype=torch.int64, device=k.device)
+    rowptr[1:] = torch.cumsum(valid.sum(1), 0)
+    return rowptr.to(torch.int32), cols[valid].to(torch.int32), vals[valid].contiguous()
+
+
+def diffusion_problem_torch(n, seed=0, sigma=1.0, ell=16.0, device="cuda"):
+    """(rowptr, colind, values, log_k [n, n], f) as torch tensors on ``device``."""
+    import torch
+    g = grf_log_k_torch(n, seed=seed, sigma=sigma, ell=ell, device=device)
+    rp, ci, v = diffusion_csr_torch(torch.exp(g))
+    gen = torch.Generator(device=device).manual_seed(10_000_000 + int(seed))
+    f = torch.randn(n * n, generator=gen, device=device, dtype=torch.float64)
+    return rp, ci, v, g[1:-1, 1:-1].contiguous(), f
