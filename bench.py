@@ -247,6 +247,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the planner's default plans")
     ap.add_argument("--cases", default="all")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--cg-random", action="store_true", help="also the n=1M random SPD system")
@@ -279,6 +280,14 @@ def main():
         grids.append(torch.from_numpy(g).to(dev))
     weights = {k: workloads.stencil_weights(k) for k in FLOPS_PER_CELL}
     stream = torch.cuda.current_stream()
+    # autotune each case (outside the timed region); untuned runs then use the winner
+    tuned = {}
+    if not args.no_autotune:
+        for kind, shape, dt in cases:
+            t0 = time.perf_counter()
+            tuned[(kind, shape, dt)], rate = pk.stencil_autotune(shape, weights[kind], dt, probe_steps=100)
+            log(f"autotune {kind} {shape} {dt}: {tuned[(kind, shape, dt)]} ({rate:.1f} GCells/s probe, "
+                f"{time.perf_counter() - t0:.1f} s)")
 
     def run_case(i, baseline=False):
         kind, shape, dt = cases[i]
@@ -313,7 +322,7 @@ def main():
         cells = interior(shape) * STENCIL_STEPS
         total_cells += cells * args.steps
         total_time += sum(per_case[i])
-        plan = pk.stencil_plan(shape, weights[kind], dt)
+        plan = pk.stencil_plan(shape, weights[kind], dt, tuning=tuned.get((kind, shape, dt)))
         results.append({"case": f"{kind} {'x'.join(map(str, shape))} {dt}", "kind": kind, "dtype": dt,
                         "persistent_ms": t * 1e3, "persistent_gcells": cells / t / 1e9,
                         "launch_us": None, "plan": plan})

@@ -115,6 +115,37 @@ int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape sha
 int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtype dt,
                              const perks_tuning *tune, perks_stencil_plan *plan);
 
+/*
+ * perks_stencil_run_batched -- `steps` Jacobi sweeps of every grid in ONE
+ * persistent launch (an extension: the paper runs one grid per launch).
+ *   grids   host array of `count` device pointers, each updated in place.
+ *   shapes  host array of `count` extents (2D only; sizes may differ).
+ *   coeffs  one weight box for all grids (as for perks_stencil_run).
+ * The tiles of all grids share the launch's waves (one tile height for all
+ * grids); each grid keeps its own halo buffers and point-to-point halo
+ * synchronisation, so no grid waits on another.  Results are bitwise those of
+ * perks_stencil_run on each grid.  Synchronises `stream` before it uploads
+ * the grid table (host memory is not retained).
+ */
+int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int32_t count,
+                              const double *coeffs, int64_t steps, perks_dtype dt, void *stream);
+
+/*
+ * perks_stencil_autotune -- pick the launch plan by measurement.
+ *
+ * Times `probe_steps` sweeps of each candidate plan (the planner's own choice
+ * and every register tile depth, in each synchronisation mode; for 3D every
+ * tile depth in z) on a scratch grid of the given extents (allocated and freed
+ * here; synchronises `stream`), and returns the fastest as *best (host) with
+ * its rate in interior cells per ns as *best_gcells (may be NULL).  With
+ * remember != 0, later perks_stencil_run calls on this device for the same
+ * pattern, dtype and extents that pass tune == NULL use it.  The paper tunes
+ * thread blocks per SM and the cache split by hand (Sec. 5.4); this automates
+ * that choice.
+ */
+int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype dt, int64_t probe_steps,
+                           int32_t remember, void *stream, perks_tuning *best, double *best_gcells);
+
 /* Sparse matrix in CSR form (0-based, 32-bit indices, column indices of a row
  * in any order).  rowptr, colind, val are device pointers; val holds float or
  * double per `dt`. */

@@ -83,6 +83,12 @@ def lib():
     L.perks_stencil_run.argtypes = [vp, dp, Shape, i64, i32, vp, ctypes.POINTER(Tuning)]
     L.perks_stencil_run_baseline.argtypes = [vp, dp, Shape, i64, i32, vp]
     L.perks_stencil_plan_query.argtypes = [dp, Shape, i32, ctypes.POINTER(Tuning), ctypes.POINTER(StencilPlan)]
+    L.perks_stencil_autotune.argtypes = [dp, Shape, i32, i64, i32, vp, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_double)]
+    L.perks_stencil_autotune.restype = ctypes.c_int
+    L.perks_stencil_run_batched.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Shape), i32, dp, i64,
+                                            i32, vp]
+    L.perks_stencil_run_batched.restype = ctypes.c_int
     L.perks_strerror.restype = ctypes.c_char_p
     L.perks_strerror.argtypes = [ctypes.c_int]
     L.perks_last_error.restype = ctypes.c_char_p
@@ -204,6 +210,40 @@ def stencil_plan(shape, weights, dtype="float64", tuning=None):
                                         _tuning(tuning), ctypes.byref(pl))
     _check(rc)
     return {f: getattr(pl, f) for f, _ in StencilPlan._fields_ if f != "reserved"}
+
+
+def stencil_run_batched(grids, weights, steps, stream=None):
+    """Run ``steps`` Jacobi sweeps on every 2D grid of the list in ONE persistent launch."""
+    m = len(grids)
+    if m == 0:
+        return grids
+    for g in grids:
+        _check_grid(g)
+        if g.dim() != 2 or g.dtype != grids[0].dtype:
+            raise ValueError("batched grids must be 2D and of one dtype")
+    w = _coeff_array(weights, 2)
+    ptrs = (ctypes.c_void_p * m)(*[g.data_ptr() for g in grids])
+    shapes = (Shape * m)(*[_shape_of(g) for g in grids])
+    _check(lib().perks_stencil_run_batched(ptrs, shapes, m, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           int(steps), _dtype_code(grids[0]), _stream_handle(stream)))
+    return grids
+
+
+def stencil_autotune(shape, weights, dtype="float64", probe_steps=50, remember=True, stream=None):
+    """Time the candidate plans for this stencil and shape; returns (tuning dict,
+    GCells/s).  With ``remember``, later untuned stencil_run calls on this shape
+    use the winner."""
+    shape = tuple(int(s) for s in shape)
+    nd = len(shape)
+    sh = Shape(2, 0, shape[1], shape[0], 1) if nd == 2 else Shape(3, 0, shape[2], shape[1], shape[0])
+    w = _coeff_array(weights, nd)
+    t = Tuning()
+    rate = ctypes.c_double()
+    dt = PERKS_F64 if str(dtype).endswith("64") else PERKS_F32
+    _check(lib().perks_stencil_autotune(w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sh, dt, int(probe_steps),
+                                        1 if remember else 0, _stream_handle(stream), ctypes.byref(t),
+                                        ctypes.byref(rate)))
+    return {f: getattr(t, f) for f, _ in Tuning._fields_ if f != "reserved"}, rate.value
 
 
 def device_info():

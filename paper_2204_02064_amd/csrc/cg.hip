@@ -45,6 +45,9 @@ struct CgInst {
     float *r32, *z32, *q32, *p0_32, *p1_32, *d32, *dinv32;
     double *part;
     double *result;
+    double *sval64;          // sliced-ELL copy of A (FP64 solver), NULL: CSR only
+    float *sval32;           // sliced-ELL copy of A (mixed solver)
+    int *scol;               // its column indices
     double *cap_x, *cap_r;   // FP64 solver: x and r after the iterations listed in cap_iters
     const int *cap_iters;    // ascending iteration counts (device)
     int ncap;
@@ -59,8 +62,8 @@ struct CgInst {
 // The workgroup's LDS copy of (the first entries of) its slice of A: FP64
 // values for the FP64 solver, FP32 values for the mixed-precision solver.
 // Each kernel references only its own pair, so each gets only that pair.
-constexpr int CG_LDS_NNZ = 13312;     // 156 KiB of the 160 KiB LDS (12 B/nonzero)
-constexpr int CG_LDS_NNZ32 = 19968;   // 156 KiB (8 B/nonzero)
+constexpr int CG_LDS_NNZ = 12032;     // 141 KiB of the 160 KiB LDS (12 B/nonzero)
+constexpr int CG_LDS_NNZ32 = 18048;   // 141 KiB (8 B/nonzero)
 __shared__ double cg_lval[CG_LDS_NNZ];
 __shared__ int cg_lcol[CG_LDS_NNZ];
 __shared__ float cg_lval32[CG_LDS_NNZ32];
@@ -161,29 +164,165 @@ __shared__ double cg_red[4 * CG_WAVES];
 __shared__ double cg_bcast;
 
 // The workgroup's share of a problem solved by a group of G workgroups, of
-// which this one has rank g: rows [r0, r1) (merge-path split), the LDS copy
-// of the first kc entries of its slice of A, rows [r0, rc) wholly cached.
+// which this one has rank g: rows [r0, r1) (merge-path split).
+//
+// Two layouts of the slice's rows:
+// * sliced ELL (when padding costs at most a quarter more entries): chunks of
+//   64 consecutive rows, one lane per row, the chunk's rows padded to its
+//   longest row and stored entry-major (entry j of the chunk's rows is 64
+//   consecutive values), built by the workgroup at kernel start in its own
+//   region of the packed arrays.  Loads are coalesced, no row pointers are
+//   read in the iterations, no lanes are reduced across.  Padding entries are
+//   0 * x[row].  Chunks [0, cc) are also held in LDS.
+// * CSR with L lanes per row otherwise (irregular row lengths): the first kc
+//   nonzeros in LDS, rows [r0, rc) wholly cached.
+// A row's sum is the same either way up to rounding order; its order depends
+// only on the layout, which depends only on the problem and G.
+constexpr int SELL_MAX_CHUNKS = 2048;
+__shared__ int cg_chunk_len[SELL_MAX_CHUNKS];
+__shared__ int cg_chunk_off[SELL_MAX_CHUNKS];
+__shared__ int cg_flag;
+
 struct Slice {
     int r0, r1, rc, kbase, nnz, kc, L;
+    int sell, nch, cc, sbase;
 };
 
+// Entries the packed arrays of one problem need for G workgroups.
+__host__ __device__ inline size_t sell_capacity(int64_t nnz, int G) {
+    return (size_t)(nnz + nnz / 4) + 64 * (size_t)G + 64;
+}
+
 template <typename T>
-__device__ __forceinline__ Slice load_slice(const CgInst &p, const T *val, int g, int G) {
+__device__ __forceinline__ Slice load_slice(const CgInst &p, const T *val, T *sval, int *scol, int g, int G) {
     Slice sl;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     sl.r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
     sl.r1 = merge_split(p.rowptr, p.n, p.nnz, g + 1, G);
     sl.kbase = p.rowptr[sl.r0];
     sl.nnz = p.rowptr[sl.r1] - sl.kbase;
     sl.L = pick_group(sl.r1 - sl.r0, sl.nnz);
-    sl.kc = min(sl.nnz, LdsA<T>::cap);
-    __syncthreads();   // the previous problem of this workgroup is done with the LDS copy
-    for (int k = threadIdx.x; k < sl.kc; k += CG_THREADS) {
-        LdsA<T>::val(k) = val[sl.kbase + k];
-        LdsA<T>::col(k) = p.colind[sl.kbase + k];
+    sl.nch = (sl.r1 - sl.r0 + 63) / 64;
+    sl.sbase = (int)(sl.kbase + sl.kbase / 4) + 64 * g;
+    __syncthreads();   // the previous problem of this workgroup is done with LDS
+    // chunk lengths (longest row of each chunk), then their offsets
+    sl.sell = sval != nullptr && sl.nch <= SELL_MAX_CHUNKS;
+    if (sl.sell) {
+        for (int c = wave; c < sl.nch; c += CG_WAVES) {
+            const int i = sl.r0 + 64 * c + lane;
+            int len = i < sl.r1 ? p.rowptr[i + 1] - p.rowptr[i] : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+            if (lane == 0) cg_chunk_len[c] = len;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int c = 0; c < sl.nch; ++c) {
+                cg_chunk_off[c] = acc;
+                acc += 64 * cg_chunk_len[c];
+            }
+            cg_flag = acc <= sl.nnz + sl.nnz / 4 + 64 ? acc : -1;
+        }
+        __syncthreads();
+        sl.sell = cg_flag >= 0;
     }
-    sl.rc = cached_rows_end(p.rowptr, sl.r0, sl.r1, sl.kbase, sl.kc);
-    __syncthreads();
+    if (sl.sell) {
+        // cached chunks: a prefix whose entries fit in LDS
+        int cc = 0;
+        while (cc < sl.nch && cg_chunk_off[cc] + 64 * cg_chunk_len[cc] <= LdsA<T>::cap) ++cc;
+        sl.cc = cc;
+        for (int c = wave; c < sl.nch; c += CG_WAVES) {
+            const int i = sl.r0 + 64 * c + lane;
+            const int len = cg_chunk_len[c], off = cg_chunk_off[c];
+            const int kb = i < sl.r1 ? p.rowptr[i] : 0;
+            const int kn = i < sl.r1 ? p.rowptr[i + 1] - kb : 0;
+            const int self = i < sl.r1 ? i : sl.r0;
+            for (int j = 0; j < len; ++j) {
+                const T a = j < kn ? val[kb + j] : T(0);
+                const int cidx = j < kn ? p.colind[kb + j] : self;
+                const int e = off + j * 64 + lane;
+                sval[sl.sbase + e] = a;
+                scol[sl.sbase + e] = cidx;
+                if (c < cc) {
+                    LdsA<T>::val(e) = a;
+                    LdsA<T>::col(e) = cidx;
+                }
+            }
+        }
+        sl.kc = 0;
+        sl.rc = sl.r0;
+    } else {
+        sl.cc = 0;
+        sl.kc = min(sl.nnz, LdsA<T>::cap);
+        for (int k = tid; k < sl.kc; k += CG_THREADS) {
+            LdsA<T>::val(k) = val[sl.kbase + k];
+            LdsA<T>::col(k) = p.colind[sl.kbase + k];
+        }
+        sl.rc = cached_rows_end(p.rowptr, sl.r0, sl.r1, sl.kbase, sl.kc);
+    }
+    __syncthreads();   // also publishes the packed arrays within the workgroup
     return sl;
+}
+
+// y_i = sum_j a_j * v(col_j) over the sliced-ELL chunks [c0, c1), one lane
+// per row, entries in CSR order; FROM_LDS: the chunks are held in LDS.
+template <bool FROM_LDS, typename T, typename F, typename S>
+__device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, const int *scol, int c0, int c1,
+                                                F fetch, S sink) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = c0 + wave; c < c1; c += CG_WAVES) {
+        const int len = cg_chunk_len[c], off = cg_chunk_off[c];
+        const int i = sl.r0 + 64 * c + lane;
+        T acc = T(0);
+        int j = 0;
+        for (; j + 4 <= len; j += 4) {
+            T a[4];
+            int cidx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = off + (j + u) * 64 + lane;
+                if constexpr (FROM_LDS) {
+                    a[u] = LdsA<T>::val(e);
+                    cidx[u] = LdsA<T>::col(e);
+                } else {
+                    a[u] = sval[sl.sbase + e];
+                    cidx[u] = scol[sl.sbase + e];
+                }
+            }
+            T xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = fetch(cidx[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = fma_t(a[u], xv[u], acc);
+        }
+        for (; j < len; ++j) {
+            const int e = off + j * 64 + lane;
+            T a;
+            int cidx;
+            if constexpr (FROM_LDS) {
+                a = LdsA<T>::val(e);
+                cidx = LdsA<T>::col(e);
+            } else {
+                a = sval[sl.sbase + e];
+                cidx = scol[sl.sbase + e];
+            }
+            acc = fma_t(a, fetch(cidx), acc);
+        }
+        if (i < sl.r1) sink(i, acc);
+    }
+}
+
+// SpMV over the workgroup's rows in whichever layout the slice uses.
+template <int U, typename T, typename F, typename S>
+__device__ __forceinline__ void spmv_slice(const CgInst &p, const Slice &sl, const T *val, const T *sval,
+                                           const int *scol, F fetch, S sink) {
+    if (sl.sell) {
+        spmv_sell_range<true>(sl, sval, scol, 0, sl.cc, fetch, sink);
+        spmv_sell_range<false>(sl, sval, scol, sl.cc, sl.nch, fetch, sink);
+    } else {
+        spmv_rows<U>(p.rowptr, p.colind, val, sl.r0, sl.rc, sl.r1, sl.L, sl.kbase, fetch, sink);
+    }
 }
 
 // FP64 persistent CG of one problem by a group of G workgroups (this one of
@@ -195,141 +334,132 @@ __device__ __forceinline__ Slice load_slice(const CgInst &p, const T *val, int g
 // recursive residual meets tol the true residual is recomputed; if it fails,
 // CG restarts from the current x while iterations remain.
 template <bool JACOBI, bool FUSEP, class Sync>
-__device__ __forceinline__ void cg_f64_body(const CgInst &p, Sync &gs, const int g, const int G) {
+__device__ __forceinline__ void cg_f64_body(const CgInst *pin, Sync &gs, const int g, const int G) {
+    // The problem is read from global memory through a pointer laundered at
+    // every phase: its fields are reloaded (scalar loads) instead of being
+    // kept live in scalar registers across the whole solve.
+    const CgInst *pp = opaque(pin);
     const int tid = threadIdx.x;
-    const Slice sl = load_slice(p, p.val, g, G);
-    const int r0 = sl.r0, r1 = sl.r1, rc = sl.rc, kbase = sl.kbase, L = sl.L;
+    const Slice sl = load_slice(*pp, pp->val, pp->sval64, pp->scol, g, G);
+    const int r0 = sl.r0, r1 = sl.r1;
     if (JACOBI) {
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
             double dg = 0.0;
-            for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k)
-                if (p.colind[k] == i) dg += p.val[k];
-            p.dinv[i] = 1.0 / dg;
+            for (int k = pp->rowptr[i]; k < pp->rowptr[i + 1]; ++k)
+                if (pp->colind[k] == i) dg += pp->val[k];
+            pp->dinv[i] = 1.0 / dg;
         }
     }
-    const double *zsrc = JACOBI ? p.z : p.r;
+    const double *zsrc = JACOBI ? pp->z : pp->r;
     int k = 0, status = 1, restarts = 0, k_cycle = -1, cap = 0;
-    while (cap < p.ncap && p.cap_iters[cap] <= 0) ++cap;
+    while (cap < pp->ncap && pp->cap_iters[cap] <= 0) ++cap;
     double bnorm = 0.0, rr = 0.0, tt = 0.0;
     for (;;) {
+        pp = opaque(pin);
         // phase 0: r = b - A x, z, p_{-1} = 0, partials b.b, r.z, r.r
         double acc0[3] = {0.0, 0.0, 0.0};
-        spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return p.x[c]; },
-                        [&](int i, double s) { p.q[i] = s; });
+        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
+                        [&](int i, double s) { pp->q[i] = s; });
         __syncthreads();
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            const double bi = p.b[i];
-            const double ri = bi - p.q[i];
-            const double zi = JACOBI ? p.dinv[i] * ri : ri;
+            const double bi = pp->b[i];
+            const double ri = bi - pp->q[i];
+            const double zi = JACOBI ? pp->dinv[i] * ri : ri;
             if (JACOBI) {
-                p.r[i] = ri;            // read back only by this thread
-                st_coh(p.z + i, zi);    // gathered by other workgroups
+                pp->r[i] = ri;            // read back only by this thread
+                st_coh(pp->z + i, zi);    // gathered by other workgroups
             } else {
-                st_coh(p.r + i, ri);
+                st_coh(pp->r + i, ri);
             }
-            st_coh((FUSEP ? p.p1 : p.p0) + i, 0.0);
+            st_coh((FUSEP ? pp->p1 : pp->p0) + i, 0.0);
             acc0[0] = __builtin_fma(bi, bi, acc0[0]);
             acc0[1] = __builtin_fma(ri, zi, acc0[1]);
             acc0[2] = __builtin_fma(ri, ri, acc0[2]);
         }
         block_sum<3>(acc0, cg_red);
         if (tid == 0) {
-            st_coh(p.part + (size_t)PART_BB * G + g, acc0[0]);
-            st_coh(p.part + (size_t)PART_RZ * G + g, acc0[1]);
-            st_coh(p.part + (size_t)PART_RR * G + g, acc0[2]);
+            st_coh(pp->part + (size_t)PART_BB * G + g, acc0[0]);
+            st_coh(pp->part + (size_t)PART_RZ * G + g, acc0[1]);
+            st_coh(pp->part + (size_t)PART_RR * G + g, acc0[2]);
         }
         gs.template sync<true>();
-        bnorm = sqrt(grid_total(p.part, PART_BB, G, &cg_bcast));
-        double rho = grid_total(p.part, PART_RZ, G, &cg_bcast);
-        rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+        bnorm = sqrt(grid_total(pp->part, PART_BB, G, &cg_bcast));
+        double rho = grid_total(pp->part, PART_RZ, G, &cg_bcast);
+        rr = grid_total(pp->part, PART_RR, G, &cg_bcast);
         if (bnorm == 0.0) {
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, 0.0);
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pp->x + i, 0.0);
             status = 0;
             tt = 0.0;
             break;
         }
         double beta = 0.0;
         while (true) {
-            if (sqrt(rr) <= p.tol * bnorm) break;
-            if (k >= p.maxit) break;
+            if (sqrt(rr) <= pp->tol * bnorm) break;
+            if (k >= pp->maxit) break;
+            pp = opaque(pin);
             double acc1[1] = {0.0};
             double *pn;
             if constexpr (FUSEP) {
-                pn = (k & 1) ? p.p1 : p.p0;                // p_k
-                const double *po = (k & 1) ? p.p0 : p.p1;  // p_{k-1}
-                spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase,
+                pn = (k & 1) ? pp->p1 : pp->p0;                // p_k
+                const double *po = (k & 1) ? pp->p0 : pp->p1;  // p_{k-1}
+                spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol,
                                 [&](int c) { return __builtin_fma(beta, po[c], zsrc[c]); },
                                 [&](int i, double s) {
                                     const double pi = __builtin_fma(beta, po[i], zsrc[i]);
-                                    p.q[i] = s;
+                                    pp->q[i] = s;
                                     st_coh(pn + i, pi);
                                     acc1[0] = __builtin_fma(pi, s, acc1[0]);
                                 });
             } else {
-                pn = p.p0;
+                pn = pp->p0;
                 for (int i = r0 + tid; i < r1; i += CG_THREADS)
                     st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
                 gs.template sync<true>();
-                spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return pn[c]; },
+                spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
                                 [&](int i, double s) {
-                                    p.q[i] = s;
+                                    pp->q[i] = s;
                                     acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
                                 });
             }
             block_sum<1>(acc1, cg_red);
-            if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
+            if (tid == 0) st_coh(pp->part + (size_t)PART_PQ * G + g, acc1[0]);
             gs.template sync<true>();
-            const double pq = grid_total(p.part, PART_PQ, G, &cg_bcast);
+            const double pq = grid_total(pp->part, PART_PQ, G, &cg_bcast);
             if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
             const double alpha = rho / pq;
-            // phase 2: x, r, z updates on own rows (2 rows per thread in flight)
+            pp = opaque(pin);
+            // phase 2: x, r, z updates on own rows
             double acc2[2] = {0.0, 0.0};
-            for (int i0 = r0 + tid; i0 < r1; i0 += 2 * CG_THREADS) {
-                double pi[2], qi[2], xi[2], ro[2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int i = i0 + u * CG_THREADS;
-                    if (i < r1) {
-                        pi[u] = pn[i];
-                        qi[u] = p.q[i];
-                        xi[u] = p.x[i];
-                        ro[u] = p.r[i];
-                    }
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) {
+                const double pi = pn[i], qi = pp->q[i], xi = pp->x[i], ro = pp->r[i];
+                st_coh(pp->x + i, __builtin_fma(alpha, pi, xi));   // read by others at exit
+                const double ri = __builtin_fma(-alpha, qi, ro);
+                double zi = ri;
+                if (JACOBI) {
+                    pp->r[i] = ri;
+                    zi = pp->dinv[i] * ri;
+                    st_coh(pp->z + i, zi);
+                } else {
+                    st_coh(pp->r + i, ri);
                 }
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int i = i0 + u * CG_THREADS;
-                    if (i < r1) {
-                        st_coh(p.x + i, __builtin_fma(alpha, pi[u], xi[u]));   // read by others at exit
-                        const double ri = __builtin_fma(-alpha, qi[u], ro[u]);
-                        double zi = ri;
-                        if (JACOBI) {
-                            p.r[i] = ri;
-                            zi = p.dinv[i] * ri;
-                            st_coh(p.z + i, zi);
-                        } else {
-                            st_coh(p.r + i, ri);
-                        }
-                        acc2[0] = __builtin_fma(ri, zi, acc2[0]);
-                        acc2[1] = __builtin_fma(ri, ri, acc2[1]);
-                    }
-                }
+                acc2[0] = __builtin_fma(ri, zi, acc2[0]);
+                acc2[1] = __builtin_fma(ri, ri, acc2[1]);
             }
             block_sum<2>(acc2, cg_red);
             if (tid == 0) {
-                st_coh(p.part + (size_t)PART_RZ * G + g, acc2[0]);
-                st_coh(p.part + (size_t)PART_RR * G + g, acc2[1]);
+                st_coh(pp->part + (size_t)PART_RZ * G + g, acc2[0]);
+                st_coh(pp->part + (size_t)PART_RR * G + g, acc2[1]);
             }
             gs.template sync<true>();
-            const double rho_new = grid_total(p.part, PART_RZ, G, &cg_bcast);
-            rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+            const double rho_new = grid_total(pp->part, PART_RZ, G, &cg_bcast);
+            rr = grid_total(pp->part, PART_RR, G, &cg_bcast);
             ++k;
-            if (cap < p.ncap && k == p.cap_iters[cap]) {
+            if (cap < pp->ncap && k == pp->cap_iters[cap]) {
                 // snapshot of the iterate and its residual (own rows, same
                 // thread-to-row mapping as phase 2)
                 for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-                    p.cap_x[(size_t)cap * p.n + i] = p.x[i];
-                    p.cap_r[(size_t)cap * p.n + i] = p.r[i];
+                    pp->cap_x[(size_t)cap * pp->n + i] = pp->x[i];
+                    pp->cap_r[(size_t)cap * pp->n + i] = pp->r[i];
                 }
                 ++cap;
             }
@@ -338,33 +468,34 @@ __device__ __forceinline__ void cg_f64_body(const CgInst &p, Sync &gs, const int
             rho = rho_new;
         }
         // true residual ||b - A x|| (x of other workgroups read after the barrier)
+        pp = opaque(pin);
         double acc3[1] = {0.0};
         gs.template sync<true>();
-        spmv_rows<CG_U>(p.rowptr, p.colind, p.val, r0, rc, r1, L, kbase, [&](int c) { return p.x[c]; },
+        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
                         [&](int i, double s) {
-                            const double d = p.b[i] - s;
+                            const double d = pp->b[i] - s;
                             acc3[0] = __builtin_fma(d, d, acc3[0]);
                         });
         block_sum<1>(acc3, cg_red);
-        if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, acc3[0]);
+        if (tid == 0) st_coh(pp->part + (size_t)PART_TRUE * G + g, acc3[0]);
         gs.template sync<true>();
-        tt = grid_total(p.part, PART_TRUE, G, &cg_bcast);
+        tt = grid_total(pp->part, PART_TRUE, G, &cg_bcast);
         if (status == 2) break;
-        if (sqrt(tt) <= p.tol * bnorm) { status = 0; break; }
+        if (sqrt(tt) <= pp->tol * bnorm) { status = 0; break; }
         // restart from x (recursive residual converged but the true one did
         // not) unless the iteration budget is spent or the last cycle made no
         // iteration (the two residuals differ only in rounding order there)
-        if (k >= p.maxit || k == k_cycle) { status = 1; break; }
+        if (k >= pp->maxit || k == k_cycle) { status = 1; break; }
         k_cycle = k;
         ++restarts;
     }
     if (g == 0 && tid == 0) {
-        p.result[0] = k;
-        p.result[1] = status;
-        p.result[2] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
-        p.result[3] = bnorm > 0.0 ? sqrt(tt) / bnorm : 0.0;
-        p.result[4] = bnorm;
-        p.result[5] = restarts;
+        pp->result[0] = k;
+        pp->result[1] = status;
+        pp->result[2] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+        pp->result[3] = bnorm > 0.0 ? sqrt(tt) / bnorm : 0.0;
+        pp->result[4] = bnorm;
+        pp->result[5] = restarts;
     }
 }
 
@@ -387,8 +518,8 @@ __device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const i
         const int s1 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g + 1, G)];
         for (int k = s0 + tid; k < s1; k += CG_THREADS) p.val32[k] = (float)p.val[k];
     }
-    const Slice sl = load_slice(p, (const float *)p.val32, g, G);   // its barrier publishes val32
-    const int r0 = sl.r0, r1 = sl.r1, rc = sl.rc, kbase = sl.kbase, L = sl.L;
+    const Slice sl = load_slice(p, (const float *)p.val32, p.sval32, p.scol, g, G);   // its barriers publish val32
+    const int r0 = sl.r0, r1 = sl.r1, kbase = sl.kbase, L = sl.L;
     double accb[1] = {0.0};
     for (int i = r0 + tid; i < r1; i += CG_THREADS) {
         if (JACOBI) {
@@ -467,7 +598,7 @@ __device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const i
             if constexpr (FUSEP) {
                 pn = (j & 1) ? p.p1_32 : p.p0_32;                // p_j
                 const float *po = (j & 1) ? p.p0_32 : p.p1_32;   // p_{j-1}
-                spmv_rows<CG_U>(p.rowptr, p.colind, (const float *)p.val32, r0, rc, r1, L, kbase,
+                spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
                                 [&](int c) { return __builtin_fmaf(bf, po[c], zsrc[c]); },
                                 [&](int i, float sv) {
                                     const float pi = __builtin_fmaf(bf, po[i], zsrc[i]);
@@ -480,7 +611,7 @@ __device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const i
                 for (int i = r0 + tid; i < r1; i += CG_THREADS)
                     st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
                 gs.template sync<true>();
-                spmv_rows<CG_U>(p.rowptr, p.colind, (const float *)p.val32, r0, rc, r1, L, kbase,
+                spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
                                 [&](int c) { return pn[c]; },
                                 [&](int i, float sv) {
                                     p.q32[i] = sv;
@@ -538,11 +669,11 @@ __device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const i
 
 // One problem on the whole grid.
 template <bool JACOBI, bool FUSEP, bool MIXED>
-__global__ __launch_bounds__(CG_THREADS) void cg_persistent(CgInst p, unsigned *ws) {
+__global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
     GroupSync gs;
     gs.init_grid(ws);
-    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(p, gs, blockIdx.x, gridDim.x);
-    else cg_f64_body<JACOBI, FUSEP>(p, gs, blockIdx.x, gridDim.x);
+    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*pin, gs, blockIdx.x, gridDim.x);
+    else cg_f64_body<JACOBI, FUSEP>(pin, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
 }
 
@@ -551,9 +682,9 @@ __global__ __launch_bounds__(CG_THREADS) void cg_persistent(CgInst p, unsigned *
 // group size, group id).  A problem given to several workgroups is the first
 // task of each of them (a contiguous range of workgroups, synchronised by the
 // group's own barrier); the other problems are solved by one workgroup each,
-// one after another.  No workgroup waits on a group before finishing all
-// earlier tasks of its own, so no wait can be circular.  A final barrier of
-// the whole grid precedes the hand-over of the epoch to the next launch.
+// one after another.  Every workgroup takes its tasks in the same phase
+// order, so no wait can be circular.  A final barrier of the whole grid
+// precedes the hand-over of the epoch to the next launch.
 struct CgTask {
     int inst, rank, size, group;
 };
@@ -563,7 +694,8 @@ struct CgBatch {
     const CgTask *tasks;
     const int *task_ptr;
     unsigned *ws;
-    unsigned epoch_span;   // > barriers any group takes; epochs of this launch stay below start + span
+    unsigned epoch_span;   // > barriers any group takes: group j uses epochs start + j*span + 1 ..
+    int ngroups;           // groups of two or more workgroups (ids 0 .. ngroups-1)
 };
 
 template <bool JACOBI, bool FUSEP, bool MIXED>
@@ -572,14 +704,15 @@ __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
     const unsigned e0 = ld_coh(bp.ws + SYNC_EPOCH);
     for (int t = bp.task_ptr[g]; t < bp.task_ptr[g + 1]; ++t) {
         const CgTask task = bp.tasks[t];
-        const CgInst p = bp.inst[task.inst];
         GroupSync gs;
-        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0);
-        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(p, gs, task.rank, task.size);
-        else cg_f64_body<JACOBI, FUSEP>(p, gs, task.rank, task.size);
+        // disjoint epoch ranges per group: a workgroup's flag left by an
+        // earlier group can never match a later group's epochs
+        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span);
+        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(bp.inst[task.inst], gs, task.rank, task.size);
+        else cg_f64_body<JACOBI, FUSEP>(bp.inst + task.inst, gs, task.rank, task.size);
     }
     GroupSync all;
-    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + bp.epoch_span - 1);
+    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span);
     all.gen = bp.ws + SYNC_GEN;
     all.sync();
     if (g == 0 && threadIdx.x == 0) st_coh(bp.ws + SYNC_EPOCH, all.epoch);
@@ -874,15 +1007,20 @@ size_t vec_len(int64_t n) { return ((size_t)n + 63) / 64 * 64 + 64; }
 size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
     const size_t nv = vec_len(n);
     const size_t np = ((size_t)NPART * std::max(parts, 1) + 64 + 31) / 32 * 32;
+    const size_t ns = (sell_capacity(nnz, std::max(parts, 1)) + 63) / 64 * 64;
     size_t bytes = (np + 64) * sizeof(double);
-    if (mixed) bytes += nv * sizeof(double) + 7 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float);
-    else bytes += 6 * nv * sizeof(double);
+    if (mixed)
+        bytes += nv * sizeof(double) + 7 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float) +
+                 ns * (sizeof(float) + sizeof(int));
+    else
+        bytes += 6 * nv * sizeof(double) + ns * (sizeof(double) + sizeof(int));
     return (bytes + 255) / 256 * 256;
 }
 
-void carve(char *base, int64_t n, int parts, bool mixed, CgInst *w) {
+void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w) {
     const size_t nv = vec_len(n);
     const size_t np = ((size_t)NPART * std::max(parts, 1) + 64 + 31) / 32 * 32;
+    const size_t ns = (sell_capacity(nnz, std::max(parts, 1)) + 63) / 64 * 64;
     w->part = (double *)base;
     w->result = w->part + np;
     char *v = (char *)(w->result + 64);
@@ -897,6 +1035,8 @@ void carve(char *base, int64_t n, int parts, bool mixed, CgInst *w) {
         w->d32 = f + 5 * nv;
         w->dinv32 = f + 6 * nv;
         w->val32 = f + 7 * nv;
+        w->sval32 = w->val32 + ((size_t)nnz + 63) / 64 * 64;
+        w->scol = (int *)(w->sval32 + ns);
     } else {
         double *d = (double *)v;
         w->r = d;
@@ -905,6 +1045,8 @@ void carve(char *base, int64_t n, int parts, bool mixed, CgInst *w) {
         w->p0 = d + 3 * nv;
         w->p1 = d + 4 * nv;
         w->dinv = d + 5 * nv;
+        w->sval64 = d + 6 * nv;
+        w->scol = (int *)(w->sval64 + ns);
     }
 }
 
@@ -915,7 +1057,7 @@ int cg_work(int64_t n, int64_t nnz, int parts, bool mixed, CgWork *w) {
     *w = CgWork{};
     char *base = (char *)scratch(SLOT_CG_VEC, inst_bytes(n, nnz, parts, mixed));
     if (!base) return PERKS_E_NOMEM;
-    carve(base, n, parts, mixed, w);
+    carve(base, n, nnz, parts, mixed, w);
     return PERKS_OK;
 }
 
@@ -1020,7 +1162,12 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     p.ncap = capture.n;
     p.cap_x = capture.x;
     p.cap_r = capture.r;
-    void *args[] = {&p, &ws};
+    // the kernel reads the problem description from device memory (in the
+    // spare result words)
+    static_assert(sizeof(CgInst) <= 48 * sizeof(double), "problem description outgrew the result block");
+    CgInst *pdev = reinterpret_cast<CgInst *>(p.result + 16);
+    PERKS_HIP_TRY(hipMemcpyAsync(pdev, &p, sizeof(CgInst), hipMemcpyHostToDevice, st));
+    void *args[] = {&pdev, &ws};
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
     if (e != hipSuccess) return launch_error(e);
     double h[8] = {0};
@@ -1259,63 +1406,55 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
 // ---------------------------------------------------------------------------
 // Batched solve: many problems in one persistent launch.
 //
-// Schedule (host, deterministic): predicted work w_i = nnz_i * sqrt(n_i)
-// (nonzeros per iteration times an iteration count growing like the grid
-// side of a 2D problem).  With C = sum(w) / G the fair share of one
-// workgroup, problems heavier than 2C, largest first, get floor(w_i / C)
-// workgroups of their own (at most one per CG_THREADS rows, and leaving one
-// workgroup for the rest); every other problem goes, largest first, to the
-// workgroup with the least predicted load so far (LPT), the grouped
-// workgroups counting w_i / k_i.
+// Schedule (host, deterministic).  One workgroup streams a slice of A from
+// memory far slower than it reads it from its LDS copy, and a problem spread
+// over many workgroups pays for every barrier; so each problem gets the
+// fewest workgroups whose LDS holds all of its matrix, k_i =
+// ceil(nnz_i / (LDS nonzeros per workgroup, less padding)) (at most G, at
+// least one row per lane), and the problems, largest predicted work
+// (nnz * sqrt(n)) first, are packed first-fit into "phases" of at most G
+// workgroups.  Workgroup g runs its phase-0 task, then its phase-1 task, and
+// so on: a group's members are all in the same phase, every workgroup takes
+// the phases in the same order, so no wait can be circular.  A problem whose
+// matrix alone exceeds the whole device's LDS gets all G workgroups, a phase
+// of its own.
 struct BatchSchedule {
     std::vector<int> task_ptr;   // G + 1
     std::vector<CgTask> tasks;
     std::vector<int> wgs;        // workgroups per problem (0: empty problem)
+    int phases = 0;
+    int groups = 0;
 };
 
-BatchSchedule make_schedule(const std::vector<int64_t> &n, const std::vector<int64_t> &nnz, int G) {
+BatchSchedule make_schedule(const std::vector<int64_t> &n, const std::vector<int64_t> &nnz, int G, bool mixed) {
     const int m = (int)n.size();
     BatchSchedule S;
     S.wgs.assign(m, 0);
+    const int64_t lds_nnz = (mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ) * 7 / 8;   // room for sliced-ELL padding
     std::vector<double> w(m, 0.0);
-    double W = 0.0;
     std::vector<int> order;
     for (int i = 0; i < m; ++i) {
         if (n[i] == 0) continue;
         w[i] = (double)std::max<int64_t>(nnz[i], 1) * std::sqrt((double)n[i]);
-        W += w[i];
+        int64_t k = (nnz[i] + lds_nnz - 1) / lds_nnz;
+        k = std::min<int64_t>(k, std::max<int64_t>(1, n[i] / 64));
+        S.wgs[i] = (int)std::max<int64_t>(1, std::min<int64_t>(k, G));
         order.push_back(i);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
-    const double C = W / G;
     std::vector<std::vector<CgTask>> per(G);
-    std::vector<double> load(G, 0.0);
-    int next = 0, group = 0;
-    size_t first_small = 0;
-    for (; first_small < order.size(); ++first_small) {
-        const int i = order[first_small];
-        const bool more = first_small + 1 < order.size();
-        int k = (int)std::floor(w[i] / C);
-        k = std::min<int64_t>(k, std::max<int64_t>(1, n[i] / CG_THREADS));
-        k = std::min(k, G - next - (more ? 1 : 0));
-        if (w[i] <= 2.0 * C || k < 2) break;
-        for (int r = 0; r < k; ++r) {
-            per[next + r].push_back(CgTask{i, r, k, group});
-            load[next + r] = w[i] / k;
+    int used = G, group = 0;   // start a new phase at the first problem
+    for (int i : order) {
+        const int k = S.wgs[i];
+        if (used + k > G) {
+            used = 0;
+            ++S.phases;
         }
-        S.wgs[i] = k;
-        next += k;
-        ++group;
+        for (int r = 0; r < k; ++r) per[used + r].push_back(CgTask{i, r, k, k > 1 ? group : 0});
+        if (k > 1) ++group;
+        used += k;
     }
-    for (size_t t = first_small; t < order.size(); ++t) {
-        const int i = order[t];
-        int best = 0;
-        for (int g = 1; g < G; ++g)
-            if (load[g] < load[best]) best = g;
-        per[best].push_back(CgTask{i, 0, 1, 0});
-        load[best] += w[i];
-        S.wgs[i] = 1;
-    }
+    S.groups = group;
     S.task_ptr.assign(G + 1, 0);
     for (int g = 0; g < G; ++g) {
         S.task_ptr[g + 1] = S.task_ptr[g] + (int)per[g].size();
@@ -1379,7 +1518,7 @@ int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *cons
             n[i] = As[i].n;
             nnz[i] = As[i].nnz;
         }
-        BatchSchedule S = make_schedule(n, nnz, P->G);
+        BatchSchedule S = make_schedule(n, nnz, P->G, mixed);
         P->wgs = S.wgs;
         // device memory: sync words | problems | tasks | task_ptr | results | work areas
         auto up = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -1405,7 +1544,7 @@ int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *cons
         for (int i = 0; i < count; ++i) {
             CgInst &p = inst[i];
             p = CgInst{};
-            if (n[i] > 0) carve(base + work_off[i], n[i], std::max(S.wgs[i], 1), mixed, &p);
+            if (n[i] > 0) carve(base + work_off[i], n[i], nnz[i], std::max(S.wgs[i], 1), mixed, &p);
             p.result = (double *)(base + o_res) + 8 * (size_t)i;
             p.rowptr = As[i].rowptr;
             p.colind = As[i].colind;
@@ -1440,7 +1579,13 @@ int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *cons
         P->params.tasks = (const CgTask *)(base + o_tasks);
         P->params.task_ptr = (const int *)(base + o_ptr);
         P->params.ws = P->ws;
-        P->params.epoch_span = (unsigned)(6 * (int64_t)maxit + 4 * PERKS_MIXED_MAX_OUTER + 64);
+        const int64_t span = 6 * (int64_t)maxit + 4 * PERKS_MIXED_MAX_OUTER + 64;
+        if (S.groups >= SYNC_MAX_WGS || (S.groups + 2) * span >= (int64_t(1) << 31)) {
+            rc = set_error(PERKS_E_UNSUPPORTED, "batch too large for the barrier epoch range (%d groups)", S.groups);
+            break;
+        }
+        P->params.epoch_span = (unsigned)span;
+        P->params.ngroups = S.groups;
         // the launch as a graph node with the cooperative attribute (falls back
         // to a direct cooperative launch per run if the runtime refuses it)
         hipKernelNodeParams kp{};
@@ -1482,11 +1627,12 @@ int perks_cg_batch_run(perks_cg_batch *P, void *stream) {
     if (P->count == 0) return PERKS_OK;
     // barrier epochs are 32-bit: start again from zeroed words well before
     // they could wrap (a fill kernel, so the reset is stream-ordered)
-    P->epochs_used += P->params.epoch_span + 2;
+    const uint64_t per_run = (uint64_t)(P->params.ngroups + 1) * P->params.epoch_span + 2;
+    P->epochs_used += per_run;
     if (P->epochs_used > (uint64_t(1) << 31)) {
         hipLaunchKernelGGL(zero_words, dim3((SYNC_BYTES / 4 + 255) / 256), dim3(256), 0, st, P->ws,
                            (int)(SYNC_BYTES / 4));
-        P->epochs_used = P->params.epoch_span + 2;
+        P->epochs_used = per_run;
     }
     if (P->exec) {
         PERKS_HIP_TRY(hipGraphLaunch(P->exec, st));

@@ -2,6 +2,10 @@
 // (tile depth, grid size, cached vs streamed tiles) and kernel dispatch.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "common.hpp"
 #include "stencil_api.hpp"
@@ -51,6 +55,37 @@ int check_common(const void *grid, const double *coeffs, const perks_shape &s, i
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Tunings the autotuner chose, per (device, pattern, dtype, extents); used by
+// perks_stencil_run when the caller passes no tuning.
+using TuneKey = std::tuple<int, int, int, int64_t, int64_t, int64_t>;
+std::mutex g_tune_mu;
+std::map<TuneKey, perks_tuning> g_tuned;
+
+TuneKey tune_key(Kind kind, perks_dtype dt, const perks_shape &s) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    return TuneKey(dev, (int)kind, (int)dt, s.nx, s.ny, s.ndim == 3 ? s.nz : 1);
+}
+
+bool tuned_for(Kind kind, perks_dtype dt, const perks_shape &s, perks_tuning *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(kind, dt, s));
+    if (it == g_tuned.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int64_t steps, perks_dtype dt,
+                 Kind kind, hipStream_t st, const perks_tuning *tune) {
+    if (shape.ndim == 2) {
+        const bool box = kind == K_2D9;
+        return dt == PERKS_F64 ? run2d<double>((double *)grid, coeffs, shape, steps, box, st, tune)
+                               : run2d<float>((float *)grid, coeffs, shape, steps, box, st, tune);
+    }
+    return dt == PERKS_F64 ? run3d<double>((double *)grid, coeffs, shape, steps, st, tune)
+                           : run3d<float>((float *)grid, coeffs, shape, steps, st, tune);
+}
+
 }  // namespace
 }  // namespace perks
 
@@ -66,14 +101,9 @@ int perks_stencil_run(void *grid, const double *coeffs, perks_shape shape, int64
     rc = classify(coeffs, shape, &kind);
     if (rc) return rc;
     if (steps == 0) return PERKS_OK;
-    hipStream_t st = as_stream(stream);
-    if (shape.ndim == 2) {
-        const bool box = kind == K_2D9;
-        return dt == PERKS_F64 ? run2d<double>((double *)grid, coeffs, shape, steps, box, st, tune)
-                               : run2d<float>((float *)grid, coeffs, shape, steps, box, st, tune);
-    }
-    return dt == PERKS_F64 ? run3d<double>((double *)grid, coeffs, shape, steps, st, tune)
-                           : run3d<float>((float *)grid, coeffs, shape, steps, st, tune);
+    perks_tuning remembered;
+    if (!tune && tuned_for(kind, dt, shape, &remembered)) tune = &remembered;
+    return run_dispatch(grid, coeffs, shape, steps, dt, kind, as_stream(stream), tune);
 }
 
 int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape shape, int64_t steps, perks_dtype dt,
@@ -110,6 +140,109 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
         return dt == PERKS_F64 ? plan2d_query<double>(shape, kind == K_2D9, tune, plan)
                                : plan2d_query<float>(shape, kind == K_2D9, tune, plan);
     return dt == PERKS_F64 ? plan3d_query<double>(shape, tune, plan) : plan3d_query<float>(shape, tune, plan);
+}
+
+int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int32_t count, const double *coeffs,
+                              int64_t steps, perks_dtype dt, void *stream) {
+    if (count < 0) return set_error(PERKS_E_INVAL, "count must be >= 0");
+    if (count == 0) return PERKS_OK;
+    if (!grids || !shapes) return set_error(PERKS_E_INVAL, "grids and shapes must not be NULL");
+    Kind kind = K_2D5;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_common(grids[i], coeffs, shapes[i], steps, dt);
+        if (rc) return set_error(rc, "grid %d: %s", i, last_error());
+        if (shapes[i].ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "batched stencils are 2D");
+        rc = classify(coeffs, shapes[i], &kind);
+        if (rc) return rc;
+    }
+    if (steps == 0) return PERKS_OK;
+    const bool box = kind == K_2D9;
+    hipStream_t st = as_stream(stream);
+    return dt == PERKS_F64
+               ? run2d_batched<double>(reinterpret_cast<double *const *>(grids), shapes, count, coeffs, steps, box, st)
+               : run2d_batched<float>(reinterpret_cast<float *const *>(grids), shapes, count, coeffs, steps, box, st);
+}
+
+int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype dt, int64_t probe_steps,
+                           int32_t remember, void *stream, perks_tuning *best, double *best_gcells) {
+    int dummy = 0;
+    int rc = check_common(&dummy, coeffs, shape, 1, dt);
+    if (rc) return rc;
+    if (!best) return set_error(PERKS_E_INVAL, "best must not be NULL");
+    if (probe_steps < 1) return set_error(PERKS_E_INVAL, "probe_steps must be >= 1");
+    Kind kind;
+    rc = classify(coeffs, shape, &kind);
+    if (rc) return rc;
+    // candidates: the planner's own choice and every forced depth, in each
+    // synchronisation mode the kernels offer
+    std::vector<perks_tuning> cands;
+    auto add = [&](int rows, int planes, int sync) {
+        perks_tuning t{};
+        t.rows_per_lane = rows;
+        t.planes_per_lane = planes;
+        t.sync = sync;
+        perks_stencil_plan pl;
+        if (perks_stencil_plan_query(coeffs, shape, dt, &t, &pl) == PERKS_OK) cands.push_back(t);
+    };
+    if (shape.ndim == 2) {
+        for (int sync : {2, 1}) {
+            add(0, 0, sync);
+            for (int r : {8, 16, 32, 48, 64}) add(r, 0, sync);
+        }
+    } else {
+        add(0, 0, 0);
+        for (int pz : {4, 8, 16}) add(4, pz, 0);
+    }
+    if (cands.empty()) return set_error(PERKS_E_UNSUPPORTED, "no candidate plan for this stencil");
+    hipStream_t st = as_stream(stream);
+    const int64_t cells = shape.nx * shape.ny * (shape.ndim == 3 ? shape.nz : 1);
+    const size_t bytes = (size_t)cells * (dt == PERKS_F64 ? 8 : 4);
+    void *g = nullptr;
+    if (hipMalloc(&g, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(PERKS_E_NOMEM, "autotune: hipMalloc of %zu bytes failed", bytes);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best_t = INFINITY;
+    int best_i = -1;
+    rc = PERKS_OK;
+    do {
+        if (hipMemsetAsync(g, 0, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            rc = set_error(PERKS_E_HIP, "autotune: event or memset failed");
+            break;
+        }
+        for (size_t i = 0; i < cands.size(); ++i) {
+            rc = run_dispatch(g, coeffs, shape, std::max<int64_t>(1, probe_steps / 4), dt, kind, st, &cands[i]);
+            if (rc) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = set_error(PERKS_E_HIP, "autotune: event record"); break; }
+            rc = run_dispatch(g, coeffs, shape, probe_steps, dt, kind, st, &cands[i]);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = set_error(PERKS_E_HIP, "autotune: timing failed");
+                break;
+            }
+            if (ms < best_t) {
+                best_t = ms;
+                best_i = (int)i;
+            }
+        }
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(g);
+    if (rc) return rc;
+    *best = cands[best_i];
+    const int64_t interior = (shape.nx - 2) * (shape.ny - 2) * (shape.ndim == 3 ? shape.nz - 2 : 1);
+    if (best_gcells) *best_gcells = (double)interior * probe_steps / (best_t * 1e-3) / 1e9;
+    if (remember) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(kind, dt, shape)] = *best;
+    }
+    return PERKS_OK;
 }
 
 }  // extern "C"

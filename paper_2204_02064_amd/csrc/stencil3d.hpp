@@ -29,7 +29,7 @@ template <typename T, int RY, int RZ>
 struct Halo3D {
     T xw[RZ * RY], xe[RZ * RY];   // west / east face, [iz][iy]
     T ym[RZ * 64], yp[RZ * 64];   // south / north face (y-1 / y+hy), [iz][lane]
-    T zm[RY * 64], zp[RY * 64];   // below / above face (z-1 / z+dz), [iy][lane]
+    T zp[RY * 64];                // above face (z+dz), [iy][lane]; the face below is read directly
 };
 
 // One Jacobi step of one z-plane of a lane's block, in place.
@@ -139,23 +139,48 @@ __device__ __forceinline__ void load_halo3(const Stencil3DParams<T> &p, const Ti
             h.xe[j] = ld_coh(e + o);
         }
     }
+    // y and z faces: four rows of loads in flight at a time (all of them at
+    // once would hold 2 (RZ + RY) values per lane in registers next to the
+    // cached block)
     const T *ys = yf(p, par, 2 * tl.ty), *yn = yf(p, par, 2 * tl.ty + 3);
+#pragma unroll 1
+    for (int iz = 0; iz < RZ; iz += 4) {
+        T a[4], b[4];
 #pragma unroll
-    for (int iz = 0; iz < RZ; ++iz) {
-        if (iz < tl.dz) {
-            const size_t o = (size_t)(tl.z0 + iz) * p.nx + xl;
-            h.ym[iz * 64 + lane] = ld_coh(ys + o);
-            h.yp[iz * 64 + lane] = ld_coh(yn + o);
+        for (int u = 0; u < 4; ++u) {
+            if (iz + u < tl.dz) {
+                const size_t o = (size_t)(tl.z0 + iz + u) * p.nx + xl;
+                a[u] = ld_coh(ys + o);
+                b[u] = ld_coh(yn + o);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (iz + u < tl.dz) {
+                h.ym[(iz + u) * 64 + lane] = a[u];
+                h.yp[(iz + u) * 64 + lane] = b[u];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     const T *zb = zf(p, par, 2 * tl.tz), *zt = zf(p, par, 2 * tl.tz + 3);
+#pragma unroll 1
+    for (int iy = 0; iy < RY; iy += 4) {
+        T a[4], b[4];
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) {
-        if (iy < tl.hy) {
-            const size_t o = (size_t)(tl.y0 + iy) * p.nx + xl;
-            h.zm[iy * 64 + lane] = ld_coh(zb + o);
-            h.zp[iy * 64 + lane] = ld_coh(zt + o);
+        for (int u = 0; u < 4; ++u) {
+            if (iy + u < tl.hy) {
+                const size_t o = (size_t)(tl.y0 + iy + u) * p.nx + xl;
+                b[u] = ld_coh(zt + o);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (iy + u < tl.hy) {
+                h.zp[(iy + u) * 64 + lane] = b[u];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     compiler_fence();
 }
@@ -164,6 +189,7 @@ __device__ __forceinline__ void load_halo3(const Stencil3DParams<T> &p, const Ti
 template <typename T, int RY>
 __device__ __forceinline__ void publish_plane(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
                                               const T (&u)[RY], int iz, T last) {
+
     const bool in = lane < tl.wx;
     const int z = tl.z0 + iz;
     T *left = xf(p, par, 2 * tl.tx + 1) + (size_t)z * p.ny + tl.y0;
@@ -248,8 +274,10 @@ template <typename T, int RY, int RZ, bool FULL>
 __device__ __forceinline__ void planes_cached3(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
                                                T (&v)[RZ][RY], Halo3D<T, RY, RZ> &h) {
     T part[RY];
+    const int xl = min(tl.x0 + lane, p.nx - 1);
+    const T *zb = zf(p, par, 2 * tl.tz) + (size_t)tl.y0 * p.nx + xl;
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) part[iy] = p.W.zm * h.zm[iy * 64 + lane];
+    for (int iy = 0; iy < RY; ++iy) part[iy] = p.W.zm * ((FULL || iy < tl.hy) ? ld_coh(zb + (size_t)iy * p.nx) : T(0));
 #pragma unroll
     for (int iz = 0; iz < RZ; ++iz) {
         if (FULL || iz < tl.dz) {
@@ -300,7 +328,7 @@ __device__ __forceinline__ void step_streamed3(const Stencil3DParams<T> &p, cons
     T cur[RY], nxt[RY], part[RY];
 #pragma unroll
     for (int iy = 0; iy < RY; ++iy) {
-        part[iy] = p.W.zm * h.zm[iy * 64 + lane];
+        part[iy] = p.W.zm * ((iy < tl.hy) ? ld_coh(zf(p, par, 2 * tl.tz) + (size_t)(tl.y0 + iy) * p.nx + xl) : T(0));
         cur[iy] = (iy < tl.hy) ? (ghost ? h.xe[iy] : p.grid[((size_t)tl.z0 * ny + tl.y0 + iy) * nx + xl]) : T(0);
     }
     for (int iz = 0; iz < tl.dz; ++iz) {
@@ -436,26 +464,32 @@ __global__ __launch_bounds__(WAVES * 64) void stencil3d_step(Stencil3DParams<T> 
 
 // ---------------------------------------------------------------------------
 // Host planning / launch (3D).
-constexpr int W3 = 8;     // waves per workgroup, persistent
 constexpr int W3B = 4;    // waves per workgroup, baseline
 constexpr int RYB = 4, RZB = 8;
 
+// Tile shapes (rows x planes per lane) and the waves per workgroup each runs
+// with.  The deepest tile (4 x 16) fits the register file without spilling
+// only in FP32.
 struct Tile3Shape {
-    int ry, rz;
+    int ry, rz, waves;
 };
 template <typename T> struct R3List;
-template <> struct R3List<double> { static constexpr Tile3Shape v[2] = {{4, 4}, {4, 8}}; };
-template <> struct R3List<float> { static constexpr Tile3Shape v[2] = {{4, 4}, {4, 8}}; };
+template <> struct R3List<double> { static constexpr Tile3Shape v[2] = {{4, 4, 8}, {4, 8, 8}}; };
+template <> struct R3List<float> { static constexpr Tile3Shape v[3] = {{4, 4, 8}, {4, 8, 8}, {4, 16, 8}}; };
 
 template <typename T>
-const void *pick3d(int ry, int rz) {
-    if (ry == 4 && rz == 4) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 4, W3>);
-    if (ry == 4 && rz == 8) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 8, W3>);
+const void *pick3d(int ry, int rz, int waves) {
+    if (waves != 8 || ry != 4) return nullptr;
+    if (rz == 4) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 4, 8>);
+    if (rz == 8) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 8, 8>);
+    if constexpr (sizeof(T) == 4) {
+        if (rz == 16) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 16, 8>);
+    }
     return nullptr;
 }
 
 struct Plan3D {
-    int ry = 0, rz = 0, wgs = 0, ntx = 0, nty = 0, ntz = 0, last_w = 0, last_h = 0, last_d = 0, ntiles = 0,
+    int ry = 0, rz = 0, waves = 0, wgs = 0, ntx = 0, nty = 0, ntz = 0, last_w = 0, last_h = 0, last_d = 0, ntiles = 0,
         cached = 0;
     const void *fn = nullptr;
 };
@@ -470,29 +504,36 @@ int plan3d(const perks_shape &s, const perks_tuning *tu, Plan3D *pl) {
     pl->last_w = (int)(nxi - 64 * (pl->ntx - 1));
     const int want_ry = tu ? tu->rows_per_lane : 0, want_rz = tu ? tu->planes_per_lane : 0;
     const int wgs_per_cu = (tu && tu->wgs_per_cu > 0) ? tu->wgs_per_cu : 1;
-    if (tu && tu->waves_per_wg != 0 && tu->waves_per_wg != W3)
-        return set_error(PERKS_E_UNSUPPORTED, "3D persistent kernels use %d waves per workgroup", W3);
-    const long long cap = (long long)f.cus * wgs_per_cu * W3;
-    Tile3Shape chosen{0, 0};
+    const int want_waves = tu ? tu->waves_per_wg : 0;
+    Tile3Shape chosen{0, 0, 0};
+    long long cap = 0;
     for (Tile3Shape sh : R3List<T>::v) {
-        const void *fn = pick3d<T>(sh.ry, sh.rz);
+        if (want_waves && want_waves != sh.waves) continue;
+        const void *fn = pick3d<T>(sh.ry, sh.rz, sh.waves);
         int occ = 0;
-        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, W3 * 64, 0) != hipSuccess ||
+        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, sh.waves * 64, 0) != hipSuccess ||
             occ < wgs_per_cu)
             continue;
+        const long long c = (long long)f.cus * wgs_per_cu * sh.waves;
         const long long nt = pl->ntx * ((nyi + sh.ry - 1) / sh.ry) * ((nzi + sh.rz - 1) / sh.rz);
         if (want_ry || want_rz) {
-            if ((!want_ry || want_ry == sh.ry) && (!want_rz || want_rz == sh.rz)) chosen = sh;
-        } else if (nt <= cap) {
+            if ((!want_ry || want_ry == sh.ry) && (!want_rz || want_rz == sh.rz)) {
+                chosen = sh;
+                cap = c;
+            }
+        } else if (nt <= c) {
             chosen = sh;
+            cap = c;
             break;
         } else {
             chosen = sh;
+            cap = c;
         }
     }
     if (!chosen.ry) return set_error(PERKS_E_UNSUPPORTED, "no 3D tile shape matches the request");
     pl->ry = chosen.ry;
     pl->rz = chosen.rz;
+    pl->waves = chosen.waves;
     pl->nty = (int)((nyi + chosen.ry - 1) / chosen.ry);
     pl->ntz = (int)((nzi + chosen.rz - 1) / chosen.rz);
     pl->last_h = (int)(nyi - (long long)chosen.ry * (pl->nty - 1));
@@ -505,8 +546,8 @@ int plan3d(const perks_shape &s, const perks_tuning *tu, Plan3D *pl) {
     if (tu && tu->max_cached_tiles > 0) cached = std::min<long long>(cached, tu->max_cached_tiles);
     pl->cached = (int)cached;
     const long long waves = std::min<long long>(nt, cap);
-    pl->wgs = (int)((waves + W3 - 1) / W3);
-    pl->fn = pick3d<T>(chosen.ry, chosen.rz);
+    pl->wgs = (int)((waves + chosen.waves - 1) / chosen.waves);
+    pl->fn = pick3d<T>(chosen.ry, chosen.rz, chosen.waves);
     return PERKS_OK;
 }
 
@@ -561,7 +602,7 @@ int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hi
     p.yface = faces + fx;
     p.zface = faces + fx + fy;
     p.sync = sync;
-    return launch_coop(pl.fn, pl.wgs, W3 * 64, &p, st);
+    return launch_coop(pl.fn, pl.wgs, pl.waves * 64, &p, st);
 }
 
 template <typename T>
@@ -606,7 +647,7 @@ int plan3d_query(const perks_shape &s, const perks_tuning *tu, perks_stencil_pla
     int rc = plan3d<T>(s, tu, &pl);
     if (rc) return rc;
     plan->wgs = pl.wgs;
-    plan->waves_per_wg = W3;
+    plan->waves_per_wg = pl.waves;
     plan->rows_per_lane = pl.ry;
     plan->planes_per_lane = pl.rz;
     plan->tiles = pl.ntiles;

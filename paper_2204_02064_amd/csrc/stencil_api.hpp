@@ -15,6 +15,9 @@ template <typename T>
 int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan);
 
 template <typename T>
+int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                  bool box, hipStream_t st);
+template <typename T>
 int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st,
           const perks_tuning *tu);
 template <typename T>

@@ -2,12 +2,12 @@
 solver-side capture of training pairs.
 
 FCG without a network is Jacobi-preconditioned CG: parity with the oracle's
-PCG (true residual within tol, iteration count within max(2, 2%)).  With a
-network that is the identity (up to the bf16 rounding of its input) FCG is
-CG: iteration count close to the oracle's FCG with the same network in bf16
-emulation.  A network that always fails (<z, r> < 0) falls back to the
-Jacobi step on every iteration.  A capture of x_k equals the iterate of a
-solve stopped after k iterations, bit for bit.
+PCG (true residual within tol, iteration count within max(2, 2%)).  A network
+that is the identity in exact arithmetic sees its input rounded to bf16, so
+FCG then matches the oracle's FCG with the same bf16 rounding (iteration
+count within max(3, 5%)), not exact CG.  A network that always fails
+(<z, r> < 0) falls back to the Jacobi step on every iteration.  A capture of
+x_k equals the iterate of a solve stopped after k iterations, bit for bit.
 """
 import math
 
@@ -66,7 +66,11 @@ def test_fcg_without_network_is_jacobi_pcg(pk, n, seed):
 
 
 @pytest.mark.parametrize("n", [20, 48])
-def test_fcg_with_identity_network_is_cg(pk, n):
+def test_fcg_with_identity_network_matches_oracle(pk, n):
+    """The identity network sees its input rounded to bf16, so it is the
+    identity only up to a relative 2^-9 per component and FCG takes more
+    steps than exact CG; the oracle's FCG with the same bf16 rounding is the
+    reference."""
     rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=5)
     layers = _identity_layers()
     params = to_dev(pk.nn_pack_params(layers))
@@ -76,9 +80,7 @@ def test_fcg_with_identity_network_is_cg(pk, n):
     assert info["status"] == "converged" and info["fallbacks"] == 0
     _, oi = ofcg.fcg(rp, ci, v, f, lambda r: onn.apply_preconditioner(layers, r.reshape(n, n), lk, bf16=True).ravel(),
                      tol=1e-9, stall=50)
-    _, ci_ = oracle.cg(rp, ci, v, f, tol=1e-9)
     assert abs(info["iters"] - oi["iters"]) <= max(3, math.ceil(0.05 * oi["iters"]))
-    assert abs(info["iters"] - ci_["iters"]) <= max(3, math.ceil(0.05 * ci_["iters"]))
     assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-9 * 1.001
 
 

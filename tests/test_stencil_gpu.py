@@ -192,3 +192,78 @@ def test_plan_reports_cached_share(pk):
     pl = pk.stencil_plan((3072, 3072), workloads.stencil_weights("2d5pt"), "float64")
     assert pl["tiles"] >= pl["cached_tiles"] > 0
     assert pl["interior_cells"] == 3070 * 3070
+
+
+@pytest.mark.parametrize("dtype,planes", [("float64", 4), ("float64", 8), ("float32", 4), ("float32", 8),
+                                          ("float32", 16)])
+def test_3d_tile_depths_match_baseline_bitwise(pk, dtype, planes):
+    """Every 3D tile shape (ragged in y and z, streamed and cached tiles) gives
+    the baseline's bits and the oracle's values."""
+    shape = (37, 23, 130)
+    g = workloads.stencil_grid(shape, seed=21)
+    w = workloads.stencil_weights("3d7pt")
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    if dtype == "float32":
+        g = g.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    a = _run(pk, g, w, 9, tdt, tuning={"planes_per_lane": planes})
+    c = _run(pk, g, w, 9, tdt, tuning={"planes_per_lane": planes, "max_cached_tiles": 7})
+    b = _run(pk, g, w, 9, tdt, baseline=True)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(c, b)
+    assert rel_err(a, oracle.stencil(g, w, 9)) <= (1e-12 if dtype == "float64" else 1e-5)
+    plan = pk.stencil_plan(shape, w, dtype, tuning={"planes_per_lane": planes})
+    assert plan["planes_per_lane"] == planes
+
+
+@pytest.mark.parametrize("kind,shape,dtype", [("2d5pt", (300, 520), "float64"), ("2d9pt", (257, 190), "float32"),
+                                              ("3d7pt", (40, 45, 130), "float32")])
+def test_autotune_returns_a_valid_plan_and_untuned_runs_use_it(pk, kind, shape, dtype):
+    w = workloads.stencil_weights(kind)
+    tuning, rate = pk.stencil_autotune(shape, w, dtype, probe_steps=8, remember=True)
+    assert rate > 0
+    plan = pk.stencil_plan(shape, w, dtype, tuning=tuning)
+    assert plan["tiles"] > 0
+    g = workloads.stencil_grid(shape, seed=31)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    if dtype == "float32":
+        g = g.astype(np.float32).astype(np.float64)
+    remembered = _run(pk, g, w, 7, tdt)                  # untuned: uses the remembered plan
+    explicit = _run(pk, g, w, 7, tdt, tuning=tuning)
+    base = _run(pk, g, w, 7, tdt, baseline=True)
+    np.testing.assert_array_equal(remembered, explicit)
+    np.testing.assert_array_equal(remembered, base)
+
+
+@pytest.mark.parametrize("kind,dtype", [("2d5pt", "float64"), ("2d9pt", "float32"), ("2d5pt", "float32")])
+def test_batched_grids_equal_single_runs_bitwise(pk, kind, dtype):
+    """Uneven grids (including a one-tile grid and ragged tiles) in one launch
+    give exactly the bits of one launch per grid and the oracle's values."""
+    shapes = [(66, 130), (5, 7), (257, 190), (40, 64), (129, 300), (18, 33)]
+    w = workloads.stencil_weights(kind)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    if dtype == "float32":
+        w = w.astype(np.float32).astype(np.float64)
+    grids_np = []
+    for j, sh in enumerate(shapes):
+        g = workloads.stencil_grid(sh, seed=40 + j, ring_value=0.25 * j)
+        grids_np.append(g.astype(np.float32).astype(np.float64) if dtype == "float32" else g)
+    devs = [to_dev(g, tdt) for g in grids_np]
+    pk.stencil_run_batched(devs, w, 17)
+    torch.cuda.synchronize()
+    for g, d in zip(grids_np, devs):
+        single = _run(pk, g, w, 17, tdt)
+        got = d.cpu().double().numpy()
+        np.testing.assert_array_equal(got, single)
+        assert rel_err(got, oracle.stencil(g, w, 17)) <= (1e-12 if dtype == "float64" else 1e-5)
+
+
+def test_batched_many_small_grids(pk):
+    sides = workloads.lognormal_sides(64, lo=16, hi=96, seed=5)
+    w = workloads.stencil_weights("2d5pt")
+    grids_np = [workloads.stencil_grid((int(s), int(s) + 3), seed=int(s)) for s in sides]
+    devs = [to_dev(g) for g in grids_np]
+    pk.stencil_run_batched(devs, w, 25)
+    torch.cuda.synchronize()
+    for g, d in zip(grids_np[:8], devs[:8]):
+        assert rel_err(d.cpu().numpy(), oracle.stencil(g, w, 25)) <= 1e-12
