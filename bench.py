@@ -203,18 +203,22 @@ def bench_learned(pk, torch, args):
     n_train = args.nn_fields
     t0 = time.perf_counter()
     probs = [workloads.diffusion_problem_torch(256, seed=s) for s in range(n_train)]
-    X, T = learned.harvest_pairs(probs)
+    planes = torch.stack([workloads.diffusion_planes_torch(torch.exp(workloads.grf_log_k_torch(256, seed=s)))
+                          for s in range(n_train)]).to(torch.float32)
+    X, T, field = learned.harvest_pairs(probs, with_field=True)
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     del probs
     t0 = time.perf_counter()
-    params, losses = learned.train(X, T, epochs=args.nn_epochs, batch=16, lr=1e-3, seed=0)
+    params, losses = learned.train(X, T, epochs=args.nn_epochs, batch=16, lr=1e-3, seed=0, planes=planes,
+                                   field=field)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     rec = {"train_fields": n_train, "pairs": int(X.shape[0]), "harvest_s": t_harvest, "train_s": t_train,
+           "loss": "energy norm of the output error (||z - e||_A^2 up to a constant)",
            "epochs": args.nn_epochs, "loss_first": float(np.mean(losses[:20])),
            "loss_last": float(np.mean(losses[-20:])), "eval": []}
-    del X, T
+    del X, T, planes
     log(f"learned: {rec['pairs']} pairs from {n_train} fields in {t_harvest:.1f} s; trained {len(losses)} steps "
         f"in {t_train:.1f} s, loss {rec['loss_first']:.3e} -> {rec['loss_last']:.3e}")
     for n in (256, 512, 1024):

@@ -309,6 +309,16 @@ int perks_nn_forward(const float *params, const float *x, int32_t B, int32_t H, 
 int perks_nn_loss_grad(const float *params, const float *x, const float *target, int32_t B, int32_t H,
                        int32_t W, float *grad, double *loss, void *stream);
 
+/* Energy-norm loss instead of the MSE: with r = x[..][0] (the scaled
+ * residual input) and A the 5-point operator of each sample given per pixel
+ * as five planes (device floats [B][5][H][W]: weights of (y-1), (x-1),
+ * centre, (x+1), (y+1), zero for neighbours outside the grid), the loss is
+ * sum (z'Az - 2 z'r) / (B*H*W) over the samples' outputs z: the A-norm error
+ * ||z - e||_A^2 of the output up to the constant e'r, for r = A e.  Same
+ * requirements and outputs as perks_nn_loss_grad. */
+int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t B, int32_t H,
+                         int32_t W, float *grad, double *loss, void *stream);
+
 /* One Adam step with bias correction (step counts from 1) on the FP32
  * master weights; m and v (device, PERKS_NN_PARAMS floats) start at zero. */
 int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr,

@@ -153,3 +153,44 @@ def apply_preconditioner(params, r, log_k, bf16=False):
     x = np.stack([np.asarray(r, dtype=np.float64) / s, np.asarray(log_k, dtype=np.float64)])
     out, _ = forward(params, x, bf16)
     return s * out[0]
+
+
+# ---------------------------------------------------------------------------
+# Energy-norm training loss.  For a residual r = A e (e the error of an
+# iterate), the preconditioner output z is judged by its error in the A-norm,
+#     ||z - e||_A^2 = z'Az - 2 z'r + e'r,
+# the quantity a CG step minimises.  Dropping the constant e'r gives the
+# functional  L(z) = (z'Az - 2 z'r) / (pixels), with gradient 2 (Az - r) /
+# (pixels); it needs A and r but not e.  r here is the network's first input
+# channel (the scaled residual), so L is scale-consistent with the output.
+# A is the 5-point operator of the diffusion problem, given per pixel as five
+# planes [S, W, C, E, N] (weights of (y-1), (x-1), centre, (x+1), (y+1); zero
+# where the neighbour is outside the grid).
+
+def apply_5pt(planes, z):
+    """y = A z for A given as five coefficient planes [5, H, W]."""
+    s, w, c, e, n = (np.asarray(p, dtype=np.float64) for p in planes)
+    z = np.asarray(z, dtype=np.float64)
+    y = c * z
+    y[1:, :] += s[1:, :] * z[:-1, :]
+    y[:, 1:] += w[:, 1:] * z[:, :-1]
+    y[:, :-1] += e[:, :-1] * z[:, 1:]
+    y[:-1, :] += n[:-1, :] * z[1:, :]
+    return y
+
+
+def energy_loss_and_grads(params, inputs, planes, bf16=False):
+    """sum over samples of (z'Az - 2 z'r), divided by the total pixel count,
+    and its gradients; r = inputs[j][0], z the network output."""
+    count = sum(x.shape[1] * x.shape[2] for x in inputs)
+    total = 0.0
+    acc = [(np.zeros(w.shape), np.zeros(b.shape)) for w, b in params]
+    for x, pl in zip(inputs, planes):
+        out, cache = forward(params, x, bf16)
+        z = out[0]
+        r = np.asarray(x[0], dtype=np.float64)
+        az = apply_5pt(pl, z)
+        total += float(np.sum(z * az) - 2.0 * np.sum(z * r))
+        grads, _ = backward(cache, (2.0 * (az - r) / count)[None])
+        acc = [(aw + gw, ab + gb) for (aw, ab), (gw, gb) in zip(acc, grads)]
+    return total / count, acc

@@ -114,7 +114,8 @@ def lib():
     L.perks_nn_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.perks_nn_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, vp]
-    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam"):
+    L.perks_nn_energy_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
+    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("perks_stencil_run", "perks_stencil_run_baseline", "perks_stencil_plan_query",
                  "perks_device_query", "perks_cg_solve", "perks_cg_solve_baseline", "perks_cg_batch_create",
@@ -451,6 +452,23 @@ def nn_loss_grad(params, x, target, grad=None, stream=None):
     _check(lib().perks_nn_loss_grad(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                     ctypes.c_void_p(target.data_ptr()), B, H, W, ctypes.c_void_p(grad.data_ptr()),
                                     ctypes.byref(loss), _stream_handle(stream)))
+    return loss.value, grad
+
+
+def nn_energy_grad(params, x, planes, grad=None, stream=None):
+    """(loss, grad) of the energy-norm loss: planes [B, 5, H, W] float32 hold
+    each sample's 5-point operator, x[..., 0] the scaled residual."""
+    import torch
+    B, H, W, _ = x.shape
+    _check_f32(params, NN_PARAMS, "params")
+    _check_f32(x, B * H * W * 2, "x")
+    _check_f32(planes, B * 5 * H * W, "planes")
+    if grad is None:
+        grad = torch.empty(NN_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double()
+    _check(lib().perks_nn_energy_grad(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(planes.data_ptr()), B, H, W, ctypes.c_void_p(grad.data_ptr()),
+                                      ctypes.byref(loss), _stream_handle(stream)))
     return loss.value, grad
 
 

@@ -11,9 +11,9 @@
 // reached a new minimum for `stall` iterations the solve continues as
 // Jacobi-preconditioned CG for good (the direction recurrence restarts).
 //
-// Per iteration, four device-wide barriers: after z and its dot products,
-// after the new direction, after q = A p and its dot products, after the
-// x / r update and ||r||.  The network runs inside the kernel: each workgroup
+// Per iteration, three device-wide barriers: after z and its dot products,
+// after q = A p (the new direction formed on the fly where it is gathered)
+// and its dot products, after the x / r update and ||r||.  The network runs inside the kernel: each workgroup
 // owns 16 x 16 tiles of the grid and computes all six layers of a tile in
 // LDS from a 28 x 28 region of r and log k (a halo of one pixel per layer,
 // recomputed instead of exchanged), on the matrix cores, so the network adds
@@ -45,7 +45,7 @@ struct FcgParams {
     const double *val;
     const double *b;
     double *x;
-    double *r, *z, *p, *q, *dinv;
+    double *r, *z, *p, *p1, *q, *dinv;   // p, p1: the direction, alternating by iteration
     const double *logk;
     const unsigned short *wf;   // packed forward fragments, NL x 5 x 64 x 8 bf16
     const float *bias;          // NL x 16
@@ -120,7 +120,7 @@ __device__ void net_tile(const FcgParams &p, int tx0, int ty0, double rms, doubl
                 st.y = (unsigned)to_bf16(o[2]) | ((unsigned)to_bf16(o[3]) << 16);
                 *reinterpret_cast<uint2 *>(bout + (row * sout + col) * NC + 4 * g) = st;
             } else if (g == 0 && inside) {
-                p.z[(size_t)gy * p.W + gx] = rms * (double)(acc[0] + bz[0]);
+                st_coh(p.z + (size_t)gy * p.W + gx, rms * (double)(acc[0] + bz[0]));   // gathered by others
             }
         }
         __syncthreads();
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
                 net_tile(p, (t % p.ntx) * FT, (t / p.ntx) * FT, rms, 1.0 / rms);
             }
         } else {
-            for_own([&](int i) { p.z[i] = p.dinv[i] * p.r[i]; });
+            for_own([&](int i) { st_coh(p.z + i, p.dinv[i] * p.r[i]); });
         }
         __syncthreads();
         double a1[2] = {0.0, 0.0};
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
             double a2[2] = {0.0, 0.0};
             for_own([&](int i) {
                 const double zi = p.dinv[i] * p.r[i];
-                p.z[i] = zi;
+                st_coh(p.z + i, zi);
                 a2[0] = __builtin_fma(zi, p.r[i], a2[0]);
                 a2[1] = __builtin_fma(zi, p.q[i], a2[1]);
             });
@@ -216,17 +216,23 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
             zr = grid_total(p.part, FP_ZR, G, &cg_bcast_fcg);
             zq = grid_total(p.part, FP_ZQ, G, &cg_bcast_fcg);
         }
-        // new direction, A-orthogonal to the previous one
+        // new direction p = z - beta p_old, A-orthogonal to the previous one,
+        // formed on the fly where q = A p gathers it (no barrier of its own):
+        // p alternates between two buffers so p_old stays intact until every
+        // workgroup has gathered it; own rows of p are stored.
         const double beta = have_dir ? zq / pq_old : 0.0;
-        for_own([&](int i) { st_coh(p.p + i, have_dir ? __builtin_fma(-beta, p.p[i], p.z[i]) : p.z[i]); });
-        gs.sync<true>();
-        // q = A p, <p, q>, <p, r>
+        double *pn = (k & 1) ? p.p1 : p.p;
+        const double *po = (k & 1) ? p.p : p.p1;
+        auto pval = [&](int c) { return have_dir ? __builtin_fma(-beta, po[c], p.z[c]) : p.z[c]; };
         double a3[2] = {0.0, 0.0};
         for_own([&](int i) {
-            const double s = row_dot(i, p.p);
+            double s = 0.0;
+            for (int kk = p.rowptr[i]; kk < p.rowptr[i + 1]; ++kk) s = __builtin_fma(p.val[kk], pval(p.colind[kk]), s);
+            const double pi = pval(i);
+            st_coh(pn + i, pi);
             p.q[i] = s;
-            a3[0] = __builtin_fma(p.p[i], s, a3[0]);
-            a3[1] = __builtin_fma(p.p[i], p.r[i], a3[1]);
+            a3[0] = __builtin_fma(pi, s, a3[0]);
+            a3[1] = __builtin_fma(pi, p.r[i], a3[1]);
         });
         post(a3, FP_PQ, FP_PR);
         gs.sync<true>();
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
         const double alpha = pr / pq;
         double a4[2] = {0.0, 0.0};
         for_own([&](int i) {
-            st_coh(p.x + i, __builtin_fma(alpha, p.p[i], p.x[i]));
+            st_coh(p.x + i, __builtin_fma(alpha, pn[i], p.x[i]));
             const double ri = __builtin_fma(-alpha, p.q[i], p.r[i]);
             st_coh(p.r + i, ri);
             a4[0] = __builtin_fma(ri, ri, a4[0]);
@@ -313,7 +319,7 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     const int G = std::min(std::min(f.cus, SYNC_MAX_WGS), p.ntx * p.nty);
     const size_t nv = ((size_t)A->n + 63) / 64 * 64;
     const size_t frag = (size_t)NL * 5 * 64 * 8 * sizeof(unsigned short);
-    const size_t bytes = 5 * nv * sizeof(double) + ((size_t)FNPART * G + 64) * sizeof(double) + 2 * frag +
+    const size_t bytes = 6 * nv * sizeof(double) + ((size_t)FNPART * G + 64) * sizeof(double) + 2 * frag +
                          NL * NC * sizeof(float) + 1024;
     char *base = (char *)scratch(SLOT_FCG, bytes);
     if (!base) return PERKS_E_NOMEM;
@@ -325,7 +331,8 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     p.p = d + 2 * nv;
     p.q = d + 3 * nv;
     p.dinv = d + 4 * nv;
-    p.part = d + 5 * nv;
+    p.p1 = d + 5 * nv;
+    p.part = d + 6 * nv;
     p.result = p.part + (size_t)FNPART * G;
     unsigned short *wf = (unsigned short *)(p.result + 64);
     unsigned short *wb = wf + frag / sizeof(unsigned short);   // backward fragments (unused here)

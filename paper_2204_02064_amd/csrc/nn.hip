@@ -145,6 +145,37 @@ __global__ __launch_bounds__(256) void nn_loss(const float *out, const float *ta
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Energy loss: az = A z with A the 5-point operator given per pixel as five
+// planes [S, W, C, E, N] (planes[b][k][y][x], floats); partial sums of
+// z*az - 2 z*r (r = input channel 0); g[p][0] = bf16(2 (az - r) / count).
+__global__ __launch_bounds__(256) void nn_energy(const float *out, const float *x, const float *planes, int B, int H,
+                                                 int W, float inv_count, unsigned short *g, double *part) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int P = B * H * W;
+    double s = 0.0;
+    if (p < P) {
+        const int b = p / (H * W), yx = p % (H * W), y = yx / W, xx = yx % W;
+        const float *pl = planes + (size_t)b * 5 * H * W;
+        const size_t hw = (size_t)H * W;
+        const float z = out[p];
+        float az = pl[2 * hw + yx] * z;
+        if (y > 0) az = fmaf(pl[yx], out[p - W], az);
+        if (xx > 0) az = fmaf(pl[hw + yx], out[p - 1], az);
+        if (xx < W - 1) az = fmaf(pl[3 * hw + yx], out[p + 1], az);
+        if (y < H - 1) az = fmaf(pl[4 * hw + yx], out[p + W], az);
+        const float r = x[2 * (size_t)p];
+        s = (double)z * (double)az - 2.0 * (double)z * (double)r;
+        uint4 *dst = reinterpret_cast<uint4 *>(g + (size_t)p * NC);
+        dst[0] = make_uint4((unsigned)to_bf16(2.f * (az - r) * inv_count), 0u, 0u, 0u);
+        dst[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // Weight gradient of one layer: dW[o][i][tap] = sum_p g[p][o] * a[p + tap][i],
 // db[o] = sum_p g[p][o], FP32 on the vector units.  Thread t owns (o = t/16,
 // i = t%16) and its nine taps; a block takes ROWS image rows, staged in LDS
@@ -359,14 +390,19 @@ int perks_nn_forward(const float *params, const float *x, int32_t B, int32_t H, 
     return PERKS_OK;
 }
 
-int perks_nn_loss_grad(const float *params, const float *x, const float *target, int32_t B, int32_t H, int32_t W,
-                       float *grad, double *loss, void *stream) {
-    if (!params || !x || !target || !grad) return set_error(PERKS_E_INVAL, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// Forward, loss (MSE against target, or the energy functional with the
+// 5-point planes), backward: grad and (if loss) the loss.
+int loss_grad_impl(const float *params, const float *x, const float *target, const float *planes, int B, int H, int W,
+                   float *grad, double *loss, hipStream_t st) {
+    if (!params || !x || !grad || (!target && !planes)) return set_error(PERKS_E_INVAL, "NULL argument");
     int rc = check_dims(B, H, W);
     if (rc) return rc;
     if (H % DW_ROWS != 0) return set_error(PERKS_E_UNSUPPORTED, "H must be a multiple of %d", DW_ROWS);
     if (W > DW_MAXW) return set_error(PERKS_E_UNSUPPORTED, "W must be <= %d for training", DW_MAXW);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int64_t P = (int64_t)B * H * W;
     NnWork w;
     rc = nn_work(P, &w);
@@ -375,8 +411,12 @@ int perks_nn_loss_grad(const float *params, const float *x, const float *target,
     const unsigned nb = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(nn_pack_input, dim3(nb), dim3(256), 0, st, x, (int)P, w.act[0]);
     forward_from_input(st, w, B, H, W);
-    hipLaunchKernelGGL(nn_loss, dim3(nb), dim3(256), 0, st, (const float *)w.out, target, (int)P,
-                       1.0f / (float)P, w.g0, w.part);
+    if (planes)
+        hipLaunchKernelGGL(nn_energy, dim3(nb), dim3(256), 0, st, (const float *)w.out, x, planes, B, H, W,
+                           1.0f / (float)P, w.g0, w.part);
+    else
+        hipLaunchKernelGGL(nn_loss, dim3(nb), dim3(256), 0, st, (const float *)w.out, target, (int)P,
+                           1.0f / (float)P, w.g0, w.part);
     hipLaunchKernelGGL(nn_reduce_f64, dim3(1), dim3(256), 0, st, (const double *)w.part, (int)nb, w.scal);
     const size_t fl = 5 * 64 * 8;
     unsigned short *g = w.g0, *gn = w.g1;
@@ -401,6 +441,22 @@ int perks_nn_loss_grad(const float *params, const float *x, const float *target,
     }
     PERKS_HIP_TRY(hipGetLastError());
     return PERKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int perks_nn_loss_grad(const float *params, const float *x, const float *target, int32_t B, int32_t H, int32_t W,
+                       float *grad, double *loss, void *stream) {
+    if (!target) return set_error(PERKS_E_INVAL, "target must not be NULL");
+    return loss_grad_impl(params, x, target, nullptr, B, H, W, grad, loss, reinterpret_cast<hipStream_t>(stream));
+}
+
+int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t B, int32_t H, int32_t W,
+                         float *grad, double *loss, void *stream) {
+    if (!planes) return set_error(PERKS_E_INVAL, "planes must not be NULL");
+    return loss_grad_impl(params, x, nullptr, planes, B, H, W, grad, loss, reinterpret_cast<hipStream_t>(stream));
 }
 
 int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, float beta1,

@@ -7,24 +7,30 @@ k = 1, 2, 4, 8, ... iterations; each snapshot gives the network input
 [r_k / rms(r_k), log k] and the target (x* - x_k) / rms(r_k), the error the
 preconditioner should return for that residual.
 
-Training: Adam on the mean squared error, mini-batches of pairs, every
-forward and backward pass and every Adam step in the library's kernels
-(perks_nn_loss_grad, perks_nn_adam); this module only chooses the batches.
+Training: Adam, mini-batches of pairs, every forward and backward pass and
+every Adam step in the library's kernels; this module only chooses the
+batches.  Two losses: the mean squared error against the scaled error
+(perks_nn_loss_grad), or the error of the output in the energy norm of the
+problem's operator, ||z - e||_A^2 up to a constant (perks_nn_energy_grad):
+the quantity a CG step minimises, dominated neither by the smooth error
+components a local network cannot represent nor by the scale of e.
 """
 import numpy as np
 
-from . import (CsrMatrix, NN_PARAMS, cg_solve, cg_solve_capture, nn_adam, nn_loss_grad, nn_pack_params)
+from . import (CsrMatrix, NN_PARAMS, cg_solve, cg_solve_capture, nn_adam, nn_energy_grad, nn_loss_grad,
+               nn_pack_params)
 
 CAPTURE_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
 
 
-def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000):
+def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000, with_field=False):
     """problems: iterable of (rowptr, colind, values, log_k [n, n], f) torch
     tensors on the device.  Returns (inputs [P, n, n, 2] float32, targets
-    [P, n, n] float32) device tensors."""
+    [P, n, n] float32) device tensors, and with ``with_field`` also the index
+    of each pair's problem (int64 [P])."""
     import torch
-    xs, ts = [], []
-    for rp, ci, v, lk, f in problems:
+    xs, ts, fi = [], [], []
+    for pid, (rp, ci, v, lk, f) in enumerate(problems):
         n = lk.shape[0]
         A = CsrMatrix(rp, ci, v)
         xstar = torch.zeros_like(f)
@@ -40,7 +46,11 @@ def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000):
                 break
             xs.append(torch.stack([(r / s).reshape(n, n), lk], dim=-1).to(torch.float32))
             ts.append(((xstar - xc[j]) / s).reshape(n, n).to(torch.float32))
-    return torch.stack(xs), torch.stack(ts)
+            fi.append(pid)
+    X, T = torch.stack(xs), torch.stack(ts)
+    if with_field:
+        return X, T, torch.tensor(fi, dtype=torch.int64, device=X.device)
+    return X, T
 
 
 def init_params(seed=0):
@@ -53,8 +63,10 @@ def init_params(seed=0):
     return nn_pack_params(layers)
 
 
-def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log=None):
-    """Adam on the MSE over (inputs, targets); returns (params, loss per step)."""
+def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log=None, planes=None, field=None):
+    """Adam over (inputs, targets); returns (params, loss per step).  With
+    ``planes`` ([F, 5, n, n] float32, the operator of each problem) and
+    ``field`` (problem index per pair) the energy-norm loss is used."""
     import torch
     dev = inputs.device
     p = torch.from_numpy(init_params(seed)).to(dev) if params is None else params.clone()
@@ -70,8 +82,12 @@ def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log
         for s in range(0, P - batch + 1, batch):
             idx = torch.from_numpy(order[s:s + batch]).to(dev)
             xb = inputs.index_select(0, idx).contiguous()
-            tb = targets.index_select(0, idx).contiguous()
-            loss, _ = nn_loss_grad(p, xb, tb, grad)
+            if planes is not None:
+                pb = planes.index_select(0, field.index_select(0, idx)).contiguous()
+                loss, _ = nn_energy_grad(p, xb, pb, grad)
+            else:
+                tb = targets.index_select(0, idx).contiguous()
+                loss, _ = nn_loss_grad(p, xb, tb, grad)
             step += 1
             nn_adam(p, grad, m, v, step, lr=lr)
             losses.append(loss)

@@ -39,3 +39,18 @@ def test_harvest_train_and_apply(pk):
     x = torch.zeros_like(f)
     info = pk.fcg_solve(A, f, x, n, n, params=params, logk=lk, tol=1e-8, stall=20)
     assert info["status"] == "converged"
+
+
+def test_energy_loss_training_reduces_the_a_norm_error(pk):
+    from paper_2204_02064_amd import learned
+    n = 32
+    seeds = range(6)
+    probs = [workloads.diffusion_problem_torch(n, seed=s) for s in seeds]
+    planes = torch.stack([workloads.diffusion_planes_torch(torch.exp(workloads.grf_log_k_torch(n, seed=s)))
+                          for s in seeds]).to(torch.float32)
+    X, T, field = learned.harvest_pairs(probs, iters=(1, 2, 4, 8, 16, 32), with_field=True)
+    assert field.shape[0] == X.shape[0] and int(field.max()) == len(seeds) - 1
+    params, losses = learned.train(X, T, epochs=30, batch=8, lr=2e-3, seed=1, planes=planes, field=field)
+    first, last = np.mean(losses[:5]), np.mean(losses[-5:])
+    print(f"energy loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < first

@@ -113,3 +113,27 @@ def test_adam_matches_oracle(pk):
     for (gw, gb), (ow, ob) in zip(got, ol):
         np.testing.assert_allclose(gw, ow, rtol=0, atol=2e-6)
         np.testing.assert_allclose(gb, ob, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 8, 16), (2, 12, 24)])
+def test_energy_gradients_match_oracle(pk, B, H, W):
+    import workloads
+    layers = _oracle_params(pk, seed=13)
+    params = to_dev(pk.nn_pack_params(layers))
+    x, _ = _inputs(B, H, W, seed=3 + H)
+    planes = []
+    for b in range(B):
+        gk = workloads.grf_log_k(max(H, W), seed=b)[:H + 2, :W + 2]
+        planes.append(workloads.diffusion_planes(np.exp(gk)).astype(np.float32))
+    pl = np.stack(planes)
+    loss, grad = pk.nn_energy_grad(params, to_dev(x), to_dev(pl))
+    xs = [np.moveaxis(x[b], -1, 0).astype(np.float64) for b in range(B)]
+    oloss, ograds = onn.energy_loss_and_grads(layers, xs, [p.astype(np.float64) for p in planes], bf16=True)
+    assert abs(loss - oloss) <= 2e-3 * max(abs(oloss), 1e-3)
+    g = pk.nn_unpack_params(grad.cpu().numpy())
+    for l, ((gw, gb), (ow, ob)) in enumerate(zip(g, ograds)):
+        a = np.concatenate([gw.ravel(), gb.ravel()]).astype(np.float64)
+        o = np.concatenate([ow.ravel(), ob.ravel()])
+        cos = a @ o / (np.linalg.norm(a) * np.linalg.norm(o))
+        rel = np.linalg.norm(a - o) / np.linalg.norm(o)
+        assert cos >= 0.999 and rel <= 2e-2, (l, cos, rel)

@@ -233,3 +233,48 @@ def test_grf_pointwise_variance_is_sigma_squared():
     vals = np.array([workloads.grf_log_k(16, seed=s)[5, 7] for s in range(400)])
     assert abs(vals.var() - 1.0) < 0.2 and abs(vals.mean()) < 0.15
     assert abs(workloads.grf_log_k(16, seed=1, sigma=2.0)[3, 3] - 2 * workloads.grf_log_k(16, seed=1)[3, 3]) < 1e-12
+
+
+def test_five_point_planes_apply_equals_csr_spmv():
+    g = workloads.grf_log_k(9, seed=3)
+    k = np.exp(g)
+    rp, ci, v = workloads.diffusion_csr(k)
+    planes = workloads.diffusion_planes(k)
+    z = np.random.default_rng(0).standard_normal((9, 9))
+    np.testing.assert_allclose(nn.apply_5pt(planes, z).ravel(), oracle.spmv(rp, ci, v, z.ravel()), rtol=1e-14,
+                               atol=1e-13)
+
+
+def test_energy_loss_is_the_a_norm_error_up_to_a_constant():
+    """(z - e)'A(z - e) = L(z) * pixels + e'r for r = A e."""
+    rng = np.random.default_rng(1)
+    k = np.exp(workloads.grf_log_k(6, seed=2))
+    planes = workloads.diffusion_planes(k)
+    e = rng.standard_normal((6, 6))
+    r = nn.apply_5pt(planes, e)
+    params = _rand_params(8, scale=0.2)
+    x = np.stack([r, rng.standard_normal((6, 6))])
+    L, _ = nn.energy_loss_and_grads(params, [x], [planes])
+    z = nn.forward(params, x)[0][0]
+    d = z - e
+    anorm = float(np.sum(d * nn.apply_5pt(planes, d)))
+    assert abs(L * 36 + float(np.sum(e * r)) - anorm) <= 1e-10 * max(1.0, abs(anorm))
+
+
+def test_energy_loss_gradients_match_finite_differences():
+    rng = np.random.default_rng(5)
+    params = _rand_params(9)
+    k = np.exp(workloads.grf_log_k(5, seed=4))
+    planes = [workloads.diffusion_planes(k)]
+    x = [rng.standard_normal((2, 5, 5))]
+    _, grads = nn.energy_loss_and_grads(params, x, planes)
+    h = 1e-6
+    for layer, idx in [(0, (2, 1, 1, 0)), (3, (5, 9, 2, 2)), (5, (0, 3, 1, 1))]:
+        w, b = params[layer]
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        lp, _ = nn.energy_loss_and_grads([(wp, b) if j == layer else params[j] for j in range(6)], x, planes)
+        lm, _ = nn.energy_loss_and_grads([(wm, b) if j == layer else params[j] for j in range(6)], x, planes)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) <= 1e-6 * max(abs(fd), 1e-3)

@@ -47,3 +47,10 @@ def test_torch_grf_statistics():
     torch = pytest.importorskip("torch")
     vals = torch.stack([workloads.grf_log_k_torch(16, seed=s, device="cpu")[5, 7] for s in range(400)])
     assert abs(float(vals.var()) - 1.0) < 0.2 and abs(float(vals.mean())) < 0.15
+
+
+def test_torch_planes_equal_numpy():
+    torch = pytest.importorskip("torch")
+    g = workloads.grf_log_k(11, seed=2)
+    np.testing.assert_allclose(workloads.diffusion_planes_torch(torch.exp(torch.from_numpy(g))).numpy(),
+                               workloads.diffusion_planes(np.exp(g)), rtol=1e-15, atol=0)

@@ -111,3 +111,38 @@ def diffusion_problem_torch(n, seed=0, sigma=1.0, ell=16.0, device="cuda"):
     gen = torch.Generator(device=device).manual_seed(10_000_000 + int(seed))
     f = torch.randn(n * n, generator=gen, device=device, dtype=torch.float64)
     return rp, ci, v, g[1:-1, 1:-1].contiguous(), f
+
+
+def diffusion_planes(k):
+    """The FV operator of diffusion_csr as five per-pixel planes [S, W, C, E, N]
+    (numpy float64, [5, n, n]); zero where the neighbour is on the ring."""
+    k = np.asarray(k, dtype=np.float64)
+    kc = k[1:-1, 1:-1]
+
+    def t(a, b):
+        return 2.0 * a * b / (a + b)
+    ts, tw, te, tn = t(kc, k[:-2, 1:-1]), t(kc, k[1:-1, :-2]), t(kc, k[1:-1, 2:]), t(kc, k[2:, 1:-1])
+    c = ts + tw + te + tn
+    s, w, e, nn = -ts.copy(), -tw.copy(), -te.copy(), -tn.copy()
+    s[0, :] = 0.0
+    w[:, 0] = 0.0
+    e[:, -1] = 0.0
+    nn[-1, :] = 0.0
+    return np.stack([s, w, c, e, nn])
+
+
+def diffusion_planes_torch(k):
+    """diffusion_planes for a torch tensor k (same values)."""
+    import torch
+    kc = k[1:-1, 1:-1]
+
+    def t(a, b):
+        return 2.0 * a * b / (a + b)
+    ts, tw, te, tn = t(kc, k[:-2, 1:-1]), t(kc, k[1:-1, :-2]), t(kc, k[1:-1, 2:]), t(kc, k[2:, 1:-1])
+    c = ts + tw + te + tn
+    s, w, e, nn = -ts.clone(), -tw.clone(), -te.clone(), -tn.clone()
+    s[0, :] = 0.0
+    w[:, 0] = 0.0
+    e[:, -1] = 0.0
+    nn[-1, :] = 0.0
+    return torch.stack([s, w, c, e, nn])
