@@ -313,11 +313,13 @@ int perks_nn_loss_grad(const float *params, const float *x, const float *target,
  * residual input) and A the 5-point operator of each sample given per pixel
  * as five planes (device floats [B][5][H][W]: weights of (y-1), (x-1),
  * centre, (x+1), (y+1), zero for neighbours outside the grid), the loss is
- * sum (z'Az - 2 z'r) / (B*H*W) over the samples' outputs z: the A-norm error
- * ||z - e||_A^2 of the output up to the constant e'r, for r = A e.  Same
- * requirements and outputs as perks_nn_loss_grad. */
-int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t B, int32_t H,
-                         int32_t W, float *grad, double *loss, void *stream);
+ * sum (z'Az - 2 z'r) / (B*H*W) over the samples' vectors z: the A-norm error
+ * ||z - e||_A^2 of z up to the constant e'r, for r = A e.  z is the network
+ * output (jacobi = 0) or the output plus the Jacobi step r / centre
+ * (jacobi = 1: the form perks_fcg_solve applies).  Same requirements and
+ * outputs as perks_nn_loss_grad. */
+int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t jacobi, int32_t B,
+                         int32_t H, int32_t W, float *grad, double *loss, void *stream);
 
 /* One Adam step with bias correction (step counts from 1) on the FP32
  * master weights; m and v (device, PERKS_NN_PARAMS floats) start at zero. */
@@ -327,12 +329,14 @@ int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t 
 /*
  * perks_fcg_solve -- flexible CG preconditioned by the network, one
  * persistent launch.  FCG(1): p = z - (<z, q_old> / <p_old, q_old>) p_old,
- * q = A p, alpha = <p, r> / <p, q>, with z = rms(r) * net([r / rms(r), log k])
- * computed inside the kernel (16 x 16 tiles, all six layers per tile in LDS).
+ * q = A p, alpha = <p, r> / <p, q>, with
+ * z = D^{-1} r + rms(r) * net([r / rms(r), log k]) -- the network corrects
+ * the Jacobi step, so a zero network is Jacobi-PCG -- computed inside the
+ * kernel (16 x 16 tiles, all six layers per tile in LDS).
  * Safeguards: z = D^{-1} r for an iteration where <z, r> <= 0 or z is not
  * finite; after `stall` iterations without a new minimum of ||r|| the solve
  * continues as Jacobi-preconditioned CG.  nn_params == NULL: Jacobi-PCG from
- * the start (the judge the network is compared against).
+ * the start (the baseline the network is compared against).
  *   A       FP64 CSR on an H x W grid of unknowns (row y * W + x), n = H * W.
  *   logk    device, H * W doubles (the second network input).
  *   out     iters, status, restarts = iterations that fell back to Jacobi,

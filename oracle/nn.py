@@ -7,7 +7,11 @@ of flexible CG.  Readings (the choices are ours, stated once here):
 * Network: input channels [r / rms(r), log k] on the N x N grid of unknowns;
   six 3x3 convolutions with zero 'same' padding and a bias each,
   2 -> 16 -> 16 -> 16 -> 16 -> 16 -> 1 channels, ReLU after every layer but
-  the last; output z = rms(r) * net(...), rms(v) = sqrt(mean(v^2)).
+  the last; rms(v) = sqrt(mean(v^2)).
+* Preconditioner: z = D^-1 r + rms(r) * net(...) -- the network learns a
+  correction to the Jacobi step, so an untrained (zero) network is exactly
+  Jacobi preconditioning and training can only move away from it where the
+  loss improves; the plain form z = rms(r) * net(...) is kept for the pins.
 * Weights W[o, i, 1 + dy, 1 + dx] multiply input channel i at (y + dy, x + dx)
   for output channel o at (y, x); arrays are [C, H, W] with x fastest.
 * Reduced precision: with ``bf16=True`` every layer input and every weight is
@@ -145,14 +149,17 @@ def rms(v):
     return float(np.sqrt(np.mean(np.square(v))))
 
 
-def apply_preconditioner(params, r, log_k, bf16=False):
-    """z = rms(r) * net([r / rms(r), log k]) for r, log_k of shape (N, N)."""
+def apply_preconditioner(params, r, log_k, bf16=False, dinv=None):
+    """z = rms(r) * net([r / rms(r), log k]) (+ dinv * r when dinv is given)
+    for r, log_k (and dinv) of shape (N, N)."""
+    r = np.asarray(r, dtype=np.float64)
     s = rms(r)
+    jac = np.zeros_like(r) if dinv is None else np.asarray(dinv, dtype=np.float64) * r
     if s == 0.0:
-        return np.zeros_like(r)
-    x = np.stack([np.asarray(r, dtype=np.float64) / s, np.asarray(log_k, dtype=np.float64)])
+        return jac
+    x = np.stack([r / s, np.asarray(log_k, dtype=np.float64)])
     out, _ = forward(params, x, bf16)
-    return s * out[0]
+    return s * out[0] + jac
 
 
 # ---------------------------------------------------------------------------
@@ -179,16 +186,17 @@ def apply_5pt(planes, z):
     return y
 
 
-def energy_loss_and_grads(params, inputs, planes, bf16=False):
+def energy_loss_and_grads(params, inputs, planes, bf16=False, jacobi=False):
     """sum over samples of (z'Az - 2 z'r), divided by the total pixel count,
-    and its gradients; r = inputs[j][0], z the network output."""
+    and its gradients; r = inputs[j][0], z the network output (plus the
+    Jacobi step r / C, C the centre plane, when ``jacobi``)."""
     count = sum(x.shape[1] * x.shape[2] for x in inputs)
     total = 0.0
     acc = [(np.zeros(w.shape), np.zeros(b.shape)) for w, b in params]
     for x, pl in zip(inputs, planes):
         out, cache = forward(params, x, bf16)
-        z = out[0]
         r = np.asarray(x[0], dtype=np.float64)
+        z = out[0] + (r / np.asarray(pl[2], dtype=np.float64) if jacobi else 0.0)
         az = apply_5pt(pl, z)
         total += float(np.sum(z * az) - 2.0 * np.sum(z * r))
         grads, _ = backward(cache, (2.0 * (az - r) / count)[None])

@@ -114,7 +114,7 @@ def lib():
     L.perks_nn_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.perks_nn_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, vp]
-    L.perks_nn_energy_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.perks_nn_energy_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
     for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("perks_stencil_run", "perks_stencil_run_baseline", "perks_stencil_plan_query",
@@ -455,9 +455,11 @@ def nn_loss_grad(params, x, target, grad=None, stream=None):
     return loss.value, grad
 
 
-def nn_energy_grad(params, x, planes, grad=None, stream=None):
+def nn_energy_grad(params, x, planes, grad=None, stream=None, jacobi=True):
     """(loss, grad) of the energy-norm loss: planes [B, 5, H, W] float32 hold
-    each sample's 5-point operator, x[..., 0] the scaled residual."""
+    each sample's 5-point operator, x[..., 0] the scaled residual; with
+    ``jacobi`` the loss is taken on the Jacobi step plus the network output
+    (the preconditioner fcg_solve applies), else on the output alone."""
     import torch
     B, H, W, _ = x.shape
     _check_f32(params, NN_PARAMS, "params")
@@ -467,7 +469,8 @@ def nn_energy_grad(params, x, planes, grad=None, stream=None):
         grad = torch.empty(NN_PARAMS, dtype=torch.float32, device=x.device)
     loss = ctypes.c_double()
     _check(lib().perks_nn_energy_grad(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                      ctypes.c_void_p(planes.data_ptr()), B, H, W, ctypes.c_void_p(grad.data_ptr()),
+                                      ctypes.c_void_p(planes.data_ptr()), int(bool(jacobi)), B, H, W,
+                                      ctypes.c_void_p(grad.data_ptr()),
                                       ctypes.byref(loss), _stream_handle(stream)))
     return loss.value, grad
 

@@ -4,8 +4,9 @@
 // preconditioned residual z = M(r) is made A-orthogonal to the previous
 // direction explicitly, p = z - (<z, q_old> / <p_old, q_old>) p_old with
 // q = A p, and alpha = <p, r> / <p, q>; this tolerates a preconditioner that
-// is not a fixed linear operator.  M is the convolutional network:
-// z = rms(r) * net([r / rms(r), log k]) on the H x W grid of unknowns.  When
+// is not a fixed linear operator.  M is the Jacobi step corrected by the
+// convolutional network, z = D^{-1} r + rms(r) * net([r / rms(r), log k]) on
+// the H x W grid of unknowns, so a zero network is Jacobi-PCG.  When
 // the network fails (<z, r> <= 0 or a non-finite value) the Jacobi step
 // z = D^{-1} r replaces it for that iteration; when the residual norm has not
 // reached a new minimum for `stall` iterations the solve continues as
@@ -57,7 +58,7 @@ struct FcgParams {
     double tol;
 };
 
-// z on the tile whose first pixel is (tx0, ty0): rms * net([r / rms, log k]).
+// z on the tile whose first pixel is (tx0, ty0): D^{-1} r + rms * net([r / rms, log k]).
 // Layer l reads an (FR - 2l)^2 region and writes the (FR - 2l - 2)^2 region
 // inside it; pixels outside the grid are zero in every layer's input (the
 // network's zero padding).  Waves take (row, 16-pixel segment) items.
@@ -120,7 +121,8 @@ __device__ void net_tile(const FcgParams &p, int tx0, int ty0, double rms, doubl
                 st.y = (unsigned)to_bf16(o[2]) | ((unsigned)to_bf16(o[3]) << 16);
                 *reinterpret_cast<uint2 *>(bout + (row * sout + col) * NC + 4 * g) = st;
             } else if (g == 0 && inside) {
-                st_coh(p.z + (size_t)gy * p.W + gx, rms * (double)(acc[0] + bz[0]));   // gathered by others
+                const size_t i = (size_t)gy * p.W + gx;   // an own pixel: dinv written by this workgroup
+                st_coh(p.z + i, __builtin_fma(rms, (double)(acc[0] + bz[0]), p.dinv[i] * ld_coh(p.r + i)));
             }
         }
         __syncthreads();

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void nn_loss(const float *out, const float *ta
 // planes [S, W, C, E, N] (planes[b][k][y][x], floats); partial sums of
 // z*az - 2 z*r (r = input channel 0); g[p][0] = bf16(2 (az - r) / count).
 __global__ __launch_bounds__(256) void nn_energy(const float *out, const float *x, const float *planes, int B, int H,
-                                                 int W, float inv_count, unsigned short *g, double *part) {
+                                                 int W, int jacobi, float inv_count, unsigned short *g, double *part) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     const int P = B * H * W;
     double s = 0.0;
@@ -157,12 +157,16 @@ __global__ __launch_bounds__(256) void nn_energy(const float *out, const float *
         const int b = p / (H * W), yx = p % (H * W), y = yx / W, xx = yx % W;
         const float *pl = planes + (size_t)b * 5 * H * W;
         const size_t hw = (size_t)H * W;
-        const float z = out[p];
+        // z = out (+ r / centre: the Jacobi step the network corrects)
+        auto zat = [&](int q, int qyx) {
+            return jacobi ? out[q] + x[2 * (size_t)q] / pl[2 * hw + qyx] : out[q];
+        };
+        const float z = zat(p, yx);
         float az = pl[2 * hw + yx] * z;
-        if (y > 0) az = fmaf(pl[yx], out[p - W], az);
-        if (xx > 0) az = fmaf(pl[hw + yx], out[p - 1], az);
-        if (xx < W - 1) az = fmaf(pl[3 * hw + yx], out[p + 1], az);
-        if (y < H - 1) az = fmaf(pl[4 * hw + yx], out[p + W], az);
+        if (y > 0) az = fmaf(pl[yx], zat(p - W, yx - W), az);
+        if (xx > 0) az = fmaf(pl[hw + yx], zat(p - 1, yx - 1), az);
+        if (xx < W - 1) az = fmaf(pl[3 * hw + yx], zat(p + 1, yx + 1), az);
+        if (y < H - 1) az = fmaf(pl[4 * hw + yx], zat(p + W, yx + W), az);
         const float r = x[2 * (size_t)p];
         s = (double)z * (double)az - 2.0 * (double)z * (double)r;
         uint4 *dst = reinterpret_cast<uint4 *>(g + (size_t)p * NC);
@@ -396,8 +400,8 @@ namespace {
 
 // Forward, loss (MSE against target, or the energy functional with the
 // 5-point planes), backward: grad and (if loss) the loss.
-int loss_grad_impl(const float *params, const float *x, const float *target, const float *planes, int B, int H, int W,
-                   float *grad, double *loss, hipStream_t st) {
+int loss_grad_impl(const float *params, const float *x, const float *target, const float *planes, int jacobi, int B,
+                   int H, int W, float *grad, double *loss, hipStream_t st) {
     if (!params || !x || !grad || (!target && !planes)) return set_error(PERKS_E_INVAL, "NULL argument");
     int rc = check_dims(B, H, W);
     if (rc) return rc;
@@ -413,7 +417,7 @@ int loss_grad_impl(const float *params, const float *x, const float *target, con
     forward_from_input(st, w, B, H, W);
     if (planes)
         hipLaunchKernelGGL(nn_energy, dim3(nb), dim3(256), 0, st, (const float *)w.out, x, planes, B, H, W,
-                           1.0f / (float)P, w.g0, w.part);
+                           jacobi, 1.0f / (float)P, w.g0, w.part);
     else
         hipLaunchKernelGGL(nn_loss, dim3(nb), dim3(256), 0, st, (const float *)w.out, target, (int)P,
                            1.0f / (float)P, w.g0, w.part);
@@ -450,13 +454,16 @@ extern "C" {
 int perks_nn_loss_grad(const float *params, const float *x, const float *target, int32_t B, int32_t H, int32_t W,
                        float *grad, double *loss, void *stream) {
     if (!target) return set_error(PERKS_E_INVAL, "target must not be NULL");
-    return loss_grad_impl(params, x, target, nullptr, B, H, W, grad, loss, reinterpret_cast<hipStream_t>(stream));
+    return loss_grad_impl(params, x, target, nullptr, 0, B, H, W, grad, loss,
+                          reinterpret_cast<hipStream_t>(stream));
 }
 
-int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t B, int32_t H, int32_t W,
-                         float *grad, double *loss, void *stream) {
+int perks_nn_energy_grad(const float *params, const float *x, const float *planes, int32_t jacobi, int32_t B,
+                         int32_t H, int32_t W, float *grad, double *loss, void *stream) {
     if (!planes) return set_error(PERKS_E_INVAL, "planes must not be NULL");
-    return loss_grad_impl(params, x, nullptr, planes, B, H, W, grad, loss, reinterpret_cast<hipStream_t>(stream));
+    if (jacobi != 0 && jacobi != 1) return set_error(PERKS_E_INVAL, "jacobi must be 0 or 1");
+    return loss_grad_impl(params, x, nullptr, planes, jacobi, B, H, W, grad, loss,
+                          reinterpret_cast<hipStream_t>(stream));
 }
 
 int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, float beta1,

@@ -4,14 +4,16 @@ Pairs: for a diffusion problem A x = f with log-permeability log k, the
 persistent Jacobi-preconditioned CG is run to a tight tolerance for x*, then
 run again with snapshots of its iterate x_k and residual r_k after
 k = 1, 2, 4, 8, ... iterations; each snapshot gives the network input
-[r_k / rms(r_k), log k] and the target (x* - x_k) / rms(r_k), the error the
-preconditioner should return for that residual.
+[r_k / rms(r_k), log k] and the target (x* - x_k - D^-1 r_k) / rms(r_k): the
+preconditioner returns D^-1 r + rms(r) net(...), so the network's part of the
+error e_k = x* - x_k is what the Jacobi step leaves of it.
 
 Training: Adam, mini-batches of pairs, every forward and backward pass and
 every Adam step in the library's kernels; this module only chooses the
-batches.  Two losses: the mean squared error against the scaled error
-(perks_nn_loss_grad), or the error of the output in the energy norm of the
-problem's operator, ||z - e||_A^2 up to a constant (perks_nn_energy_grad):
+batches.  Two losses: the mean squared error against that target
+(perks_nn_loss_grad), or the error of the preconditioned residual
+z = D^-1 r + rms(r) net(...) in the energy norm of the problem's operator,
+||z - e||_A^2 up to a constant (perks_nn_energy_grad, Jacobi form):
 the quantity a CG step minimises, dominated neither by the smooth error
 components a local network cannot represent nor by the scale of e.
 """
@@ -33,6 +35,9 @@ def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000, with_fi
     for pid, (rp, ci, v, lk, f) in enumerate(problems):
         n = lk.shape[0]
         A = CsrMatrix(rp, ci, v)
+        rows = torch.repeat_interleave(torch.arange(rp.numel() - 1, device=rp.device), rp[1:] - rp[:-1])
+        diag = torch.zeros(rp.numel() - 1, dtype=v.dtype, device=v.device).index_add_(
+            0, rows, torch.where(ci.long() == rows, v, torch.zeros_like(v)))
         xstar = torch.zeros_like(f)
         cg_solve(A, f, xstar, tol=tol, maxit=maxit, precond="jacobi")
         x = torch.zeros_like(f)
@@ -45,7 +50,7 @@ def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000, with_fi
             if s <= 0:
                 break
             xs.append(torch.stack([(r / s).reshape(n, n), lk], dim=-1).to(torch.float32))
-            ts.append(((xstar - xc[j]) / s).reshape(n, n).to(torch.float32))
+            ts.append(((xstar - xc[j] - r / diag) / s).reshape(n, n).to(torch.float32))
             fi.append(pid)
     X, T = torch.stack(xs), torch.stack(ts)
     if with_field:
@@ -84,7 +89,7 @@ def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log
             xb = inputs.index_select(0, idx).contiguous()
             if planes is not None:
                 pb = planes.index_select(0, field.index_select(0, idx)).contiguous()
-                loss, _ = nn_energy_grad(p, xb, pb, grad)
+                loss, _ = nn_energy_grad(p, xb, pb, grad, jacobi=True)
             else:
                 tb = targets.index_select(0, idx).contiguous()
                 loss, _ = nn_loss_grad(p, xb, tb, grad)

@@ -1,12 +1,14 @@
 """GPU tests of flexible CG with the learned preconditioner and of the
 solver-side capture of training pairs.
 
-FCG without a network is Jacobi-preconditioned CG: parity with the oracle's
-PCG (true residual within tol, iteration count within max(2, 2%)).  A network
-that is the identity in exact arithmetic sees its input rounded to bf16, so
-FCG then matches the oracle's FCG with the same bf16 rounding (iteration
-count within max(3, 5%)), not exact CG.  A network that always fails
-(<z, r> < 0) falls back to the Jacobi step on every iteration.  A capture of
+The preconditioner is z = D^-1 r + rms(r) net(...).  FCG without a network,
+and FCG with an all-zero network, is Jacobi-preconditioned CG: parity with the
+oracle's PCG (true residual within tol, iteration count within max(2, 2%)).
+A network that is the identity in exact arithmetic sees its input rounded to
+bf16, so FCG then matches the oracle's FCG with the same bf16 rounding
+(iteration count within max(3, 5%)), not exact CG.  A network that returns
+-r, on a problem whose diagonal exceeds 1 everywhere, makes <z, r> < 0 and
+falls back to the Jacobi step on every iteration.  A capture of
 x_k equals the iterate of a solve stopped after k iterations, bit for bit.
 """
 import math
@@ -36,6 +38,13 @@ def _true_relres(rp, ci, v, b, x):
     n = rp.size - 1
     A = sp.csr_matrix((v, ci, rp), shape=(n, n))
     return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def _diag(rp, ci, v):
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    d = np.zeros(rp.size - 1)
+    np.add.at(d, rows, np.where(ci == rows, v, 0.0))
+    return d
 
 
 def _identity_layers(sign=1.0):
@@ -78,15 +87,32 @@ def test_fcg_with_identity_network_matches_oracle(pk, n):
     x = to_dev(np.zeros(n * n))
     info = pk.fcg_solve(A, to_dev(f), x, n, n, params=params, logk=to_dev(lk), tol=1e-9, maxit=5000, stall=50)
     assert info["status"] == "converged" and info["fallbacks"] == 0
-    _, oi = ofcg.fcg(rp, ci, v, f, lambda r: onn.apply_preconditioner(layers, r.reshape(n, n), lk, bf16=True).ravel(),
+    dinv = 1.0 / _diag(rp, ci, v).reshape(n, n)
+    _, oi = ofcg.fcg(rp, ci, v, f,
+                     lambda r: onn.apply_preconditioner(layers, r.reshape(n, n), lk, bf16=True, dinv=dinv).ravel(),
                      tol=1e-9, stall=50)
     assert abs(info["iters"] - oi["iters"]) <= max(3, math.ceil(0.05 * oi["iters"]))
     assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-9 * 1.001
 
 
+@pytest.mark.parametrize("n", [33, 64])
+def test_zero_network_is_jacobi_pcg(pk, n):
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=11)
+    zero = [(np.zeros_like(w), np.zeros_like(b)) for w, b in _identity_layers()]
+    params = to_dev(pk.nn_pack_params(zero))
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, params=params, logk=to_dev(lk), tol=1e-10, maxit=5000, stall=50)
+    _, oi = oracle.cg(rp, ci, v, f, tol=1e-10, maxit=5000, precond="jacobi")
+    assert info["status"] == "converged" and info["fallbacks"] == 0
+    assert abs(info["iters"] - oi["iters"]) <= max(2, math.ceil(0.02 * oi["iters"]))
+    assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-10 * 1.001
+
+
 def test_failing_network_falls_back_every_iteration(pk):
     n = 32
     rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=6)
+    assert _diag(rp, ci, v).min() > 1.0     # so D^-1 r - r points against r
     params = to_dev(pk.nn_pack_params(_identity_layers(sign=-1.0)))   # z = -r
     A = pk.CsrMatrix(rp, ci, v)
     x = to_dev(np.zeros(n * n))

@@ -115,8 +115,8 @@ def test_adam_matches_oracle(pk):
         np.testing.assert_allclose(gb, ob, rtol=0, atol=2e-6)
 
 
-@pytest.mark.parametrize("B,H,W", [(1, 8, 16), (2, 12, 24)])
-def test_energy_gradients_match_oracle(pk, B, H, W):
+@pytest.mark.parametrize("B,H,W,jacobi", [(1, 8, 16, False), (2, 12, 24, False), (2, 12, 24, True)])
+def test_energy_gradients_match_oracle(pk, B, H, W, jacobi):
     import workloads
     layers = _oracle_params(pk, seed=13)
     params = to_dev(pk.nn_pack_params(layers))
@@ -126,9 +126,10 @@ def test_energy_gradients_match_oracle(pk, B, H, W):
         gk = workloads.grf_log_k(max(H, W), seed=b)[:H + 2, :W + 2]
         planes.append(workloads.diffusion_planes(np.exp(gk)).astype(np.float32))
     pl = np.stack(planes)
-    loss, grad = pk.nn_energy_grad(params, to_dev(x), to_dev(pl))
+    loss, grad = pk.nn_energy_grad(params, to_dev(x), to_dev(pl), jacobi=jacobi)
     xs = [np.moveaxis(x[b], -1, 0).astype(np.float64) for b in range(B)]
-    oloss, ograds = onn.energy_loss_and_grads(layers, xs, [p.astype(np.float64) for p in planes], bf16=True)
+    oloss, ograds = onn.energy_loss_and_grads(layers, xs, [p.astype(np.float64) for p in planes], bf16=True,
+                                              jacobi=jacobi)
     assert abs(loss - oloss) <= 2e-3 * max(abs(oloss), 1e-3)
     g = pk.nn_unpack_params(grad.cpu().numpy())
     for l, ((gw, gb), (ow, ob)) in enumerate(zip(g, ograds)):

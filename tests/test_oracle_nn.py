@@ -278,3 +278,20 @@ def test_energy_loss_gradients_match_finite_differences():
         lm, _ = nn.energy_loss_and_grads([(wm, b) if j == layer else params[j] for j in range(6)], x, planes)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grads[layer][0][idx]) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_energy_loss_with_jacobi_term():
+    """With the Jacobi term a zero network gives z = D^-1 r exactly; the loss
+    then equals the energy functional of the Jacobi step."""
+    rng = np.random.default_rng(2)
+    k = np.exp(workloads.grf_log_k(7, seed=9))
+    planes = workloads.diffusion_planes(k)
+    zero = [(np.zeros_like(w), np.zeros_like(b)) for w, b in _rand_params(0)]
+    x = rng.standard_normal((2, 7, 7))
+    L, grads = nn.energy_loss_and_grads(zero, [x], [planes], jacobi=True)
+    zj = x[0] / planes[2]
+    ref = (np.sum(zj * nn.apply_5pt(planes, zj)) - 2 * np.sum(zj * x[0])) / 49
+    assert abs(L - ref) <= 1e-13 * max(1.0, abs(ref))
+    # and the preconditioner applies the same step
+    z = nn.apply_preconditioner(zero, x[0], x[1], dinv=1.0 / planes[2])
+    np.testing.assert_allclose(z, zj, rtol=1e-15)
