@@ -263,6 +263,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batched-baseline", action="store_true",
                     help="also time the host-looped baseline on every batched system (slow)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (a plain copy kernel of known traffic, the "
+                         "reference for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the method and this "
@@ -277,6 +280,15 @@ def main():
 
     pk.lib()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 1 GiB read + 1 GiB written in {(time.perf_counter() - t0) * 1e3:.3f} ms")
+        del src, dst
     cases = CASES if args.cases == "all" else [c for c in CASES if c[0] in args.cases.split(",")]
     grids = []
     for kind, shape, dt in cases:

@@ -61,11 +61,12 @@ typedef struct {
 typedef struct perks_tuning {
     int32_t waves_per_wg;     /* wavefronts per workgroup (1..16)                      */
     int32_t wgs_per_cu;       /* co-resident workgroups per CU used by the plan        */
-    int32_t rows_per_lane;    /* cells each lane keeps in registers along y            */
-    int32_t planes_per_lane;  /* 3D: cells each lane keeps along z                     */
+    int32_t rows_per_lane;    /* cells each lane keeps in registers along y (3D: 4)   */
+    int32_t planes_per_lane;  /* 3D: column depth, planes per column (1..32; 0 auto)   */
     int32_t sync;             /* 0 auto, 1 grid barrier, 2 neighbour flags             */
     int32_t max_cached_tiles; /* <0: none cached (all tiles stream through HBM);
-                                 0: as many as fit; >0: at most this many              */
+                                 0: as many as fit; >0: at most this many (3D: columns
+                                 whose top planes stay in registers)                   */
     int32_t reserved[2];
 } perks_tuning;
 
@@ -75,8 +76,8 @@ typedef struct {
     int32_t waves_per_wg;
     int32_t rows_per_lane;
     int32_t planes_per_lane;
-    int64_t tiles;            /* wave tiles covering the interior                     */
-    int64_t cached_tiles;     /* tiles held in registers across steps                 */
+    int64_t tiles;            /* wave tiles covering the interior (3D: columns)       */
+    int64_t cached_tiles;     /* tiles (3D: columns) with cells held in registers     */
     int64_t cached_cells;     /* interior cells held on chip                          */
     int64_t interior_cells;
     int64_t halo_bytes_per_step;  /* face traffic written + read per step             */

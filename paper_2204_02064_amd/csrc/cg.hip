@@ -59,6 +59,13 @@ struct CgInst {
     double inner_tol;
 };
 
+// The problem description as kernels read it: through the constant address
+// space (the host writes it before the launch, no kernel writes it), so that
+// the compiler takes every pointer loaded from it to address global memory
+// and emits global_* accesses instead of flat ones (which also count in
+// lgkmcnt, making every LDS wait of the SpMV wait for the gathers too).
+using CInst = const __attribute__((address_space(4))) CgInst;
+
 // The workgroup's LDS copy of (the first entries of) its slice of A: FP64
 // values for the FP64 solver, FP32 values for the mixed-precision solver.
 // Each kernel references only its own pair, so each gets only that pair.
@@ -194,7 +201,7 @@ __host__ __device__ inline size_t sell_capacity(int64_t nnz, int G) {
 }
 
 template <typename T>
-__device__ __forceinline__ Slice load_slice(const CgInst &p, const T *val, T *sval, int *scol, int g, int G) {
+__device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int *scol, int g, int G) {
     Slice sl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     sl.r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
@@ -315,7 +322,7 @@ __device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, 
 
 // SpMV over the workgroup's rows in whichever layout the slice uses.
 template <int U, typename T, typename F, typename S>
-__device__ __forceinline__ void spmv_slice(const CgInst &p, const Slice &sl, const T *val, const T *sval,
+__device__ __forceinline__ void spmv_slice(CInst &p, const Slice &sl, const T *val, const T *sval,
                                            const int *scol, F fetch, S sink) {
     if (sl.sell) {
         spmv_sell_range<true>(sl, sval, scol, 0, sl.cc, fetch, sink);
@@ -334,11 +341,11 @@ __device__ __forceinline__ void spmv_slice(const CgInst &p, const Slice &sl, con
 // recursive residual meets tol the true residual is recomputed; if it fails,
 // CG restarts from the current x while iterations remain.
 template <bool JACOBI, bool FUSEP, class Sync>
-__device__ __forceinline__ void cg_f64_body(const CgInst *pin, Sync &gs, const int g, const int G) {
+__device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, const int G) {
     // The problem is read from global memory through a pointer laundered at
     // every phase: its fields are reloaded (scalar loads) instead of being
     // kept live in scalar registers across the whole solve.
-    const CgInst *pp = opaque(pin);
+    CInst *pp = opaque(pin);
     const int tid = threadIdx.x;
     const Slice sl = load_slice(*pp, pp->val, pp->sval64, pp->scol, g, G);
     const int r0 = sl.r0, r1 = sl.r1;
@@ -510,7 +517,7 @@ __device__ __forceinline__ void cg_f64_body(const CgInst *pin, Sync &gs, const i
 // LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
 // nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
 template <bool JACOBI, bool FUSEP, class Sync>
-__device__ __forceinline__ void cg_mixed_body(const CgInst &p, Sync &gs, const int g, const int G) {
+__device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, const int G) {
     const int tid = threadIdx.x;
     {
         // FP32 copy of this workgroup's slice (only this workgroup reads it)
@@ -672,8 +679,9 @@ template <bool JACOBI, bool FUSEP, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
     GroupSync gs;
     gs.init_grid(ws);
-    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*pin, gs, blockIdx.x, gridDim.x);
-    else cg_f64_body<JACOBI, FUSEP>(pin, gs, blockIdx.x, gridDim.x);
+    CInst *in = (CInst *)pin;
+    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*in, gs, blockIdx.x, gridDim.x);
+    else cg_f64_body<JACOBI, FUSEP>(in, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
 }
 
@@ -708,8 +716,9 @@ __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
         // disjoint epoch ranges per group: a workgroup's flag left by an
         // earlier group can never match a later group's epochs
         gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span);
-        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(bp.inst[task.inst], gs, task.rank, task.size);
-        else cg_f64_body<JACOBI, FUSEP>(bp.inst + task.inst, gs, task.rank, task.size);
+        CInst *in = (CInst *)(bp.inst + task.inst);
+        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*in, gs, task.rank, task.size);
+        else cg_f64_body<JACOBI, FUSEP>(in, gs, task.rank, task.size);
     }
     GroupSync all;
     all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span);

@@ -25,10 +25,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Fused multiply-add in the operands' own precision.
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
 // Sum over groups of L lanes (L a power of two, runtime-uniform).
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int L) {

@@ -78,17 +78,40 @@ int launch_coop(const void *fn, int wgs, int threads, void *params, hipStream_t 
 
 namespace perks {
 
+// Global-memory pointers.  Pointers held in structures that kernels load at
+// run time, or laundered through opaque(), are generic to the compiler, and
+// every access through a generic pointer is a flat instruction: a 64-bit
+// address per lane, and counted in lgkmcnt as well as vmcnt, so that each
+// wait for an LDS or scalar load also waits for every flat load in flight.
+// Pointer fields typed gmem<T> * keep the global address space: accesses are
+// global_* instructions with a uniform base in scalar registers and a 32-bit
+// lane offset, counted by vmcnt alone.  The casts below emit no instruction.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__host__ __device__ __forceinline__ gmem<T> *to_global(T *p) {
+    return (gmem<T> *)p;
+}
+
 // Loads and stores of data produced or consumed by another workgroup.  They
 // are relaxed agent-scope atomics: the compiler emits them with the sc1 cache
 // policy, which keeps them coherent across the eight XCD-private L2 caches
 // without a device-wide cache write-back or invalidate.
 template <typename T>
+__device__ __forceinline__ T ld_coh(const gmem<T> *p) {
+    return __hip_atomic_load(const_cast<gmem<T> *>(p), __ATOMIC_RELAXED, PERKS_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(gmem<T> *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, PERKS_AGENT);
+}
+template <typename T>
 __device__ __forceinline__ T ld_coh(const T *p) {
-    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, PERKS_AGENT);
+    return ld_coh<T>((const gmem<T> *)p);
 }
 template <typename T>
 __device__ __forceinline__ void st_coh(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, PERKS_AGENT);
+    st_coh<T>((gmem<T> *)p, v);
 }
 
 // Lane shifts across the 64-lane wavefront with DPP wave_shr:1 / wave_shl:1.
@@ -116,6 +139,11 @@ __device__ __forceinline__ T from_west(T v, T fill) { return dpp_move<DPP_WAVE_S
 template <typename T>
 __device__ __forceinline__ T from_east(T v, T fill) { return dpp_move<DPP_WAVE_SHL1>(v, fill); }
 
+// a*b+c with one rounding in the operands' own precision (__builtin_fma
+// alone would widen float operands to double and round twice).
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // a*b+c (one rounding) in the three-address VOP3 form.  The compiler's own
 // FMA is the two-address v_fmac whose result must stay in the accumulator's
 // register; when a new grid value must replace its old value in place (the
@@ -136,14 +164,14 @@ __device__ __forceinline__ float fma_untied(float a, float b, float c) {
 // step loops re-derive their face-buffer addresses from laundered bases every
 // step; otherwise loop-invariant code motion keeps dozens of per-lane 64-bit
 // addresses alive across the whole time loop, in the same registers that
-// should hold the cached domain.
-template <typename T>
-__device__ __forceinline__ T *opaque(T *p) {
-    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+// should hold the cached domain.  P is a pointer type (any address space).
+template <typename P>
+__device__ __forceinline__ P opaque(P p) {
+    const unsigned long long a = (unsigned long long)p;
     unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
     unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
-    return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
+    return (P)(((unsigned long long)hi << 32) | lo);
 }
 
 // Keeps the compiler from moving memory operations across this point.  LDS

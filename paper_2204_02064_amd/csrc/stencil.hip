@@ -191,7 +191,7 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
         }
     } else {
         add(0, 0, 0);
-        for (int pz : {4, 8, 16}) add(4, pz, 0);
+        for (int pz : {8, 16, 24, 32}) add(0, pz, 0);   // column depths
     }
     if (cands.empty()) return set_error(PERKS_E_UNSUPPORTED, "no candidate plan for this stencil");
     hipStream_t st = as_stream(stream);

@@ -71,8 +71,8 @@ __device__ __forceinline__ T compute_rows(T (&u)[RC], int nrows, RowVal<T> &abov
     T acc;
     if (BOX) {
         acc = W.w[0] * above.w;
-        acc = __builtin_fma(W.w[1], above.c, acc);
-        acc = __builtin_fma(W.w[2], above.e, acc);
+        acc = fma_t(W.w[1], above.c, acc);
+        acc = fma_t(W.w[2], above.e, acc);
     } else {
         acc = W.w[1] * above.c;
     }
@@ -88,16 +88,16 @@ __device__ __forceinline__ T compute_rows(T (&u)[RC], int nrows, RowVal<T> &abov
                 n = (FULL || i + 1 < nrows) ? u[i + 1] : below;
             else
                 n = below;
-            acc = __builtin_fma(W.w[3], cw, acc);
-            acc = __builtin_fma(W.w[4], c, acc);
-            acc = __builtin_fma(W.w[5], ce, acc);
+            acc = fma_t(W.w[3], cw, acc);
+            acc = fma_t(W.w[4], c, acc);
+            acc = fma_t(W.w[5], ce, acc);
             // south-row terms of row i+1 come from old row i: take them now, so
             // old row i is dead before the new value of row i is complete
             T nxt;
             if (BOX) {
                 nxt = W.w[0] * cw;
-                nxt = __builtin_fma(W.w[1], c, nxt);
-                nxt = __builtin_fma(W.w[2], ce, nxt);
+                nxt = fma_t(W.w[1], c, nxt);
+                nxt = fma_t(W.w[2], ce, nxt);
             } else {
                 nxt = W.w[1] * c;
             }
@@ -110,8 +110,8 @@ __device__ __forceinline__ T compute_rows(T (&u)[RC], int nrows, RowVal<T> &abov
                 ne = from_east(n, le[i + 2]);
             }
             if (BOX) {
-                acc = __builtin_fma(W.w[6], nw, acc);
-                acc = __builtin_fma(W.w[7], n, acc);
+                acc = fma_t(W.w[6], nw, acc);
+                acc = fma_t(W.w[7], n, acc);
                 acc = fma_untied(W.w[8], ne, acc);
             } else {
                 acc = fma_untied(W.w[7], n, acc);

@@ -1,18 +1,36 @@
-// 3D 7-point Jacobi stencil (tab:domain "3d7pt") on gfx950: tile arithmetic,
-// persistent kernel, per-step-launch baseline kernel, and host planning.
+// 3D 7-point Jacobi stencil (tab:domain "3d7pt") on gfx950: plane
+// arithmetic, the persistent column kernel, the per-step-launch baseline
+// kernel, and host planning.
 //
-// Tiling.  The interior is cut into wave tiles of 64 (x) x RY (y) x RZ (z)
-// cells.  Lane l owns column x0+l and keeps its RY x RZ block in registers:
-// y and z neighbours are in the lane's registers, x neighbours arrive through
-// DPP lane shifts, and the tile's six outer faces (halo) come from face
-// buffers in global coordinates, double-buffered by step parity:
-//   xface[par][slot][z][y]  (slot 2tx+1 / 2tx+2 = left / right edge plane of
-//                            tile column tx; 0 and 2*ntx+1 = the fixed ring)
+// Persistent kernel: column tiling.  The interior is cut into columns of
+// 64 (x) x WAVES*RY (y) x dz (z) cells, one workgroup per column (more than
+// one per workgroup, in turn, when the grid has more columns than the device
+// holds workgroups).  Wave w of the workgroup owns rows [w RY, (w+1) RY) of
+// the column, lane l the x position x0 + l, and a lane holds RY cells of each
+// plane: y neighbours inside the wave are the lane's own registers, x
+// neighbours arrive through DPP lane shifts, z neighbours are the next and
+// previous planes of the same lane.
+//
+// On chip (Eq. 5): the top min(NC, dz) planes of each workgroup's first
+// column stay in registers for the whole run; every other plane is streamed:
+// read from the grid, updated in place, in chunks of SC planes with the next
+// chunk's loads in flight while the current one is computed.
+//
+// Halo.  Between the waves of a workgroup the y halo goes through LDS plane
+// by plane (each wave posts the old values of its edge rows, a workgroup
+// barrier, each reads its neighbours'), so only the column's outer faces go
+// through global memory, in face buffers in global coordinates,
+// double-buffered by step parity:
+//   xface[par][slot][z][y]  (slot 2tx+1 / 2tx+2 = west / east edge plane of
+//                            the columns at x index tx; 0 and 2*ntx+1 = the
+//                            fixed ring)
 //   yface[par][slot][z][x], zface[par][slot][y][x]  likewise for y and z.
-// Halo faces are staged in LDS for the step.
+// A column's faces are staged in LDS (x, y) and registers (z) at the start of
+// each step with all loads in flight at once.
 #pragma once
 
 #include <algorithm>
+#include <utility>
 
 #include "barrier.hpp"
 #include "common.hpp"
@@ -22,14 +40,6 @@ namespace perks {
 template <typename T>
 struct Weights3D {
     T zm, ym, xm, c, xp, yp, zp;  // offsets (-1,0,0) (0,-1,0) (0,0,-1) (0,0,0) (0,0,1) (0,1,0) (1,0,0)
-};
-
-// LDS halo of one wave tile.
-template <typename T, int RY, int RZ>
-struct Halo3D {
-    T xw[RZ * RY], xe[RZ * RY];   // west / east face, [iz][iy]
-    T ym[RZ * 64], yp[RZ * 64];   // south / north face (y-1 / y+hy), [iz][lane]
-    T zp[RY * 64];                // above face (z+dz), [iy][lane]; the face below is read directly
 };
 
 // One Jacobi step of one z-plane of a lane's block, in place.
@@ -48,7 +58,7 @@ template <typename T, int RY, bool FULLY>
 __device__ __forceinline__ T compute_plane(T (&cur)[RY], T (&part)[RY], const T (&znext)[RY], int hy, T ym, T yp,
                                            const T *lw, const T *le, const Weights3D<T> &W) {
     T last = T(0);
-    T acc_next = __builtin_fma(W.ym, ym, part[0]);   // (dz=-1) then (dy=-1) for cell 0
+    T acc_next = fma_t(W.ym, ym, part[0]);   // (dz=-1) then (dy=-1) for cell 0
 #pragma unroll
     for (int iy = 0; iy < RY; ++iy) {
         if (FULLY || iy < hy) {
@@ -56,19 +66,19 @@ __device__ __forceinline__ T compute_plane(T (&cur)[RY], T (&part)[RY], const T 
             T acc = acc_next;
             const T w = from_west(c, lw[iy]);
             const T e = from_east(c, le[iy]);
-            acc = __builtin_fma(W.xm, w, acc);
-            acc = __builtin_fma(W.c, c, acc);
-            acc = __builtin_fma(W.xp, e, acc);
+            acc = fma_t(W.xm, w, acc);
+            acc = fma_t(W.c, c, acc);
+            acc = fma_t(W.xp, e, acc);
             // what old c contributes to later cells: (dy=-1) of cell iy+1 and
             // (dz=-1) of this cell in the plane above
-            if (iy + 1 < RY) acc_next = __builtin_fma(W.ym, c, part[iy + 1]);
+            if (iy + 1 < RY) acc_next = fma_t(W.ym, c, part[iy + 1]);
             part[iy] = W.zm * c;
             T yn;
             if (iy + 1 < RY)
                 yn = (FULLY || iy + 1 < hy) ? cur[iy + 1] : yp;
             else
                 yn = yp;
-            acc = __builtin_fma(W.yp, yn, acc);
+            acc = fma_t(W.yp, yn, acc);
             const T nv = fma_untied(W.zp, znext[iy], acc);
             cur[iy] = nv;
             if (FULLY ? (iy == RY - 1) : true) last = (FULLY || iy == hy - 1) ? nv : last;
@@ -78,27 +88,24 @@ __device__ __forceinline__ T compute_plane(T (&cur)[RY], T (&part)[RY], const T 
     return last;
 }
 
+// Wave tiles of the per-step baseline: 64 (x) x RY (y) x RZ (z).
 struct Tile3D {
     int tx, ty, tz, x0, y0, z0, wx, hy, dz;
 };
 
 template <typename T>
-struct Stencil3DParams {
-    T *grid;
-    T *src, *dst;      // baseline buffers
-    T *xface, *yface, *zface;
-    unsigned *sync;
-    long long steps;
+struct Step3DParams {
+    gmem<T> *src, *dst;
     int nx, ny, nz;
     int ntx, nty, ntz;
     int RY, RZ;
     int last_w, last_h, last_d;
-    int ntiles, cached;
+    int ntiles;
     Weights3D<T> W;
 };
 
 template <typename T>
-__device__ __forceinline__ Tile3D tile3_of(const Stencil3DParams<T> &p, int t) {
+__device__ __forceinline__ Tile3D tile3_of(const Step3DParams<T> &p, int t) {
     Tile3D tl;
     tl.tx = t % p.ntx;
     tl.ty = (t / p.ntx) % p.nty;
@@ -112,298 +119,509 @@ __device__ __forceinline__ Tile3D tile3_of(const Stencil3DParams<T> &p, int t) {
     return tl;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent column kernel.
+constexpr int C3_RY = 4;      // rows per lane
+constexpr int C3_WAVES = 8;   // waves per workgroup (two per SIMD)
+constexpr int C3_DZMAX = 32;  // deepest column (LDS staging of its faces)
+constexpr int C3_SC = 2;      // planes per streamed chunk
+// register-cached planes per lane: NC * RY values of 128 VGPRs
+template <typename T> struct C3Cache { static constexpr int NC = sizeof(T) == 8 ? 12 : 32; };
+
 template <typename T>
-__device__ __forceinline__ T *xf(const Stencil3DParams<T> &p, int par, int slot) {
+struct Col3DParams {
+    gmem<T> *grid;
+    gmem<T> *xface, *yface, *zface;
+    unsigned *sync;
+    long long steps;
+    int nx, ny, nz;
+    int ntx, nty, ntz, dz;
+    int last_w, last_rows, last_d;
+    int ncols, cached;   // cached: workgroups whose first column keeps planes in registers
+    Weights3D<T> W;
+};
+
+struct Col3D {
+    int tx, ty, tz, x0, wx, yb, rows, z0, dz;
+};
+
+template <typename T>
+__device__ __forceinline__ Col3D col_of(const Col3DParams<T> &p, int t) {
+    Col3D c;
+    c.tx = t % p.ntx;
+    c.ty = (t / p.ntx) % p.nty;
+    c.tz = t / (p.ntx * p.nty);
+    c.x0 = 1 + 64 * c.tx;
+    c.wx = c.tx == p.ntx - 1 ? p.last_w : 64;
+    c.yb = 1 + C3_WAVES * C3_RY * c.ty;
+    c.rows = c.ty == p.nty - 1 ? p.last_rows : C3_WAVES * C3_RY;
+    c.z0 = 1 + p.dz * c.tz;
+    c.dz = c.tz == p.ntz - 1 ? p.last_d : p.dz;
+    return c;
+}
+
+// Rows of wave w in column c.  first: its south neighbour is outside the
+// workgroup; last: its north neighbour is.
+struct WaveRows {
+    int y0, hy;
+    bool first, last;
+};
+__device__ __forceinline__ WaveRows rows_of(const Col3D &c, int w) {
+    WaveRows r;
+    r.y0 = c.yb + w * C3_RY;
+    r.hy = min(max(c.rows - w * C3_RY, 0), C3_RY);
+    r.first = w == 0;
+    r.last = r.hy > 0 && (w + 1) * C3_RY >= c.rows;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ gmem<T> *cxf(const Col3DParams<T> &p, int par, int slot) {
     return p.xface + ((size_t)par * (2 * p.ntx + 2) + slot) * p.nz * p.ny;
 }
 template <typename T>
-__device__ __forceinline__ T *yf(const Stencil3DParams<T> &p, int par, int slot) {
+__device__ __forceinline__ gmem<T> *cyf(const Col3DParams<T> &p, int par, int slot) {
     return p.yface + ((size_t)par * (2 * p.nty + 2) + slot) * p.nz * p.nx;
 }
 template <typename T>
-__device__ __forceinline__ T *zf(const Stencil3DParams<T> &p, int par, int slot) {
+__device__ __forceinline__ gmem<T> *czf(const Col3DParams<T> &p, int par, int slot) {
     return p.zface + ((size_t)par * (2 * p.ntz + 2) + slot) * p.ny * p.nx;
 }
 
-// Stage the six halo faces of tile tl (parity par) into LDS.
-template <typename T, int RY, int RZ>
-__device__ __forceinline__ void load_halo3(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
-                                           Halo3D<T, RY, RZ> &h) {
-    const int xl = min(tl.x0 + lane, p.nx - 1);
-    const T *w = xf(p, par, 2 * tl.tx), *e = xf(p, par, 2 * tl.tx + 3);
-    for (int j = lane; j < RY * RZ; j += 64) {
-        const int iz = j / RY, iy = j % RY;
-        if (iz < tl.dz && iy < tl.hy) {
-            const size_t o = (size_t)(tl.z0 + iz) * p.ny + tl.y0 + iy;
-            h.xw[j] = ld_coh(w + o);
-            h.xe[j] = ld_coh(e + o);
-        }
-    }
-    // y and z faces: four rows of loads in flight at a time (all of them at
-    // once would hold 2 (RZ + RY) values per lane in registers next to the
-    // cached block)
-    const T *ys = yf(p, par, 2 * tl.ty), *yn = yf(p, par, 2 * tl.ty + 3);
-#pragma unroll 1
-    for (int iz = 0; iz < RZ; iz += 4) {
-        T a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (iz + u < tl.dz) {
-                const size_t o = (size_t)(tl.z0 + iz + u) * p.nx + xl;
-                a[u] = ld_coh(ys + o);
-                b[u] = ld_coh(yn + o);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (iz + u < tl.dz) {
-                h.ym[(iz + u) * 64 + lane] = a[u];
-                h.yp[(iz + u) * 64 + lane] = b[u];
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    const T *zb = zf(p, par, 2 * tl.tz), *zt = zf(p, par, 2 * tl.tz + 3);
-#pragma unroll 1
-    for (int iy = 0; iy < RY; iy += 4) {
-        T a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (iy + u < tl.hy) {
-                const size_t o = (size_t)(tl.y0 + iy + u) * p.nx + xl;
-                b[u] = ld_coh(zt + o);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (iy + u < tl.hy) {
-                h.zp[(iy + u) * 64 + lane] = b[u];
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    compiler_fence();
+// Element e (a 32-bit lane offset) of a uniform base: the address stays a
+// scalar base plus a 32-bit vector offset instead of a 64-bit vector address.
+template <typename T>
+__device__ __forceinline__ gmem<T> *at(gmem<T> *base, unsigned e) {
+    return (gmem<T> *)((gmem<char> *)base + e * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const gmem<T> *at(const gmem<T> *base, unsigned e) {
+    return (const gmem<T> *)((const gmem<char> *)base + e * (unsigned)sizeof(T));
 }
 
-// Publish the edges of plane iz (values in u[0..hy-1]) of tile tl.
-template <typename T, int RY>
-__device__ __forceinline__ void publish_plane(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
-                                              const T (&u)[RY], int iz, T last) {
-
-    const bool in = lane < tl.wx;
-    const int z = tl.z0 + iz;
-    T *left = xf(p, par, 2 * tl.tx + 1) + (size_t)z * p.ny + tl.y0;
-    T *right = xf(p, par, 2 * tl.tx + 2) + (size_t)z * p.ny + tl.y0;
+// Ties the values to this point of the program: the compiler waits here for
+// the loads that produce them, and later uses no longer refer to the loads.
+template <typename T, int N>
+__device__ __forceinline__ void settle(T (&a)[N]) {
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) {
-        if (iy < tl.hy) {
-            if (lane == 0) st_coh(left + iy, u[iy]);
-            if (lane == tl.wx - 1) st_coh(right + iy, u[iy]);
-        }
-    }
-    if (in) {
-        const size_t ox = (size_t)z * p.nx + tl.x0 + lane;
-        st_coh(yf(p, par, 2 * tl.ty + 1) + ox, u[0]);
-        st_coh(yf(p, par, 2 * tl.ty + 2) + ox, last);
-        if (iz == 0) {
-#pragma unroll
-            for (int iy = 0; iy < RY; ++iy)
-                if (iy < tl.hy) st_coh(zf(p, par, 2 * tl.tz + 1) + (size_t)(tl.y0 + iy) * p.nx + tl.x0 + lane, u[iy]);
-        }
-        if (iz == tl.dz - 1) {
-#pragma unroll
-            for (int iy = 0; iy < RY; ++iy)
-                if (iy < tl.hy) st_coh(zf(p, par, 2 * tl.tz + 2) + (size_t)(tl.y0 + iy) * p.nx + tl.x0 + lane, u[iy]);
-        }
-    }
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(a[i]));
 }
 
 template <typename T>
-__device__ void init_ring_faces3(const Stencil3DParams<T> &p) {
+struct ColShared {
+    T xs[C3_WAVES][2][C3_DZMAX][C3_RY];   // west / east face of each wave's rows, per plane
+    T ysf[2][C3_DZMAX][64];               // south / north face of the column, per plane
+    T ex[2][C3_WAVES][2][64];             // per-plane exchange (slot = plane parity): bottom / top row
+};
+
+// The fixed ring (both parities) from the grid.
+template <typename T>
+__device__ __forceinline__ void init_ring_faces_col(const Col3DParams<T> &p) {
     const size_t nthreads = (size_t)gridDim.x * blockDim.x;
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const T *g = p.grid;
+    const gmem<T> *g = p.grid;
     const size_t nx = p.nx, ny = p.ny, nz = p.nz;
     for (int par = 0; par < 2; ++par) {
         for (size_t i = tid; i < nz * ny; i += nthreads) {  // planes x = 0, nx-1; i = z*ny + y
-            st_coh(xf(p, par, 0) + i, g[i * nx]);
-            st_coh(xf(p, par, 2 * p.ntx + 1) + i, g[i * nx + nx - 1]);
+            st_coh(cxf(p, par, 0) + i, g[i * nx]);
+            st_coh(cxf(p, par, 2 * p.ntx + 1) + i, g[i * nx + nx - 1]);
         }
         for (size_t i = tid; i < nz * nx; i += nthreads) {  // planes y = 0, ny-1; i = z*nx + x
             const size_t z = i / nx, x = i % nx;
-            st_coh(yf(p, par, 0) + i, g[(z * ny) * nx + x]);
-            st_coh(yf(p, par, 2 * p.nty + 1) + i, g[(z * ny + ny - 1) * nx + x]);
+            st_coh(cyf(p, par, 0) + i, g[(z * ny) * nx + x]);
+            st_coh(cyf(p, par, 2 * p.nty + 1) + i, g[(z * ny + ny - 1) * nx + x]);
         }
         for (size_t i = tid; i < ny * nx; i += nthreads) {  // planes z = 0, nz-1; i = y*nx + x
-            st_coh(zf(p, par, 0) + i, g[i]);
-            st_coh(zf(p, par, 2 * p.ntz + 1) + i, g[(nz - 1) * ny * nx + i]);
+            st_coh(czf(p, par, 0) + i, g[i]);
+            st_coh(czf(p, par, 2 * p.ntz + 1) + i, g[(nz - 1) * ny * nx + i]);
         }
+    }
+}
+
+// Parity-0 faces of column c from the grid (wave w's share).
+template <typename T>
+__device__ __forceinline__ void publish_initial_col(const Col3DParams<T> &p, const Col3D &c, int w, int lane) {
+    const WaveRows wr = rows_of(c, w);
+    if (wr.hy == 0) return;
+    const gmem<T> *g = p.grid;
+    const size_t nx = p.nx, ny = p.ny;
+    for (int j = lane; j < wr.hy * c.dz; j += 64) {
+        const int iz = j / wr.hy, iy = j % wr.hy;
+        const size_t zy = (size_t)(c.z0 + iz) * ny + wr.y0 + iy;
+        st_coh(cxf(p, 0, 2 * c.tx + 1) + zy, g[zy * nx + c.x0]);
+        st_coh(cxf(p, 0, 2 * c.tx + 2) + zy, g[zy * nx + c.x0 + c.wx - 1]);
+    }
+    if (lane < c.wx) {
+        const size_t x = c.x0 + lane;
+        for (int iz = 0; iz < c.dz; ++iz) {
+            const size_t z = c.z0 + iz;
+            if (wr.first) st_coh(cyf(p, 0, 2 * c.ty + 1) + z * nx + x, g[(z * ny + wr.y0) * nx + x]);
+            if (wr.last) st_coh(cyf(p, 0, 2 * c.ty + 2) + z * nx + x, g[(z * ny + wr.y0 + wr.hy - 1) * nx + x]);
+        }
+        for (int iy = 0; iy < wr.hy; ++iy) {
+            const size_t y = wr.y0 + iy;
+            st_coh(czf(p, 0, 2 * c.tz + 1) + y * nx + x, g[((size_t)c.z0 * ny + y) * nx + x]);
+            st_coh(czf(p, 0, 2 * c.tz + 2) + y * nx + x, g[((size_t)(c.z0 + c.dz - 1) * ny + y) * nx + x]);
+        }
+    }
+}
+
+// Stage the x and y faces of column c (parity par) in LDS: every load of the
+// workgroup in flight at once, then the LDS writes.
+template <typename T>
+__device__ __forceinline__ void stage_faces_col(const Col3DParams<T> &p, const Col3D &c, int par, ColShared<T> &sh) {
+    constexpr int NT = C3_WAVES * 64;
+    constexpr int NXV = C3_WAVES * 2 * C3_DZMAX * C3_RY, NYV = 2 * C3_DZMAX * 64;
+    constexpr int KX = (NXV + NT - 1) / NT, KY = (NYV + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    T xv[KX], yv[KY];
+    const gmem<T> *fw = cxf(p, par, 2 * c.tx), *fe = cxf(p, par, 2 * c.tx + 3);
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+        const int e = tid + k * NT;
+        const int iy = e % C3_RY, iz = (e / C3_RY) % C3_DZMAX, side = (e / (C3_RY * C3_DZMAX)) % 2,
+                  w = e / (2 * C3_RY * C3_DZMAX);
+        const int hy = min(max(c.rows - w * C3_RY, 0), C3_RY);
+        const bool ok = e < NXV && iz < c.dz && iy < hy;
+        const unsigned o = (unsigned)(iz * p.ny + w * C3_RY + iy);
+        xv[k] = ok ? ld_coh(at((side ? fe : fw) + ((size_t)c.z0 * p.ny + c.yb), o)) : T(0);
+    }
+    const gmem<T> *fs = cyf(p, par, 2 * c.ty), *fn = cyf(p, par, 2 * c.ty + 3);
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int e = tid + k * NT;
+        const int x = e % 64, iz = (e / 64) % C3_DZMAX, side = e / (64 * C3_DZMAX);
+        const bool ok = e < NYV && iz < c.dz && x < c.wx;
+        const unsigned o = (unsigned)(iz * p.nx + x);
+        yv[k] = ok ? ld_coh(at((side ? fn : fs) + ((size_t)c.z0 * p.nx + c.x0), o)) : T(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    T *xs = &sh.xs[0][0][0][0];
+    T *ys = &sh.ysf[0][0][0];
+#pragma unroll
+    for (int k = 0; k < KX; ++k)
+        if (tid + k * NT < NXV) xs[tid + k * NT] = xv[k];
+#pragma unroll
+    for (int k = 0; k < KY; ++k)
+        if (tid + k * NT < NYV) ys[tid + k * NT] = yv[k];
+}
+
+// One plane iz of wave w's rows: exchange of the edge rows' old values with
+// the neighbouring waves (one workgroup barrier; every wave of the workgroup
+// calls this for every plane of the column), the update of cur in place, and
+// the new values of the column's outer faces published to parity par ^ 1.
+// Returns with cur holding the new values.
+template <typename T, bool FULL>
+__device__ __forceinline__ void col_plane(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                          int lane, int par, int iz, T (&cur)[C3_RY], const T (&znext)[C3_RY],
+                                          T (&part)[C3_RY], ColShared<T> &sh) {
+    constexpr int RY = C3_RY;
+    const int slot = iz & 1;
+    if (wr.hy > 0) {
+        T top = cur[0];
+#pragma unroll
+        for (int iy = 1; iy < RY; ++iy)
+            if (FULL || iy < wr.hy) top = cur[iy];
+        sh.ex[slot][w][0][lane] = cur[0];
+        sh.ex[slot][w][1][lane] = top;
+    }
+    __syncthreads();
+    if (wr.hy == 0) return;
+    const T ym = wr.first ? sh.ysf[0][iz][lane] : sh.ex[slot][w - 1][1][lane];
+    const T yp = wr.last ? sh.ysf[1][iz][lane] : sh.ex[slot][w + 1][0][lane];
+    const T *lw = &sh.xs[w][0][iz][0];
+    const T *le = &sh.xs[w][1][iz][0];
+    if (lane >= c.wx) {
+        // ghost lanes carry the east face so the last real lane's DPP east
+        // shift picks it up
+#pragma unroll
+        for (int iy = 0; iy < RY; ++iy) cur[iy] = le[iy];
+    }
+    const T last = compute_plane<T, RY, FULL>(cur, part, znext, wr.hy, ym, yp, lw, le, p.W);
+    // The column's new west / east edges and south / north boundary rows go
+    // to the LDS slots just consumed (xs[w], ysf), published to global memory
+    // in one batch after the last plane; only the bottom and top planes are
+    // stored here.
+    T *nw = &sh.xs[w][0][iz][0];
+    T *ne = &sh.xs[w][1][iz][0];
+#pragma unroll
+    for (int iy = 0; iy < RY; ++iy) {
+        if (FULL || iy < wr.hy) {
+            if (lane == 0) nw[iy] = cur[iy];
+            if (lane == c.wx - 1) ne[iy] = cur[iy];
+        }
+    }
+    if (lane < c.wx) {
+        if (wr.first) sh.ysf[0][iz][lane] = cur[0];
+        if (wr.last) sh.ysf[1][iz][lane] = last;
+        if (iz == 0 || iz == c.dz - 1) {
+            // plane index laundered: the addresses are formed here, not
+            // hoisted for every plane of the unrolled cached-plane loop
+            int z = __builtin_amdgcn_readfirstlane(iz == 0 ? 1 : 2);
+            asm volatile("" : "+s"(z));
+            gmem<T> *f = opaque(czf(p, par ^ 1, 2 * c.tz + z) + (size_t)wr.y0 * p.nx);
+            const unsigned xo = (unsigned)(c.x0 + lane);
+#pragma unroll
+            for (int iy = 0; iy < RY; ++iy)
+                if (FULL || iy < wr.hy) st_coh(at(f, (unsigned)(iy * p.nx) + xo), cur[iy]);
+            if (iz == 0 && c.dz == 1) {
+                gmem<T> *f2 = opaque(czf(p, par ^ 1, 2 * c.tz + 2) + (size_t)wr.y0 * p.nx);
+#pragma unroll
+                for (int iy = 0; iy < RY; ++iy)
+                    if (FULL || iy < wr.hy) st_coh(at(f2, (unsigned)(iy * p.nx) + xo), cur[iy]);
+            }
+        }
+    }
+}
+
+// Publish the column's west / east edges and south / north boundary rows,
+// gathered in LDS during the step, to parity par ^ 1 (the whole workgroup,
+// after a barrier).
+template <typename T>
+__device__ __forceinline__ void publish_faces_col(const Col3DParams<T> &p, const Col3D &c, int par,
+                                                  const ColShared<T> &sh) {
+    constexpr int NT = C3_WAVES * 64;
+    constexpr int NXV = C3_WAVES * 2 * C3_DZMAX * C3_RY, NYV = 2 * C3_DZMAX * 64;
+    const int tid = threadIdx.x;
+    gmem<T> *fw = cxf(p, par ^ 1, 2 * c.tx + 1) + ((size_t)c.z0 * p.ny + c.yb);
+    gmem<T> *fe = cxf(p, par ^ 1, 2 * c.tx + 2) + ((size_t)c.z0 * p.ny + c.yb);
+    const T *xs = &sh.xs[0][0][0][0];
+    for (int e = tid; e < NXV; e += NT) {
+        const int iy = e % C3_RY, iz = (e / C3_RY) % C3_DZMAX, side = (e / (C3_RY * C3_DZMAX)) % 2,
+                  w = e / (2 * C3_RY * C3_DZMAX);
+        const int hy = min(max(c.rows - w * C3_RY, 0), C3_RY);
+        if (iz < c.dz && iy < hy) st_coh(at(side ? fe : fw, (unsigned)(iz * p.ny + w * C3_RY + iy)), xs[e]);
+    }
+    gmem<T> *fs = cyf(p, par ^ 1, 2 * c.ty + 1) + ((size_t)c.z0 * p.nx + c.x0);
+    gmem<T> *fn = cyf(p, par ^ 1, 2 * c.ty + 2) + ((size_t)c.z0 * p.nx + c.x0);
+    const T *ys = &sh.ysf[0][0][0];
+    for (int e = tid; e < NYV; e += NT) {
+        const int x = e % 64, iz = (e / 64) % C3_DZMAX, side = e / (64 * C3_DZMAX);
+        if (iz < c.dz && x < c.wx) st_coh(at(side ? fn : fs, (unsigned)(iz * p.nx + x)), ys[e]);
     }
 }
 
 template <typename T>
-__device__ void publish_initial3(const Stencil3DParams<T> &p, const Tile3D &tl, int lane) {
-    const T *g = p.grid;
-    const size_t nx = p.nx, ny = p.ny;
-    for (int j = lane; j < tl.hy * tl.dz; j += 64) {
-        const int iz = j / tl.hy, iy = j % tl.hy;
-        const size_t row = ((size_t)(tl.z0 + iz) * ny + tl.y0 + iy) * nx;
-        const size_t o = (size_t)(tl.z0 + iz) * ny + tl.y0 + iy;
-        st_coh(xf(p, 0, 2 * tl.tx + 1) + o, g[row + tl.x0]);
-        st_coh(xf(p, 0, 2 * tl.tx + 2) + o, g[row + tl.x0 + tl.wx - 1]);
-    }
-    if (lane < tl.wx) {
-        const int x = tl.x0 + lane;
-        for (int iz = 0; iz < tl.dz; ++iz) {
-            const size_t z = tl.z0 + iz;
-            st_coh(yf(p, 0, 2 * tl.ty + 1) + z * nx + x, g[(z * ny + tl.y0) * nx + x]);
-            st_coh(yf(p, 0, 2 * tl.ty + 2) + z * nx + x, g[(z * ny + tl.y0 + tl.hy - 1) * nx + x]);
-        }
-        for (int iy = 0; iy < tl.hy; ++iy) {
-            const size_t y = tl.y0 + iy;
-            st_coh(zf(p, 0, 2 * tl.tz + 1) + y * nx + x, g[((size_t)tl.z0 * ny + y) * nx + x]);
-            st_coh(zf(p, 0, 2 * tl.tz + 2) + y * nx + x, g[((size_t)(tl.z0 + tl.dz - 1) * ny + y) * nx + x]);
-        }
-    }
-}
-
-// Step of a register-cached tile: v[iz][iy] holds the block.  FULL tiles
-// (hy == RY, dz == RZ) take halo values at compile-time positions; ragged
-// tiles select them with wave-uniform conditions.
-template <typename T, int RY, int RZ, bool FULL>
-__device__ __forceinline__ void planes_cached3(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
-                                               T (&v)[RZ][RY], Halo3D<T, RY, RZ> &h) {
-    T part[RY];
-    const int xl = min(tl.x0 + lane, p.nx - 1);
-    const T *zb = zf(p, par, 2 * tl.tz) + (size_t)tl.y0 * p.nx + xl;
-#pragma unroll
-    for (int iy = 0; iy < RY; ++iy) part[iy] = p.W.zm * ((FULL || iy < tl.hy) ? ld_coh(zb + (size_t)iy * p.nx) : T(0));
-#pragma unroll
-    for (int iz = 0; iz < RZ; ++iz) {
-        if (FULL || iz < tl.dz) {
-            const T ym = h.ym[iz * 64 + lane], yp = h.yp[iz * 64 + lane];
-            T last;
-            if (iz + 1 < RZ && (FULL || iz + 1 < tl.dz)) {
-                last = compute_plane<T, RY, FULL>(v[iz], part, v[iz + 1], tl.hy, ym, yp, h.xw + iz * RY,
-                                                  h.xe + iz * RY, p.W);
-            } else {
-                T zh[RY];
-#pragma unroll
-                for (int iy = 0; iy < RY; ++iy) zh[iy] = h.zp[iy * 64 + lane];
-                last = compute_plane<T, RY, FULL>(v[iz], part, zh, tl.hy, ym, yp, h.xw + iz * RY, h.xe + iz * RY,
-                                                  p.W);
-            }
-            publish_plane<T, RY>(p, tl, par ^ 1, lane, v[iz], iz, last);
-        }
-    }
-}
-
-template <typename T, int RY, int RZ>
-__device__ __forceinline__ void step_cached3(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
-                                             T (&v)[RZ][RY], Halo3D<T, RY, RZ> &h) {
-    load_halo3<T, RY, RZ>(p, tl, par, lane, h);
-    if (lane >= tl.wx) {
-        // ghost lanes carry the east face so the last real lane's DPP east
-        // shift picks it up
-#pragma unroll
-        for (int iz = 0; iz < RZ; ++iz)
-#pragma unroll
-            for (int iy = 0; iy < RY; ++iy) v[iz][iy] = h.xe[iz * RY + iy];
-    }
-    if (tl.hy == RY && tl.dz == RZ)
-        planes_cached3<T, RY, RZ, true>(p, tl, par, lane, v, h);
+__device__ __forceinline__ void col_plane_any(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                              int lane, int par, int iz, T (&cur)[C3_RY], const T (&znext)[C3_RY],
+                                              T (&part)[C3_RY], ColShared<T> &sh) {
+    if (wr.hy == C3_RY)
+        col_plane<T, true>(p, c, wr, w, lane, par, iz, cur, znext, part, sh);
     else
-        planes_cached3<T, RY, RZ, false>(p, tl, par, lane, v, h);
+        col_plane<T, false>(p, c, wr, w, lane, par, iz, cur, znext, part, sh);
 }
 
-// Step of a tile that lives in the grid (uncached): planes streamed through
-// registers, updated in place.
-template <typename T, int RY, int RZ>
-__device__ __forceinline__ void step_streamed3(const Stencil3DParams<T> &p, const Tile3D &tl, int par, int lane,
-                                               Halo3D<T, RY, RZ> &h) {
-    load_halo3<T, RY, RZ>(p, tl, par, lane, h);
-    const bool ghost = lane >= tl.wx;
-    const int xl = min(tl.x0 + lane, p.nx - 1);
-    const size_t nx = p.nx, ny = p.ny;
-    T cur[RY], nxt[RY], part[RY];
+// Loads of streamed planes [j, j + SC) (those below `n`) of wave w's rows.
+template <typename T>
+__device__ __forceinline__ void load_chunk(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int xl,
+                                           int j, int n, T (&buf)[C3_SC][C3_RY]) {
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) {
-        part[iy] = p.W.zm * ((iy < tl.hy) ? ld_coh(zf(p, par, 2 * tl.tz) + (size_t)(tl.y0 + iy) * p.nx + xl) : T(0));
-        cur[iy] = (iy < tl.hy) ? (ghost ? h.xe[iy] : p.grid[((size_t)tl.z0 * ny + tl.y0 + iy) * nx + xl]) : T(0);
-    }
-    for (int iz = 0; iz < tl.dz; ++iz) {
-        if (iz + 1 < tl.dz) {
-            const size_t zo = ((size_t)(tl.z0 + iz + 1) * ny + tl.y0) * nx + xl;
+    for (int k = 0; k < C3_SC; ++k) {
+        const gmem<T> *g = opaque(p.grid + ((size_t)(c.z0 + j + k) * p.ny + wr.y0) * p.nx);
 #pragma unroll
-            for (int iy = 0; iy < RY; ++iy)
-                nxt[iy] = (iy < tl.hy) ? (ghost ? h.xe[(iz + 1) * RY + iy] : p.grid[zo + (size_t)iy * nx]) : T(0);
-        } else {
-#pragma unroll
-            for (int iy = 0; iy < RY; ++iy) nxt[iy] = h.zp[iy * 64 + lane];
-        }
-        const T ym = h.ym[iz * 64 + lane], yp = h.yp[iz * 64 + lane];
-        const T last =
-            (tl.hy == RY)
-                ? compute_plane<T, RY, true>(cur, part, nxt, RY, ym, yp, h.xw + iz * RY, h.xe + iz * RY, p.W)
-                : compute_plane<T, RY, false>(cur, part, nxt, tl.hy, ym, yp, h.xw + iz * RY, h.xe + iz * RY, p.W);
-        if (!ghost) {
-            const size_t zo = ((size_t)(tl.z0 + iz) * ny + tl.y0) * nx + xl;
-#pragma unroll
-            for (int iy = 0; iy < RY; ++iy)
-                if (iy < tl.hy) p.grid[zo + (size_t)iy * nx] = cur[iy];
-        }
-        publish_plane<T, RY>(p, tl, par ^ 1, lane, cur, iz, last);
-#pragma unroll
-        for (int iy = 0; iy < RY; ++iy) cur[iy] = nxt[iy];
+        for (int iy = 0; iy < C3_RY; ++iy)
+            buf[k][iy] = (j + k < n && iy < wr.hy) ? *at(g, (unsigned)(iy * p.nx + xl)) : T(0);
     }
 }
 
-template <typename T, int RY, int RZ, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void stencil3d_persistent(Stencil3DParams<T> p) {
-    __shared__ Halo3D<T, RY, RZ> halo[WAVES];
+template <typename T>
+__device__ __forceinline__ void store_plane(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int lane,
+                                            int iz, const T (&v)[C3_RY]) {
+    if (lane >= c.wx) return;
+    gmem<T> *g = opaque(p.grid + ((size_t)(c.z0 + iz) * p.ny + wr.y0) * p.nx);
+#pragma unroll
+    for (int iy = 0; iy < C3_RY; ++iy)
+        if (iy < wr.hy) *at(g, (unsigned)(iy * p.nx + c.x0 + lane)) = v[iy];
+}
+
+// rows[k] = src for the k (runtime, uniform) given; no-op when k >= N.
+// Every entry is rewritten with a select, so that no store has a run-time
+// index (which would move the whole array to scratch memory).
+template <int N, typename T>
+__device__ __forceinline__ void put_plane(T (&rows)[N][C3_RY], int k, const T (&src)[C3_RY]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int iy = 0; iy < C3_RY; ++iy) rows[i][iy] = i == k ? src[iy] : rows[i][iy];
+}
+
+// Streamed planes [j, j + SC) of the column from buf (planes below nstream);
+// the plane after buf's last is nxt[0].  The caller has put the plane above
+// the last streamed one where the chunk that ends the stream looks for it.
+template <typename T>
+__device__ __forceinline__ void run_chunk(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                          int lane, int par, int j, int nstream, T (&buf)[C3_SC][C3_RY],
+                                          const T (&nxt)[C3_SC][C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+    // the chunk's loads complete here, once, not at every later use
+#pragma unroll
+    for (int k = 0; k < C3_SC; ++k) settle(buf[k]);
+#pragma unroll
+    for (int k = 0; k < C3_SC; ++k) {
+        const int iz = j + k;
+        if (iz < nstream) {
+            if (k + 1 < C3_SC)
+                col_plane_any(p, c, wr, w, lane, par, iz, buf[k], buf[k + 1 < C3_SC ? k + 1 : 0], part, sh);
+            else
+                col_plane_any(p, c, wr, w, lane, par, iz, buf[k], nxt[0], part, sh);
+            if (wr.hy > 0) store_plane(p, c, wr, lane, iz, buf[k]);
+        }
+    }
+}
+
+// Cached plane I (compile-time, so that v is indexed statically: the planes
+// are expanded by a fold, not by the loop unroller, whose size limit would
+// otherwise leave v in scratch memory).
+template <typename T, int NC, int I>
+__device__ __forceinline__ void cached_plane(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                             int lane, int par, int nstream, int ncache, T (&v)[NC][C3_RY],
+                                             const T (&zt)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+    if (I < ncache) {
+        if constexpr (I + 1 < NC)
+            col_plane_any(p, c, wr, w, lane, par, nstream + I, v[I], v[I + 1], part, sh);
+        else
+            col_plane_any(p, c, wr, w, lane, par, nstream + I, v[I], zt, part, sh);
+    }
+}
+template <typename T, int NC, int... I>
+__device__ __forceinline__ void cached_planes(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                              int lane, int par, int nstream, int ncache, T (&v)[NC][C3_RY],
+                                              const T (&zt)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh,
+                                              std::integer_sequence<int, I...>) {
+    (cached_plane<T, NC, I>(p, c, wr, w, lane, par, nstream, ncache, v, zt, part, sh), ...);
+}
+
+// One step of column c: the streamed planes (bottom dz - ncache) then the
+// register-cached ones (top ncache, in v[0 .. ncache)).  STREAM = false: the
+// plan has every plane of every column in registers (nstream == 0).
+template <typename T, int NC, bool STREAM>
+__device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D &c, int w, int lane, int par,
+                                            int ncache, T (&v)[NC][C3_RY], ColShared<T> &sh) {
+    constexpr int RY = C3_RY, SC = C3_SC;
+    const WaveRows wr = rows_of(c, w);
+    const int xl = min(c.x0 + lane, p.nx - 1);
+    const int nstream = STREAM ? c.dz - ncache : 0;
+    __syncthreads();   // the previous column's readers are done with sh
+    T zb[RY], zt[RY];
+    T sa[SC][RY], sb[SC][RY];
+    {
+        const gmem<T> *fb = czf(p, par, 2 * c.tz) + (size_t)wr.y0 * p.nx;
+        const gmem<T> *ft = czf(p, par, 2 * c.tz + 3) + (size_t)wr.y0 * p.nx;
+#pragma unroll
+        for (int iy = 0; iy < RY; ++iy) {
+            zb[iy] = iy < wr.hy ? ld_coh(at(fb, (unsigned)(iy * p.nx + xl))) : T(0);
+            zt[iy] = iy < wr.hy ? ld_coh(at(ft, (unsigned)(iy * p.nx + xl))) : T(0);
+        }
+    }
+    if (STREAM && nstream > 0) load_chunk(p, c, wr, xl, 0, nstream, sa);
+    stage_faces_col(p, c, par, sh);
+    // every load so far (faces, first chunk) completes here, before any
+    // store of the step: a wait placed later would also wait for the stores
+    settle(zb);
+    settle(zt);
+    if constexpr (STREAM) {
+#pragma unroll
+        for (int k = 0; k < SC; ++k) settle(sa[k]);
+    }
+    __syncthreads();
+    T part[RY];
+#pragma unroll
+    for (int iy = 0; iy < RY; ++iy) part[iy] = p.W.zm * zb[iy];
+    if constexpr (STREAM) {
+    // old values of the plane above the last streamed plane
+    T above[RY];
+#pragma unroll
+    for (int iy = 0; iy < RY; ++iy) above[iy] = ncache > 0 ? v[0][iy] : zt[iy];
+    for (int j = 0; j < nstream; j += 2 * SC) {
+        if (j + SC < nstream) load_chunk(p, c, wr, xl, j + SC, nstream, sb);
+        if (nstream - j <= SC) {
+            put_plane<SC>(sa, nstream - j, above);
+            put_plane<SC>(sb, nstream - j - SC, above);
+        }
+        run_chunk(p, c, wr, w, lane, par, j, nstream, sa, sb, part, sh);
+        if (j + SC >= nstream) break;
+        if (j + 2 * SC < nstream) load_chunk(p, c, wr, xl, j + 2 * SC, nstream, sa);
+        if (nstream - j - SC <= SC) {
+            put_plane<SC>(sb, nstream - j - SC, above);
+            put_plane<SC>(sa, nstream - j - 2 * SC, above);
+        }
+        run_chunk(p, c, wr, w, lane, par, j + SC, nstream, sb, sa, part, sh);
+    }
+    // no chunk load is left in flight; telling the compiler so keeps it from
+    // waiting for one (and for every store after it) in the cached planes
+#pragma unroll
+    for (int k = 0; k < SC; ++k) {
+        settle(sa[k]);
+        settle(sb[k]);
+    }
+    }
+    // cached planes: the plane above the last one is v[ncache] (a free slot
+    // when ncache < NC; with ncache == 0 there are none and v, which may
+    // hold the workgroup's first column, is left alone) or the face above
+    if (ncache > 0 && ncache < NC) put_plane<NC>(v, ncache, zt);
+    cached_planes<T, NC>(p, c, wr, w, lane, par, nstream, ncache, v, zt, part, sh, std::make_integer_sequence<int, NC>());
+    __syncthreads();
+    publish_faces_col(p, c, par, sh);
+}
+
+template <typename T, int NC, bool STREAM>
+__global__ __launch_bounds__(C3_WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, C3_WAVES / 4))) void
+stencil3d_column(Col3DParams<T> p) {
+    constexpr int RY = C3_RY;
+    __shared__ ColShared<T> sh;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int gw = blockIdx.x * WAVES + wave;
-    const int nwaves = gridDim.x * WAVES;
-    Halo3D<T, RY, RZ> &h = halo[wave];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     GridSync gs;
     gs.init(p.sync);
-    init_ring_faces3(p);
-    for (int t = gw; t < p.ntiles; t += nwaves) publish_initial3(p, tile3_of(p, t), lane);
+    init_ring_faces_col(p);
+    for (int t = blockIdx.x; t < p.ncols; t += gridDim.x) publish_initial_col(p, col_of(p, t), w, lane);
     gs.sync();
 
-    const bool has_cached = gw < p.cached;
-    T v[RZ][RY];
-    Tile3D ct{};
-    if (has_cached) {
-        ct = tile3_of(p, gw);
-        const int xl = min(ct.x0 + lane, p.nx - 1);
+    // the first column's top planes, in registers
+    T v[NC][RY];
+    int ncache0 = 0;
+    if ((int)blockIdx.x < p.ncols) {
+        const Col3D c = col_of(p, blockIdx.x);
+        const WaveRows wr = rows_of(c, w);
+        ncache0 = (int)blockIdx.x < p.cached ? min(NC, c.dz) : 0;
+        const int xl = min(c.x0 + lane, p.nx - 1);
+        const int zc = c.z0 + c.dz - ncache0;
 #pragma unroll
-        for (int iz = 0; iz < RZ; ++iz)
+        for (int i = 0; i < NC; ++i)
 #pragma unroll
             for (int iy = 0; iy < RY; ++iy)
-                v[iz][iy] = (iz < ct.dz && iy < ct.hy)
-                                ? p.grid[(((size_t)(ct.z0 + iz)) * p.ny + ct.y0 + iy) * p.nx + xl]
-                                : T(0);
+                v[i][iy] = (i < ncache0 && iy < wr.hy)
+                               ? p.grid[((size_t)(zc + i) * p.ny + wr.y0 + iy) * p.nx + xl]
+                               : T(0);
     }
+    // The register cache's initial loads complete here: otherwise their waits
+    // land inside the step loop, where each would also wait, every step, for
+    // all the stores issued before it (vmcnt counts loads and stores alike).
+#pragma unroll
+    for (int i = 0; i < NC; ++i) settle(v[i]);
     for (long long s = 0; s < p.steps; ++s) {
         const int par = (int)(s & 1);
-        Stencil3DParams<T> q = p;
+        Col3DParams<T> q = p;
         q.grid = opaque(q.grid);
         q.xface = opaque(q.xface);
         q.yface = opaque(q.yface);
         q.zface = opaque(q.zface);
-        if (has_cached) step_cached3<T, RY, RZ>(q, ct, par, lane, v, h);
-        for (int t = p.cached + gw; t < p.ntiles; t += nwaves) step_streamed3<T, RY, RZ>(q, tile3_of(p, t), par, lane, h);
+        int k = 0;
+        for (int t = blockIdx.x; t < p.ncols; t += gridDim.x, ++k)
+            column_step<T, NC, STREAM>(q, col_of(q, t), w, lane, par, k == 0 ? ncache0 : 0, v, sh);
         gs.sync();
     }
-    if (has_cached && lane < ct.wx) {
+    if ((int)blockIdx.x < p.ncols && ncache0 > 0) {
+        const Col3D c = col_of(p, blockIdx.x);
+        const WaveRows wr = rows_of(c, w);
+        const int zc = c.z0 + c.dz - ncache0;
+        if (lane < c.wx) {
 #pragma unroll
-        for (int iz = 0; iz < RZ; ++iz)
+            for (int i = 0; i < NC; ++i)
 #pragma unroll
-            for (int iy = 0; iy < RY; ++iy)
-                if (iz < ct.dz && iy < ct.hy)
-                    p.grid[(((size_t)(ct.z0 + iz)) * p.ny + ct.y0 + iy) * p.nx + ct.x0 + lane] = v[iz][iy];
+                for (int iy = 0; iy < RY; ++iy)
+                    if (i < ncache0 && iy < wr.hy)
+                        p.grid[((size_t)(zc + i) * p.ny + wr.y0 + iy) * p.nx + c.x0 + lane] = v[i][iy];
+        }
     }
     gs.finish();
 }
@@ -413,7 +631,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
 // is applied, so the two paths round identically; every other neighbour is
 // read straight from src (ghost lanes read the real east column).
 template <typename T, int RY, int RZ, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void stencil3d_step(Stencil3DParams<T> p) {
+__global__ __launch_bounds__(WAVES * 64) void stencil3d_step(Step3DParams<T> p) {
     __shared__ T hx[WAVES][2][RY * RZ];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -422,7 +640,7 @@ __global__ __launch_bounds__(WAVES * 64) void stencil3d_step(Stencil3DParams<T> 
     T *lw = hx[wave][0];
     T *le = hx[wave][1];
     const Tile3D tl = tile3_of(p, t);
-    const T *src = p.src;
+    const gmem<T> *src = p.src;
     const size_t nx = p.nx, ny = p.ny;
     const int xl = min(tl.x0 + lane, p.nx - 1);
     for (int j = lane; j < RY * RZ; j += 64) {
@@ -467,87 +685,68 @@ __global__ __launch_bounds__(WAVES * 64) void stencil3d_step(Stencil3DParams<T> 
 constexpr int W3B = 4;    // waves per workgroup, baseline
 constexpr int RYB = 4, RZB = 8;
 
-// Tile shapes (rows x planes per lane) and the waves per workgroup each runs
-// with.  The deepest tile (4 x 16) fits the register file without spilling
-// only in FP32.
-struct Tile3Shape {
-    int ry, rz, waves;
-};
-template <typename T> struct R3List;
-template <> struct R3List<double> { static constexpr Tile3Shape v[2] = {{4, 4, 8}, {4, 8, 8}}; };
-template <> struct R3List<float> { static constexpr Tile3Shape v[3] = {{4, 4, 8}, {4, 8, 8}, {4, 16, 8}}; };
-
-template <typename T>
-const void *pick3d(int ry, int rz, int waves) {
-    if (waves != 8 || ry != 4) return nullptr;
-    if (rz == 4) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 4, 8>);
-    if (rz == 8) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 8, 8>);
-    if constexpr (sizeof(T) == 4) {
-        if (rz == 16) return reinterpret_cast<const void *>(&stencil3d_persistent<T, 4, 16, 8>);
-    }
-    return nullptr;
-}
-
-struct Plan3D {
-    int ry = 0, rz = 0, waves = 0, wgs = 0, ntx = 0, nty = 0, ntz = 0, last_w = 0, last_h = 0, last_d = 0, ntiles = 0,
-        cached = 0;
+struct PlanCol {
+    int dz = 0, ntx = 0, nty = 0, ntz = 0, last_w = 0, last_rows = 0, last_d = 0, ncols = 0, cached = 0, wgs = 0,
+        nc = 0;
     const void *fn = nullptr;
 };
 
+// Column depth: the request (planes_per_lane, 1..C3_DZMAX), else the
+// shallowest column for which the grid has no more columns than the device
+// holds workgroups (so every workgroup's planes can be on chip), else the
+// deepest.
 template <typename T>
-int plan3d(const perks_shape &s, const perks_tuning *tu, Plan3D *pl) {
+int plan3d(const perks_shape &s, const perks_tuning *tu, PlanCol *pl) {
     DeviceFacts f;
     int rc = device_facts(&f);
     if (rc) return rc;
+    if (tu && tu->rows_per_lane && tu->rows_per_lane != C3_RY)
+        return set_error(PERKS_E_UNSUPPORTED, "3D: rows_per_lane must be %d (or 0)", C3_RY);
+    if (tu && tu->waves_per_wg && tu->waves_per_wg != C3_WAVES)
+        return set_error(PERKS_E_UNSUPPORTED, "3D: waves_per_wg must be %d (or 0)", C3_WAVES);
+    if (tu && (tu->planes_per_lane < 0 || tu->planes_per_lane > C3_DZMAX))
+        return set_error(PERKS_E_UNSUPPORTED, "3D: planes_per_lane (column depth) must be 0..%d", C3_DZMAX);
+    constexpr int NC = C3Cache<T>::NC;
+    pl->fn = reinterpret_cast<const void *>(&stencil3d_column<T, NC, true>);
+    pl->nc = NC;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl->fn, C3_WAVES * 64, 0) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        return set_error(PERKS_E_NOTCORESIDENT, "3D column kernel does not fit a CU");
+    }
+    const long long cap = (long long)f.cus * std::min(occ, (tu && tu->wgs_per_cu > 0) ? tu->wgs_per_cu : 1);
     const long long nxi = s.nx - 2, nyi = s.ny - 2, nzi = s.nz - 2;
+    const int rows = C3_WAVES * C3_RY;
     pl->ntx = (int)((nxi + 63) / 64);
     pl->last_w = (int)(nxi - 64 * (pl->ntx - 1));
-    const int want_ry = tu ? tu->rows_per_lane : 0, want_rz = tu ? tu->planes_per_lane : 0;
-    const int wgs_per_cu = (tu && tu->wgs_per_cu > 0) ? tu->wgs_per_cu : 1;
-    const int want_waves = tu ? tu->waves_per_wg : 0;
-    Tile3Shape chosen{0, 0, 0};
-    long long cap = 0;
-    for (Tile3Shape sh : R3List<T>::v) {
-        if (want_waves && want_waves != sh.waves) continue;
-        const void *fn = pick3d<T>(sh.ry, sh.rz, sh.waves);
-        int occ = 0;
-        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, sh.waves * 64, 0) != hipSuccess ||
-            occ < wgs_per_cu)
-            continue;
-        const long long c = (long long)f.cus * wgs_per_cu * sh.waves;
-        const long long nt = pl->ntx * ((nyi + sh.ry - 1) / sh.ry) * ((nzi + sh.rz - 1) / sh.rz);
-        if (want_ry || want_rz) {
-            if ((!want_ry || want_ry == sh.ry) && (!want_rz || want_rz == sh.rz)) {
-                chosen = sh;
-                cap = c;
+    pl->nty = (int)((nyi + rows - 1) / rows);
+    pl->last_rows = (int)(nyi - (long long)rows * (pl->nty - 1));
+    const long long nxy = (long long)pl->ntx * pl->nty;
+    int dz = tu ? tu->planes_per_lane : 0;
+    if (!dz) {
+        dz = C3_DZMAX;
+        for (int d = 1; d <= C3_DZMAX; ++d)
+            if (nxy * ((nzi + d - 1) / d) <= cap) {
+                dz = d;
+                break;
             }
-        } else if (nt <= c) {
-            chosen = sh;
-            cap = c;
-            break;
-        } else {
-            chosen = sh;
-            cap = c;
-        }
     }
-    if (!chosen.ry) return set_error(PERKS_E_UNSUPPORTED, "no 3D tile shape matches the request");
-    pl->ry = chosen.ry;
-    pl->rz = chosen.rz;
-    pl->waves = chosen.waves;
-    pl->nty = (int)((nyi + chosen.ry - 1) / chosen.ry);
-    pl->ntz = (int)((nzi + chosen.rz - 1) / chosen.rz);
-    pl->last_h = (int)(nyi - (long long)chosen.ry * (pl->nty - 1));
-    pl->last_d = (int)(nzi - (long long)chosen.rz * (pl->ntz - 1));
-    const long long nt = (long long)pl->ntx * pl->nty * pl->ntz;
-    if (nt > (1LL << 30)) return set_error(PERKS_E_UNSUPPORTED, "too many tiles");
-    pl->ntiles = (int)nt;
-    long long cached = std::min<long long>(nt, cap);
+    dz = (int)std::min<long long>(dz, nzi);
+    pl->dz = dz;
+    pl->ntz = (int)((nzi + dz - 1) / dz);
+    pl->last_d = (int)(nzi - (long long)dz * (pl->ntz - 1));
+    const long long nc = nxy * pl->ntz;
+    if (nc > (1LL << 30)) return set_error(PERKS_E_UNSUPPORTED, "too many columns");
+    pl->ncols = (int)nc;
+    pl->wgs = (int)std::min(nc, cap);
+    long long cached = pl->wgs;
     if (tu && tu->max_cached_tiles < 0) cached = 0;
     if (tu && tu->max_cached_tiles > 0) cached = std::min<long long>(cached, tu->max_cached_tiles);
     pl->cached = (int)cached;
-    const long long waves = std::min<long long>(nt, cap);
-    pl->wgs = (int)((waves + chosen.waves - 1) / chosen.waves);
-    pl->fn = pick3d<T>(chosen.ry, chosen.rz, chosen.waves);
+    // every plane of every column in registers: the kernel without the
+    // streaming path (less code, fewer registers)
+    if (pl->cached == pl->ncols && dz <= NC)
+        pl->fn = reinterpret_cast<const void *>(&stencil3d_column<T, NC, false>);
     return PERKS_OK;
 }
 
@@ -562,33 +761,26 @@ void fill_weights3(Weights3D<T> &W, const double *c) {
     W.zp = (T)c[(2 * 3 + 1) * 3 + 1];
 }
 
-template <typename T>
-size_t faces3_elems(const perks_shape &s, int ntx, int nty, int ntz) {
-    return (size_t)2 * ((size_t)(2 * ntx + 2) * s.nz * s.ny + (size_t)(2 * nty + 2) * s.nz * s.nx +
-                        (size_t)(2 * ntz + 2) * s.ny * s.nx);
-}
-
 
 template <typename T>
 int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st,
           const perks_tuning *tu) {
-    Plan3D pl;
+    PlanCol pl;
     int rc = plan3d<T>(s, tu, &pl);
     if (rc) return rc;
-    Stencil3DParams<T> p{};
-    p.grid = grid;
+    Col3DParams<T> p{};
+    p.grid = to_global(grid);
     p.nx = (int)s.nx;
     p.ny = (int)s.ny;
     p.nz = (int)s.nz;
     p.ntx = pl.ntx;
     p.nty = pl.nty;
     p.ntz = pl.ntz;
-    p.RY = pl.ry;
-    p.RZ = pl.rz;
+    p.dz = pl.dz;
     p.last_w = pl.last_w;
-    p.last_h = pl.last_h;
+    p.last_rows = pl.last_rows;
     p.last_d = pl.last_d;
-    p.ntiles = pl.ntiles;
+    p.ncols = pl.ncols;
     p.cached = pl.cached;
     p.steps = steps;
     fill_weights3(p.W, coeffs);
@@ -598,11 +790,11 @@ int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hi
     T *faces = (T *)scratch(SLOT_FACES, (fx + fy + fz) * sizeof(T));
     unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
     if (!faces || !sync) return PERKS_E_NOMEM;
-    p.xface = faces;
-    p.yface = faces + fx;
-    p.zface = faces + fx + fy;
+    p.xface = to_global(faces);
+    p.yface = to_global(faces + fx);
+    p.zface = to_global(faces + fx + fy);
     p.sync = sync;
-    return launch_coop(pl.fn, pl.wgs, pl.waves * 64, &p, st);
+    return launch_coop(pl.fn, pl.wgs, C3_WAVES * 64, &p, st);
 }
 
 template <typename T>
@@ -610,7 +802,7 @@ int baseline3d(T *grid, const double *coeffs, const perks_shape &s, int64_t step
     const size_t cells = (size_t)s.nx * s.ny * s.nz;
     T *other = (T *)scratch(SLOT_PINGPONG, cells * sizeof(T));
     if (!other) return PERKS_E_NOMEM;
-    Stencil3DParams<T> p{};
+    Step3DParams<T> p{};
     p.nx = (int)s.nx;
     p.ny = (int)s.ny;
     p.nz = (int)s.nz;
@@ -631,8 +823,8 @@ int baseline3d(T *grid, const double *coeffs, const perks_shape &s, int64_t step
     const int wgs = (int)((nt + W3B - 1) / W3B);
     T *a = grid, *b = other;
     for (int64_t k = 0; k < steps; ++k) {
-        p.src = a;
-        p.dst = b;
+        p.src = to_global(a);
+        p.dst = to_global(b);
         hipLaunchKernelGGL((stencil3d_step<T, RYB, RZB, W3B>), dim3(wgs), dim3(W3B * 64), 0, st, p);
         std::swap(a, b);
     }
@@ -643,27 +835,30 @@ int baseline3d(T *grid, const double *coeffs, const perks_shape &s, int64_t step
 
 template <typename T>
 int plan3d_query(const perks_shape &s, const perks_tuning *tu, perks_stencil_plan *plan) {
-    Plan3D pl;
+    PlanCol pl;
     int rc = plan3d<T>(s, tu, &pl);
     if (rc) return rc;
     plan->wgs = pl.wgs;
-    plan->waves_per_wg = pl.waves;
-    plan->rows_per_lane = pl.ry;
-    plan->planes_per_lane = pl.rz;
-    plan->tiles = pl.ntiles;
+    plan->waves_per_wg = C3_WAVES;
+    plan->rows_per_lane = C3_RY;
+    plan->planes_per_lane = pl.dz;
+    plan->tiles = pl.ncols;
     plan->cached_tiles = pl.cached;
     plan->interior_cells = (s.nx - 2) * (s.ny - 2) * (s.nz - 2);
     int64_t cc = 0, face = 0;
-    for (int t = 0; t < pl.ntiles; ++t) {
-        int tx = t % pl.ntx, ty = (t / pl.ntx) % pl.nty, tz = t / (pl.ntx * pl.nty);
-        int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64, hy = ty == pl.nty - 1 ? pl.last_h : pl.ry,
-                dz = tz == pl.ntz - 1 ? pl.last_d : pl.rz;
-        if (t < pl.cached) cc += wx * hy * dz;
-        face += 2 * (2 * hy * dz + 2 * wx * dz + 2 * wx * hy);
+    for (int t = 0; t < pl.ncols; ++t) {
+        const int tx = t % pl.ntx, ty = (t / pl.ntx) % pl.nty, tz = t / (pl.ntx * pl.nty);
+        const int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64,
+                      rows = ty == pl.nty - 1 ? pl.last_rows : C3_WAVES * C3_RY,
+                      dz = tz == pl.ntz - 1 ? pl.last_d : pl.dz;
+        if (t < pl.cached) cc += wx * rows * std::min<int64_t>(dz, pl.nc);
+        // the column's outer faces, written and read once per step
+        face += 2 * (2 * rows * dz + 2 * wx * dz + 2 * wx * rows);
     }
     plan->cached_cells = cc;
     plan->halo_bytes_per_step = face * (int64_t)sizeof(T);
     plan->sync = 1;
+    plan->lds_rows_per_lane = 0;
     return PERKS_OK;
 }
 

@@ -194,26 +194,32 @@ def test_plan_reports_cached_share(pk):
     assert pl["interior_cells"] == 3070 * 3070
 
 
-@pytest.mark.parametrize("dtype,planes", [("float64", 4), ("float64", 8), ("float32", 4), ("float32", 8),
-                                          ("float32", 16)])
-def test_3d_tile_depths_match_baseline_bitwise(pk, dtype, planes):
-    """Every 3D tile shape (ragged in y and z, streamed and cached tiles) gives
-    the baseline's bits and the oracle's values."""
-    shape = (37, 23, 130)
+@pytest.mark.parametrize("dtype,planes", [("float64", 1), ("float64", 5), ("float64", 13), ("float64", 32),
+                                          ("float32", 3), ("float32", 8), ("float32", 32)])
+def test_3d_column_depths_match_baseline_bitwise(pk, dtype, planes):
+    """Every 3D column depth (ragged in x, y and z; all planes in registers,
+    and deeper than the register cache so that the bottom planes stream;
+    several columns per workgroup when the depth is small) gives the
+    baseline's bits and the oracle's values."""
+    shape = (37, 23, 131)     # interior 35 x 21 x 129: x tiles 64 + 64 + 1
     g = workloads.stencil_grid(shape, seed=21)
     w = workloads.stencil_weights("3d7pt")
     tdt = torch.float64 if dtype == "float64" else torch.float32
     if dtype == "float32":
         g = g.astype(np.float32).astype(np.float64)
         w = w.astype(np.float32).astype(np.float64)
-    a = _run(pk, g, w, 9, tdt, tuning={"planes_per_lane": planes})
-    c = _run(pk, g, w, 9, tdt, tuning={"planes_per_lane": planes, "max_cached_tiles": 7})
+    tu = {"planes_per_lane": planes}
+    a = _run(pk, g, w, 9, tdt, tuning=tu)
+    c = _run(pk, g, w, 9, tdt, tuning=dict(tu, max_cached_tiles=7))
+    n = _run(pk, g, w, 9, tdt, tuning=dict(tu, max_cached_tiles=-1))
     b = _run(pk, g, w, 9, tdt, baseline=True)
     np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(c, b)
+    np.testing.assert_array_equal(n, b)
     assert rel_err(a, oracle.stencil(g, w, 9)) <= (1e-12 if dtype == "float64" else 1e-5)
-    plan = pk.stencil_plan(shape, w, dtype, tuning={"planes_per_lane": planes})
+    plan = pk.stencil_plan(shape, w, dtype, tuning=tu)
     assert plan["planes_per_lane"] == planes
+    assert plan["tiles"] == 3 * 1 * -(-35 // planes)     # columns: 3 along x, 1 along y
 
 
 @pytest.mark.parametrize("kind,shape,dtype", [("2d5pt", (300, 520), "float64"), ("2d9pt", (257, 190), "float32"),
