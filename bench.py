@@ -35,6 +35,31 @@ FLOPS_PER_CELL = {"2d5pt": 10, "2d9pt": 18, "3d7pt": 14}
 PEAK_TFLOPS = {"float64": 78.6, "float32": 157.3}   # MI355X vector FP64 / FP32
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: the factors a 1 GiB device
+# copy reads back), with the SHA-256 of the kernel's source file they were
+# taken on: a changed source reports null until measured again.
+MEASURED_TRAFFIC = {
+    ("3d7pt", (256, 256, 256), "float64"): {
+        "bytes": 235.93e9,   # profiles/stencil3d_column_f64_256cubed.md
+        "source": "paper_2204_02064_amd/csrc/stencil3d.hpp",
+        "sha256": "ad2002d7c883d098423bc71ae043d090fd3b1be47c2d3c13c8f1d8567c57649b",
+    },
+}
+
+
+def measured_traffic(case):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(case)
+    if not m or m["bytes"] is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), m["source"])
+    try:
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return m["bytes"] if digest == m["sha256"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -385,8 +410,9 @@ def main():
             nbytes = (2 * pl["cached_cells"] * esz + 2 * STENCIL_STEPS * streamed * esz
                       + STENCIL_STEPS * pl["halo_bytes_per_step"])
             achieved = nbytes / t_dom / 1e9
+            traffic = measured_traffic(cases[dom])
             roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                         "algorithmic": f"Eq. 5: 2*{pl['cached_cells']} cached + 2*{STENCIL_STEPS}*{streamed} streamed "
                                        f"cells x {esz} B + {STENCIL_STEPS} x {pl['halo_bytes_per_step']} halo B"}
 

@@ -212,6 +212,7 @@ struct ColShared {
     T xs[C3_WAVES][2][C3_DZMAX][C3_RY];   // west / east face of each wave's rows, per plane
     T ysf[2][C3_DZMAX][64];               // south / north face of the column, per plane
     T ex[2][C3_WAVES][2][64];             // per-plane exchange (slot = plane parity): bottom / top row
+    T sink[C3_WAVES][64][C3_RY];          // edge writes of the lanes that hold no edge
 };
 
 // The fixed ring (both parities) from the grid.
@@ -331,45 +332,50 @@ __device__ __forceinline__ void col_plane(const Col3DParams<T> &p, const Col3D &
     const T yp = wr.last ? sh.ysf[1][iz][lane] : sh.ex[slot][w + 1][0][lane];
     const T *lw = &sh.xs[w][0][iz][0];
     const T *le = &sh.xs[w][1][iz][0];
-    if (lane >= c.wx) {
-        // ghost lanes carry the east face so the last real lane's DPP east
-        // shift picks it up
+    // ghost lanes carry the east face so the last real lane's DPP east shift
+    // picks it up (a select: no branch, no exec-mask change per plane)
+    const bool ghost = lane >= c.wx;
+    T e[RY];
 #pragma unroll
-        for (int iy = 0; iy < RY; ++iy) cur[iy] = le[iy];
-    }
+    for (int iy = 0; iy < RY; ++iy) e[iy] = le[iy];
+    settle(e);   // read by every lane: keeps the select below from becoming a branch
+#pragma unroll
+    for (int iy = 0; iy < RY; ++iy) cur[iy] = ghost ? e[iy] : cur[iy];
     const T last = compute_plane<T, RY, FULL>(cur, part, znext, wr.hy, ym, yp, lw, le, p.W);
     // The column's new west / east edges and south / north boundary rows go
     // to the LDS slots just consumed (xs[w], ysf), published to global memory
     // in one batch after the last plane; only the bottom and top planes are
-    // stored here.
-    T *nw = &sh.xs[w][0][iz][0];
-    T *ne = &sh.xs[w][1][iz][0];
+    // stored here.  Every lane writes its rows, unconditionally: lane 0 into
+    // the west slot, lane wx-1 into the east one, the others into a private
+    // sink (no exec-mask changes in the plane loop); rows beyond hy are
+    // never published.  With wx == 1 lane 0 holds both edges.
+    {
+        const bool edge = lane == 0 || lane == c.wx - 1;
+        T *dst = edge ? &sh.xs[w][lane == 0 ? 0 : 1][iz][0] : &sh.sink[w][lane][0];
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) {
-        if (FULL || iy < wr.hy) {
-            if (lane == 0) nw[iy] = cur[iy];
-            if (lane == c.wx - 1) ne[iy] = cur[iy];
+        for (int iy = 0; iy < RY; ++iy) dst[iy] = cur[iy];
+        if (c.wx == 1 && lane == 0) {
+#pragma unroll
+            for (int iy = 0; iy < RY; ++iy) sh.xs[w][1][iz][iy] = cur[iy];
         }
     }
-    if (lane < c.wx) {
-        if (wr.first) sh.ysf[0][iz][lane] = cur[0];
-        if (wr.last) sh.ysf[1][iz][lane] = last;
-        if (iz == 0 || iz == c.dz - 1) {
-            // plane index laundered: the addresses are formed here, not
-            // hoisted for every plane of the unrolled cached-plane loop
-            int z = __builtin_amdgcn_readfirstlane(iz == 0 ? 1 : 2);
-            asm volatile("" : "+s"(z));
-            gmem<T> *f = opaque(czf(p, par ^ 1, 2 * c.tz + z) + (size_t)wr.y0 * p.nx);
-            const unsigned xo = (unsigned)(c.x0 + lane);
+    if (wr.first) sh.ysf[0][iz][lane] = cur[0];
+    if (wr.last) sh.ysf[1][iz][lane] = last;
+    if ((iz == 0 || iz == c.dz - 1) && !ghost) {
+        // plane index laundered: the addresses are formed here, not
+        // hoisted for every plane of the unrolled cached-plane loop
+        int z = __builtin_amdgcn_readfirstlane(iz == 0 ? 1 : 2);
+        asm volatile("" : "+s"(z));
+        gmem<T> *f = opaque(czf(p, par ^ 1, 2 * c.tz + z) + (size_t)wr.y0 * p.nx);
+        const unsigned xo = (unsigned)(c.x0 + lane);
+#pragma unroll
+        for (int iy = 0; iy < RY; ++iy)
+            if (FULL || iy < wr.hy) st_coh(at(f, (unsigned)(iy * p.nx) + xo), cur[iy]);
+        if (iz == 0 && c.dz == 1) {
+            gmem<T> *f2 = opaque(czf(p, par ^ 1, 2 * c.tz + 2) + (size_t)wr.y0 * p.nx);
 #pragma unroll
             for (int iy = 0; iy < RY; ++iy)
-                if (FULL || iy < wr.hy) st_coh(at(f, (unsigned)(iy * p.nx) + xo), cur[iy]);
-            if (iz == 0 && c.dz == 1) {
-                gmem<T> *f2 = opaque(czf(p, par ^ 1, 2 * c.tz + 2) + (size_t)wr.y0 * p.nx);
-#pragma unroll
-                for (int iy = 0; iy < RY; ++iy)
-                    if (FULL || iy < wr.hy) st_coh(at(f2, (unsigned)(iy * p.nx) + xo), cur[iy]);
-            }
+                if (FULL || iy < wr.hy) st_coh(at(f2, (unsigned)(iy * p.nx) + xo), cur[iy]);
         }
     }
 }
