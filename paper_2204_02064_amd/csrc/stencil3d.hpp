@@ -125,6 +125,11 @@ constexpr int C3_RY = 4;      // rows per lane
 constexpr int C3_WAVES = 8;   // waves per workgroup (two per SIMD)
 constexpr int C3_DZMAX = 32;  // deepest column (LDS staging of its faces)
 constexpr int C3_SC = 2;      // planes per streamed chunk
+// planes of each workgroup's first column kept in LDS (streaming kernel
+// only): FP64 4 planes of 8 waves x 4 rows x 64 lanes = 64 KiB; FP32 none (its
+// register planes already cover the deepest column)
+template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 4 : 0; };
+template <typename T> using LdsPlane = T[C3_WAVES][C3_RY][64];
 // register-cached planes per lane: NC * RY values of 128 VGPRs
 template <typename T> struct C3Cache { static constexpr int NC = sizeof(T) == 8 ? 12 : 32; };
 
@@ -137,7 +142,8 @@ struct Col3DParams {
     int nx, ny, nz;
     int ntx, nty, ntz, dz;
     int last_w, last_rows, last_d;
-    int ncols, cached;   // cached: workgroups whose first column keeps planes in registers
+    int ncols, cached;   // cached: workgroups whose first column keeps planes on chip
+    int nlds;            // planes of a cached column kept in LDS (below the register planes)
     Weights3D<T> W;
 };
 
@@ -496,16 +502,18 @@ __device__ __forceinline__ void cached_planes(const Col3DParams<T> &p, const Col
     (cached_plane<T, NC, I>(p, c, wr, w, lane, par, nstream, ncache, v, zt, part, sh), ...);
 }
 
-// One step of column c: the streamed planes (bottom dz - ncache) then the
-// register-cached ones (top ncache, in v[0 .. ncache)).  STREAM = false: the
-// plan has every plane of every column in registers (nstream == 0).
+// One step of column c: the streamed planes (bottom dz - nlds - ncache),
+// the LDS-cached ones (next nlds, in lp) and the register-cached ones (top
+// ncache, in v[0 .. ncache)).  STREAM = false: the plan has every plane of
+// every column in registers (nstream == nlds == 0).
 template <typename T, int NC, bool STREAM>
 __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D &c, int w, int lane, int par,
-                                            int ncache, T (&v)[NC][C3_RY], ColShared<T> &sh) {
+                                            int ncache, int nlds, T (&v)[NC][C3_RY], LdsPlane<T> *lp,
+                                            ColShared<T> &sh) {
     constexpr int RY = C3_RY, SC = C3_SC;
     const WaveRows wr = rows_of(c, w);
     const int xl = min(c.x0 + lane, p.nx - 1);
-    const int nstream = STREAM ? c.dz - ncache : 0;
+    const int nstream = STREAM ? c.dz - ncache - nlds : 0;
     __syncthreads();   // the previous column's readers are done with sh
     T zb[RY], zt[RY];
     T sa[SC][RY], sb[SC][RY];
@@ -536,7 +544,7 @@ __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D
     // old values of the plane above the last streamed plane
     T above[RY];
 #pragma unroll
-    for (int iy = 0; iy < RY; ++iy) above[iy] = ncache > 0 ? v[0][iy] : zt[iy];
+    for (int iy = 0; iy < RY; ++iy) above[iy] = nlds > 0 ? lp[0][w][iy][lane] : ncache > 0 ? v[0][iy] : zt[iy];
     for (int j = 0; j < nstream; j += 2 * SC) {
         if (j + SC < nstream) load_chunk(p, c, wr, xl, j + SC, nstream, sb);
         if (nstream - j <= SC) {
@@ -559,12 +567,26 @@ __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D
         settle(sa[k]);
         settle(sb[k]);
     }
+    // LDS planes: read, updated, written back; the plane above the last one
+    // is the first register plane or the face above the column
+    for (int l = 0; l < nlds; ++l) {
+        T cur[RY], zn[RY];
+#pragma unroll
+        for (int iy = 0; iy < RY; ++iy) {
+            cur[iy] = lp[l][w][iy][lane];
+            zn[iy] = l + 1 < nlds ? lp[l + 1][w][iy][lane] : ncache > 0 ? v[0][iy] : zt[iy];
+        }
+        col_plane_any(p, c, wr, w, lane, par, nstream + l, cur, zn, part, sh);
+#pragma unroll
+        for (int iy = 0; iy < RY; ++iy) lp[l][w][iy][lane] = cur[iy];
+    }
     }
     // cached planes: the plane above the last one is v[ncache] (a free slot
     // when ncache < NC; with ncache == 0 there are none and v, which may
     // hold the workgroup's first column, is left alone) or the face above
     if (ncache > 0 && ncache < NC) put_plane<NC>(v, ncache, zt);
-    cached_planes<T, NC>(p, c, wr, w, lane, par, nstream, ncache, v, zt, part, sh, std::make_integer_sequence<int, NC>());
+    cached_planes<T, NC>(p, c, wr, w, lane, par, nstream + nlds, ncache, v, zt, part, sh,
+                         std::make_integer_sequence<int, NC>());
     __syncthreads();
     publish_faces_col(p, c, par, sh);
 }
@@ -574,6 +596,7 @@ __global__ __launch_bounds__(C3_WAVES * 64) __attribute__((amdgpu_waves_per_eu(1
 stencil3d_column(Col3DParams<T> p) {
     constexpr int RY = C3_RY;
     __shared__ ColShared<T> sh;
+    __shared__ LdsPlane<T> lp[STREAM && C3Lds<T>::L > 0 ? C3Lds<T>::L : 1];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     GridSync gs;
@@ -582,15 +605,22 @@ stencil3d_column(Col3DParams<T> p) {
     for (int t = blockIdx.x; t < p.ncols; t += gridDim.x) publish_initial_col(p, col_of(p, t), w, lane);
     gs.sync();
 
-    // the first column's top planes, in registers
+    // the first column's top planes, in registers, and the planes below
+    // them in LDS
     T v[NC][RY];
-    int ncache0 = 0;
+    int ncache0 = 0, nlds0 = 0;
     if ((int)blockIdx.x < p.ncols) {
         const Col3D c = col_of(p, blockIdx.x);
         const WaveRows wr = rows_of(c, w);
         ncache0 = (int)blockIdx.x < p.cached ? min(NC, c.dz) : 0;
+        nlds0 = STREAM && (int)blockIdx.x < p.cached ? min(p.nlds, c.dz - ncache0) : 0;
         const int xl = min(c.x0 + lane, p.nx - 1);
         const int zc = c.z0 + c.dz - ncache0;
+        for (int l = 0; l < nlds0; ++l)
+#pragma unroll
+            for (int iy = 0; iy < RY; ++iy)
+                lp[l][w][iy][lane] =
+                    iy < wr.hy ? p.grid[((size_t)(zc - nlds0 + l) * p.ny + wr.y0 + iy) * p.nx + xl] : T(0);
 #pragma unroll
         for (int i = 0; i < NC; ++i)
 #pragma unroll
@@ -613,14 +643,20 @@ stencil3d_column(Col3DParams<T> p) {
         q.zface = opaque(q.zface);
         int k = 0;
         for (int t = blockIdx.x; t < p.ncols; t += gridDim.x, ++k)
-            column_step<T, NC, STREAM>(q, col_of(q, t), w, lane, par, k == 0 ? ncache0 : 0, v, sh);
+            column_step<T, NC, STREAM>(q, col_of(q, t), w, lane, par, k == 0 ? ncache0 : 0, k == 0 ? nlds0 : 0, v,
+                                       lp, sh);
         gs.sync();
     }
-    if ((int)blockIdx.x < p.ncols && ncache0 > 0) {
+    if ((int)blockIdx.x < p.ncols && ncache0 + nlds0 > 0) {
         const Col3D c = col_of(p, blockIdx.x);
         const WaveRows wr = rows_of(c, w);
         const int zc = c.z0 + c.dz - ncache0;
         if (lane < c.wx) {
+            for (int l = 0; l < nlds0; ++l)
+#pragma unroll
+                for (int iy = 0; iy < RY; ++iy)
+                    if (iy < wr.hy)
+                        p.grid[((size_t)(zc - nlds0 + l) * p.ny + wr.y0 + iy) * p.nx + c.x0 + lane] = lp[l][w][iy][lane];
 #pragma unroll
             for (int i = 0; i < NC; ++i)
 #pragma unroll
@@ -693,7 +729,7 @@ constexpr int RYB = 4, RZB = 8;
 
 struct PlanCol {
     int dz = 0, ntx = 0, nty = 0, ntz = 0, last_w = 0, last_rows = 0, last_d = 0, ncols = 0, cached = 0, wgs = 0,
-        nc = 0;
+        nc = 0, nlds = 0;
     const void *fn = nullptr;
 };
 
@@ -751,8 +787,11 @@ int plan3d(const perks_shape &s, const perks_tuning *tu, PlanCol *pl) {
     pl->cached = (int)cached;
     // every plane of every column in registers: the kernel without the
     // streaming path (less code, fewer registers)
-    if (pl->cached == pl->ncols && dz <= NC)
+    pl->nlds = pl->cached > 0 ? C3Lds<T>::L : 0;
+    if (pl->cached == pl->ncols && dz <= NC) {
         pl->fn = reinterpret_cast<const void *>(&stencil3d_column<T, NC, false>);
+        pl->nlds = 0;
+    }
     return PERKS_OK;
 }
 
@@ -788,6 +827,7 @@ int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hi
     p.last_d = pl.last_d;
     p.ncols = pl.ncols;
     p.cached = pl.cached;
+    p.nlds = pl.nlds;
     p.steps = steps;
     fill_weights3(p.W, coeffs);
     const size_t fx = (size_t)2 * (2 * pl.ntx + 2) * s.nz * s.ny;
@@ -857,14 +897,14 @@ int plan3d_query(const perks_shape &s, const perks_tuning *tu, perks_stencil_pla
         const int64_t wx = tx == pl.ntx - 1 ? pl.last_w : 64,
                       rows = ty == pl.nty - 1 ? pl.last_rows : C3_WAVES * C3_RY,
                       dz = tz == pl.ntz - 1 ? pl.last_d : pl.dz;
-        if (t < pl.cached) cc += wx * rows * std::min<int64_t>(dz, pl.nc);
+        if (t < pl.cached) cc += wx * rows * std::min<int64_t>(dz, pl.nc + pl.nlds);
         // the column's outer faces, written and read once per step
         face += 2 * (2 * rows * dz + 2 * wx * dz + 2 * wx * rows);
     }
     plan->cached_cells = cc;
     plan->halo_bytes_per_step = face * (int64_t)sizeof(T);
     plan->sync = 1;
-    plan->lds_rows_per_lane = 0;
+    plan->lds_rows_per_lane = pl.nlds;   // 3D: planes of each cached column in LDS
     return PERKS_OK;
 }
 
