@@ -254,7 +254,7 @@ def bench_learned(pk, torch, args):
             e = {"n": n, "seed": s}
             for label, fn in (("jacobi_pcg", lambda: pk.cg_solve(A, f, x, tol=1e-8, maxit=20000, precond="jacobi")),
                               ("fcg_net", lambda: pk.fcg_solve(A, f, x, n, n, params=params, logk=lk, tol=1e-8,
-                                                               maxit=20000, stall=20))):
+                                                               maxit=20000, stall=args.nn_stall))):
                 x.zero_()
                 fn()
                 t, info = _time(lambda: (x.zero_(), fn())[1], torch, 2)
@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned preconditioner")
     ap.add_argument("--nn-fields", type=int, default=200, help="training fields (256^2) for the network")
     ap.add_argument("--nn-epochs", type=int, default=3)
+    ap.add_argument("--nn-stall", type=int, default=20,
+                    help="FCG iterations without a new residual minimum before it continues as Jacobi-PCG")
     ap.add_argument("--nn-test", type=int, default=2, help="held-out problems per size")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batched-baseline", action="store_true",

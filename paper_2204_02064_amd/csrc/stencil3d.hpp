@@ -126,9 +126,9 @@ constexpr int C3_WAVES = 8;   // waves per workgroup (two per SIMD)
 constexpr int C3_DZMAX = 32;  // deepest column (LDS staging of its faces)
 constexpr int C3_SC = 2;      // planes per streamed chunk
 // planes of each workgroup's first column kept in LDS (streaming kernel
-// only): FP64 4 planes of 8 waves x 4 rows x 64 lanes = 64 KiB; FP32 none (its
+// only): FP64 3 planes of 8 waves x 4 rows x 64 lanes = 48 KiB; FP32 none (its
 // register planes already cover the deepest column)
-template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 4 : 0; };
+template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 3 : 0; };
 template <typename T> using LdsPlane = T[C3_WAVES][C3_RY][64];
 // register-cached planes per lane: NC * RY values of 128 VGPRs
 template <typename T> struct C3Cache { static constexpr int NC = sizeof(T) == 8 ? 12 : 32; };
@@ -217,7 +217,7 @@ template <typename T>
 struct ColShared {
     T xs[C3_WAVES][2][C3_DZMAX][C3_RY];   // west / east face of each wave's rows, per plane
     T ysf[2][C3_DZMAX][64];               // south / north face of the column, per plane
-    T ex[2][C3_WAVES][2][64];             // per-plane exchange (slot = plane parity): bottom / top row
+    T ex[2][2][C3_WAVES][2][64];          // exchange [slot][plane of the pair][wave]: bottom / top row
     T sink[C3_WAVES][64][C3_RY];          // edge writes of the lanes that hold no edge
 };
 
@@ -313,29 +313,28 @@ __device__ __forceinline__ void stage_faces_col(const Col3DParams<T> &p, const C
         if (tid + k * NT < NYV) ys[tid + k * NT] = yv[k];
 }
 
-// One plane iz of wave w's rows: exchange of the edge rows' old values with
-// the neighbouring waves (one workgroup barrier; every wave of the workgroup
-// calls this for every plane of the column), the update of cur in place, and
-// the new values of the column's outer faces published to parity par ^ 1.
-// Returns with cur holding the new values.
+// Old values of the bottom and top rows of one plane of wave w's rows, posted
+// for the neighbouring waves (exchange slot `slot`, plane k of the pair).
 template <typename T, bool FULL>
-__device__ __forceinline__ void col_plane(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
-                                          int lane, int par, int iz, T (&cur)[C3_RY], const T (&znext)[C3_RY],
-                                          T (&part)[C3_RY], ColShared<T> &sh) {
-    constexpr int RY = C3_RY;
-    const int slot = iz & 1;
-    if (wr.hy > 0) {
-        T top = cur[0];
+__device__ __forceinline__ void post_rows(const WaveRows &wr, int w, int lane, int slot, int k,
+                                          const T (&cur)[C3_RY], ColShared<T> &sh) {
+    T top = cur[0];
 #pragma unroll
-        for (int iy = 1; iy < RY; ++iy)
-            if (FULL || iy < wr.hy) top = cur[iy];
-        sh.ex[slot][w][0][lane] = cur[0];
-        sh.ex[slot][w][1][lane] = top;
-    }
-    __syncthreads();
-    if (wr.hy == 0) return;
-    const T ym = wr.first ? sh.ysf[0][iz][lane] : sh.ex[slot][w - 1][1][lane];
-    const T yp = wr.last ? sh.ysf[1][iz][lane] : sh.ex[slot][w + 1][0][lane];
+    for (int iy = 1; iy < C3_RY; ++iy)
+        if (FULL || iy < wr.hy) top = cur[iy];
+    sh.ex[slot][k][w][0][lane] = cur[0];
+    sh.ex[slot][k][w][1][lane] = top;
+}
+
+// Plane iz of wave w's rows, after the exchange: the neighbours' rows, the
+// update of cur in place, and the new values of the column's outer faces.
+template <typename T, bool FULL>
+__device__ __forceinline__ void plane_work(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                           int lane, int par, int iz, int slot, int k, T (&cur)[C3_RY],
+                                           const T (&znext)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+    constexpr int RY = C3_RY;
+    const T ym = wr.first ? sh.ysf[0][iz][lane] : sh.ex[slot][k][w - 1][1][lane];
+    const T yp = wr.last ? sh.ysf[1][iz][lane] : sh.ex[slot][k][w + 1][0][lane];
     const T *lw = &sh.xs[w][0][iz][0];
     const T *le = &sh.xs[w][1][iz][0];
     // ghost lanes carry the east face so the last real lane's DPP east shift
@@ -386,6 +385,44 @@ __device__ __forceinline__ void col_plane(const Col3DParams<T> &p, const Col3D &
     }
 }
 
+
+// One or two consecutive planes (iz, and iz + 1 when `two`) of wave w's rows
+// behind one workgroup barrier: each wave posts the old values of its edge
+// rows of both planes, then updates them (a in place with the plane above
+// being b, then b with zn; a alone with zn when !two).  Every wave of the
+// workgroup calls this for the same planes; `phase` alternates the exchange
+// slot from one call to the next.
+template <typename T, bool FULL>
+__device__ __forceinline__ void col_pair(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                         int lane, int par, int iz, bool two, int &phase, T (&a)[C3_RY],
+                                         T (&b)[C3_RY], const T (&zn)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+    const int slot = phase;
+    phase ^= 1;
+    if (wr.hy > 0) {
+        post_rows<T, FULL>(wr, w, lane, slot, 0, a, sh);
+        if (two) post_rows<T, FULL>(wr, w, lane, slot, 1, b, sh);
+    }
+    __syncthreads();
+    if (wr.hy == 0) return;
+    if (two) {
+        plane_work<T, FULL>(p, c, wr, w, lane, par, iz, slot, 0, a, b, part, sh);
+        plane_work<T, FULL>(p, c, wr, w, lane, par, iz + 1, slot, 1, b, zn, part, sh);
+    } else {
+        plane_work<T, FULL>(p, c, wr, w, lane, par, iz, slot, 0, a, zn, part, sh);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void col_pair_any(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                             int lane, int par, int iz, bool two, int &phase, T (&a)[C3_RY],
+                                             T (&b)[C3_RY], const T (&zn)[C3_RY], T (&part)[C3_RY],
+                                             ColShared<T> &sh) {
+    if (wr.hy == C3_RY)
+        col_pair<T, true>(p, c, wr, w, lane, par, iz, two, phase, a, b, zn, part, sh);
+    else
+        col_pair<T, false>(p, c, wr, w, lane, par, iz, two, phase, a, b, zn, part, sh);
+}
+
 // Publish the column's west / east edges and south / north boundary rows,
 // gathered in LDS during the step, to parity par ^ 1 (the whole workgroup,
 // after a barrier).
@@ -411,16 +448,6 @@ __device__ __forceinline__ void publish_faces_col(const Col3DParams<T> &p, const
         const int x = e % 64, iz = (e / 64) % C3_DZMAX, side = e / (64 * C3_DZMAX);
         if (iz < c.dz && x < c.wx) st_coh(at(side ? fn : fs, (unsigned)(iz * p.nx + x)), ys[e]);
     }
-}
-
-template <typename T>
-__device__ __forceinline__ void col_plane_any(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
-                                              int lane, int par, int iz, T (&cur)[C3_RY], const T (&znext)[C3_RY],
-                                              T (&part)[C3_RY], ColShared<T> &sh) {
-    if (wr.hy == C3_RY)
-        col_plane<T, true>(p, c, wr, w, lane, par, iz, cur, znext, part, sh);
-    else
-        col_plane<T, false>(p, c, wr, w, lane, par, iz, cur, znext, part, sh);
 }
 
 // Loads of streamed planes [j, j + SC) (those below `n`) of wave w's rows.
@@ -457,49 +484,60 @@ __device__ __forceinline__ void put_plane(T (&rows)[N][C3_RY], int k, const T (&
         for (int iy = 0; iy < C3_RY; ++iy) rows[i][iy] = i == k ? src[iy] : rows[i][iy];
 }
 
-// Streamed planes [j, j + SC) of the column from buf (planes below nstream);
-// the plane after buf's last is nxt[0].  The caller has put the plane above
-// the last streamed one where the chunk that ends the stream looks for it.
+// Streamed planes j, j + 1 (those below nstream) of the column from buf, as
+// one pair; the plane after buf's last is nxt[0].  The caller has put the
+// plane above the last streamed one where the chunk that ends the stream
+// looks for it (buf[1] when only plane j remains).
 template <typename T>
 __device__ __forceinline__ void run_chunk(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
-                                          int lane, int par, int j, int nstream, T (&buf)[C3_SC][C3_RY],
-                                          const T (&nxt)[C3_SC][C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+                                          int lane, int par, int j, int nstream, int &phase,
+                                          T (&buf)[C3_SC][C3_RY], const T (&nxt)[C3_SC][C3_RY], T (&part)[C3_RY],
+                                          ColShared<T> &sh) {
+    static_assert(C3_SC == 2, "a streamed chunk is one pair of planes");
     // the chunk's loads complete here, once, not at every later use
 #pragma unroll
     for (int k = 0; k < C3_SC; ++k) settle(buf[k]);
+    const bool two = j + 1 < nstream;
+    T zn[C3_RY];
 #pragma unroll
-    for (int k = 0; k < C3_SC; ++k) {
-        const int iz = j + k;
-        if (iz < nstream) {
-            if (k + 1 < C3_SC)
-                col_plane_any(p, c, wr, w, lane, par, iz, buf[k], buf[k + 1 < C3_SC ? k + 1 : 0], part, sh);
-            else
-                col_plane_any(p, c, wr, w, lane, par, iz, buf[k], nxt[0], part, sh);
-            if (wr.hy > 0) store_plane(p, c, wr, lane, iz, buf[k]);
-        }
+    for (int iy = 0; iy < C3_RY; ++iy) zn[iy] = two ? nxt[0][iy] : buf[1][iy];
+    col_pair_any(p, c, wr, w, lane, par, j, two, phase, buf[0], buf[1], zn, part, sh);
+    if (wr.hy > 0) {
+        store_plane(p, c, wr, lane, j, buf[0]);
+        if (two) store_plane(p, c, wr, lane, j + 1, buf[1]);
     }
 }
 
-// Cached plane I (compile-time, so that v is indexed statically: the planes
-// are expanded by a fold, not by the loop unroller, whose size limit would
-// otherwise leave v in scratch memory).
+// Cached planes I and I + 1 (I even, compile-time, so that v is indexed
+// statically: the planes are expanded by a fold, not by the loop unroller,
+// whose size limit would otherwise leave v in scratch memory).  v[ncache]
+// holds the plane above the last cached one when ncache < NC.
 template <typename T, int NC, int I>
-__device__ __forceinline__ void cached_plane(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
-                                             int lane, int par, int nstream, int ncache, T (&v)[NC][C3_RY],
-                                             const T (&zt)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
-    if (I < ncache) {
-        if constexpr (I + 1 < NC)
-            col_plane_any(p, c, wr, w, lane, par, nstream + I, v[I], v[I + 1], part, sh);
-        else
-            col_plane_any(p, c, wr, w, lane, par, nstream + I, v[I], zt, part, sh);
+__device__ __forceinline__ void cached_pair(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
+                                            int lane, int par, int iz0, int ncache, int &phase, T (&v)[NC][C3_RY],
+                                            const T (&zt)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh) {
+    static_assert(NC % 2 == 0, "register planes come in pairs");
+    if constexpr (I % 2 == 0) {
+        if (I < ncache) {
+            const bool two = I + 1 < ncache;
+            T zn[C3_RY];
+#pragma unroll
+            for (int iy = 0; iy < C3_RY; ++iy) {
+                if constexpr (I + 2 < NC)
+                    zn[iy] = two ? v[I + 2][iy] : v[I + 1][iy];
+                else
+                    zn[iy] = two ? zt[iy] : v[I + 1][iy];
+            }
+            col_pair_any(p, c, wr, w, lane, par, iz0 + I, two, phase, v[I], v[I + 1], zn, part, sh);
+        }
     }
 }
 template <typename T, int NC, int... I>
 __device__ __forceinline__ void cached_planes(const Col3DParams<T> &p, const Col3D &c, const WaveRows &wr, int w,
-                                              int lane, int par, int nstream, int ncache, T (&v)[NC][C3_RY],
+                                              int lane, int par, int iz0, int ncache, int &phase, T (&v)[NC][C3_RY],
                                               const T (&zt)[C3_RY], T (&part)[C3_RY], ColShared<T> &sh,
                                               std::integer_sequence<int, I...>) {
-    (cached_plane<T, NC, I>(p, c, wr, w, lane, par, nstream, ncache, v, zt, part, sh), ...);
+    (cached_pair<T, NC, I>(p, c, wr, w, lane, par, iz0, ncache, phase, v, zt, part, sh), ...);
 }
 
 // One step of column c: the streamed planes (bottom dz - nlds - ncache),
@@ -540,6 +578,7 @@ __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D
     T part[RY];
 #pragma unroll
     for (int iy = 0; iy < RY; ++iy) part[iy] = p.W.zm * zb[iy];
+    int phase = 0;
     if constexpr (STREAM) {
     // old values of the plane above the last streamed plane
     T above[RY];
@@ -551,14 +590,14 @@ __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D
             put_plane<SC>(sa, nstream - j, above);
             put_plane<SC>(sb, nstream - j - SC, above);
         }
-        run_chunk(p, c, wr, w, lane, par, j, nstream, sa, sb, part, sh);
+        run_chunk(p, c, wr, w, lane, par, j, nstream, phase, sa, sb, part, sh);
         if (j + SC >= nstream) break;
         if (j + 2 * SC < nstream) load_chunk(p, c, wr, xl, j + 2 * SC, nstream, sa);
         if (nstream - j - SC <= SC) {
             put_plane<SC>(sb, nstream - j - SC, above);
             put_plane<SC>(sa, nstream - j - 2 * SC, above);
         }
-        run_chunk(p, c, wr, w, lane, par, j + SC, nstream, sb, sa, part, sh);
+        run_chunk(p, c, wr, w, lane, par, j + SC, nstream, phase, sb, sa, part, sh);
     }
     // no chunk load is left in flight; telling the compiler so keeps it from
     // waiting for one (and for every store after it) in the cached planes
@@ -569,23 +608,29 @@ __device__ __forceinline__ void column_step(const Col3DParams<T> &p, const Col3D
     }
     // LDS planes: read, updated, written back; the plane above the last one
     // is the first register plane or the face above the column
-    for (int l = 0; l < nlds; ++l) {
-        T cur[RY], zn[RY];
+    for (int l = 0; l < nlds; l += 2) {
+        const bool two = l + 1 < nlds;
+        const int la = l + (two ? 2 : 1);   // the plane above the pair (or the single plane)
+        T a[RY], b[RY], zn[RY];
 #pragma unroll
         for (int iy = 0; iy < RY; ++iy) {
-            cur[iy] = lp[l][w][iy][lane];
-            zn[iy] = l + 1 < nlds ? lp[l + 1][w][iy][lane] : ncache > 0 ? v[0][iy] : zt[iy];
+            a[iy] = lp[l][w][iy][lane];
+            b[iy] = two ? lp[l + 1][w][iy][lane] : T(0);
+            zn[iy] = la < nlds ? lp[la][w][iy][lane] : ncache > 0 ? v[0][iy] : zt[iy];
         }
-        col_plane_any(p, c, wr, w, lane, par, nstream + l, cur, zn, part, sh);
+        col_pair_any(p, c, wr, w, lane, par, nstream + l, two, phase, a, b, zn, part, sh);
 #pragma unroll
-        for (int iy = 0; iy < RY; ++iy) lp[l][w][iy][lane] = cur[iy];
+        for (int iy = 0; iy < RY; ++iy) {
+            lp[l][w][iy][lane] = a[iy];
+            if (two) lp[l + 1][w][iy][lane] = b[iy];
+        }
     }
     }
     // cached planes: the plane above the last one is v[ncache] (a free slot
     // when ncache < NC; with ncache == 0 there are none and v, which may
     // hold the workgroup's first column, is left alone) or the face above
     if (ncache > 0 && ncache < NC) put_plane<NC>(v, ncache, zt);
-    cached_planes<T, NC>(p, c, wr, w, lane, par, nstream + nlds, ncache, v, zt, part, sh,
+    cached_planes<T, NC>(p, c, wr, w, lane, par, nstream + nlds, ncache, phase, v, zt, part, sh,
                          std::make_integer_sequence<int, NC>());
     __syncthreads();
     publish_faces_col(p, c, par, sh);
