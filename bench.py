@@ -144,6 +144,42 @@ def bench_cg(pk, torch, args):
     return out
 
 
+def bench_batched_stencil(pk, torch, args):
+    """512 2D 5-point FP64 grids, sides round(exp(U[ln 64, ln 1024])), 100 Jacobi
+    steps each: one batched persistent launch vs one persistent launch per grid
+    vs one launch per step per grid (HIP events on the current stream)."""
+    import numpy as np
+
+    import workloads
+    count, steps = args.batch_count, 100
+    sides = workloads.lognormal_sides(count, seed=0)
+    w = workloads.stencil_weights("2d5pt")
+    grids = [torch.from_numpy(workloads.stencil_grid((int(n), int(n)), seed=j)).cuda() for j, n in enumerate(sides)]
+    cells = sum(interior((int(n), int(n))) for n in sides) * steps
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()                                   # warm-up (plans, scratch)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    t_batch = timed(lambda: pk.stencil_run_batched(grids, w, steps))
+    t_seq = timed(lambda: [pk.stencil_run(g, w, steps) for g in grids])
+    t_base = timed(lambda: [pk.stencil_run_baseline(g, w, steps) for g in grids])
+    log(f"batched stencil: {count} 2d5pt FP64 grids ({cells / steps / 1e6:.1f}M cells), {steps} steps: one launch "
+        f"{t_batch * 1e3:.2f} ms ({cells / t_batch / 1e9:.1f} GCells/s) | per-grid persistent {t_seq * 1e3:.2f} ms "
+        f"(x{t_seq / t_batch:.2f}) | per-step launches {t_base * 1e3:.2f} ms (x{t_base / t_batch:.2f})")
+    return {"grids": count, "steps": steps, "cells": int(cells // steps), "batched_ms": t_batch * 1e3,
+            "batched_gcells": cells / t_batch / 1e9, "per_grid_persistent_ms": t_seq * 1e3,
+            "per_step_launch_ms": t_base * 1e3, "speedup_vs_per_grid": t_seq / t_batch,
+            "speedup_vs_per_step": t_base / t_batch}
+
+
 def bench_batched(pk, torch, args):
     """512 independent 2D 5-point Poisson systems, sides round(exp(U[ln 64, ln 1024])),
     rhs N(0,1), mixed precision to 1e-8 each: one batched persistent launch vs the
@@ -241,11 +277,10 @@ def bench_learned(pk, torch, args):
     t_train = time.perf_counter() - t0
     rec = {"train_fields": n_train, "pairs": int(X.shape[0]), "harvest_s": t_harvest, "train_s": t_train,
            "loss": "energy norm of the output error (||z - e||_A^2 up to a constant)",
-           "epochs": args.nn_epochs, "loss_first": float(np.mean(losses[:20])),
-           "loss_last": float(np.mean(losses[-20:])), "eval": []}
+           "epochs": args.nn_epochs, "loss_per_epoch": [float(l) for l in losses], "eval": []}
     del X, T, planes
-    log(f"learned: {rec['pairs']} pairs from {n_train} fields in {t_harvest:.1f} s; trained {len(losses)} steps "
-        f"in {t_train:.1f} s, loss {rec['loss_first']:.3e} -> {rec['loss_last']:.3e}")
+    log(f"learned: {rec['pairs']} pairs from {n_train} fields in {t_harvest:.1f} s; trained {len(losses)} epochs "
+        f"in {t_train:.1f} s, loss per epoch {losses[0]:.3e} -> {losses[-1]:.3e}")
     for n in (256, 512, 1024):
         for s in range(10000, 10000 + args.nn_test):
             rp, ci, v, lk, f = workloads.diffusion_problem_torch(n, seed=s)
@@ -446,6 +481,7 @@ def main():
     if not args.no_cg:
         out["cg"] = bench_cg(pk, torch, args)
     if not args.no_batched:
+        out["batched_stencil"] = bench_batched_stencil(pk, torch, args)
         out["batched_cg"] = bench_batched(pk, torch, args)
     if not args.no_learned:
         out["learned_preconditioner"] = bench_learned(pk, torch, args)

@@ -327,6 +327,25 @@ int perks_nn_energy_grad(const float *params, const float *x, const float *plane
 int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr,
                   float beta1, float beta2, float eps, void *stream);
 
+/* Training of the network on P samples, every pass on the device: `epochs`
+ * passes over the samples in a fresh seeded order each (splitmix64 from
+ * `seed`, Fisher-Yates shuffle), mini-batches of `batch` samples (the last
+ * P % batch of an order are skipped), each one forward + backward pass and
+ * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, rate lr).
+ *   params  device, PERKS_NN_PARAMS floats: the initial weights in, the
+ *           trained ones out; m, v: device Adam moments (zero to start afresh)
+ *   x       device [P][H][W][2] network inputs
+ *   target  device [P][H][W] targets of the MSE loss, or NULL for the energy
+ *           loss of perks_nn_energy_grad in its Jacobi form with
+ *   planes  device [F][5][H][W] operators and field (device int32 [P]) the
+ *           operator of each sample
+ *   step    host in/out: Adam steps taken so far (0 to start)
+ *   losses  host, `epochs` doubles (mean batch loss of each epoch) or NULL
+ * Requires batch <= P, H even and W <= 512.  Synchronises the stream. */
+int perks_nn_train(float *params, const float *x, const float *target, const float *planes, const int32_t *field,
+                   int32_t P, int32_t H, int32_t W, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                   float *m, float *v, int32_t *step, double *losses, void *stream);
+
 /*
  * perks_fcg_solve -- flexible CG preconditioned by the network, one
  * persistent launch.  FCG(1): p = z - (<z, q_old> / <p_old, q_old>) p_old,

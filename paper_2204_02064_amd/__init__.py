@@ -115,7 +115,9 @@ def lib():
     L.perks_nn_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, vp]
     L.perks_nn_energy_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
-    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad"):
+    L.perks_nn_train.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
+    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad", "perks_nn_train"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("perks_stencil_run", "perks_stencil_run_baseline", "perks_stencil_plan_query",
                  "perks_device_query", "perks_cg_solve", "perks_cg_solve_baseline", "perks_cg_batch_create",
@@ -473,6 +475,35 @@ def nn_energy_grad(params, x, planes, grad=None, stream=None, jacobi=True):
                                       ctypes.c_void_p(grad.data_ptr()),
                                       ctypes.byref(loss), _stream_handle(stream)))
     return loss.value, grad
+
+
+def nn_train(params, x, epochs, batch, lr=1e-3, seed=0, target=None, planes=None, field=None, m=None, v=None,
+             step=0, stream=None):
+    """Adam training on the device (perks_nn_train): params is updated in place.
+    Give ``target`` ([P, H, W], MSE loss) or ``planes`` ([F, 5, H, W]) with
+    ``field`` ([P] int32, operator of each sample: energy loss, Jacobi form).
+    Returns (per-epoch mean losses, Adam step count, m, v)."""
+    import torch
+    P, H, W, _ = x.shape
+    _check_f32(params, NN_PARAMS, "params")
+    _check_f32(x, P * H * W * 2, "x")
+    if (target is None) == (planes is None):
+        raise ValueError("give target or planes")
+    if target is not None:
+        _check_f32(target, P * H * W, "target")
+    else:
+        _check_f32(planes, planes.shape[0] * 5 * H * W, "planes")
+        if field is None or field.dtype != torch.int32 or field.numel() != P or not field.is_contiguous():
+            raise ValueError("field must be a contiguous int32 tensor of P entries")
+    m = torch.zeros(NN_PARAMS, dtype=torch.float32, device=x.device) if m is None else m
+    v = torch.zeros_like(m) if v is None else v
+    st = ctypes.c_int32(int(step))
+    losses = (ctypes.c_double * max(1, int(epochs)))()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    _check(lib().perks_nn_train(ptr(params), ptr(x), ptr(target), ptr(planes), ptr(field), P, H, W, int(epochs),
+                                int(batch), float(lr), int(seed) & ((1 << 64) - 1), ptr(m), ptr(v), ctypes.byref(st),
+                                losses, _stream_handle(stream)))
+    return [losses[i] for i in range(int(epochs))], st.value, m, v
 
 
 def nn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -398,10 +398,25 @@ int perks_nn_forward(const float *params, const float *x, int32_t B, int32_t H, 
 
 namespace {
 
+__global__ void nn_accum(const double *scal, double *acc, double scale) {
+    if (threadIdx.x == 0) acc[0] += scal[0] * scale;
+}
+
+// dst[b][e] = src[idx[b]][e] for b < n, e < elems.
+__global__ __launch_bounds__(256) void nn_gather(const float *src, const int *idx, int n, int64_t elems, float *dst) {
+    const int64_t total = (int64_t)n * elems;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t b = i / elems, e = i % elems;
+        dst[i] = src[(int64_t)idx[b] * elems + e];
+    }
+}
+
 // Forward, loss (MSE against target, or the energy functional with the
-// 5-point planes), backward: grad and (if loss) the loss.
+// 5-point planes), backward: grad and (if loss) the loss; with loss_acc the
+// loss times acc_scale is also added to that device double (no sync).
 int loss_grad_impl(const float *params, const float *x, const float *target, const float *planes, int jacobi, int B,
-                   int H, int W, float *grad, double *loss, hipStream_t st) {
+                   int H, int W, float *grad, double *loss, hipStream_t st, double *loss_acc = nullptr,
+                   double acc_scale = 0.0) {
     if (!params || !x || !grad || (!target && !planes)) return set_error(PERKS_E_INVAL, "NULL argument");
     int rc = check_dims(B, H, W);
     if (rc) return rc;
@@ -422,6 +437,9 @@ int loss_grad_impl(const float *params, const float *x, const float *target, con
         hipLaunchKernelGGL(nn_loss, dim3(nb), dim3(256), 0, st, (const float *)w.out, target, (int)P,
                            1.0f / (float)P, w.g0, w.part);
     hipLaunchKernelGGL(nn_reduce_f64, dim3(1), dim3(256), 0, st, (const double *)w.part, (int)nb, w.scal);
+    if (loss_acc)
+        hipLaunchKernelGGL(nn_accum, dim3(1), dim3(64), 0, st, (const double *)w.scal, loss_acc,
+                           acc_scale / (double)P);
     const size_t fl = 5 * 64 * 8;
     unsigned short *g = w.g0, *gn = w.g1;
     const int rows = B * H;
@@ -475,6 +493,106 @@ int perks_nn_adam(float *params, const float *grad, float *m, float *v, int32_t 
     const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
     hipLaunchKernelGGL(nn_adam, dim3((n + 255) / 256), dim3(256), 0, st, params, grad, m, v, n, lr, beta1, beta2, eps,
                        c1, c2);
+    PERKS_HIP_TRY(hipGetLastError());
+    return PERKS_OK;
+}
+
+int perks_nn_train(float *params, const float *x, const float *target, const float *planes, const int32_t *field,
+                   int32_t P, int32_t H, int32_t W, int32_t epochs, int32_t batch, float lr, uint64_t seed, float *m,
+                   float *v, int32_t *step, double *losses, void *stream) {
+    if (!params || !x || !m || !v || !step) return set_error(PERKS_E_INVAL, "NULL argument");
+    if ((target != nullptr) == (planes != nullptr)) return set_error(PERKS_E_INVAL, "give target or planes, not both");
+    if (planes && !field) return set_error(PERKS_E_INVAL, "planes need field");
+    if (P < 1 || batch < 1 || batch > P || epochs < 0) return set_error(PERKS_E_INVAL, "bad P, batch or epochs");
+    if (!(lr > 0.f)) return set_error(PERKS_E_INVAL, "lr must be > 0");
+    if (*step < 0) return set_error(PERKS_E_INVAL, "step must be >= 0");
+    int rc = check_dims(batch, H, W);
+    if (rc) return rc;
+    if (H % DW_ROWS != 0) return set_error(PERKS_E_UNSUPPORTED, "H must be a multiple of %d", DW_ROWS);
+    if (W > DW_MAXW) return set_error(PERKS_E_UNSUPPORTED, "W must be <= %d for training", DW_MAXW);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t px = (int64_t)H * W;
+    std::vector<int> fld;
+    if (planes) {
+        fld.resize(P);
+        PERKS_HIP_TRY(hipMemcpyAsync(fld.data(), field, (size_t)P * sizeof(int), hipMemcpyDeviceToHost, st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+    }
+    // batch buffers: indices (samples, operators), inputs, targets or planes,
+    // gradient, loss accumulator
+    const size_t bx = (size_t)batch * px * 2, bt = (size_t)batch * px * (planes ? 5 : 1);
+    char *buf = nullptr;
+    const size_t bytes = 2 * 256 + (size_t)batch * 2 * sizeof(int) + (bx + bt + PERKS_NN_PARAMS) * sizeof(float) + 64;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(PERKS_E_NOMEM, "nn_train: %zu bytes", bytes);
+    }
+    double *acc = reinterpret_cast<double *>(buf);
+    int *idx = reinterpret_cast<int *>(buf + 256);
+    int *pidx = idx + batch;
+    float *xb = reinterpret_cast<float *>(buf + 512 + (size_t)batch * 2 * sizeof(int));
+    float *tb = xb + bx;
+    float *grad = tb + bt;
+    // splitmix64 (Steele, Lea and Flood, 2014) drives the per-epoch shuffles
+    uint64_t state = seed;
+    auto next = [&]() {
+        uint64_t z = (state += 0x9e3779b97f4a7c15ULL);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        return z ^ (z >> 31);
+    };
+    std::vector<int> perm(P), hidx(batch), hpidx(batch);
+    const int nbatch = P / batch;
+    for (int e = 0; e < epochs && rc == PERKS_OK; ++e) {
+        for (int i = 0; i < P; ++i) perm[i] = i;
+        for (int i = P - 1; i > 0; --i) std::swap(perm[i], perm[(int)(next() % (uint64_t)(i + 1))]);
+        if (hipMemsetAsync(acc, 0, sizeof(double), st) != hipSuccess) {
+            rc = set_error(PERKS_E_HIP, "nn_train: memset");
+            break;
+        }
+        for (int b = 0; b < nbatch; ++b) {
+            for (int j = 0; j < batch; ++j) {
+                hidx[j] = perm[b * batch + j];
+                if (planes) hpidx[j] = fld[hidx[j]];
+            }
+            if (hipMemcpyAsync(idx, hidx.data(), batch * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+                (planes && hipMemcpyAsync(pidx, hpidx.data(), batch * sizeof(int), hipMemcpyHostToDevice, st) !=
+                               hipSuccess)) {
+                rc = set_error(PERKS_E_HIP, "nn_train: index copy");
+                break;
+            }
+            // the host index arrays are rewritten next batch: the copies must be done
+            if (hipStreamSynchronize(st) != hipSuccess) {
+                rc = set_error(PERKS_E_HIP, "nn_train: sync");
+                break;
+            }
+            const unsigned gb = (unsigned)std::min<int64_t>(4096, ((int64_t)bx + 255) / 256);
+            hipLaunchKernelGGL(nn_gather, dim3(gb), dim3(256), 0, st, x, (const int *)idx, batch, px * 2, xb);
+            if (planes)
+                hipLaunchKernelGGL(nn_gather, dim3(gb), dim3(256), 0, st, planes, (const int *)pidx, batch, px * 5, tb);
+            else
+                hipLaunchKernelGGL(nn_gather, dim3(gb), dim3(256), 0, st, target, (const int *)idx, batch, px, tb);
+            rc = loss_grad_impl(params, xb, planes ? nullptr : tb, planes ? tb : nullptr, 1, batch, H, W, grad,
+                                nullptr, st, acc, 1.0 / nbatch);
+            if (rc) break;
+            ++*step;
+            rc = perks_nn_adam(params, grad, m, v, *step, lr, 0.9f, 0.999f, 1e-8f, stream);
+            if (rc) break;
+        }
+        if (rc) break;
+        if (losses) {
+            double h = 0.0;
+            if (hipMemcpyAsync(&h, acc, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = set_error(PERKS_E_HIP, "nn_train: loss copy");
+                break;
+            }
+            losses[e] = h;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (rc) return rc;
     PERKS_HIP_TRY(hipGetLastError());
     return PERKS_OK;
 }

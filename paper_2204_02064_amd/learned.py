@@ -8,9 +8,9 @@ k = 1, 2, 4, 8, ... iterations; each snapshot gives the network input
 preconditioner returns D^-1 r + rms(r) net(...), so the network's part of the
 error e_k = x* - x_k is what the Jacobi step leaves of it.
 
-Training: Adam, mini-batches of pairs, every forward and backward pass and
-every Adam step in the library's kernels; this module only chooses the
-batches.  Two losses: the mean squared error against that target
+Training: Adam over mini-batches of pairs, the whole loop in the library
+(perks_nn_train: seeded shuffles, batch gathers, forward and backward passes,
+Adam steps).  Two losses: the mean squared error against that target
 (perks_nn_loss_grad), or the error of the preconditioned residual
 z = D^-1 r + rms(r) net(...) in the energy norm of the problem's operator,
 ||z - e||_A^2 up to a constant (perks_nn_energy_grad, Jacobi form):
@@ -19,8 +19,7 @@ components a local network cannot represent nor by the scale of e.
 """
 import numpy as np
 
-from . import (CsrMatrix, NN_PARAMS, cg_solve, cg_solve_capture, nn_adam, nn_energy_grad, nn_loss_grad,
-               nn_pack_params)
+from . import CsrMatrix, cg_solve, cg_solve_capture, nn_pack_params, nn_train
 
 CAPTURE_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
 
@@ -69,33 +68,18 @@ def init_params(seed=0):
 
 
 def train(inputs, targets, epochs=4, batch=16, lr=1e-3, seed=0, params=None, log=None, planes=None, field=None):
-    """Adam over (inputs, targets); returns (params, loss per step).  With
-    ``planes`` ([F, 5, n, n] float32, the operator of each problem) and
-    ``field`` (problem index per pair) the energy-norm loss is used."""
+    """Adam over (inputs, targets) in the library (perks_nn_train); returns
+    (params, mean loss per epoch).  With ``planes`` ([F, 5, n, n] float32, the
+    operator of each problem) and ``field`` (problem index per pair) the
+    energy-norm loss is used."""
     import torch
     dev = inputs.device
     p = torch.from_numpy(init_params(seed)).to(dev) if params is None else params.clone()
-    m = torch.zeros(NN_PARAMS, dtype=torch.float32, device=dev)
-    v = torch.zeros_like(m)
-    grad = torch.empty_like(m)
-    rng = np.random.default_rng(seed)
-    P = inputs.shape[0]
-    losses = []
-    step = 0
-    for ep in range(epochs):
-        order = rng.permutation(P)
-        for s in range(0, P - batch + 1, batch):
-            idx = torch.from_numpy(order[s:s + batch]).to(dev)
-            xb = inputs.index_select(0, idx).contiguous()
-            if planes is not None:
-                pb = planes.index_select(0, field.index_select(0, idx)).contiguous()
-                loss, _ = nn_energy_grad(p, xb, pb, grad, jacobi=True)
-            else:
-                tb = targets.index_select(0, idx).contiguous()
-                loss, _ = nn_loss_grad(p, xb, tb, grad)
-            step += 1
-            nn_adam(p, grad, m, v, step, lr=lr)
-            losses.append(loss)
-        if log:
-            log(f"epoch {ep}: loss {np.mean(losses[-max(1, P // batch):]):.4e}")
+    fld = field.to(torch.int32).contiguous() if field is not None else None
+    losses, _, _, _ = nn_train(p, inputs.contiguous(), epochs, batch, lr=lr, seed=seed,
+                               target=None if planes is not None else targets.contiguous(),
+                               planes=planes.contiguous() if planes is not None else None, field=fld)
+    if log:
+        for ep, l in enumerate(losses):
+            log(f"epoch {ep}: loss {l:.4e}")
     return p, losses

@@ -91,3 +91,13 @@ def test_solver_arguments_are_rejected_before_any_device_call(L):
     assert L.perks_nn_loss_grad(fake, fake, fake, 1, 3, 4, fake, None, None) == -5   # H must be even
     assert L.perks_nn_loss_grad(fake, fake, fake, 1, 4, 600, fake, None, None) == -5  # W <= 512
     assert L.perks_nn_adam(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    st = ctypes.c_int32(0)
+    # nn_train: exactly one of target / planes; planes need field; batch <= P
+    assert L.perks_nn_train(fake, fake, fake, fake, fake, 4, 4, 4, 1, 2, 1e-3, 0, fake, fake, ctypes.byref(st), None,
+                            None) == -1
+    assert L.perks_nn_train(fake, fake, None, fake, None, 4, 4, 4, 1, 2, 1e-3, 0, fake, fake, ctypes.byref(st), None,
+                            None) == -1
+    assert L.perks_nn_train(fake, fake, fake, None, None, 4, 4, 4, 1, 8, 1e-3, 0, fake, fake, ctypes.byref(st), None,
+                            None) == -1
+    assert L.perks_nn_train(fake, fake, fake, None, None, 4, 3, 4, 1, 2, 1e-3, 0, fake, fake, ctypes.byref(st), None,
+                            None) == -5

@@ -32,7 +32,7 @@ def test_harvest_train_and_apply(pk):
     assert torch.allclose(rms, torch.ones_like(rms), atol=1e-5)
     params, losses = learned.train(X, T, epochs=30, batch=8, lr=2e-3, seed=0)
     first, last = np.mean(losses[:5]), np.mean(losses[-5:])
-    print(f"loss {first:.4f} -> {last:.4f} over {len(losses)} steps", flush=True)
+    print(f"loss {first:.4f} -> {last:.4f} over {len(losses)} epochs", flush=True)
     assert last < 0.6 * first
     rp, ci, v, lk, f = workloads.diffusion_problem_torch(n, seed=1000)
     A = pk.CsrMatrix(rp, ci, v)

@@ -138,3 +138,65 @@ def test_energy_gradients_match_oracle(pk, B, H, W, jacobi):
         cos = a @ o / (np.linalg.norm(a) * np.linalg.norm(o))
         rel = np.linalg.norm(a - o) / np.linalg.norm(o)
         assert cos >= 0.999 and rel <= 2e-2, (l, cos, rel)
+
+
+def _splitmix_orders(seed, P, epochs):
+    """The sample orders perks_nn_train draws: splitmix64 (Steele, Lea and
+    Flood) feeding a Fisher-Yates shuffle per epoch."""
+    state = seed
+    M = (1 << 64) - 1
+    orders = []
+    for _ in range(epochs):
+        perm = list(range(P))
+        for i in range(P - 1, 0, -1):
+            state = (state + 0x9E3779B97F4A7C15) & M
+            z = state
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+            z ^= z >> 31
+            j = z % (i + 1)
+            perm[i], perm[j] = perm[j], perm[i]
+        orders.append(perm)
+    return orders
+
+
+@pytest.mark.parametrize("energy", [False, True])
+def test_native_training_loop_equals_the_step_by_step_loop(pk, energy):
+    """perks_nn_train gives the bits of the same batches taken one call at a
+    time (gather, loss and gradient, Adam), and reports each epoch's mean
+    batch loss."""
+    import workloads
+    P, H, W, batch, epochs, seed = 7, 8, 16, 3, 2, 12345
+    layers = _oracle_params(pk, seed=21)
+    x, t = _inputs(P, H, W, seed=4)
+    X, T = to_dev(x), to_dev(t)
+    planes = np.stack([workloads.diffusion_planes(np.exp(workloads.grf_log_k(16, seed=f)[:H + 2, :W + 2]))
+                       for f in range(3)]).astype(np.float32)
+    field = np.array([0, 1, 2, 0, 1, 2, 0], np.int32)
+    PL, F = to_dev(planes), torch.from_numpy(field).cuda()
+    p0 = to_dev(pk.nn_pack_params(layers))
+    pa = p0.clone()
+    if energy:
+        losses, steps, _, _ = pk.nn_train(pa, X, epochs, batch, lr=2e-3, seed=seed, planes=PL, field=F)
+    else:
+        losses, steps, _, _ = pk.nn_train(pa, X, epochs, batch, lr=2e-3, seed=seed, target=T)
+    assert steps == epochs * (P // batch) and len(losses) == epochs
+    pb = p0.clone()
+    m = torch.zeros_like(pb)
+    v = torch.zeros_like(pb)
+    k = 0
+    for order in _splitmix_orders(seed, P, epochs):
+        tot = 0.0
+        for b in range(P // batch):
+            idx = torch.tensor(order[b * batch:(b + 1) * batch], device="cuda")
+            xb = X.index_select(0, idx).contiguous()
+            if energy:
+                pl = PL.index_select(0, F.long().index_select(0, idx)).contiguous()
+                loss, g = pk.nn_energy_grad(pb, xb, pl, jacobi=True)
+            else:
+                loss, g = pk.nn_loss_grad(pb, xb, T.index_select(0, idx).contiguous())
+            k += 1
+            pk.nn_adam(pb, g, m, v, k, lr=2e-3)
+            tot += loss
+        assert abs(losses.pop(0) - tot / (P // batch)) <= 1e-9 * max(1.0, abs(tot))
+    assert torch.equal(pa, pb)
