@@ -174,6 +174,16 @@ __device__ __forceinline__ P opaque(P p) {
     return (P)(((unsigned long long)hi << 32) | lo);
 }
 
+// Ties the values to this point of the program: the compiler waits here for
+// the loads that produce them, and later uses no longer refer to the loads.
+// (vmcnt counts loads and stores alike, so a wait the compiler places after a
+// step's stores would also wait for every one of them.)
+template <typename T, int N>
+__device__ __forceinline__ void settle(T (&a)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(a[i]));
+}
+
 // Keeps the compiler from moving memory operations across this point.  LDS
 // operations of one wavefront complete in program order, so a wave that
 // writes LDS and then reads it needs no hardware barrier.

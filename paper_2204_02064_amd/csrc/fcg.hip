@@ -62,7 +62,7 @@ struct FcgParams {
 // Layer l reads an (FR - 2l)^2 region and writes the (FR - 2l - 2)^2 region
 // inside it; pixels outside the grid are zero in every layer's input (the
 // network's zero padding).  Waves take (row, 16-pixel segment) items.
-__device__ void net_tile(const FcgParams &p, int tx0, int ty0, double rms, double inv_rms) {
+__device__ __forceinline__ void net_tile(const FcgParams &p, int tx0, int ty0, double rms, double inv_rms) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ox = tx0 - NL, oy = ty0 - NL;
     for (int e = tid; e < FR * FR; e += CG_THREADS) {

@@ -137,11 +137,11 @@ struct Tile2D {
 
 template <typename T>
 struct Stencil2DParams {
-    T *grid;
-    T *src;            // baseline: read buffer
-    T *dst;            // baseline: write buffer
-    T *rowbuf;         // [2][2*nty+2][nx]
-    T *colbuf;         // [2][2*ntx+2][ny]
+    gmem<T> *grid;
+    gmem<T> *src;      // baseline: read buffer
+    gmem<T> *dst;      // baseline: write buffer
+    gmem<T> *rowbuf;   // [2][2*nty+2][nx]
+    gmem<T> *colbuf;   // [2][2*ntx+2][ny]
     unsigned *sync;
     long long steps;
     int nx, ny;
@@ -185,8 +185,8 @@ __device__ __forceinline__ void load_halo(const Stencil2DParams<T> &p, const Til
     const int xl = min(tl.x0 + lane, p.nx - 1);
     hn = ld_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty) + xl);
     hs = ld_coh(p.rowbuf + rb_off(p, par, 2 * tl.ty + 3) + xl);
-    const T *cw = p.colbuf + cb_off(p, par, 2 * tl.tx) + (tl.y0 - 1);
-    const T *ce = p.colbuf + cb_off(p, par, 2 * tl.tx + 3) + (tl.y0 - 1);
+    const gmem<T> *cw = p.colbuf + cb_off(p, par, 2 * tl.tx) + (tl.y0 - 1);
+    const gmem<T> *ce = p.colbuf + cb_off(p, par, 2 * tl.tx + 3) + (tl.y0 - 1);
     for (int j = lane; j < tl.hy + 2; j += 64) {
         lw[j] = ld_coh(cw + j);
         le[j] = ld_coh(ce + j);
@@ -199,8 +199,8 @@ __device__ __forceinline__ void load_halo(const Stencil2DParams<T> &p, const Til
 template <typename T, int RC, bool FULL>
 __device__ __forceinline__ void publish_rows(const Stencil2DParams<T> &p, const Tile2D &tl, int par, int lane,
                                              const T (&u)[RC], int r0, int n, T lastval) {
-    T *left = p.colbuf + cb_off(p, par, 2 * tl.tx + 1) + tl.y0 + r0;
-    T *right = p.colbuf + cb_off(p, par, 2 * tl.tx + 2) + tl.y0 + r0;
+    gmem<T> *left = p.colbuf + cb_off(p, par, 2 * tl.tx + 1) + tl.y0 + r0;
+    gmem<T> *right = p.colbuf + cb_off(p, par, 2 * tl.tx + 2) + tl.y0 + r0;
     const bool in = lane < tl.wx;
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void publish_rows(const Stencil2DParams<T> &p, const 
 // Fixed ring entries of the face buffers, both parities (grid-stride loop
 // over all threads of the launch).
 template <typename T>
-__device__ void init_ring_faces(const Stencil2DParams<T> &p, const T *g) {
+__device__ __forceinline__ void init_ring_faces(const Stencil2DParams<T> &p, const gmem<T> *g) {
     const int nthreads = gridDim.x * blockDim.x;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nrs = 2 * p.nty + 2, ncs = 2 * p.ntx + 2;
@@ -248,8 +248,8 @@ __device__ void init_ring_faces(const Stencil2DParams<T> &p, const T *g) {
 
 // Edges of a tile straight from the grid into parity-0 face buffers.
 template <typename T>
-__device__ void publish_initial(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
-    const T *g = p.grid;
+__device__ __forceinline__ void publish_initial(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
+    const gmem<T> *g = p.grid;
     if (lane < tl.wx) {
         st_coh(p.rowbuf + rb_off(p, 0, 2 * tl.ty + 1) + tl.x0 + lane, g[(size_t)tl.y0 * p.nx + tl.x0 + lane]);
         st_coh(p.rowbuf + rb_off(p, 0, 2 * tl.ty + 2) + tl.x0 + lane,
@@ -283,7 +283,7 @@ struct LLTraits {
 };
 
 template <typename T>
-__device__ __forceinline__ void ll_store(llword *w, T v, unsigned e) {
+__device__ __forceinline__ void ll_store(gmem<llword> *w, T v, unsigned e) {
     const llword tag = (llword)e << 32;
     if constexpr (sizeof(T) == 4) {
         st_coh(w, tag | __float_as_uint(v));
@@ -297,7 +297,7 @@ __device__ __forceinline__ void ll_store(llword *w, T v, unsigned e) {
 // Loads one element; clears ok when `need` and a word is neither of epoch e
 // nor a ring word of this launch (epoch er).
 template <typename T>
-__device__ __forceinline__ T ll_load(const llword *w, unsigned e, unsigned er, bool need, bool &ok) {
+__device__ __forceinline__ T ll_load(const gmem<llword> *w, unsigned e, unsigned er, bool need, bool &ok) {
     if constexpr (sizeof(T) == 4) {
         const llword a = ld_coh(w);
         const unsigned f = (unsigned)(a >> 32);
@@ -312,12 +312,12 @@ __device__ __forceinline__ T ll_load(const llword *w, unsigned e, unsigned er, b
 }
 
 template <typename T>
-__device__ __forceinline__ llword *ll_row(const Stencil2DParams<T> &p, int par, int slot) {
-    return reinterpret_cast<llword *>(p.rowbuf) + rb_off(p, par, slot) * LLTraits<T>::WPE;
+__device__ __forceinline__ gmem<llword> *ll_row(const Stencil2DParams<T> &p, int par, int slot) {
+    return reinterpret_cast<gmem<llword> *>(p.rowbuf) + rb_off(p, par, slot) * LLTraits<T>::WPE;
 }
 template <typename T>
-__device__ __forceinline__ llword *ll_col(const Stencil2DParams<T> &p, int par, int slot) {
-    return reinterpret_cast<llword *>(p.colbuf) + cb_off(p, par, slot) * LLTraits<T>::WPE;
+__device__ __forceinline__ gmem<llword> *ll_col(const Stencil2DParams<T> &p, int par, int slot) {
+    return reinterpret_cast<gmem<llword> *>(p.colbuf) + cb_off(p, par, slot) * LLTraits<T>::WPE;
 }
 
 // Polls the halo of tile tl (parity par, epoch e) until every word it needs
@@ -330,10 +330,10 @@ __device__ __forceinline__ void load_halo_ll(const Stencil2DParams<T> &p, const 
     constexpr int WPE = LLTraits<T>::WPE;
     const int xl = min(tl.x0 + lane, p.nx - 1);
     const bool need_row = lane < tl.wx || (BOX && lane == tl.wx);
-    const llword *rn = ll_row(p, par, 2 * tl.ty) + (size_t)xl * WPE;
-    const llword *rs = ll_row(p, par, 2 * tl.ty + 3) + (size_t)xl * WPE;
-    const llword *cw = ll_col(p, par, 2 * tl.tx) + (size_t)(tl.y0 - 1) * WPE;
-    const llword *ce = ll_col(p, par, 2 * tl.tx + 3) + (size_t)(tl.y0 - 1) * WPE;
+    const gmem<llword> *rn = ll_row(p, par, 2 * tl.ty) + (size_t)xl * WPE;
+    const gmem<llword> *rs = ll_row(p, par, 2 * tl.ty + 3) + (size_t)xl * WPE;
+    const gmem<llword> *cw = ll_col(p, par, 2 * tl.tx) + (size_t)(tl.y0 - 1) * WPE;
+    const gmem<llword> *ce = ll_col(p, par, 2 * tl.tx + 3) + (size_t)(tl.y0 - 1) * WPE;
     const int jlo = BOX ? 0 : 1, jhi = BOX ? tl.hy + 2 : tl.hy + 1;
     while (true) {
         bool ok = true;
@@ -375,8 +375,8 @@ __device__ __forceinline__ void publish_cols_ll(const Stencil2DParams<T> &p, con
                                                 int lane, const T *ow, const T *oe) {
     constexpr int WPE = LLTraits<T>::WPE;
     compiler_fence();
-    llword *cl = ll_col(p, par, 2 * tl.tx + 1) + (size_t)tl.y0 * WPE;
-    llword *cr = ll_col(p, par, 2 * tl.tx + 2) + (size_t)tl.y0 * WPE;
+    gmem<llword> *cl = ll_col(p, par, 2 * tl.tx + 1) + (size_t)tl.y0 * WPE;
+    gmem<llword> *cr = ll_col(p, par, 2 * tl.tx + 2) + (size_t)tl.y0 * WPE;
     for (int j = lane; j < tl.hy; j += 64) {
         ll_store(cl + (size_t)j * WPE, ow[j], e);
         ll_store(cr + (size_t)j * WPE, oe[j], e);
@@ -385,9 +385,9 @@ __device__ __forceinline__ void publish_cols_ll(const Stencil2DParams<T> &p, con
 }
 
 template <typename T>
-__device__ void init_ring_faces_ll(const Stencil2DParams<T> &p) {
+__device__ __forceinline__ void init_ring_faces_ll(const Stencil2DParams<T> &p) {
     constexpr int WPE = LLTraits<T>::WPE;
-    const T *g = p.grid;
+    const gmem<T> *g = p.grid;
     const int nthreads = gridDim.x * blockDim.x;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nrs = 2 * p.nty + 2, ncs = 2 * p.ntx + 2;
@@ -416,9 +416,9 @@ __device__ void init_ring_faces_ll(const Stencil2DParams<T> &p) {
 }
 
 template <typename T>
-__device__ void publish_initial_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
+__device__ __forceinline__ void publish_initial_ll(const Stencil2DParams<T> &p, const Tile2D &tl, int lane) {
     constexpr int WPE = LLTraits<T>::WPE;
-    const T *g = p.grid;
+    const gmem<T> *g = p.grid;
     const unsigned e = p.epoch0;
     if (lane < tl.wx) {
         const size_t xo = (size_t)(tl.x0 + lane) * WPE;
@@ -521,7 +521,7 @@ __device__ __forceinline__ void step_streamed(const Stencil2DParams<T> &p, const
     T u[CH];
     for (int c = 0; c < tl.hy; c += CH) {
         const int n = min(CH, tl.hy - c);
-        T *row0 = p.grid + (size_t)(tl.y0 + c) * p.nx + xl;
+        gmem<T> *row0 = p.grid + (size_t)(tl.y0 + c) * p.nx + xl;
 #pragma unroll
         for (int i = 0; i < CH; ++i)
             u[i] = (i < n) ? (ghost ? le[c + i + 1] : row0[(size_t)i * p.nx]) : T(0);
@@ -592,6 +592,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
         for (int i = 0; i < R; ++i) v[i] = (i < ct.hy) ? p.grid[(size_t)(ct.y0 + i) * p.nx + xl] : T(0);
         for (int i = R; i < ct.hy; ++i) lt[(i - R) * 64 + lane] = p.grid[(size_t)(ct.y0 + i) * p.nx + xl];
     }
+    settle(v);   // the initial loads complete before the time loop
     const int first_streamed = p.cached + gw;
     for (long long s = 0; s < p.steps; ++s) {
         const int par = (int)(s & 1);
@@ -690,6 +691,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
         for (int i = 0; i < R; ++i) v[i] = (i < ct.hy) ? q.grid[(size_t)(ct.y0 + i) * q.nx + xl] : T(0);
         for (int i = R; i < ct.hy; ++i) lt[(i - R) * 64 + lane] = q.grid[(size_t)(ct.y0 + i) * q.nx + xl];
     }
+    settle(v);   // the initial loads complete before the time loop
     for (long long s = 0; s < bp.steps; ++s) {
         const int par = (int)(s & 1);
         const unsigned e_in = epoch0 + (unsigned)s;
@@ -734,7 +736,7 @@ __global__ __launch_bounds__(WAVES * 64) void stencil2d_step(Stencil2DParams<T> 
     const Tile2D tl = tile_of(p, t);
     T *lw = lds[wave][0];
     T *le = lds[wave][1];
-    const T *src = p.src;
+    const gmem<T> *src = p.src;
     const int xl = min(tl.x0 + lane, p.nx - 1);
     for (int j = lane; j < tl.hy + 2; j += 64) {
         const size_t row = (size_t)(tl.y0 - 1 + j) * p.nx;
@@ -889,7 +891,7 @@ int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bo
     int rc = plan2d<T>(s, box, tu, &pl);
     if (rc) return rc;
     Stencil2DParams<T> p{};
-    p.grid = grid;
+    p.grid = to_global(grid);
     p.nx = (int)s.nx;
     p.ny = (int)s.ny;
     p.ntx = pl.ntx;
@@ -910,8 +912,8 @@ int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bo
     T *faces = (T *)scratch(pl.ll ? SLOT_FACES_LL : SLOT_FACES, (rb + cb) * sizeof(T));
     unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
     if (!faces || !sync) return PERKS_E_NOMEM;
-    p.rowbuf = faces;
-    p.colbuf = faces + rb;
+    p.rowbuf = to_global(faces);
+    p.colbuf = to_global(faces + rb);
     p.sync = sync;
     return launch_coop(pl.fn, pl.wgs, W2 * 64, &p, st);
 }
@@ -959,7 +961,7 @@ int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const d
     for (int i = 0; i < count; ++i) {
         Stencil2DParams<T> &p = inst[i];
         p = Stencil2DParams<T>{};
-        p.grid = grids[i];
+        p.grid = to_global(grids[i]);
         p.nx = (int)shapes[i].nx;
         p.ny = (int)shapes[i].ny;
         const int nxi = p.nx - 2, nyi = p.ny - 2;
@@ -983,8 +985,8 @@ int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const d
     for (int i = 0; i < count; ++i) {
         Stencil2DParams<T> &p = inst[i];
         const size_t rb = (size_t)2 * (2 * p.nty + 2) * p.nx * 2, cb = (size_t)2 * (2 * p.ntx + 2) * p.ny * 2;
-        p.rowbuf = faces;
-        p.colbuf = faces + rb;
+        p.rowbuf = to_global(faces);
+        p.colbuf = to_global(faces + rb);
         p.sync = sync;
         faces += rb + cb;
     }
@@ -1028,8 +1030,8 @@ int baseline2d(T *grid, const double *coeffs, const perks_shape &s, int64_t step
     const int wgs = (p.ntiles + WB - 1) / WB;
     T *a = grid, *b = other;
     for (int64_t k = 0; k < steps; ++k) {
-        p.src = a;
-        p.dst = b;
+        p.src = to_global(a);
+        p.dst = to_global(b);
         hipLaunchKernelGGL((stencil2d_step<T, RB, BOX, WB>), dim3(wgs), dim3(WB * 64), 0, st, p);
         std::swap(a, b);
     }

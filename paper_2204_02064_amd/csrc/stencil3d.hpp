@@ -205,14 +205,6 @@ __device__ __forceinline__ const gmem<T> *at(const gmem<T> *base, unsigned e) {
     return (const gmem<T> *)((const gmem<char> *)base + e * (unsigned)sizeof(T));
 }
 
-// Ties the values to this point of the program: the compiler waits here for
-// the loads that produce them, and later uses no longer refer to the loads.
-template <typename T, int N>
-__device__ __forceinline__ void settle(T (&a)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(a[i]));
-}
-
 template <typename T>
 struct ColShared {
     T xs[C3_WAVES][2][C3_DZMAX][C3_RY];   // west / east face of each wave's rows, per plane
