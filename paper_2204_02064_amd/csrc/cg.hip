@@ -48,6 +48,7 @@ struct CgInst {
     double *sval64;          // sliced-ELL copy of A (FP64 solver), NULL: CSR only
     float *sval32;           // sliced-ELL copy of A (mixed solver)
     int *scol;               // its column indices
+    int *sperm;              // rows of each workgroup's slice in sliced-ELL order (n entries)
     double *cap_x, *cap_r;   // FP64 solver: x and r after the iterations listed in cap_iters
     const int *cap_iters;    // ascending iteration counts (device)
     int ncap;
@@ -193,6 +194,7 @@ __shared__ int cg_flag;
 struct Slice {
     int r0, r1, rc, kbase, nnz, kc, L;
     int sell, nch, cc, sbase;
+    const int *perm;   // sliced-ELL row order (rows sorted by length), or NULL: natural order
 };
 
 // Entries the packed arrays of one problem need for G workgroups.
@@ -234,13 +236,96 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
         __syncthreads();
         sl.sell = cg_flag >= 0;
     }
+    sl.perm = nullptr;
+    const int nrows = sl.r1 - sl.r0;
+    if (!sl.sell && sval != nullptr && p.sperm != nullptr && sl.nch <= SELL_MAX_CHUNKS && nrows <= LdsA<T>::cap) {
+        // Irregular rows: sliced ELL over the slice's rows sorted by length,
+        // longest first (SELL-C-sigma with sigma = the slice), so that each
+        // chunk's rows have nearly equal lengths.  A stable counting sort on
+        // min(length, 255); its order depends only on the problem and G.
+        int *key = &LdsA<T>::col(0);
+        int *cnt = cg_chunk_off;   // 256 bucket counters, then starts
+        for (int r = tid; r < nrows; r += CG_THREADS) {
+            const int i = sl.r0 + r;
+            key[r] = 255 - min(p.rowptr[i + 1] - p.rowptr[i], 255);
+        }
+        for (int b = tid; b < 256; b += CG_THREADS) cnt[b] = 0;
+        __syncthreads();
+        for (int r = tid; r < nrows; r += CG_THREADS) atomicAdd(&cnt[key[r]], 1);
+        __syncthreads();
+        if (wave == 0) {
+            // exclusive prefix over the 256 buckets: 4 per lane, then a wave scan
+            int c4[4], tot = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c4[u] = cnt[4 * lane + u];
+                tot += c4[u];
+            }
+            int incl = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += t;
+            }
+            int run = incl - tot;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cnt[4 * lane + u] = run;
+                run += c4[u];
+            }
+            // stable scatter, 64 rows at a time: rank among equal keys from
+            // ballots over the key bits
+            const unsigned long long lt = (1ULL << lane) - 1ULL;
+            for (int base = 0; base < nrows; base += 64) {
+                const int r = base + lane;
+                const int k = r < nrows ? key[r] : 256;
+                unsigned long long same = __ballot(1);
+#pragma unroll
+                for (int bit = 0; bit < 9; ++bit) {
+                    const unsigned long long m = __ballot((k >> bit) & 1);
+                    same &= ((k >> bit) & 1) ? m : ~m;
+                }
+                const int rank = __popcll(same & lt);
+                if (r < nrows) {
+                    const int pos = cnt[k] + rank;
+                    st_coh(p.sperm + sl.r0 + pos, sl.r0 + r);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (r < nrows && rank == 0) cnt[k] += __popcll(same);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        sl.perm = p.sperm + sl.r0;
+        for (int c = wave; c < sl.nch; c += CG_WAVES) {
+            const int r = 64 * c + lane;
+            const int i = r < nrows ? ld_coh(sl.perm + r) : sl.r0;
+            int len = r < nrows ? p.rowptr[i + 1] - p.rowptr[i] : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+            if (lane == 0) cg_chunk_len[c] = len;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int c = 0; c < sl.nch; ++c) {
+                cg_chunk_off[c] = acc;
+                acc += 64 * cg_chunk_len[c];
+            }
+            cg_flag = acc <= sl.nnz + sl.nnz / 4 + 64 ? acc : -1;
+        }
+        __syncthreads();
+        sl.sell = cg_flag >= 0;
+        if (!sl.sell) sl.perm = nullptr;
+    }
     if (sl.sell) {
         // cached chunks: a prefix whose entries fit in LDS
         int cc = 0;
         while (cc < sl.nch && cg_chunk_off[cc] + 64 * cg_chunk_len[cc] <= LdsA<T>::cap) ++cc;
         sl.cc = cc;
         for (int c = wave; c < sl.nch; c += CG_WAVES) {
-            const int i = sl.r0 + 64 * c + lane;
+            const int r = 64 * c + lane;
+            const int i = r < nrows ? (sl.perm ? ld_coh(sl.perm + r) : sl.r0 + r) : sl.r1;
             const int len = cg_chunk_len[c], off = cg_chunk_off[c];
             const int kb = i < sl.r1 ? p.rowptr[i] : 0;
             const int kn = i < sl.r1 ? p.rowptr[i + 1] - kb : 0;
@@ -280,7 +365,8 @@ __device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = c0 + wave; c < c1; c += CG_WAVES) {
         const int len = cg_chunk_len[c], off = cg_chunk_off[c];
-        const int i = sl.r0 + 64 * c + lane;
+        const int r = 64 * c + lane;
+        const int i = sl.perm ? (sl.r0 + r < sl.r1 ? sl.perm[r] : sl.r1) : sl.r0 + r;
         T acc = T(0);
         int j = 0;
         for (; j + 4 <= len; j += 4) {
@@ -1023,6 +1109,7 @@ size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
                  ns * (sizeof(float) + sizeof(int));
     else
         bytes += 6 * nv * sizeof(double) + ns * (sizeof(double) + sizeof(int));
+    bytes += nv * sizeof(int);   // sperm
     return (bytes + 255) / 256 * 256;
 }
 
@@ -1046,6 +1133,7 @@ void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w)
         w->val32 = f + 7 * nv;
         w->sval32 = w->val32 + ((size_t)nnz + 63) / 64 * 64;
         w->scol = (int *)(w->sval32 + ns);
+        w->sperm = w->scol + ns;
     } else {
         double *d = (double *)v;
         w->r = d;
@@ -1056,6 +1144,7 @@ void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w)
         w->dinv = d + 5 * nv;
         w->sval64 = d + 6 * nv;
         w->scol = (int *)(w->sval64 + ns);
+        w->sperm = w->scol + ns;
     }
 }
 
@@ -1193,14 +1282,22 @@ struct BaseShape {
     BaseScalars *S;
 };
 
+// Launch shape of the baseline kernels: L lanes per row (the power of two at
+// or above the mean row length, at most 64), nb blocks of 256 rows for the
+// vector kernels, nbs SpMV blocks of (256 / L) * BASE_U rows (more than nb
+// when L > 4: the partial-sum arrays are sized for the larger).
+void base_dims(const perks_csr *A, int *n, int *nb, int *L, int *nbs) {
+    *n = (int)A->n;
+    *nb = (*n + 255) / 256;
+    const int avg = (int)((A->nnz + *n - 1) / *n);
+    *L = 1;
+    while (*L < avg && *L < 64) *L <<= 1;
+    *nbs = (*n + (256 / *L) * BASE_U - 1) / ((256 / *L) * BASE_U);
+}
+
 BaseShape base_shape(const perks_csr *A, const CgWork &w) {
     BaseShape b{};
-    b.n = (int)A->n;
-    b.nb = (b.n + 255) / 256;
-    const int avg = (int)((A->nnz + b.n - 1) / b.n);
-    b.L = 1;
-    while (b.L < avg && b.L < 64) b.L <<= 1;
-    b.nbs = (b.n + (256 / b.L) * BASE_U - 1) / ((256 / b.L) * BASE_U);
+    base_dims(A, &b.n, &b.nb, &b.L, &b.nbs);
     const int m = std::max(b.nb, b.nbs);
     b.part_a = w.part;
     b.part_b = w.part + m + 16;
@@ -1209,10 +1306,11 @@ BaseShape base_shape(const perks_csr *A, const CgWork &w) {
     return b;
 }
 
+// Partial-sum entries the baseline needs: three arrays of max(nb, nbs) + 16.
 int base_parts(const perks_csr *A) {
-    const int n = (int)A->n;
-    const int nb = (n + 255) / 256;
-    return nb * 3 + 64;   // >= 3 * max(nb, nbs) + 48 (nbs <= nb)
+    int n, nb, L, nbs;
+    base_dims(A, &n, &nb, &L, &nbs);
+    return 3 * (std::max(nb, nbs) + 16) + 16;
 }
 
 int cg_baseline_f64(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, int check_every,

@@ -6,6 +6,7 @@ the returned x) meets tol, the returned x agrees with the oracle's solution
 within kappa * tol, and the iteration count is within max(2, 2%) of the
 oracle's.
 """
+import functools
 import math
 
 import numpy as np
@@ -158,3 +159,23 @@ def test_baseline_check_every_delays_stop_by_less_than_the_interval(pk):
         assert info["status"] == "converged"
         its[ce] = info["iters"]
     assert its[1] <= its[8] <= its[1] + 7
+
+
+@functools.lru_cache(maxsize=1)
+def _random_million():
+    rp, ci, v = workloads.random_spd_csr(1 << 20, seed=0)
+    b = workloads.rhs_uniform(rp.size - 1, seed=0)
+    _, oinfo = oracle.cg(rp, ci, v, b, tol=1e-10, maxit=5000, precond="jacobi")
+    return rp, ci, v, b, oinfo
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+def test_random_spd_one_million_rows_jacobi(pk, baseline):
+    """n = 2^20, mean row length 20.6: the baseline SpMV then runs 32 lanes per
+    row and more blocks than the vector kernels, and its partial sums must be
+    sized for those (they once overran into the solver's vectors here)."""
+    rp, ci, v, b, oinfo = _random_million()
+    x, info = _solve(pk, rp, ci, v, b, 1e-10, precond="jacobi", baseline=baseline)
+    assert info["status"] == "converged" and oinfo["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x) <= 1e-10
+    assert _iters_close(info["iters"], oinfo["iters"]), (info["iters"], oinfo["iters"])
