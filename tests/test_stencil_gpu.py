@@ -188,6 +188,25 @@ def test_full_size_matches_oracle_for_a_few_steps(pk):
     np.testing.assert_array_equal(got, base)
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_full_size_3d_matches_oracle_for_a_few_steps(pk, dtype):
+    """256^3 in the benchmark's launch configuration (columns 64 x 32 x 32,
+    streamed, LDS and register planes in FP64; every plane in registers in
+    FP32), five steps against the oracle, and bitwise against the per-step
+    baseline."""
+    g = workloads.stencil_grid((256, 256, 256), seed=0)
+    w = workloads.stencil_weights("3d7pt")
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    if dtype == "float32":
+        g = g.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    got = _run(pk, g, w, 5, tdt)
+    assert rel_err(got, oracle.stencil(g, w, 5)) <= (1e-12 if dtype == "float64" else 1e-5)
+    np.testing.assert_array_equal(got, _run(pk, g, w, 5, tdt, baseline=True))
+    plan = pk.stencil_plan((256, 256, 256), w, dtype)
+    assert plan["planes_per_lane"] == 32 and plan["tiles"] == 256 and plan["cached_tiles"] == 256
+
+
 def test_plan_reports_cached_share(pk):
     pl = pk.stencil_plan((3072, 3072), workloads.stencil_weights("2d5pt"), "float64")
     assert pl["tiles"] >= pl["cached_tiles"] > 0
