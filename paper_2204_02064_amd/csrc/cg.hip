@@ -1,14 +1,19 @@
 // Conjugate gradient (Sec. 2.2.2, Sec. 4.3): the fused persistent solver and
 // the host-looped multi-kernel baseline, FP64, CSR matrices.
 //
-// Persistent solver, per iteration (two device-wide barriers):
-//   phase 1  q = A p on the workgroup's rows, gathering p_j = z_j + beta*pold_j
-//            on the fly (z = r unpreconditioned, z = D^{-1} r for Jacobi), so
-//            the update of p needs no barrier of its own; the new p of the
-//            workgroup's own rows is stored to the other p buffer; partial p.q.
+// Persistent solver, per iteration (three device-wide barriers):
+//   phase P  p = z + beta p on own rows (z = r unpreconditioned, z = D^{-1} r
+//            for Jacobi)
+//   barrier  every workgroup's p complete
+//   phase 1  q = A p on the workgroup's rows (one gather of p per nonzero);
+//            partial p.q
 //   barrier  every workgroup sums the partials in the same fixed order -> alpha
 //   phase 2  x += alpha p, r -= alpha q, z = D^{-1} r on own rows; partials r.z, r.r
 //   barrier  -> beta and the (uniform) convergence decision.
+// Forming p where it is gathered instead (p_j = z_j + beta pold_j inside the
+// SpMV, no barrier of its own) costs a second gather per nonzero; measured on
+// gfx950 it was slower on both a 7-point Poisson matrix (4%) and a random
+// sparse matrix (2.1x), so the solver takes the extra barrier.
 // The row partition is a merge-path split of (rows + nonzeros) into equal
 // shares, searched once at kernel start (the paper keeps its thread-block
 // search result for the whole solve because A is static, Sec. 4.3.2).  The
@@ -30,7 +35,7 @@ namespace {
 enum { PART_PQ = 0, PART_RZ = 1, PART_RR = 2, PART_BB = 3, PART_TRUE = 4, NPART = 5 };
 
 // One CG problem and its work vectors (device pointers).  FP64 solves use
-// r, z, q, p0, p1, dinv; mixed solves use r64 and the FP32 vectors.  part
+// r, z, q, p, dinv; mixed solves use r64 and the FP32 vectors.  part
 // holds NPART partial sums per workgroup of the problem's group; result
 // receives iters, status, relres, relres_true, ||b||, restarts or outer steps.
 struct CgInst {
@@ -39,10 +44,10 @@ struct CgInst {
     const double *val;
     const double *b;
     double *x;
-    double *r, *z, *q, *p0, *p1, *dinv;
+    double *r, *z, *q, *p, *dinv;
     float *val32;
     double *r64;
-    float *r32, *z32, *q32, *p0_32, *p1_32, *d32, *dinv32;
+    float *r32, *z32, *q32, *p32, *d32, *dinv32;
     double *part;
     double *result;
     double *sval64;          // sliced-ELL copy of A (FP64 solver), NULL: CSR only
@@ -357,6 +362,12 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
     return sl;
 }
 
+#ifndef PERKS_SELL_U
+#define PERKS_SELL_U 4
+#endif
+// Entries of a row whose loads and gathers are issued before their products.
+constexpr int SELL_U = PERKS_SELL_U;
+
 // y_i = sum_j a_j * v(col_j) over the sliced-ELL chunks [c0, c1), one lane
 // per row, entries in CSR order; FROM_LDS: the chunks are held in LDS.
 template <bool FROM_LDS, typename T, typename F, typename S>
@@ -369,11 +380,11 @@ __device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, 
         const int i = sl.perm ? (sl.r0 + r < sl.r1 ? sl.perm[r] : sl.r1) : sl.r0 + r;
         T acc = T(0);
         int j = 0;
-        for (; j + 4 <= len; j += 4) {
-            T a[4];
-            int cidx[4];
+        for (; j + SELL_U <= len; j += SELL_U) {
+            T a[SELL_U];
+            int cidx[SELL_U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < SELL_U; ++u) {
                 const int e = off + (j + u) * 64 + lane;
                 if constexpr (FROM_LDS) {
                     a[u] = LdsA<T>::val(e);
@@ -383,11 +394,11 @@ __device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, 
                     cidx[u] = scol[sl.sbase + e];
                 }
             }
-            T xv[4];
+            T xv[SELL_U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) xv[u] = fetch(cidx[u]);
+            for (int u = 0; u < SELL_U; ++u) xv[u] = fetch(cidx[u]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = fma_t(a[u], xv[u], acc);
+            for (int u = 0; u < SELL_U; ++u) acc = fma_t(a[u], xv[u], acc);
         }
         for (; j < len; ++j) {
             const int e = off + j * 64 + lane;
@@ -421,12 +432,11 @@ __device__ __forceinline__ void spmv_slice(CInst &p, const Slice &sl, const T *v
 // FP64 persistent CG of one problem by a group of G workgroups (this one of
 // rank g) synchronised by `gs`.  Per iteration: phase 1 q = A p and p.q,
 // phase 2 x, r, z updates and r.z, r.r, each followed by a group barrier and
-// a fixed-order all-reduce.  FUSEP forms p = z + beta p_old on the fly in
-// phase 1 (two gathers per nonzero, no barrier of its own); otherwise a
-// phase P updates p in place on own rows before a third barrier.  When the
+// a fixed-order all-reduce; before phase 1, phase P updates p in place on
+// own rows and a third barrier publishes it.  When the
 // recursive residual meets tol the true residual is recomputed; if it fails,
 // CG restarts from the current x while iterations remain.
-template <bool JACOBI, bool FUSEP, class Sync>
+template <bool JACOBI, class Sync>
 __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, const int G) {
     // The problem is read from global memory through a pointer laundered at
     // every phase: its fields are reloaded (scalar loads) instead of being
@@ -464,7 +474,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
             } else {
                 st_coh(pp->r + i, ri);
             }
-            st_coh((FUSEP ? pp->p1 : pp->p0) + i, 0.0);
+            st_coh(pp->p + i, 0.0);
             acc0[0] = __builtin_fma(bi, bi, acc0[0]);
             acc0[1] = __builtin_fma(ri, zi, acc0[1]);
             acc0[2] = __builtin_fma(ri, ri, acc0[2]);
@@ -491,29 +501,14 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
             if (k >= pp->maxit) break;
             pp = opaque(pin);
             double acc1[1] = {0.0};
-            double *pn;
-            if constexpr (FUSEP) {
-                pn = (k & 1) ? pp->p1 : pp->p0;                // p_k
-                const double *po = (k & 1) ? pp->p0 : pp->p1;  // p_{k-1}
-                spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol,
-                                [&](int c) { return __builtin_fma(beta, po[c], zsrc[c]); },
-                                [&](int i, double s) {
-                                    const double pi = __builtin_fma(beta, po[i], zsrc[i]);
-                                    pp->q[i] = s;
-                                    st_coh(pn + i, pi);
-                                    acc1[0] = __builtin_fma(pi, s, acc1[0]);
-                                });
-            } else {
-                pn = pp->p0;
-                for (int i = r0 + tid; i < r1; i += CG_THREADS)
-                    st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
-                gs.template sync<true>();
-                spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
-                                [&](int i, double s) {
-                                    pp->q[i] = s;
-                                    acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
-                                });
-            }
+            double *pn = pp->p;
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
+            gs.template sync<true>();
+            spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
+                            [&](int i, double s) {
+                                pp->q[i] = s;
+                                acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
+                            });
             block_sum<1>(acc1, cg_red);
             if (tid == 0) st_coh(pp->part + (size_t)PART_PQ * G + g, acc1[0]);
             gs.template sync<true>();
@@ -602,7 +597,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
 // each workgroup's slice of A is made by the workgroup itself (global copy +
 // LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
 // nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
-template <bool JACOBI, bool FUSEP, class Sync>
+template <bool JACOBI, class Sync>
 __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, const int G) {
     const int tid = threadIdx.x;
     {
@@ -669,7 +664,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             } else {
                 st_coh(p.r32 + i, ri);
             }
-            st_coh((FUSEP ? p.p1_32 : p.p0_32) + i, 0.0f);
+            st_coh(p.p32 + i, 0.0f);
             p.d32[i] = 0.0f;
             acc0[0] = __builtin_fma((double)ri, (double)zi, acc0[0]);
             acc0[1] = __builtin_fma((double)ri, (double)ri, acc0[1]);
@@ -687,30 +682,15 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
         for (int j = 0; sqrt(rr) > stop && k < p.maxit; ++j) {
             const float bf = (float)beta;
             double acc1[1] = {0.0};
-            float *pn;
-            if constexpr (FUSEP) {
-                pn = (j & 1) ? p.p1_32 : p.p0_32;                // p_j
-                const float *po = (j & 1) ? p.p0_32 : p.p1_32;   // p_{j-1}
-                spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
-                                [&](int c) { return __builtin_fmaf(bf, po[c], zsrc[c]); },
-                                [&](int i, float sv) {
-                                    const float pi = __builtin_fmaf(bf, po[i], zsrc[i]);
-                                    p.q32[i] = sv;
-                                    st_coh(pn + i, pi);
-                                    acc1[0] = __builtin_fma((double)pi, (double)sv, acc1[0]);
-                                });
-            } else {
-                pn = p.p0_32;
-                for (int i = r0 + tid; i < r1; i += CG_THREADS)
-                    st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
-                gs.template sync<true>();
-                spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
-                                [&](int c) { return pn[c]; },
-                                [&](int i, float sv) {
-                                    p.q32[i] = sv;
-                                    acc1[0] = __builtin_fma((double)pn[i], (double)sv, acc1[0]);
-                                });
-            }
+            float *pn = p.p32;
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
+            gs.template sync<true>();
+            spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
+                            [&](int c) { return pn[c]; },
+                            [&](int i, float sv) {
+                                p.q32[i] = sv;
+                                acc1[0] = __builtin_fma((double)pn[i], (double)sv, acc1[0]);
+                            });
             block_sum<1>(acc1, cg_red);
             if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
             gs.template sync<true>();
@@ -761,13 +741,13 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
 }
 
 // One problem on the whole grid.
-template <bool JACOBI, bool FUSEP, bool MIXED>
+template <bool JACOBI, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
     GroupSync gs;
     gs.init_grid(ws);
     CInst *in = (CInst *)pin;
-    if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*in, gs, blockIdx.x, gridDim.x);
-    else cg_f64_body<JACOBI, FUSEP>(in, gs, blockIdx.x, gridDim.x);
+    if (MIXED) cg_mixed_body<JACOBI>(*in, gs, blockIdx.x, gridDim.x);
+    else cg_f64_body<JACOBI>(in, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
 }
 
@@ -792,7 +772,7 @@ struct CgBatch {
     int ngroups;           // groups of two or more workgroups (ids 0 .. ngroups-1)
 };
 
-template <bool JACOBI, bool FUSEP, bool MIXED>
+template <bool JACOBI, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
     const int g = blockIdx.x;
     const unsigned e0 = ld_coh(bp.ws + SYNC_EPOCH);
@@ -803,8 +783,8 @@ __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
         // earlier group can never match a later group's epochs
         gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span);
         CInst *in = (CInst *)(bp.inst + task.inst);
-        if (MIXED) cg_mixed_body<JACOBI, FUSEP>(*in, gs, task.rank, task.size);
-        else cg_f64_body<JACOBI, FUSEP>(in, gs, task.rank, task.size);
+        if (MIXED) cg_mixed_body<JACOBI>(*in, gs, task.rank, task.size);
+        else cg_f64_body<JACOBI>(in, gs, task.rank, task.size);
     }
     GroupSync all;
     all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span);
@@ -1093,8 +1073,8 @@ int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int 
 }
 
 // Work area of one problem: the partial-sum table (NPART per workgroup) and
-// 64 result words, then the vectors.  FP64 solver: r, z, q, p0, p1, dinv (n
-// doubles each).  Mixed solver: r64 (n doubles); r, z, q, p0, p1, d, dinv (n
+// 64 result words, then the vectors.  FP64 solver: r, z, q, p, dinv (n
+// doubles each).  Mixed solver: r64 (n doubles); r, z, q, p, d, dinv (n
 // floats each); the FP32 copy of A's values (nnz floats).  Every vector starts
 // on a 256-byte boundary.
 size_t vec_len(int64_t n) { return ((size_t)n + 63) / 64 * 64 + 64; }
@@ -1105,10 +1085,10 @@ size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
     const size_t ns = (sell_capacity(nnz, std::max(parts, 1)) + 63) / 64 * 64;
     size_t bytes = (np + 64) * sizeof(double);
     if (mixed)
-        bytes += nv * sizeof(double) + 7 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float) +
+        bytes += nv * sizeof(double) + 6 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float) +
                  ns * (sizeof(float) + sizeof(int));
     else
-        bytes += 6 * nv * sizeof(double) + ns * (sizeof(double) + sizeof(int));
+        bytes += 5 * nv * sizeof(double) + ns * (sizeof(double) + sizeof(int));
     bytes += nv * sizeof(int);   // sperm
     return (bytes + 255) / 256 * 256;
 }
@@ -1126,11 +1106,10 @@ void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w)
         w->r32 = f;
         w->z32 = f + nv;
         w->q32 = f + 2 * nv;
-        w->p0_32 = f + 3 * nv;
-        w->p1_32 = f + 4 * nv;
-        w->d32 = f + 5 * nv;
-        w->dinv32 = f + 6 * nv;
-        w->val32 = f + 7 * nv;
+        w->p32 = f + 3 * nv;
+        w->d32 = f + 4 * nv;
+        w->dinv32 = f + 5 * nv;
+        w->val32 = f + 6 * nv;
         w->sval32 = w->val32 + ((size_t)nnz + 63) / 64 * 64;
         w->scol = (int *)(w->sval32 + ns);
         w->sperm = w->scol + ns;
@@ -1139,10 +1118,9 @@ void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w)
         w->r = d;
         w->z = d + nv;
         w->q = d + 2 * nv;
-        w->p0 = d + 3 * nv;
-        w->p1 = d + 4 * nv;
-        w->dinv = d + 5 * nv;
-        w->sval64 = d + 6 * nv;
+        w->p = d + 3 * nv;
+        w->dinv = d + 4 * nv;
+        w->sval64 = d + 5 * nv;
         w->scol = (int *)(w->sval64 + ns);
         w->sperm = w->scol + ns;
     }
@@ -1187,24 +1165,18 @@ int launch_error(hipError_t e) {
                      hipGetErrorString(e));
 }
 
-#ifndef PERKS_CG_FUSEP
-#define PERKS_CG_FUSEP true
-#endif
-
 const void *persistent_fn(bool jac, bool mixed) {
-    constexpr bool F = PERKS_CG_FUSEP;
-    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_persistent<true, F, true>)
-                          : reinterpret_cast<const void *>(&cg_persistent<false, F, true>);
-    return jac ? reinterpret_cast<const void *>(&cg_persistent<true, F, false>)
-               : reinterpret_cast<const void *>(&cg_persistent<false, F, false>);
+    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_persistent<true, true>)
+                          : reinterpret_cast<const void *>(&cg_persistent<false, true>);
+    return jac ? reinterpret_cast<const void *>(&cg_persistent<true, false>)
+               : reinterpret_cast<const void *>(&cg_persistent<false, false>);
 }
 
 const void *batched_fn(bool jac, bool mixed) {
-    constexpr bool F = PERKS_CG_FUSEP;
-    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_batched<true, F, true>)
-                          : reinterpret_cast<const void *>(&cg_batched<false, F, true>);
-    return jac ? reinterpret_cast<const void *>(&cg_batched<true, F, false>)
-               : reinterpret_cast<const void *>(&cg_batched<false, F, false>);
+    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_batched<true, true>)
+                          : reinterpret_cast<const void *>(&cg_batched<false, true>);
+    return jac ? reinterpret_cast<const void *>(&cg_batched<true, false>)
+               : reinterpret_cast<const void *>(&cg_batched<false, false>);
 }
 
 // Workgroups the device holds at once for a CG kernel (one per CU).
@@ -1332,7 +1304,7 @@ int cg_baseline_f64(const perks_csr *A, const void *b, void *x, double tol, int 
         // (re)start: r = b - A x, z, p = z, rho = r.z
         hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, xd, w.q,
                            (const double *)nullptr, (double *)nullptr);
-        hipLaunchKernelGGL(base_init, dim3(nb), dim3(256), 0, st, n, (const double *)b, w.q, w.r, w.z, w.p0, dinv,
+        hipLaunchKernelGGL(base_init, dim3(nb), dim3(256), 0, st, n, (const double *)b, w.q, w.r, w.z, w.p, dinv,
                            B.part_a, B.part_b, B.part_c);
         hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nb, &S->bb);
         hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho);
@@ -1354,16 +1326,16 @@ int cg_baseline_f64(const perks_csr *A, const void *b, void *x, double tol, int 
         int k = 0;
         bool conv = std::sqrt(rr) <= tol * bnorm, broke = false;
         while (!conv && total + k < maxit) {
-            hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, w.p0,
-                               w.q, (const double *)w.p0, B.part_a);
+            hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L, w.p,
+                               w.q, (const double *)w.p, B.part_a);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nbs, &S->pq);
             hipLaunchKernelGGL(base_alpha, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_update<double>, dim3(nb), dim3(256), 0, st, n, S, w.p0, w.q, xd, w.r, w.z, dinv,
+            hipLaunchKernelGGL(base_update<double>, dim3(nb), dim3(256), 0, st, n, S, w.p, w.q, xd, w.r, w.z, dinv,
                                B.part_b, B.part_c);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
             hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_pupdate<double>, dim3(nb), dim3(256), 0, st, n, S, (const double *)z, w.p0);
+            hipLaunchKernelGGL(base_pupdate<double>, dim3(nb), dim3(256), 0, st, n, S, (const double *)z, w.p);
             ++k;
             if (k % check_every == 0 || total + k >= maxit) {
                 PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
@@ -1467,7 +1439,7 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
         (void)std::frexp(rn, &ex);
         const double sc = std::ldexp(1.0, 1 - ex);
         hipLaunchKernelGGL(base_mixed_init, dim3(nb), dim3(256), 0, st, n, (const double *)w.r64, sc, w.r32, w.z32,
-                           w.p0_32, w.d32, dinv, B.part_b, B.part_c);
+                           w.p32, w.d32, dinv, B.part_b, B.part_c);
         hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho);
         hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
         PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
@@ -1479,16 +1451,16 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
         int k = 0;
         while (!done && total + k < maxit) {
             hipLaunchKernelGGL(base_spmv<float>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind,
-                               (const float *)w.val32, n, L, (const float *)w.p0_32, w.q32, (const float *)w.p0_32,
+                               (const float *)w.val32, n, L, (const float *)w.p32, w.q32, (const float *)w.p32,
                                B.part_a);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_a, nbs, &S->pq);
             hipLaunchKernelGGL(base_alpha, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_update<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)w.p0_32,
+            hipLaunchKernelGGL(base_update<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)w.p32,
                                (const float *)w.q32, w.d32, w.r32, w.z32, dinv, B.part_b, B.part_c);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
             hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_pupdate<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)z, w.p0_32);
+            hipLaunchKernelGGL(base_pupdate<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)z, w.p32);
             ++k;
             if (k % check_every == 0 || total + k >= maxit) {
                 PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
