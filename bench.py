@@ -145,6 +145,50 @@ def bench_cg(pk, torch, args):
     return out
 
 
+WIDE_FLOPS = {"2ds9pt": 18, "2d13pt": 26, "2d17pt": 34, "2d25pt": 50}
+
+
+def bench_wide(pk, torch, args):
+    """The rest of tab:domain's 2D suite (stars of radius 2, 3, 4 and the
+    radius-2 box) at 3072^2, FP64 and FP32, 1000 steps: persistent (default
+    plan) vs one launch per step."""
+    import numpy as np
+    import workloads
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = []
+    for kind in workloads.WIDE_KINDS:
+        r = workloads.stencil_radius(kind)
+        w = workloads.stencil_weights(kind)
+        cells = (3072 - 2 * r) ** 2 * STENCIL_STEPS
+        for dt in ("float64", "float32"):
+            g = torch.from_numpy(workloads.stencil_grid((3072, 3072), seed=0, r=r).astype(dt)).to(dev)
+
+            def timed(fn):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / 1e3
+
+            pk.stencil_run(g, w, 100)
+            tp = float(np.median([timed(lambda: pk.stencil_run(g, w, STENCIL_STEPS)) for _ in range(max(1, args.steps))]))
+            tb = timed(lambda: pk.stencil_run_baseline(g, w, STENCIL_STEPS))
+            plan = pk.stencil_plan((3072, 3072), w, dt)
+            flops = WIDE_FLOPS[kind] * cells / tp / 1e12
+            peak = PEAK_TFLOPS[dt]
+            out.append({"case": f"{kind} 3072x3072 {dt}", "persistent_ms": tp * 1e3,
+                        "persistent_gcells": cells / tp / 1e9, "baseline_ms": tb * 1e3,
+                        "baseline_gcells": cells / tb / 1e9, "speedup": tb / tp, "tflops": flops,
+                        "alu_frac": flops / peak, "plan": plan})
+            log(f"{kind} 3072x3072 {dt:8s} persistent {cells / tp / 1e9:8.1f} GCells/s ({flops:5.1f} TFLOP/s, "
+                f"{flops / peak:.2f} of vector peak)  baseline {cells / tb / 1e9:8.1f} GCells/s  x{tb / tp:.2f}  "
+                f"plan R={plan['rows_per_lane']} cached {plan['cached_tiles']}/{plan['tiles']}")
+            del g
+    return out
+
+
 def bench_batched_stencil(pk, torch, args):
     """512 2D 5-point FP64 grids, sides round(exp(U[ln 64, ln 1024])), 100 Jacobi
     steps each: one batched persistent launch vs one persistent launch per grid
@@ -315,6 +359,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default plans")
     ap.add_argument("--cases", default="all")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-wide", action="store_true", help="skip the radius-2..4 2D stencils")
     ap.add_argument("--no-cg-random", action="store_true", help="skip the n=1M random SPD system")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision CG")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned preconditioner")
@@ -479,6 +524,8 @@ def main():
         base_time = sum(r["baseline_ms"] for r in results) / 1e3
         out["baseline_value"] = sum(interior(c[1]) * STENCIL_STEPS for c in cases) / base_time / 1e9
         out["speedup_vs_per_step_launch"] = value / out["baseline_value"]
+    if not args.no_wide:
+        out["wide_stencils"] = bench_wide(pk, torch, args)
     if not args.no_cg:
         out["cg"] = bench_cg(pk, torch, args)
     if not args.no_batched:

@@ -47,10 +47,11 @@ typedef enum { PERKS_F32 = 0, PERKS_F64 = 1 } perks_dtype;
 
 /* Full extents of a grid INCLUDING its fixed boundary ring.  ndim = 2: the
  * array is [ny][nx]; ndim = 3: [nz][ny][nx]; x is the fastest index.  nz is
- * ignored for ndim = 2. */
+ * ignored for ndim = 2.  radius: the stencil's radius r (0 is read as 1);
+ * the weight box has (2r+1)^ndim entries and the ring is r cells wide. */
 typedef struct {
     int32_t ndim;
-    int32_t reserved;
+    int32_t radius;
     int64_t nx, ny, nz;
 } perks_shape;
 
@@ -89,19 +90,22 @@ typedef struct {
  * perks_stencil_run -- `steps` Jacobi sweeps of an explicit stencil, in place.
  *
  * Computes x^{k+1} = F(x^k) (Sec. 2.2, Eq. 1) with F the weighted box sum of
- * Eq. 2 (2D 5-point) generalised to a radius-1 weight box: every interior cell
- * becomes sum_{o in box} coeffs[o] * x^k[c + o]; the ring of width 1 is a fixed
+ * Eq. 2 (2D 5-point) generalised to a radius-r weight box: every interior cell
+ * becomes sum_{o in box} coeffs[o] * x^k[c + o]; the ring of width r is a fixed
  * Dirichlet boundary.  Step k+1 reads only step k (Listing 1 keeps separate
  * input and output buffers).
  *   grid    device, [nz][ny][nx] (or [ny][nx]) of float or double per `dt`;
  *           read as the initial state, overwritten with the state after `steps`.
- *   coeffs  host, 3^ndim doubles, [dz][dy][dx] with offsets -1..1 (dx fastest);
- *           Eq. 2's E is offset dx=+1, N is dy=+1.  Zeros mark unused points.
- *           Supported patterns: 2D 5-point star, 2D 9-point box, 3D 7-point
- *           star (others -> PERKS_E_UNSUPPORTED).  FP32 grids use the weights
- *           rounded to float.
+ *   shape   extents and radius r = max(1, shape.radius).
+ *   coeffs  host, (2r+1)^ndim doubles, [dz][dy][dx] with offsets -r..r (dx
+ *           fastest); Eq. 2's E is offset dx=+1, N is dy=+1.  Zeros mark
+ *           unused points.  Supported patterns (tab:domain): r = 1: the 2D
+ *           5-point star, the 2D 9-point box, the 3D 7-point star; 2D r = 2,
+ *           3, 4: the stars (2ds9pt, 2d13pt, 2d17pt: no weight off both
+ *           axes) and r = 2: the 5x5 box (2d25pt).  Others ->
+ *           PERKS_E_UNSUPPORTED.  FP32 grids use the weights rounded to float.
  *   steps   >= 0; 0 leaves grid untouched.
- * Every extent must be >= 3.  The whole run is ONE kernel launch.
+ * Every extent must be >= 2r+1.  The whole run is ONE kernel launch.
  */
 int perks_stencil_run(void *grid, const double *coeffs, perks_shape shape, int64_t steps,
                       perks_dtype dt, void *stream, const perks_tuning *tune);
@@ -120,7 +124,7 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
  * perks_stencil_run_batched -- `steps` Jacobi sweeps of every grid in ONE
  * persistent launch (an extension: the paper runs one grid per launch).
  *   grids   host array of `count` device pointers, each updated in place.
- *   shapes  host array of `count` extents (2D only; sizes may differ).
+ *   shapes  host array of `count` extents (2D, radius 1 only; sizes may differ).
  *   coeffs  one weight box for all grids (as for perks_stencil_run).
  * The tiles of all grids share the launch's waves (one tile height for all
  * grids); each grid keeps its own halo buffers and point-to-point halo

@@ -29,7 +29,7 @@ class PerksError(RuntimeError):
 
 
 class Shape(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("ndim", ctypes.c_int32), ("radius", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
 
 
@@ -150,19 +150,27 @@ def _dtype_code(t):
     raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
 
 
-def _shape_of(t):
-    if t.dim() == 2:
-        return Shape(2, 0, t.shape[1], t.shape[0], 1)
-    if t.dim() == 3:
-        return Shape(3, 0, t.shape[2], t.shape[1], t.shape[0])
+def _shape_from(dims, r=1):
+    """perks_shape of full extents ``dims`` ([ny, nx] or [nz, ny, nx]) for a
+    stencil of radius ``r``."""
+    dims = tuple(int(d) for d in dims)
+    if len(dims) == 2:
+        return Shape(2, r, dims[1], dims[0], 1)
+    if len(dims) == 3:
+        return Shape(3, r, dims[2], dims[1], dims[0])
     raise ValueError("grid must be 2D [ny, nx] or 3D [nz, ny, nx]")
 
 
+def _shape_of(t, r=1):
+    return _shape_from(tuple(t.shape), r)
+
+
 def _coeff_array(weights, ndim):
+    """The weight box as contiguous float64 and its radius: a (2r+1)^ndim box."""
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
-    if w.shape != (3,) * ndim:
-        raise ValueError(f"weights must be a {'x'.join(['3'] * ndim)} box")
-    return w
+    if w.ndim != ndim or len(set(w.shape)) != 1 or w.shape[0] % 2 != 1 or w.shape[0] < 3:
+        raise ValueError(f"weights must be a (2r+1)^{ndim} box with r >= 1")
+    return w, w.shape[0] // 2
 
 
 def _tuning(tuning):
@@ -182,9 +190,9 @@ def _check_grid(grid):
 def stencil_run(grid, weights, steps, tuning=None, stream=None):
     """Run ``steps`` Jacobi sweeps in place as ONE persistent kernel launch."""
     _check_grid(grid)
-    w = _coeff_array(weights, grid.dim())
+    w, r = _coeff_array(weights, grid.dim())
     rc = lib().perks_stencil_run(ctypes.c_void_p(grid.data_ptr()), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                 _shape_of(grid), int(steps), _dtype_code(grid), _stream_handle(stream),
+                                 _shape_of(grid, r), int(steps), _dtype_code(grid), _stream_handle(stream),
                                  _tuning(tuning))
     _check(rc)
     return grid
@@ -193,9 +201,9 @@ def stencil_run(grid, weights, steps, tuning=None, stream=None):
 def stencil_run_baseline(grid, weights, steps, stream=None):
     """Same sweeps with one kernel launch per step (the host-looped baseline)."""
     _check_grid(grid)
-    w = _coeff_array(weights, grid.dim())
+    w, r = _coeff_array(weights, grid.dim())
     rc = lib().perks_stencil_run_baseline(ctypes.c_void_p(grid.data_ptr()),
-                                          w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _shape_of(grid),
+                                          w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _shape_of(grid, r),
                                           int(steps), _dtype_code(grid), _stream_handle(stream))
     _check(rc)
     return grid
@@ -204,9 +212,8 @@ def stencil_run_baseline(grid, weights, steps, stream=None):
 def stencil_plan(shape, weights, dtype="float64", tuning=None):
     """The launch plan perks_stencil_run would use, as a dict."""
     shape = tuple(int(s) for s in shape)
-    nd = len(shape)
-    sh = Shape(2, 0, shape[1], shape[0], 1) if nd == 2 else Shape(3, 0, shape[2], shape[1], shape[0])
-    w = _coeff_array(weights, nd)
+    w, r = _coeff_array(weights, len(shape))
+    sh = _shape_from(shape, r)
     pl = StencilPlan()
     dt = PERKS_F64 if str(dtype).endswith("64") else PERKS_F32
     rc = lib().perks_stencil_plan_query(w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sh, dt,
@@ -224,9 +231,9 @@ def stencil_run_batched(grids, weights, steps, stream=None):
         _check_grid(g)
         if g.dim() != 2 or g.dtype != grids[0].dtype:
             raise ValueError("batched grids must be 2D and of one dtype")
-    w = _coeff_array(weights, 2)
+    w, r = _coeff_array(weights, 2)
     ptrs = (ctypes.c_void_p * m)(*[g.data_ptr() for g in grids])
-    shapes = (Shape * m)(*[_shape_of(g) for g in grids])
+    shapes = (Shape * m)(*[_shape_of(g, r) for g in grids])
     _check(lib().perks_stencil_run_batched(ptrs, shapes, m, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            int(steps), _dtype_code(grids[0]), _stream_handle(stream)))
     return grids
@@ -237,9 +244,8 @@ def stencil_autotune(shape, weights, dtype="float64", probe_steps=50, remember=T
     GCells/s).  With ``remember``, later untuned stencil_run calls on this shape
     use the winner."""
     shape = tuple(int(s) for s in shape)
-    nd = len(shape)
-    sh = Shape(2, 0, shape[1], shape[0], 1) if nd == 2 else Shape(3, 0, shape[2], shape[1], shape[0])
-    w = _coeff_array(weights, nd)
+    w, r = _coeff_array(weights, len(shape))
+    sh = _shape_from(shape, r)
     t = Tuning()
     rate = ctypes.c_double()
     dt = PERKS_F64 if str(dtype).endswith("64") else PERKS_F32

@@ -38,6 +38,7 @@ enum ScratchSlot {
     SLOT_CG_PART,       // CG partition table / partial sums
     SLOT_NN,            // network activations, gradients, packed weights
     SLOT_FCG,           // flexible-CG work vectors
+    SLOT_WIDE,          // second grid buffer of the radius-2..4 persistent stencils
     SLOT_COUNT
 };
 // Returns a device pointer of at least `bytes`, or nullptr (error already set).

@@ -13,9 +13,31 @@
 namespace perks {
 namespace {
 
-enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2 };
+// Patterns: radius 1 (2D 5-point star, 2D 9-point box, 3D 7-point star) and
+// the radius-2..4 2D stars and radius-2 2D box.
+enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2, K_W2S = 3, K_W3S = 4, K_W4S = 5, K_W2B = 6 };
+
+int radius_of(const perks_shape &s) { return s.radius <= 0 ? 1 : s.radius; }
+bool is_wide(Kind k) { return k >= K_W2S; }
+int wide_radius(Kind k) { return k == K_W2B ? 2 : (int)k - 1; }
 
 int classify(const double *c, const perks_shape &s, Kind *kind) {
+    const int r = radius_of(s);
+    if (r > 1) {
+        if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "3D stencils of radius %d are not supported", r);
+        const int w = 2 * r + 1;
+        bool off_axis = false;
+        for (int dy = 0; dy < w; ++dy)
+            for (int dx = 0; dx < w; ++dx)
+                if (dy != r && dx != r && c[dy * w + dx] != 0.0) off_axis = true;
+        if (!off_axis) {
+            *kind = (Kind)(K_W2S + (r - 2));
+            return PERKS_OK;
+        }
+        if (r != 2) return set_error(PERKS_E_UNSUPPORTED, "2D boxes of radius %d are not supported (radius 2 is)", r);
+        *kind = K_W2B;
+        return PERKS_OK;
+    }
     if (s.ndim == 2) {
         // [dy][dx]: corners are indices 0, 2, 6, 8
         bool corners = c[0] != 0.0 || c[2] != 0.0 || c[6] != 0.0 || c[8] != 0.0;
@@ -40,14 +62,17 @@ int check_common(const void *grid, const double *coeffs, const perks_shape &s, i
     if (s.ndim != 2 && s.ndim != 3) return set_error(PERKS_E_INVAL, "ndim must be 2 or 3 (got %d)", s.ndim);
     if (dt != PERKS_F32 && dt != PERKS_F64) return set_error(PERKS_E_INVAL, "dtype must be PERKS_F32 or PERKS_F64");
     if (steps < 0) return set_error(PERKS_E_INVAL, "steps must be >= 0");
-    if (s.nx < 3 || s.ny < 3 || (s.ndim == 3 && s.nz < 3))
-        return set_error(PERKS_E_INVAL, "every extent must be >= 3 (ring of width 1 on both sides)");
+    if (s.radius < 0 || s.radius > 4) return set_error(PERKS_E_INVAL, "radius must be 0..4 (got %d)", s.radius);
+    const int r = radius_of(s);
+    if (s.nx < 2 * r + 1 || s.ny < 2 * r + 1 || (s.ndim == 3 && s.nz < 2 * r + 1))
+        return set_error(PERKS_E_INVAL, "every extent must be >= %d (ring of width %d on both sides)", 2 * r + 1, r);
     const int64_t lim = int64_t(1) << 30;
     if (s.nx > lim || s.ny > lim || (s.ndim == 3 && s.nz > lim))
         return set_error(PERKS_E_INVAL, "extent too large");
     const int64_t cells = s.nx * s.ny * (s.ndim == 3 ? s.nz : 1);
     if (cells > (int64_t(1) << 36)) return set_error(PERKS_E_INVAL, "grid too large");
-    const int n = s.ndim == 3 ? 27 : 9;
+    const int w = 2 * r + 1;
+    const int n = s.ndim == 3 ? w * w * w : w * w;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(coeffs[i])) return set_error(PERKS_E_INVAL, "coeffs must be finite");
     return PERKS_OK;
@@ -77,6 +102,12 @@ bool tuned_for(Kind kind, perks_dtype dt, const perks_shape &s, perks_tuning *ou
 
 int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int64_t steps, perks_dtype dt,
                  Kind kind, hipStream_t st, const perks_tuning *tune) {
+    if (is_wide(kind)) {
+        const int r = wide_radius(kind);
+        const bool box = kind == K_W2B;
+        return dt == PERKS_F64 ? run2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
+                               : run2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
+    }
     if (shape.ndim == 2) {
         const bool box = kind == K_2D9;
         return dt == PERKS_F64 ? run2d<double>((double *)grid, coeffs, shape, steps, box, st, tune)
@@ -115,6 +146,12 @@ int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape sha
     if (rc) return rc;
     if (steps == 0) return PERKS_OK;
     hipStream_t st = as_stream(stream);
+    if (is_wide(kind)) {
+        const int r = wide_radius(kind);
+        const bool box = kind == K_W2B;
+        return dt == PERKS_F64 ? baseline2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st)
+                               : baseline2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
+    }
     if (shape.ndim == 2) {
         if (kind == K_2D9)
             return dt == PERKS_F64 ? baseline2d<double, true>((double *)grid, coeffs, shape, steps, st)
@@ -136,6 +173,12 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
     rc = classify(coeffs, shape, &kind);
     if (rc) return rc;
     memset(plan, 0, sizeof(*plan));
+    if (is_wide(kind)) {
+        const int r = wide_radius(kind);
+        const bool box = kind == K_W2B;
+        return dt == PERKS_F64 ? plan2d_wide_query<double>(shape, r, box, tune, plan)
+                               : plan2d_wide_query<float>(shape, r, box, tune, plan);
+    }
     if (shape.ndim == 2)
         return dt == PERKS_F64 ? plan2d_query<double>(shape, kind == K_2D9, tune, plan)
                                : plan2d_query<float>(shape, kind == K_2D9, tune, plan);
@@ -152,6 +195,7 @@ int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int
         int rc = check_common(grids[i], coeffs, shapes[i], steps, dt);
         if (rc) return set_error(rc, "grid %d: %s", i, last_error());
         if (shapes[i].ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "batched stencils are 2D");
+        if (radius_of(shapes[i]) != 1) return set_error(PERKS_E_UNSUPPORTED, "batched stencils have radius 1");
         rc = classify(coeffs, shapes[i], &kind);
         if (rc) return rc;
     }
@@ -184,7 +228,10 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
         perks_stencil_plan pl;
         if (perks_stencil_plan_query(coeffs, shape, dt, &t, &pl) == PERKS_OK) cands.push_back(t);
     };
-    if (shape.ndim == 2) {
+    if (is_wide(kind)) {
+        add(0, 0, 0);
+        for (int r : {32, 80}) add(r, 0, 1);
+    } else if (shape.ndim == 2) {
         for (int sync : {2, 1}) {
             add(0, 0, sync);
             for (int r : {8, 16, 32, 48, 64}) add(r, 0, sync);
@@ -236,7 +283,8 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
     (void)hipFree(g);
     if (rc) return rc;
     *best = cands[best_i];
-    const int64_t interior = (shape.nx - 2) * (shape.ny - 2) * (shape.ndim == 3 ? shape.nz - 2 : 1);
+    const int r = radius_of(shape);
+    const int64_t interior = (shape.nx - 2 * r) * (shape.ny - 2 * r) * (shape.ndim == 3 ? shape.nz - 2 * r : 1);
     if (best_gcells) *best_gcells = (double)interior * probe_steps / (best_t * 1e-3) / 1e9;
     if (remember) {
         std::lock_guard<std::mutex> lk(g_tune_mu);

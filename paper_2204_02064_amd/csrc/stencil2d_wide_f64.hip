@@ -1,0 +1,43 @@
+// Radius-2..4 2D stencil kernels and launchers instantiated for double.
+#include "stencil2d_wide.hpp"
+#include "stencil_api.hpp"
+
+namespace perks {
+
+template <>
+int run2d_wide<double>(double *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius, bool box,
+                    hipStream_t st, const perks_tuning *tu) {
+    if (box) return radius == 2 ? run_wide<double, 2, true>(grid, coeffs, s, steps, st, tu) : PERKS_E_UNSUPPORTED;
+    switch (radius) {
+        case 2: return run_wide<double, 2, false>(grid, coeffs, s, steps, st, tu);
+        case 3: return run_wide<double, 3, false>(grid, coeffs, s, steps, st, tu);
+        case 4: return run_wide<double, 4, false>(grid, coeffs, s, steps, st, tu);
+        default: return PERKS_E_UNSUPPORTED;
+    }
+}
+
+template <>
+int baseline2d_wide<double>(double *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius,
+                         bool box, hipStream_t st) {
+    if (box) return radius == 2 ? baseline_wide<double, 2, true>(grid, coeffs, s, steps, st) : PERKS_E_UNSUPPORTED;
+    switch (radius) {
+        case 2: return baseline_wide<double, 2, false>(grid, coeffs, s, steps, st);
+        case 3: return baseline_wide<double, 3, false>(grid, coeffs, s, steps, st);
+        case 4: return baseline_wide<double, 4, false>(grid, coeffs, s, steps, st);
+        default: return PERKS_E_UNSUPPORTED;
+    }
+}
+
+template <>
+int plan2d_wide_query<double>(const perks_shape &s, int radius, bool box, const perks_tuning *tu,
+                           perks_stencil_plan *plan) {
+    if (box) return radius == 2 ? plan_wide_query<double, 2, true>(s, tu, plan) : PERKS_E_UNSUPPORTED;
+    switch (radius) {
+        case 2: return plan_wide_query<double, 2, false>(s, tu, plan);
+        case 3: return plan_wide_query<double, 3, false>(s, tu, plan);
+        case 4: return plan_wide_query<double, 4, false>(s, tu, plan);
+        default: return PERKS_E_UNSUPPORTED;
+    }
+}
+
+}  // namespace perks

@@ -17,6 +17,17 @@ int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, p
 template <typename T>
 int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
                   bool box, hipStream_t st);
+// Radius-2..4 2D stencils: `radius` 2..4 with `box` false (stars) or radius
+// 2 with `box` true.
+template <typename T>
+int run2d_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius, bool box,
+               hipStream_t st, const perks_tuning *tu);
+template <typename T>
+int baseline2d_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius, bool box,
+                    hipStream_t st);
+template <typename T>
+int plan2d_wide_query(const perks_shape &s, int radius, bool box, const perks_tuning *tu, perks_stencil_plan *plan);
+
 template <typename T>
 int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st,
           const perks_tuning *tu);

@@ -48,6 +48,22 @@ def test_invalid_arguments_are_rejected(L):
     w27[0] = 1.0          # a 3D corner weight: outside the 7-point star
     assert L.perks_stencil_run(fake, w27.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                pk.Shape(3, 0, 8, 8, 8), 1, 1, None, None) == -5
+    # radius: 0..4; ring of width r; 3D only radius 1; boxes only radius 2
+    w25 = np.zeros(25)
+    w25[12] = 1.0
+    w25p = w25.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.perks_stencil_run(fake, w25p, pk.Shape(2, 5, 64, 64, 1), 1, 1, None, None) == -1
+    assert L.perks_stencil_run(fake, w25p, pk.Shape(2, -1, 64, 64, 1), 1, 1, None, None) == -1
+    assert L.perks_stencil_run(fake, w25p, pk.Shape(2, 2, 4, 64, 1), 1, 1, None, None) == -1
+    w125 = np.zeros(125)
+    assert L.perks_stencil_run(fake, w125.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               pk.Shape(3, 2, 16, 16, 16), 1, 1, None, None) == -5
+    w49 = np.zeros(49)
+    w49[0] = 1.0           # a corner of the radius-3 box: no 7x7 box kernel
+    assert L.perks_stencil_run(fake, w49.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               pk.Shape(2, 3, 64, 64, 1), 1, 1, None, None) == -5
+    assert L.perks_stencil_run_batched((ctypes.c_void_p * 1)(fake), (pk.Shape * 1)(pk.Shape(2, 2, 64, 64, 1)), 1,
+                                       w25p, 1, 1, None) == -5
     wn = np.full(9, np.nan)
     assert L.perks_stencil_run(fake, wn.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                pk.Shape(2, 0, 8, 8, 1), 1, 1, None, None) == -1

@@ -12,6 +12,19 @@ i along x and j along y, i.e. ``w[1+1][1]`` is N, ``w[1][1+1]`` is E.
 import numpy as np
 
 STENCIL_KINDS = ("2d5pt", "2d9pt", "3d7pt")
+# the rest of the 2D suite of tab:domain: stars of radius 2, 3, 4 and the
+# radius-2 box
+WIDE_KINDS = ("2ds9pt", "2d13pt", "2d17pt", "2d25pt")
+_WIDE = {"2ds9pt": (2, False), "2d13pt": (3, False), "2d17pt": (4, False), "2d25pt": (2, True)}
+
+
+def stencil_radius(kind):
+    """Radius of a named stencil."""
+    if kind in _WIDE:
+        return _WIDE[kind][0]
+    if kind in STENCIL_KINDS:
+        return 1
+    raise ValueError(f"unknown stencil kind {kind!r}")
 
 
 def stencil_weights(kind, dtype=np.float64):
@@ -20,7 +33,22 @@ def stencil_weights(kind, dtype=np.float64):
     2d5pt: centre and four neighbours 0.2 each (Eq. 2 with C=N=S=W=E=0.2).
     2d9pt: the radius-1 box, uniform 1/9 (tab:domain "2d9pt", order 1, 18 FLOPs).
     3d7pt: centre 0.4, six face neighbours 0.1 (tab:domain "3d7pt", 14 FLOPs).
+    2ds9pt, 2d13pt, 2d17pt: the stars of radius 2, 3, 4 (centre and r cells
+    along each axis direction; tab:domain orders 2, 3, 4 and 18, 26, 34
+    FLOPs), 2d25pt: the 5x5 box (order 2, 50 FLOPs).  The paper names the
+    patterns only; their weights here are uniform over the footprint (they
+    sum to one, as the 2d9pt box's do).
     """
+    if kind in _WIDE:
+        r, box = _WIDE[kind]
+        n = 2 * r + 1
+        if box:
+            w = np.full((n, n), 1.0 / (n * n))
+        else:
+            w = np.zeros((n, n))
+            w[r, :] = 1.0 / (4 * r + 1)
+            w[:, r] = 1.0 / (4 * r + 1)
+        return w.astype(dtype)
     if kind == "2d5pt":
         w = np.zeros((3, 3))
         w[1, 1] = 0.2
