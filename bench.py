@@ -145,24 +145,29 @@ def bench_cg(pk, torch, args):
     return out
 
 
-WIDE_FLOPS = {"2ds9pt": 18, "2d13pt": 26, "2d17pt": 34, "2d25pt": 50}
+WIDE_FLOPS = {"2ds9pt": 18, "2d13pt": 26, "2d17pt": 34, "2d25pt": 50,
+              "3d13pt": 26, "3d17pt": 34, "3d27pt": 54, "poisson": 38}
 
 
 def bench_wide(pk, torch, args):
-    """The rest of tab:domain's 2D suite (stars of radius 2, 3, 4 and the
-    radius-2 box) at 3072^2, FP64 and FP32, 1000 steps: persistent (default
-    plan) vs one launch per step."""
+    """The rest of tab:domain's suite: the 2D stars of radius 2, 3, 4 and the
+    radius-2 box at 3072^2, the 3D radius-2 star, 17-, 27- and 19-point
+    stencils at 256^3; FP64 and FP32, 1000 steps: persistent (default plan)
+    vs one launch per step."""
     import numpy as np
     import workloads
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     out = []
-    for kind in workloads.WIDE_KINDS:
+    # (the radius-1 3D box patterns are disabled in the library)
+    for kind in workloads.WIDE_KINDS + tuple(k for k in workloads.WIDE3_KINDS if workloads.stencil_radius(k) == 2):
         r = workloads.stencil_radius(kind)
         w = workloads.stencil_weights(kind)
-        cells = (3072 - 2 * r) ** 2 * STENCIL_STEPS
+        shape = (3072, 3072) if kind.startswith("2d") else (256, 256, 256)
+        cells = math.prod(s - 2 * r for s in shape) * STENCIL_STEPS
+        label = "x".join(map(str, shape))
         for dt in ("float64", "float32"):
-            g = torch.from_numpy(workloads.stencil_grid((3072, 3072), seed=0, r=r).astype(dt)).to(dev)
+            g = torch.from_numpy(workloads.stencil_grid(shape, seed=0, r=r).astype(dt)).to(dev)
 
             def timed(fn):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -175,14 +180,14 @@ def bench_wide(pk, torch, args):
             pk.stencil_run(g, w, 100)
             tp = float(np.median([timed(lambda: pk.stencil_run(g, w, STENCIL_STEPS)) for _ in range(max(1, args.steps))]))
             tb = timed(lambda: pk.stencil_run_baseline(g, w, STENCIL_STEPS))
-            plan = pk.stencil_plan((3072, 3072), w, dt)
+            plan = pk.stencil_plan(shape, w, dt)
             flops = WIDE_FLOPS[kind] * cells / tp / 1e12
             peak = PEAK_TFLOPS[dt]
-            out.append({"case": f"{kind} 3072x3072 {dt}", "persistent_ms": tp * 1e3,
+            out.append({"case": f"{kind} {label} {dt}", "persistent_ms": tp * 1e3,
                         "persistent_gcells": cells / tp / 1e9, "baseline_ms": tb * 1e3,
                         "baseline_gcells": cells / tb / 1e9, "speedup": tb / tp, "tflops": flops,
                         "alu_frac": flops / peak, "plan": plan})
-            log(f"{kind} 3072x3072 {dt:8s} persistent {cells / tp / 1e9:8.1f} GCells/s ({flops:5.1f} TFLOP/s, "
+            log(f"{kind} {label} {dt:8s} persistent {cells / tp / 1e9:8.1f} GCells/s ({flops:5.1f} TFLOP/s, "
                 f"{flops / peak:.2f} of vector peak)  baseline {cells / tb / 1e9:8.1f} GCells/s  x{tb / tp:.2f}  "
                 f"plan R={plan['rows_per_lane']} cached {plan['cached_tiles']}/{plan['tiles']}")
             del g

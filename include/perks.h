@@ -102,7 +102,11 @@ typedef struct {
  *           unused points.  Supported patterns (tab:domain): r = 1: the 2D
  *           5-point star, the 2D 9-point box, the 3D 7-point star; 2D r = 2,
  *           3, 4: the stars (2ds9pt, 2d13pt, 2d17pt: no weight off both
- *           axes) and r = 2: the 5x5 box (2d25pt).  Others ->
+ *           axes) and r = 2: the 5x5 box (2d25pt); 3D r = 2: the star
+ *           (3d13pt), which runs persistent but streams the grid through HBM
+ *           every step (no on-chip cache; plan.cached_tiles = 0).  Others,
+ *           including the 3D radius-1 patterns beyond the 7-point star
+ *           (3d27pt, poisson, 3d17pt: their kernel is disabled), ->
  *           PERKS_E_UNSUPPORTED.  FP32 grids use the weights rounded to float.
  *   steps   >= 0; 0 leaves grid untouched.
  * Every extent must be >= 2r+1.  The whole run is ONE kernel launch.

@@ -13,18 +13,32 @@
 namespace perks {
 namespace {
 
-// Patterns: radius 1 (2D 5-point star, 2D 9-point box, 3D 7-point star) and
-// the radius-2..4 2D stars and radius-2 2D box.
-enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2, K_W2S = 3, K_W3S = 4, K_W4S = 5, K_W2B = 6 };
+// Patterns: radius 1 (2D 5-point star, 2D 9-point box, 3D 7-point star),
+// the radius-2..4 2D stars and radius-2 2D box, any other radius-1 3D
+// pattern (27-point box, 19-point, 17-point) and the radius-2 3D star.
+enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2, K_W2S = 3, K_W3S = 4, K_W4S = 5, K_W2B = 6, K_3B1 = 7, K_3S2 = 8 };
 
 int radius_of(const perks_shape &s) { return s.radius <= 0 ? 1 : s.radius; }
-bool is_wide(Kind k) { return k >= K_W2S; }
+bool is_wide(Kind k) { return k >= K_W2S && k <= K_W2B; }
 int wide_radius(Kind k) { return k == K_W2B ? 2 : (int)k - 1; }
+bool is_wide3(Kind k) { return k == K_3B1 || k == K_3S2; }
 
 int classify(const double *c, const perks_shape &s, Kind *kind) {
     const int r = radius_of(s);
+    if (r > 1 && s.ndim == 3) {
+        if (r != 2) return set_error(PERKS_E_UNSUPPORTED, "3D stencils of radius %d are not supported", r);
+        const int w = 5;
+        for (int dz = 0; dz < w; ++dz)
+            for (int dy = 0; dy < w; ++dy)
+                for (int dx = 0; dx < w; ++dx) {
+                    const int off = (dz != 2) + (dy != 2) + (dx != 2);
+                    if (off > 1 && c[(dz * w + dy) * w + dx] != 0.0)
+                        return set_error(PERKS_E_UNSUPPORTED, "3D radius-2 weights must form a star");
+                }
+        *kind = K_3S2;
+        return PERKS_OK;
+    }
     if (r > 1) {
-        if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "3D stencils of radius %d are not supported", r);
         const int w = 2 * r + 1;
         bool off_axis = false;
         for (int dy = 0; dy < w; ++dy)
@@ -44,14 +58,18 @@ int classify(const double *c, const perks_shape &s, Kind *kind) {
         *kind = corners ? K_2D9 : K_2D5;
         return PERKS_OK;
     }
-    // 3D: only the centre and the six face neighbours may be non-zero
+    // 3D: the 7-point star (centre and face neighbours), else the box kernel
     for (int dz = 0; dz < 3; ++dz)
         for (int dy = 0; dy < 3; ++dy)
             for (int dx = 0; dx < 3; ++dx) {
                 int off = (dz != 1) + (dy != 1) + (dx != 1);
                 if (off > 1 && c[(dz * 3 + dy) * 3 + dx] != 0.0)
+                    // the radius-1 box variant of the 3D streamed kernels
+                    // (3d27pt, poisson, 3d17pt) passes its small-grid parity
+                    // tests but hung once at 256^3 with four workgroups per
+                    // CU, cause not found; it stays off until that is understood
                     return set_error(PERKS_E_UNSUPPORTED,
-                                     "3D weights outside the 7-point star are not supported");
+                                     "3D weights outside the 7-point star are not supported at radius 1");
             }
     *kind = K_3D7;
     return PERKS_OK;
@@ -108,6 +126,12 @@ int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int
         return dt == PERKS_F64 ? run2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
                                : run2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
     }
+    if (is_wide3(kind)) {
+        const int r = kind == K_3B1 ? 1 : 2;
+        const bool box = kind == K_3B1;
+        return dt == PERKS_F64 ? run3d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
+                               : run3d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
+    }
     if (shape.ndim == 2) {
         const bool box = kind == K_2D9;
         return dt == PERKS_F64 ? run2d<double>((double *)grid, coeffs, shape, steps, box, st, tune)
@@ -152,6 +176,12 @@ int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape sha
         return dt == PERKS_F64 ? baseline2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st)
                                : baseline2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
     }
+    if (is_wide3(kind)) {
+        const int r = kind == K_3B1 ? 1 : 2;
+        const bool box = kind == K_3B1;
+        return dt == PERKS_F64 ? baseline3d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st)
+                               : baseline3d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
+    }
     if (shape.ndim == 2) {
         if (kind == K_2D9)
             return dt == PERKS_F64 ? baseline2d<double, true>((double *)grid, coeffs, shape, steps, st)
@@ -178,6 +208,12 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
         const bool box = kind == K_W2B;
         return dt == PERKS_F64 ? plan2d_wide_query<double>(shape, r, box, tune, plan)
                                : plan2d_wide_query<float>(shape, r, box, tune, plan);
+    }
+    if (is_wide3(kind)) {
+        const int r = kind == K_3B1 ? 1 : 2;
+        const bool box = kind == K_3B1;
+        return dt == PERKS_F64 ? plan3d_wide_query<double>(shape, r, box, tune, plan)
+                               : plan3d_wide_query<float>(shape, r, box, tune, plan);
     }
     if (shape.ndim == 2)
         return dt == PERKS_F64 ? plan2d_query<double>(shape, kind == K_2D9, tune, plan)
@@ -230,7 +266,9 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
     };
     if (is_wide(kind)) {
         add(0, 0, 0);
-        for (int r : {32, 80}) add(r, 0, 1);
+        for (int r : {32, 48, 80}) add(r, 0, 1);
+    } else if (is_wide3(kind)) {
+        add(0, 0, 0);
     } else if (shape.ndim == 2) {
         for (int sync : {2, 1}) {
             add(0, 0, sync);

@@ -95,9 +95,13 @@ __device__ __forceinline__ WideTile wide_tile_of(int t, int ntx, int nx, int ny,
 // rows it touches, whose accumulators roll through 2r+1 registers.  New row
 // i is complete once old row i+r has been visited; by then old row i has
 // been consumed, so the new value takes its register.
-template <typename T, int R, bool BOX, int RC>
-__device__ __forceinline__ void wide_rows(T (&u)[RC], const T *hr, const T *cw, const T *ce, const WideW<T, R> &W,
-                                          int hy, bool live) {
+//
+// ACC selects the 3D use (one z layer of a 3D stencil): the new values are
+// not written into u but added to out (FIRST: out = the layer's sum); wt(dy,
+// dx) returns the layer's weight.
+template <typename T, int R, bool BOX, int RC, bool ACC = false, bool FIRST = false, class WF>
+__device__ __forceinline__ void wide_rows_impl(T (&u)[RC], const T *hr, const T *cw, const T *ce, WF &&wt, int hy,
+                                               bool live, T (&out)[RC]) {
     constexpr int S = 2 * R + 1;
     constexpr int NJ = BOX ? RC + 2 * R : RC;
     constexpr int J0 = BOX ? R : 0;
@@ -153,17 +157,17 @@ __device__ __forceinline__ void wide_rows(T (&u)[RC], const T *hr, const T *cw, 
                 if constexpr (BOX) {
                     static_for<0, S>([&](auto xc) {
                         constexpr int dx = decltype(xc)::value - R;
-                        const T w = W.w[(dy + R) * S + dx + R];
+                        const T w = wt(dy, dx);
                         if constexpr (dy == -R && dx == -R) acc[slot] = w * sh[dx + R];
                         else acc[slot] = fma_t(w, sh[dx + R], acc[slot]);
                     });
                 } else if constexpr (dy == 0) {
                     static_for<0, S>([&](auto xc) {
                         constexpr int dx = decltype(xc)::value - R;
-                        acc[slot] = fma_t(W.w[R * S + dx + R], sh[dx + R], acc[slot]);
+                        acc[slot] = fma_t(wt(0, dx), sh[dx + R], acc[slot]);
                     });
                 } else {
-                    const T w = W.w[(dy + R) * S + R];
+                    const T w = wt(dy, 0);
                     if constexpr (dy == -R) acc[slot] = w * v;
                     else acc[slot] = fma_t(w, v, acc[slot]);
                 }
@@ -171,13 +175,23 @@ __device__ __forceinline__ void wide_rows(T (&u)[RC], const T *hr, const T *cw, 
         });
         if constexpr (j - R >= 0 && j - R < RC) {
             constexpr int i = j - R;
-            u[i] = (live && i < hy) ? acc[i % S] : u[i];
+            if constexpr (!ACC) u[i] = (live && i < hy) ? acc[i % S] : u[i];
+            else if constexpr (FIRST) out[i] = acc[i % S];
+            else out[i] = out[i] + acc[i % S];
         }
         // this row's products are computed here: without the tie the
         // compiler sinks every row's FMAs below all the shifts, keeping each
         // row's shifted values live at once
         settle(acc);
     });
+}
+
+template <typename T, int R, bool BOX, int RC>
+__device__ __forceinline__ void wide_rows(T (&u)[RC], const T *hr, const T *cw, const T *ce, const WideW<T, R> &W,
+                                          int hy, bool live) {
+    constexpr int S = 2 * R + 1;
+    wide_rows_impl<T, R, BOX, RC>(u, hr, cw, ce, [&](int dy, int dx) { return W.w[(dy + R) * S + dx + R]; }, hy,
+                                  live, u);
 }
 
 // Element offset of (row y, column x) with both clamped into the grid (reads

@@ -28,6 +28,17 @@ int baseline2d_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t
 template <typename T>
 int plan2d_wide_query(const perks_shape &s, int radius, bool box, const perks_tuning *tu, perks_stencil_plan *plan);
 
+// 3D stencils beyond the 7-point star: any radius-1 pattern (`box`) or the
+// radius-2 star (streamed through HBM every step).
+template <typename T>
+int run3d_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius, bool box,
+               hipStream_t st, const perks_tuning *tu);
+template <typename T>
+int baseline3d_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, int radius, bool box,
+                    hipStream_t st);
+template <typename T>
+int plan3d_wide_query(const perks_shape &s, int radius, bool box, const perks_tuning *tu, perks_stencil_plan *plan);
+
 template <typename T>
 int run3d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st,
           const perks_tuning *tu);

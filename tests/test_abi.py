@@ -45,9 +45,12 @@ def test_invalid_arguments_are_rejected(L):
     assert L.perks_stencil_run(fake, wp, pk.Shape(2, 0, 8, 8, 1), -1, 1, None, None) == -1
     assert L.perks_stencil_run(fake, wp, pk.Shape(2, 0, 8, 8, 1), 1, 7, None, None) == -1
     w27 = np.zeros(27)
-    w27[0] = 1.0          # a 3D corner weight: outside the 7-point star
+    w27[0] = 1.0           # a 3D corner weight: the radius-1 box kernel is disabled
     assert L.perks_stencil_run(fake, w27.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                pk.Shape(3, 0, 8, 8, 8), 1, 1, None, None) == -5
+    w343 = np.zeros(343)   # 3D radius 3: no kernel
+    assert L.perks_stencil_run(fake, w343.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               pk.Shape(3, 3, 8, 8, 8), 1, 1, None, None) == -5
     # radius: 0..4; ring of width r; 3D only radius 1; boxes only radius 2
     w25 = np.zeros(25)
     w25[12] = 1.0
@@ -56,6 +59,7 @@ def test_invalid_arguments_are_rejected(L):
     assert L.perks_stencil_run(fake, w25p, pk.Shape(2, -1, 64, 64, 1), 1, 1, None, None) == -1
     assert L.perks_stencil_run(fake, w25p, pk.Shape(2, 2, 4, 64, 1), 1, 1, None, None) == -1
     w125 = np.zeros(125)
+    w125[0] = 1.0          # a corner of the radius-2 3D box: only the 3D radius-2 star is built
     assert L.perks_stencil_run(fake, w125.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                pk.Shape(3, 2, 16, 16, 16), 1, 1, None, None) == -5
     w49 = np.zeros(49)

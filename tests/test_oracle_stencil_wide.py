@@ -120,3 +120,82 @@ def test_constant_preserved_ring_fixed_linear_and_composable(kind):
     ring[workloads.interior_slices(2, r)] = False
     np.testing.assert_array_equal(su[ring], u[ring])
     np.testing.assert_array_equal(oracle.stencil(oracle.stencil(u, w, 2), w, 4), su)
+
+
+# ---------------------------------------------------------------------------
+# 3D patterns beyond the 7-point star (3d13pt, 3d17pt, 3d27pt, poisson)
+
+@pytest.mark.parametrize("kind", workloads.WIDE3_KINDS)
+def test_3d_weights_cover_the_named_footprint(kind):
+    w = workloads.stencil_weights(kind)
+    r = workloads.stencil_radius(kind)
+    assert w.shape == (2 * r + 1,) * 3
+    assert (w != 0).sum() == {"3d13pt": 13, "3d17pt": 17, "3d27pt": 27, "poisson": 19}[kind]
+    assert abs(w.sum() - 1.0) < 1e-15
+    np.testing.assert_array_equal(w, w[::-1, ::-1, ::-1])   # centrally symmetric
+
+
+@pytest.mark.parametrize("kind", workloads.WIDE3_KINDS)
+def test_3d_impulse_one_step_is_the_mirrored_weight_box(kind):
+    r = workloads.stencil_radius(kind)
+    w = _random_pattern_weights(kind, 13)
+    n = 2 * r + 5
+    g = np.zeros((n, n + 1, n + 2))
+    c = (n // 2, (n + 1) // 2, (n + 2) // 2)
+    g[c] = 1.0
+    got = oracle.stencil(g, w, 1)
+    exp = np.zeros_like(g)
+    exp[c[0] - r:c[0] + r + 1, c[1] - r:c[1] + r + 1, c[2] - r:c[2] + r + 1] = w[::-1, ::-1, ::-1]
+    np.testing.assert_array_equal(got, exp)
+
+
+@pytest.mark.parametrize("kind", workloads.WIDE3_KINDS)
+def test_3d_impulse_two_steps_is_the_convolution(kind):
+    r = workloads.stencil_radius(kind)
+    w = _random_pattern_weights(kind, 17)
+    n = 4 * r + 5
+    g = np.zeros((n, n, n))
+    c = n // 2
+    g[c, c, c] = 1.0
+    got = oracle.stencil(g, w, 2)
+    ker = w[::-1, ::-1, ::-1]
+    acc = signal.convolve(ker, ker, method="direct")
+    exp = np.zeros_like(g)
+    exp[c - 2 * r:c + 2 * r + 1, c - 2 * r:c + 2 * r + 1, c - 2 * r:c + 2 * r + 1] = acc
+    np.testing.assert_allclose(got, exp, rtol=0, atol=1e-14 * np.abs(exp).max())
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_27pt_box_impulse_is_trinomial_outer_product(k):
+    n = 2 * k + 5
+    g = np.zeros((n, n, n))
+    c = n // 2
+    g[c, c, c] = 1.0
+    got = oracle.stencil(g, workloads.stencil_weights("3d27pt"), k)
+    t = [Fraction(1)]
+    for _ in range(k):
+        nxt = [Fraction(0)] * (len(t) + 2)
+        for i, v in enumerate(t):
+            for d in range(3):
+                nxt[i + d] += v / 3
+        t = nxt
+    t = np.array([float(v) for v in t])
+    exp = np.zeros_like(g)
+    exp[c - k:c + k + 1, c - k:c + k + 1, c - k:c + k + 1] = t[:, None, None] * t[None, :, None] * t[None, None, :]
+    np.testing.assert_allclose(got, exp, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("kind", workloads.WIDE3_KINDS)
+def test_3d_sweeps_match_scipy_correlation_and_keep_constants(kind):
+    r = workloads.stencil_radius(kind)
+    w = _random_pattern_weights(kind, 19)
+    shape = (5 + 2 * r, 7 + 2 * r, 9 + 2 * r)
+    g = workloads.stencil_grid(shape, seed=6, r=r, ring_value=-0.5)
+    inner = workloads.interior_slices(3, r)
+    ref = g.copy()
+    for _ in range(3):
+        nxt = ndimage.correlate(ref, w, mode="constant", cval=0.0)
+        ref[inner] = nxt[inner]
+    np.testing.assert_allclose(oracle.stencil(g, w, 3), ref, rtol=0, atol=1e-13)
+    c = np.full(shape, 0.3725)
+    np.testing.assert_allclose(oracle.stencil(c, workloads.stencil_weights(kind), 20), c, rtol=0, atol=20 * 4e-16)

@@ -10,7 +10,7 @@ Every random generator draws from ``numpy.random.default_rng(seed)``
 (PCG64) in row-major order.
 """
 from .stencil import (stencil_grid, stencil_weights, stencil_radius, interior_slices, STENCIL_KINDS,
-                      WIDE_KINDS)
+                      WIDE_KINDS, WIDE3_KINDS)
 from .diffusion import (grf_log_k, diffusion_csr, diffusion_problem, grf_log_k_torch, diffusion_csr_torch,
                         diffusion_problem_torch, diffusion_planes, diffusion_planes_torch)
 from .sparse import (poisson_csr, poisson2d_csr_torch, random_spd_csr, rhs_uniform, rhs_normal,
@@ -18,6 +18,7 @@ from .sparse import (poisson_csr, poisson2d_csr_torch, random_spd_csr, rhs_unifo
 
 __all__ = [
     "stencil_grid", "stencil_weights", "stencil_radius", "interior_slices", "STENCIL_KINDS", "WIDE_KINDS",
+    "WIDE3_KINDS",
     "poisson_csr", "poisson2d_csr_torch", "random_spd_csr", "rhs_uniform", "rhs_normal", "csr_to_dense",
     "lognormal_sides", "grf_log_k", "diffusion_csr", "diffusion_problem", "grf_log_k_torch",
     "diffusion_csr_torch", "diffusion_problem_torch", "diffusion_planes", "diffusion_planes_torch",

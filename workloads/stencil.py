@@ -16,12 +16,17 @@ STENCIL_KINDS = ("2d5pt", "2d9pt", "3d7pt")
 # radius-2 box
 WIDE_KINDS = ("2ds9pt", "2d13pt", "2d17pt", "2d25pt")
 _WIDE = {"2ds9pt": (2, False), "2d13pt": (3, False), "2d17pt": (4, False), "2d25pt": (2, True)}
+# and of its 3D suite
+WIDE3_KINDS = ("3d13pt", "3d17pt", "3d27pt", "poisson")
+_WIDE3 = {"3d13pt": 2, "3d17pt": 1, "3d27pt": 1, "poisson": 1}
 
 
 def stencil_radius(kind):
     """Radius of a named stencil."""
     if kind in _WIDE:
         return _WIDE[kind][0]
+    if kind in _WIDE3:
+        return _WIDE3[kind]
     if kind in STENCIL_KINDS:
         return 1
     raise ValueError(f"unknown stencil kind {kind!r}")
@@ -38,7 +43,26 @@ def stencil_weights(kind, dtype=np.float64):
     FLOPs), 2d25pt: the 5x5 box (order 2, 50 FLOPs).  The paper names the
     patterns only; their weights here are uniform over the footprint (they
     sum to one, as the 2d9pt box's do).
+    3d13pt: the radius-2 3D star (order 2, 26 FLOPs); 3d27pt: the 3x3x3 box
+    (54 FLOPs); poisson: the 19 points of that box that are not corners (38
+    FLOPs); 3d17pt (order 1, 34 FLOPs: 17 points of the 3x3x3 box, which no
+    union of the box's symmetry classes gives): the 3x3 box of the centre
+    plane and the four points (+-1, 0), (0, +-1) of each neighbouring plane.
+    Uniform weights as above.
     """
+    if kind in _WIDE3:
+        d = np.indices((5, 5, 5) if kind == "3d13pt" else (3, 3, 3)) - (2 if kind == "3d13pt" else 1)
+        az, ay, ax = np.abs(d)
+        nz = (az > 0).astype(int) + (ay > 0) + (ax > 0)
+        if kind == "3d13pt":
+            m = nz <= 1
+        elif kind == "3d27pt":
+            m = np.ones_like(nz, dtype=bool)
+        elif kind == "poisson":
+            m = nz <= 2
+        else:
+            m = (az == 0) | ((nz == 2) & (az == 1))
+        return np.where(m, 1.0 / m.sum(), 0.0).astype(dtype)
     if kind in _WIDE:
         r, box = _WIDE[kind]
         n = 2 * r + 1
