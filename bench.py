@@ -37,25 +37,35 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: the factors a 1 GiB device
-# copy reads back), with the SHA-256 of the kernel's source file they were
-# taken on: a changed source reports null until measured again.
+# copy reads back), with one SHA-256 over the source files the kernel is built
+# from: a changed source reports null until measured again.
 MEASURED_TRAFFIC = {
     ("3d7pt", (256, 256, 256), "float64"): {
-        "bytes": 209.81e9,   # profiles/stencil3d_column_f64_256cubed.md
-        "source": "paper_2204_02064_amd/csrc/stencil3d.hpp",
-        "sha256": "dc1b259708f12db6d892270516ac62caf4f6a21050cf2351f2dd9dd0b08adeb6",
+        "bytes": None,   # profiles/stencil3d_column_f64_256cubed.md
+        "sources": ["paper_2204_02064_amd/csrc/stencil3d.hpp", "paper_2204_02064_amd/csrc/barrier.hpp",
+                    "paper_2204_02064_amd/csrc/common.hpp", "paper_2204_02064_amd/csrc/stencil3d_f64.hip"],
+        "sha256": None,
     },
 }
 
 
-def measured_traffic(case):
+def sources_digest(paths):
+    """SHA-256 over the named files (repository-relative), in order."""
     import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in paths:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(case):
     m = MEASURED_TRAFFIC.get(case)
     if not m or m["bytes"] is None:
         return None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), m["source"])
     try:
-        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+        digest = sources_digest(m["sources"])
     except OSError:
         return None
     return m["bytes"] if digest == m["sha256"] else None

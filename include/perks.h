@@ -362,9 +362,12 @@ int perks_nn_train(float *params, const float *x, const float *target, const flo
  * the Jacobi step, so a zero network is Jacobi-PCG -- computed inside the
  * kernel (16 x 16 tiles, all six layers per tile in LDS).
  * Safeguards: z = D^{-1} r for an iteration where <z, r> <= 0 or z is not
- * finite; after `stall` iterations without a new minimum of ||r|| the solve
- * continues as Jacobi-preconditioned CG.  nn_params == NULL: Jacobi-PCG from
- * the start (the baseline the network is compared against).
+ * finite; after `stall` iterations without a new minimum of ||r|| the kernel
+ * ends and the solve continues from the current iterate as
+ * perks_cg_solve(..., PERKS_PRECOND_JACOBI, PERKS_PREC_F64, ...) with the
+ * remaining iterations (a restart of the direction recurrence, which FCG with
+ * a fixed Jacobi step would take too).  nn_params == NULL: Jacobi-PCG inside
+ * the FCG kernel from the start.
  *   A       FP64 CSR on an H x W grid of unknowns (row y * W + x), n = H * W.
  *   logk    device, H * W doubles (the second network input).
  *   out     iters, status, restarts = iterations that fell back to Jacobi,

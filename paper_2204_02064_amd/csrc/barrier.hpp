@@ -3,8 +3,9 @@
 //
 // Design (measured on MI355X, 256 workgroups of 512 threads):
 //   * One packed arrival word per workgroup; a single master wavefront
-//     (workgroup 0, wave 0) polls all of them with 64 lanes at a time and then
-//     publishes a generation word that the other workgroups poll.  No
+//     (workgroup 0, wave 0) polls all of them, eight independent loads per
+//     lane per round, and then publishes a generation word that the other
+//     workgroups poll.  No
 //     read-modify-write atomics: a shared counter serialises arrivals at the
 //     memory side (~70 ns each).
 //   * Only workgroup-scope fences.  All data that crosses workgroups is moved
@@ -22,6 +23,28 @@
 #include "common.hpp"
 
 namespace perks {
+
+// Called by the 64 lanes of one wavefront: returns once flags[0 .. G) all
+// equal e.  Each lane issues up to 8 independent flag loads per round, so one
+// memory round trip covers 512 workgroups (a poll of G flags costs G / 512
+// round trips, not G / 64).
+__device__ __forceinline__ void wait_flags(const unsigned *flags, unsigned G, unsigned e) {
+    const unsigned lane = threadIdx.x & 63;
+    while (true) {
+        bool ok = true;
+        for (unsigned base = 0; base < G; base += 512) {
+            // lanes past the last workgroup load its flag again (no branch,
+            // so the eight loads stay in flight together) and ignore it
+            unsigned v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = ld_coh(flags + min(base + 64u * u + lane, G - 1));
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ok = ok & ((base + 64u * u + lane >= G) | (v[u] == e));
+        }
+        if (__all(ok)) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
 
 struct GridSync {
     unsigned *ws;
@@ -47,15 +70,7 @@ struct GridSync {
         if (threadIdx.x == 0) st_coh(ws + SYNC_FLAGS + blockIdx.x, e);
         if (blockIdx.x == 0) {
             if (threadIdx.x < 64) {
-                const unsigned G = gridDim.x;
-                for (unsigned base = 0; base < G; base += 64) {
-                    const unsigned i = base + threadIdx.x;
-                    while (true) {
-                        bool ok = (i >= G) || (ld_coh(ws + SYNC_FLAGS + i) == e);
-                        if (__all(ok)) break;
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
+                wait_flags(ws + SYNC_FLAGS, gridDim.x, e);
                 if (threadIdx.x == 0) st_coh(ws + SYNC_GEN, e);
             }
         } else if (threadIdx.x == 0) {
@@ -117,15 +132,7 @@ struct GroupSync {
         if (threadIdx.x == 0) st_coh(flags + rank, e);
         if (rank == 0) {
             if (threadIdx.x < 64) {
-                const unsigned G = size;
-                for (unsigned base = 0; base < G; base += 64) {
-                    const unsigned i = base + threadIdx.x;
-                    while (true) {
-                        bool ok = (i >= G) || (ld_coh(flags + i) == e);
-                        if (__all(ok)) break;
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
+                wait_flags(flags, (unsigned)size, e);
                 if (threadIdx.x == 0) st_coh(gen, e);
             }
         } else if (threadIdx.x == 0) {

@@ -9,8 +9,10 @@
 // the H x W grid of unknowns, so a zero network is Jacobi-PCG.  When
 // the network fails (<z, r> <= 0 or a non-finite value) the Jacobi step
 // z = D^{-1} r replaces it for that iteration; when the residual norm has not
-// reached a new minimum for `stall` iterations the solve continues as
-// Jacobi-preconditioned CG for good (the direction recurrence restarts).
+// reached a new minimum for `stall` iterations the kernel ends and the host
+// continues from the current iterate with the persistent Jacobi-PCG solver
+// (a restart of the direction recurrence, as FCG with a fixed Jacobi step
+// would take, at that solver's cost per iteration).
 //
 // Per iteration, three device-wide barriers: after z and its dot products,
 // after q = A p (the new direction formed on the fly where it is gathered)
@@ -262,10 +264,10 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
         } else {
             ++since;
         }
-        if (use_net && since >= p.stall) {
-            use_net = false;
+        if (use_net && since >= p.stall) {   // the host continues with Jacobi-PCG
             switched = k;
-            have_dir = false;
+            status = 3;
+            break;
         }
     }
     // true residual
@@ -369,14 +371,26 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
     PERKS_HIP_TRY(hipStreamSynchronize(st));
     const int s = (int)h[1];
+    int iters = (int)h[0];
+    double relres = h[2], relres_true = h[3];
     int status = s == 2 ? PERKS_BREAKDOWN : (s == 0 && h[3] <= tol) ? PERKS_OK : PERKS_NOT_CONVERGED;
+    if (s == 3 && iters < maxit) {
+        // the network stalled: Jacobi-PCG from the current iterate for the
+        // remaining iterations
+        perks_cg_result cg{};
+        status = perks_cg_solve(A, b, x, tol, maxit - iters, PERKS_PRECOND_JACOBI, PERKS_PREC_F64, stream, &cg);
+        if (status < 0) return status;
+        iters += cg.iters;
+        relres = cg.relres;
+        relres_true = cg.relres_true;
+    }
     if (out) {
-        out->iters = (int)h[0];
+        out->iters = iters;
         out->status = status;
         out->restarts = (int)h[5];
         out->wgs = G;
-        out->relres = h[2];
-        out->relres_true = h[3];
+        out->relres = relres;
+        out->relres_true = relres_true;
         out->cached_nnz_frac = 0.0;
         out->reserved = h[6];
     }

@@ -48,6 +48,15 @@ struct Wide3DStep {
 constexpr int W3RC = 16;   // rows per lane of a 3D tile
 constexpr int W3W = 4;     // waves per workgroup (both kernels)
 
+// Waves per SIMD the persistent kernel is built for: streaming needs many
+// waves in flight, and a step's tiles spread over more waves leave a shorter
+// tail (16,128 tiles at 256^3: about 2 per wave in FP32, 4 in FP64).  The
+// per-step baseline keeps the compiler's own choice (measured faster there).
+template <typename T>
+struct Wide3Occ {
+    static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+};
+
 // Tile t: (tx, ty) in its plane, interior plane z = R + t / (ntx * nty).
 template <int R>
 __device__ __forceinline__ WideTile wide3_tile_of(int t, int ntx, int nty, int nx, int ny, int *z) {
@@ -59,7 +68,12 @@ __device__ __forceinline__ WideTile wide3_tile_of(int t, int ntx, int nty, int n
 // New values of one tile (plane z) from `src` into out[].  BOX: every layer
 // is a full (2R+1)^2 box (any radius-1 3D pattern); otherwise a star: the
 // centre layer is the 2D star, the other layers hold their centre only.
-template <typename T, int R, bool BOX>
+//
+// PIN: each layer's sum is completed before the next layer's loads are
+// issued (one layer's rows live at a time: fewer registers, more waves);
+// otherwise the compiler may issue every layer's loads at once.  The
+// arithmetic, and so the result, is the same either way.
+template <typename T, int R, bool BOX, bool PIN>
 __device__ __forceinline__ void wide3_tile(const gmem<T> *src, const WideTile &tl, int z, int nx, int ny, int lane,
                                            const Wide3W<T, R> &W, WideLds<T, R, BOX, W3RC> &lds, T (&out)[W3RC]) {
     constexpr int S = 2 * R + 1;
@@ -86,11 +100,13 @@ __device__ __forceinline__ void wide3_tile(const gmem<T> *src, const WideTile &t
                 else out[i] = fma_t(w, u[i], out[i]);
             }
         }
+        if constexpr (PIN) settle(out);
     });
 }
 
 template <typename T, int R, bool BOX>
-__global__ __launch_bounds__(W3W * 64) void stencil3d_wide(Wide3DParams<T, R> p) {
+__global__ __launch_bounds__(W3W * 64) __attribute__((amdgpu_waves_per_eu(Wide3Occ<T>::value))) void stencil3d_wide(
+    Wide3DParams<T, R> p) {
     __shared__ WideLds<T, R, BOX, W3RC> lds[W3W];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * W3W + wave, nw = gridDim.x * W3W;
@@ -104,7 +120,7 @@ __global__ __launch_bounds__(W3W * 64) void stencil3d_wide(Wide3DParams<T, R> p)
             int z;
             const WideTile tl = wide3_tile_of<R>(t, p.ntx, p.nty, p.nx, p.ny, &z);
             T out[W3RC];
-            wide3_tile<T, R, BOX>(src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
+            wide3_tile<T, R, BOX, true>(src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
             wide_store<T, R, W3RC, false, true>(dst + (size_t)z * p.nx * p.ny, tl, p.nx, lane, out);
         }
         gs.sync();
@@ -131,7 +147,7 @@ __global__ __launch_bounds__(W3W * 64) void stencil3d_wide_step(Wide3DStep<T, R>
     int z;
     const WideTile tl = wide3_tile_of<R>(t, p.ntx, p.nty, p.nx, p.ny, &z);
     T out[W3RC];
-    wide3_tile<T, R, BOX>(p.src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
+    wide3_tile<T, R, BOX, false>(p.src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
     wide_store<T, R, W3RC, false, false>(p.dst + (size_t)z * p.nx * p.ny, tl, p.nx, lane, out);
 }
 
