@@ -14,14 +14,13 @@ namespace perks {
 namespace {
 
 // Patterns: radius 1 (2D 5-point star, 2D 9-point box, 3D 7-point star),
-// the radius-2..4 2D stars and radius-2 2D box, any other radius-1 3D
-// pattern (27-point box, 19-point, 17-point) and the radius-2 3D star.
-enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2, K_W2S = 3, K_W3S = 4, K_W4S = 5, K_W2B = 6, K_3B1 = 7, K_3S2 = 8 };
+// the radius-2..4 2D stars and radius-2 2D box, and the radius-2 3D star.
+enum Kind { K_2D5 = 0, K_2D9 = 1, K_3D7 = 2, K_W2S = 3, K_W3S = 4, K_W4S = 5, K_W2B = 6, K_3S2 = 7 };
 
 int radius_of(const perks_shape &s) { return s.radius <= 0 ? 1 : s.radius; }
 bool is_wide(Kind k) { return k >= K_W2S && k <= K_W2B; }
 int wide_radius(Kind k) { return k == K_W2B ? 2 : (int)k - 1; }
-bool is_wide3(Kind k) { return k == K_3B1 || k == K_3S2; }
+bool is_wide3(Kind k) { return k == K_3S2; }
 
 int classify(const double *c, const perks_shape &s, Kind *kind) {
     const int r = radius_of(s);
@@ -127,10 +126,8 @@ int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int
                                : run2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
     }
     if (is_wide3(kind)) {
-        const int r = kind == K_3B1 ? 1 : 2;
-        const bool box = kind == K_3B1;
-        return dt == PERKS_F64 ? run3d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
-                               : run3d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
+        return dt == PERKS_F64 ? run3d_wide<double>((double *)grid, coeffs, shape, steps, 2, false, st, tune)
+                               : run3d_wide<float>((float *)grid, coeffs, shape, steps, 2, false, st, tune);
     }
     if (shape.ndim == 2) {
         const bool box = kind == K_2D9;
@@ -177,10 +174,8 @@ int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape sha
                                : baseline2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
     }
     if (is_wide3(kind)) {
-        const int r = kind == K_3B1 ? 1 : 2;
-        const bool box = kind == K_3B1;
-        return dt == PERKS_F64 ? baseline3d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st)
-                               : baseline3d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
+        return dt == PERKS_F64 ? baseline3d_wide<double>((double *)grid, coeffs, shape, steps, 2, false, st)
+                               : baseline3d_wide<float>((float *)grid, coeffs, shape, steps, 2, false, st);
     }
     if (shape.ndim == 2) {
         if (kind == K_2D9)
@@ -210,10 +205,8 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
                                : plan2d_wide_query<float>(shape, r, box, tune, plan);
     }
     if (is_wide3(kind)) {
-        const int r = kind == K_3B1 ? 1 : 2;
-        const bool box = kind == K_3B1;
-        return dt == PERKS_F64 ? plan3d_wide_query<double>(shape, r, box, tune, plan)
-                               : plan3d_wide_query<float>(shape, r, box, tune, plan);
+        return dt == PERKS_F64 ? plan3d_wide_query<double>(shape, 2, false, tune, plan)
+                               : plan3d_wide_query<float>(shape, 2, false, tune, plan);
     }
     if (shape.ndim == 2)
         return dt == PERKS_F64 ? plan2d_query<double>(shape, kind == K_2D9, tune, plan)

@@ -48,13 +48,15 @@ struct Wide3DStep {
 constexpr int W3RC = 16;   // rows per lane of a 3D tile
 constexpr int W3W = 4;     // waves per workgroup (both kernels)
 
-// Waves per SIMD the persistent kernel is built for: streaming needs many
-// waves in flight, and a step's tiles spread over more waves leave a shorter
-// tail (16,128 tiles at 256^3: about 2 per wave in FP32, 4 in FP64).  The
-// per-step baseline keeps the compiler's own choice (measured faster there).
+// Launch shape of the persistent kernel, chosen by measurement at 256^3:
+// FP64 completes each z layer before the next layer's loads (PIN) to run
+// four waves per SIMD; FP32 lets the compiler issue every layer's loads at
+// once and runs five.  The per-step baseline keeps the compiler's own
+// choices (measured faster there).
 template <typename T>
 struct Wide3Occ {
-    static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int value = sizeof(T) == 4 ? 5 : 4;
+    static constexpr bool pin = sizeof(T) == 8;
 };
 
 // Tile t: (tx, ty) in its plane, interior plane z = R + t / (ntx * nty).
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(W3W * 64) __attribute__((amdgpu_waves_per_eu(Wide3O
             int z;
             const WideTile tl = wide3_tile_of<R>(t, p.ntx, p.nty, p.nx, p.ny, &z);
             T out[W3RC];
-            wide3_tile<T, R, BOX, true>(src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
+            wide3_tile<T, R, BOX, Wide3Occ<T>::pin>(src, tl, z, p.nx, p.ny, lane, p.W, lds[wave], out);
             wide_store<T, R, W3RC, false, true>(dst + (size_t)z * p.nx * p.ny, tl, p.nx, lane, out);
         }
         gs.sync();
