@@ -68,7 +68,10 @@ typedef struct perks_tuning {
     int32_t max_cached_tiles; /* <0: none cached (all tiles stream through HBM);
                                  0: as many as fit; >0: at most this many (3D: columns
                                  whose top planes stay in registers)                   */
-    int32_t reserved[2];
+    int32_t kernel;           /* 2D radius 1: 0 or 1 the radius-1 kernel (LDS rows,
+                                 point-to-point halos); 2 the radius-2..4 kernel run at
+                                 radius 1 (grid barrier, 32/48/80 register rows)       */
+    int32_t reserved;
 } perks_tuning;
 
 /* Plan a call would use (for reporting and for the performance model). */

@@ -37,7 +37,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_wg", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("planes_per_lane", ctypes.c_int32),
                 ("sync", ctypes.c_int32), ("max_cached_tiles", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class StencilPlan(ctypes.Structure):

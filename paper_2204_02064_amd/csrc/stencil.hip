@@ -74,6 +74,18 @@ int classify(const double *c, const perks_shape &s, Kind *kind) {
     return PERKS_OK;
 }
 
+// 2D radius-1 patterns may run on the radius-2..4 kernel family
+// (perks_tuning.kernel = 2); the per-step baseline always uses that family's
+// per-step kernel, the faster of the two per-step kernels.
+bool use_wide_family(Kind k, const perks_tuning *tu) {
+    return (k == K_2D5 || k == K_2D9) && tu && tu->kernel == 2;
+}
+
+int check_tuning(const perks_tuning *tu) {
+    if (tu && (tu->kernel < 0 || tu->kernel > 2)) return set_error(PERKS_E_INVAL, "tuning.kernel must be 0, 1 or 2");
+    return PERKS_OK;
+}
+
 int check_common(const void *grid, const double *coeffs, const perks_shape &s, int64_t steps, perks_dtype dt) {
     if (!grid || !coeffs) return set_error(PERKS_E_INVAL, "grid and coeffs must not be NULL");
     if (s.ndim != 2 && s.ndim != 3) return set_error(PERKS_E_INVAL, "ndim must be 2 or 3 (got %d)", s.ndim);
@@ -119,9 +131,9 @@ bool tuned_for(Kind kind, perks_dtype dt, const perks_shape &s, perks_tuning *ou
 
 int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int64_t steps, perks_dtype dt,
                  Kind kind, hipStream_t st, const perks_tuning *tune) {
-    if (is_wide(kind)) {
-        const int r = wide_radius(kind);
-        const bool box = kind == K_W2B;
+    if (is_wide(kind) || use_wide_family(kind, tune)) {
+        const int r = is_wide(kind) ? wide_radius(kind) : 1;
+        const bool box = kind == K_W2B || kind == K_2D9;
         return dt == PERKS_F64 ? run2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
                                : run2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st, tune);
     }
@@ -149,6 +161,8 @@ int perks_stencil_run(void *grid, const double *coeffs, perks_shape shape, int64
                       void *stream, const perks_tuning *tune) {
     int rc = check_common(grid, coeffs, shape, steps, dt);
     if (rc) return rc;
+    rc = check_tuning(tune);
+    if (rc) return rc;
     Kind kind;
     rc = classify(coeffs, shape, &kind);
     if (rc) return rc;
@@ -167,22 +181,15 @@ int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape sha
     if (rc) return rc;
     if (steps == 0) return PERKS_OK;
     hipStream_t st = as_stream(stream);
-    if (is_wide(kind)) {
-        const int r = wide_radius(kind);
-        const bool box = kind == K_W2B;
+    if (shape.ndim == 2) {
+        const int r = is_wide(kind) ? wide_radius(kind) : 1;
+        const bool box = kind == K_W2B || kind == K_2D9;
         return dt == PERKS_F64 ? baseline2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st)
                                : baseline2d_wide<float>((float *)grid, coeffs, shape, steps, r, box, st);
     }
     if (is_wide3(kind)) {
         return dt == PERKS_F64 ? baseline3d_wide<double>((double *)grid, coeffs, shape, steps, 2, false, st)
                                : baseline3d_wide<float>((float *)grid, coeffs, shape, steps, 2, false, st);
-    }
-    if (shape.ndim == 2) {
-        if (kind == K_2D9)
-            return dt == PERKS_F64 ? baseline2d<double, true>((double *)grid, coeffs, shape, steps, st)
-                                   : baseline2d<float, true>((float *)grid, coeffs, shape, steps, st);
-        return dt == PERKS_F64 ? baseline2d<double, false>((double *)grid, coeffs, shape, steps, st)
-                               : baseline2d<float, false>((float *)grid, coeffs, shape, steps, st);
     }
     return dt == PERKS_F64 ? baseline3d<double>((double *)grid, coeffs, shape, steps, st)
                            : baseline3d<float>((float *)grid, coeffs, shape, steps, st);
@@ -197,10 +204,12 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
     Kind kind;
     rc = classify(coeffs, shape, &kind);
     if (rc) return rc;
+    rc = check_tuning(tune);
+    if (rc) return rc;
     memset(plan, 0, sizeof(*plan));
-    if (is_wide(kind)) {
-        const int r = wide_radius(kind);
-        const bool box = kind == K_W2B;
+    if (is_wide(kind) || use_wide_family(kind, tune)) {
+        const int r = is_wide(kind) ? wide_radius(kind) : 1;
+        const bool box = kind == K_W2B || kind == K_2D9;
         return dt == PERKS_F64 ? plan2d_wide_query<double>(shape, r, box, tune, plan)
                                : plan2d_wide_query<float>(shape, r, box, tune, plan);
     }
@@ -249,11 +258,12 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
     // candidates: the planner's own choice and every forced depth, in each
     // synchronisation mode the kernels offer
     std::vector<perks_tuning> cands;
-    auto add = [&](int rows, int planes, int sync) {
+    auto add = [&](int rows, int planes, int sync, int kernel = 0) {
         perks_tuning t{};
         t.rows_per_lane = rows;
         t.planes_per_lane = planes;
         t.sync = sync;
+        t.kernel = kernel;
         perks_stencil_plan pl;
         if (perks_stencil_plan_query(coeffs, shape, dt, &t, &pl) == PERKS_OK) cands.push_back(t);
     };
@@ -267,6 +277,9 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
             add(0, 0, sync);
             for (int r : {8, 16, 32, 48, 64}) add(r, 0, sync);
         }
+        // the radius-2..4 kernel family at radius 1
+        add(0, 0, 1, 2);
+        for (int r : {32, 48, 80}) add(r, 0, 1, 2);
     } else {
         add(0, 0, 0);
         for (int pz : {8, 16, 24, 32}) add(0, pz, 0);   // column depths

@@ -1,6 +1,7 @@
 // 2D radius-1 Jacobi stencils (Eq. 2 and the 2d9pt box of tab:domain) on
-// gfx950: the shared tile arithmetic, the persistent kernel and the
-// per-step-launch baseline kernel.
+// gfx950: the tile arithmetic, the persistent kernel and the batched kernel.
+// (Their per-step baseline is the radius-2..4 family's per-step kernel run at
+// radius 1, which sums the same terms in the same order.)
 //
 // Tiling.  The interior (x in [1,nx-2], y in [1,ny-2]) is cut into wave tiles
 // of 64 columns x R rows.  Lane l of the wavefront owns column x0+l and keeps
@@ -58,8 +59,9 @@ struct RowVal {
 // FULL means nrows == RC; otherwise the last row's south neighbour is picked
 // with a wave-uniform select (never a register-array index that depends on a
 // run-time value, which would move the array to scratch memory).
-// Terms are summed in ascending (dy, dx) order, one multiply then FMAs; the
-// per-step baseline uses this same function, so both paths round identically.
+// Terms are summed in ascending (dy, dx) order, one multiply then FMAs, the
+// order of the radius-2..4 tile routine too, so the per-step baseline (that
+// routine at radius 1) rounds identically.
 // Returns the new value of row nrows-1 (the tile's bottom edge when the strip
 // ends the tile), taken from the computed values rather than from u.
 template <typename T, int RC, bool BOX, bool FULL>
@@ -138,8 +140,6 @@ struct Tile2D {
 template <typename T>
 struct Stencil2DParams {
     gmem<T> *grid;
-    gmem<T> *src;      // baseline: read buffer
-    gmem<T> *dst;      // baseline: write buffer
     gmem<T> *rowbuf;   // [2][2*nty+2][nx]
     gmem<T> *colbuf;   // [2][2*ntx+2][ny]
     unsigned *sync;
@@ -724,53 +724,9 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
     gs.finish();
 }
 
-// The per-step-launch baseline: one wave per tile, one step per launch, read
-// `src`, write `dst` (ring cells are not written: both buffers hold the ring).
-template <typename T, int R, bool BOX, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void stencil2d_step(Stencil2DParams<T> p) {
-    __shared__ T lds[WAVES][2][R + 2];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = blockIdx.x * WAVES + wave;
-    if (t >= p.ntiles) return;
-    const Tile2D tl = tile_of(p, t);
-    T *lw = lds[wave][0];
-    T *le = lds[wave][1];
-    const gmem<T> *src = p.src;
-    const int xl = min(tl.x0 + lane, p.nx - 1);
-    for (int j = lane; j < tl.hy + 2; j += 64) {
-        const size_t row = (size_t)(tl.y0 - 1 + j) * p.nx;
-        lw[j] = src[row + tl.x0 - 1];
-        le[j] = src[row + tl.x0 + tl.wx];
-    }
-    compiler_fence();
-    const bool ghost = lane >= tl.wx;
-    T u[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-        u[i] = (i < tl.hy) ? (ghost ? le[i + 1] : src[(size_t)(tl.y0 + i) * p.nx + xl]) : T(0);
-    const T hs = ghost ? le[tl.hy + 1] : src[(size_t)(tl.y0 + tl.hy) * p.nx + xl];
-    T hn = ghost ? le[0] : src[(size_t)(tl.y0 - 1) * p.nx + xl];
-    RowVal<T> above;
-    above.c = hn;
-    above.w = from_west(hn, lw[0]);
-    above.e = from_east(hn, le[0]);
-    if (tl.hy == R)
-        compute_rows<T, R, BOX, true>(u, R, above, hs, lw, le, p.W);
-    else
-        compute_rows<T, R, BOX, false>(u, tl.hy, above, hs, lw, le, p.W);
-    if (!ghost) {
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-            if (i < tl.hy) p.dst[(size_t)(tl.y0 + i) * p.nx + xl] = u[i];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host planning / launch (2D).
 constexpr int W2 = 8;       // wavefronts per workgroup of the persistent kernel
-constexpr int WB = 4;       // wavefronts per workgroup of the baseline kernel
-constexpr int RB = 16;      // tile depth of the baseline kernel
 
 template <typename T> struct RList;
 template <> struct RList<double> { static constexpr int v[4] = {8, 16, 32, 48}; };
@@ -1008,38 +964,6 @@ int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const d
     const void *fn = box ? pick2d_batched<T, true>(R) : pick2d_batched<T, false>(R);
     return launch_coop(fn, wgs, W2 * 64, &bp, st);
 }
-
-template <typename T, bool BOX>
-int baseline2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st) {
-    const size_t cells = (size_t)s.nx * s.ny;
-    T *other = (T *)scratch(SLOT_PINGPONG, cells * sizeof(T));
-    if (!other) return PERKS_E_NOMEM;
-    Stencil2DParams<T> p{};
-    p.nx = (int)s.nx;
-    p.ny = (int)s.ny;
-    const int nxi = p.nx - 2, nyi = p.ny - 2;
-    p.ntx = (nxi + 63) / 64;
-    p.last_w = nxi - 64 * (p.ntx - 1);
-    p.R = RB;
-    p.nty = (nyi + RB - 1) / RB;
-    p.last_h = nyi - RB * (p.nty - 1);
-    p.ntiles = p.ntx * p.nty;
-    fill_weights(p.W, coeffs);
-    // the second buffer needs the fixed ring; copy the whole grid once
-    PERKS_HIP_TRY(hipMemcpyAsync(other, grid, cells * sizeof(T), hipMemcpyDeviceToDevice, st));
-    const int wgs = (p.ntiles + WB - 1) / WB;
-    T *a = grid, *b = other;
-    for (int64_t k = 0; k < steps; ++k) {
-        p.src = to_global(a);
-        p.dst = to_global(b);
-        hipLaunchKernelGGL((stencil2d_step<T, RB, BOX, WB>), dim3(wgs), dim3(WB * 64), 0, st, p);
-        std::swap(a, b);
-    }
-    PERKS_HIP_TRY(hipGetLastError());
-    if (a != grid) PERKS_HIP_TRY(hipMemcpyAsync(grid, a, cells * sizeof(T), hipMemcpyDeviceToDevice, st));
-    return PERKS_OK;
-}
-
 
 template <typename T>
 int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan) {

@@ -4,8 +4,6 @@
 
 namespace perks {
 template int run2d<float>(float *, const double *, const perks_shape &, int64_t, bool, hipStream_t, const perks_tuning *);
-template int baseline2d<float, false>(float *, const double *, const perks_shape &, int64_t, hipStream_t);
-template int baseline2d<float, true>(float *, const double *, const perks_shape &, int64_t, hipStream_t);
 template int plan2d_query<float>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
 template int run2d_batched<float>(float *const *, const perks_shape *, int, const double *, int64_t, bool,
                                   hipStream_t);

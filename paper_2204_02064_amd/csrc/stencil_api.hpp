@@ -9,8 +9,6 @@ namespace perks {
 template <typename T>
 int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
           const perks_tuning *tu);
-template <typename T, bool BOX>
-int baseline2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, hipStream_t st);
 template <typename T>
 int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan);
 

@@ -65,6 +65,30 @@ def test_persistent_matches_oracle(pk, kind, shape, steps, dtype):
     np.testing.assert_array_equal(got, base)
 
 
+@pytest.mark.parametrize("kind,shape", [("2d5pt", (45, 150)), ("2d9pt", (70, 99)), ("2d5pt", (3072, 300)),
+                                        ("2d9pt", (5, 7))])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_radius1_on_the_wide_kernel_family_is_bitwise_the_same(pk, kind, shape, dtype):
+    """tuning.kernel = 2 runs a radius-1 pattern on the radius-2..4 kernels
+    (grid barrier, 32/48/80 register rows, cached or streamed); both families
+    sum the same terms in the same order, so they agree bitwise with each
+    other and with the per-step baseline, and match the oracle."""
+    rng = np.random.default_rng(7)
+    w = workloads.stencil_weights(kind)
+    w = np.where(w != 0, rng.uniform(0.05, 0.3, w.shape), 0.0)
+    tdt = getattr(torch, dtype)
+    g = workloads.stencil_grid(shape, seed=8, ring_value=0.3)
+    if dtype == "float32":
+        g = g.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    ref = _run(pk, g, w, 9, tdt)
+    assert rel_err(ref, oracle.stencil(g, w, 9)) <= (1e-12 if dtype == "float64" else 1e-5)
+    np.testing.assert_array_equal(_run(pk, g, w, 9, tdt, baseline=True), ref)
+    for tu in ({"kernel": 2}, {"kernel": 2, "rows_per_lane": 80}, {"kernel": 2, "max_cached_tiles": -1}):
+        np.testing.assert_array_equal(_run(pk, g, w, 9, tdt, tuning=tu), ref, err_msg=str(tu))
+    assert pk.stencil_plan(shape, w, dtype, tuning={"kernel": 2})["sync"] == 1
+
+
 @pytest.mark.parametrize("kind,shape", [("2d5pt", (45, 150)), ("2d9pt", (70, 99)), ("3d7pt", (11, 21, 67))])
 def test_asymmetric_weights_fix_orientation(pk, kind, shape):
     rng = np.random.default_rng(42)
