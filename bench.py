@@ -391,8 +391,8 @@ def main():
                          "reference for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the method and this "
-              "library are single-GPU; see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library runs each "
+              "solve on one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

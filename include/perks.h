@@ -40,7 +40,7 @@ enum {
     PERKS_E_NOMEM = -2,           /* scratch allocation failed                        */
     PERKS_E_HIP = -3,             /* a HIP runtime call failed (detail string)        */
     PERKS_E_NOTCORESIDENT = -4,   /* the persistent grid cannot be co-resident        */
-    PERKS_E_UNSUPPORTED = -5      /* valid request outside what this build supports   */
+    PERKS_E_UNSUPPORTED = -5      /* valid request outside what the library supports  */
 };
 
 typedef enum { PERKS_F32 = 0, PERKS_F64 = 1 } perks_dtype;
