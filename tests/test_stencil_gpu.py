@@ -266,14 +266,15 @@ def test_3d_column_depths_match_baseline_bitwise(pk, dtype, planes):
 
 
 @pytest.mark.parametrize("kind,shape,dtype", [("2d5pt", (300, 520), "float64"), ("2d9pt", (257, 190), "float32"),
-                                              ("3d7pt", (40, 45, 130), "float32")])
+                                              ("3d7pt", (40, 45, 130), "float32"), ("2d13pt", (210, 333), "float64"),
+                                              ("2d25pt", (99, 150), "float32"), ("3d13pt", (20, 37, 90), "float64")])
 def test_autotune_returns_a_valid_plan_and_untuned_runs_use_it(pk, kind, shape, dtype):
     w = workloads.stencil_weights(kind)
     tuning, rate = pk.stencil_autotune(shape, w, dtype, probe_steps=8, remember=True)
     assert rate > 0
     plan = pk.stencil_plan(shape, w, dtype, tuning=tuning)
     assert plan["tiles"] > 0
-    g = workloads.stencil_grid(shape, seed=31)
+    g = workloads.stencil_grid(shape, seed=31, r=workloads.stencil_radius(kind))
     tdt = torch.float64 if dtype == "float64" else torch.float32
     if dtype == "float32":
         g = g.astype(np.float32).astype(np.float64)
