@@ -269,7 +269,7 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
     };
     if (is_wide(kind)) {
         add(0, 0, 0);
-        for (int r : {32, 48, 80}) add(r, 0, 1);
+        for (int r : {24, 32, 48, 80}) add(r, 0, 1);
     } else if (is_wide3(kind)) {
         add(0, 0, 0);
     } else if (shape.ndim == 2) {
@@ -279,7 +279,7 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
         }
         // the radius-2..4 kernel family at radius 1
         add(0, 0, 1, 2);
-        for (int r : {32, 48, 80}) add(r, 0, 1, 2);
+        for (int r : {24, 32, 48, 80}) add(r, 0, 1, 2);
     } else {
         add(0, 0, 0);
         for (int pz : {8, 16, 24, 32}) add(0, pz, 0);   // column depths

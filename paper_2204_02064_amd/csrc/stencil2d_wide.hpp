@@ -274,14 +274,15 @@ struct WideLds {
 
 // Waves per SIMD a tile depth is built for (the register budget of a wave is
 // 512 / that): deeper tiles hold more of the grid per wave, shallower ones
-// leave more waves to hide each row's latency.
-template <int RC>
+// leave more waves to hide each row's latency. The shallowest depth runs
+// five FP64 or six FP32 waves per SIMD.
+template <typename T, int RC>
 struct WideOcc {
-    static constexpr int value = RC <= 32 ? 4 : RC <= 48 ? 3 : 2;
+    static constexpr int value = RC <= 24 ? (sizeof(T) == 4 ? 6 : 5) : RC <= 32 ? 4 : RC <= 48 ? 3 : 2;
 };
 
 template <typename T, int R, bool BOX, int RC, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WideOcc<RC>::value))) void
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WideOcc<T, RC>::value))) void
 stencil2d_wide(Wide2DParams<T, R> p) {
     __shared__ WideLds<T, R, BOX, RC> lds[WAVES];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -355,11 +356,12 @@ __global__ __launch_bounds__(WAVES * 64) void stencil2d_wide_step(Wide2DStep<T, 
 constexpr int WW = 4;          // waves per workgroup (persistent)
 constexpr int WWB = 4;         // waves per workgroup (baseline)
 constexpr int WRB = 16;        // tile depth of the baseline
-constexpr int WR_DEPTHS[3] = {32, 48, 80};   // tile depths of the persistent kernel
+constexpr int WR_DEPTHS[4] = {24, 32, 48, 80};   // tile depths of the persistent kernel
 
 template <typename T, int R, bool BOX>
 const void *wide_fn(int rc) {
     switch (rc) {
+        case 24: return reinterpret_cast<const void *>(&stencil2d_wide<T, R, BOX, 24, WW>);
         case 32: return reinterpret_cast<const void *>(&stencil2d_wide<T, R, BOX, 32, WW>);
         case 48: return reinterpret_cast<const void *>(&stencil2d_wide<T, R, BOX, 48, WW>);
         case 80: return reinterpret_cast<const void *>(&stencil2d_wide<T, R, BOX, 80, WW>);
@@ -382,7 +384,7 @@ int plan_wide(const perks_shape &s, const perks_tuning *tu, PlanWide *pl) {
     if (tu && tu->sync > 1) return set_error(PERKS_E_UNSUPPORTED, "wide 2D stencils synchronise with a grid barrier");
     const int want = tu ? tu->rows_per_lane : 0;
     if (want && !wide_fn<T, R, BOX>(want))
-        return set_error(PERKS_E_UNSUPPORTED, "wide 2D stencils keep 32, 48 or 80 rows per lane (got %d)", want);
+        return set_error(PERKS_E_UNSUPPORTED, "wide 2D stencils keep 24, 32, 48 or 80 rows per lane (got %d)", want);
     const long long nxi = s.nx - 2 * R, nyi = s.ny - 2 * R;
     pl->ntx = (int)((nxi + 63) / 64);
     auto tiles = [&](int h) { return (long long)pl->ntx * ((nyi + h - 1) / h); };

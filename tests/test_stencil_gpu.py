@@ -84,7 +84,8 @@ def test_radius1_on_the_wide_kernel_family_is_bitwise_the_same(pk, kind, shape, 
     ref = _run(pk, g, w, 9, tdt)
     assert rel_err(ref, oracle.stencil(g, w, 9)) <= (1e-12 if dtype == "float64" else 1e-5)
     np.testing.assert_array_equal(_run(pk, g, w, 9, tdt, baseline=True), ref)
-    for tu in ({"kernel": 2}, {"kernel": 2, "rows_per_lane": 80}, {"kernel": 2, "max_cached_tiles": -1}):
+    for tu in ({"kernel": 2}, {"kernel": 2, "rows_per_lane": 32}, {"kernel": 2, "rows_per_lane": 80},
+               {"kernel": 2, "max_cached_tiles": -1}):
         np.testing.assert_array_equal(_run(pk, g, w, 9, tdt, tuning=tu), ref, err_msg=str(tu))
     assert pk.stencil_plan(shape, w, dtype, tuning={"kernel": 2})["sync"] == 1
 
