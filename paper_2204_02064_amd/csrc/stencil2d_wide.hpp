@@ -60,6 +60,7 @@ struct Wide2DParams {
     int nx, ny;       // full extents
     int ntx, nty;     // tiles along x and y
     int cached;       // 1: one tile per wave kept in registers; 0: all tiles stream
+    gmem<T> *cols;    // cached: two step-parity copies of every tile's edge-column block
     WideW<T, R> W;
 };
 
@@ -210,10 +211,15 @@ __device__ __forceinline__ P wide_row(P buf, int y, int nx, int ny) {
 
 // Loads the halo of one tile from `src`: the R rows above and below into
 // registers, the R columns on each side into the wave's LDS (k fastest, so
-// that R neighbouring lanes read one row's R cells together).
+// that R neighbouring lanes read one row's R cells together). Where `cwb`
+// (`ceb`) is given, the west (east) columns of the tile's own rows come from
+// that neighbour's edge-column block instead ([k][row], written by
+// wide_cols_store), read with contiguous lanes; corners and rows past a
+// ragged tile's end still come from `src`.
 template <typename T, int R, bool BOX, int RC>
 __device__ __forceinline__ void wide_halo(const gmem<T> *src, const WideTile &tl, int nx, int ny, int lane, T *hr,
-                                          T *cw, T *ce) {
+                                          T *cw, T *ce, const gmem<T> *cwb = nullptr,
+                                          const gmem<T> *ceb = nullptr) {
     constexpr int NJ = BOX ? RC + 2 * R : RC;
     constexpr int J0 = BOX ? R : 0;
     const int xl = min(tl.x0 + lane, nx - 1);
@@ -230,11 +236,51 @@ __device__ __forceinline__ void wide_halo(const gmem<T> *src, const WideTile &tl
             const int side = e >= PER_SIDE;
             const int rem = e - side * PER_SIDE;
             const int jj = rem / R, k = rem - jj * R;
-            const int y = max(tl.y0 + jj - J0, 0);
-            const int x = side ? tl.x0 + 64 + k : tl.x0 - 1 - k;
-            const T val = ld_coh(src + wide_at(y, x, nx, ny));
-            (side ? ce : cw)[k * NJ + jj] = val;
+            const bool banded = (side ? ceb : cwb) != nullptr && jj >= J0 && jj < J0 + tl.hy;
+            if (!banded) {
+                const int y = max(tl.y0 + jj - J0, 0);
+                const int x = side ? tl.x0 + 64 + k : tl.x0 - 1 - k;
+                const T val = ld_coh(src + wide_at(y, x, nx, ny));
+                (side ? ce : cw)[k * NJ + jj] = val;
+            }
         }
+    }
+    if (cwb || ceb) {
+        constexpr int BAND = R * RC;
+#pragma unroll
+        for (int e0 = 0; e0 < 2 * BAND; e0 += 64) {
+            const int e = e0 + lane;
+            if (e < 2 * BAND) {
+                const int side = e >= BAND;
+                const int rem = e - side * BAND;
+                const int k = rem / RC, i = rem - k * RC;
+                const gmem<T> *b = side ? ceb : cwb;
+                if (b && i < tl.hy) (side ? ce : cw)[k * NJ + J0 + i] = ld_coh(b + rem);
+            }
+        }
+    }
+    compiler_fence();
+}
+
+// Writes the tile's R westmost and R eastmost columns (lanes k and 63 - k,
+// all RC rows) as one contiguous block [side][k][row] for the neighbours'
+// next step. The block is transposed through the wave's LDS (`stage`, at
+// least 2 R RC elements, free once the step's rows are done) so that the
+// store is coalesced instead of one cell per row.
+template <typename T, int R, int RC>
+__device__ __forceinline__ void wide_cols_store(gmem<T> *blk, int lane, const T (&u)[RC], T *stage) {
+    constexpr int BAND = R * RC;
+    const bool west = lane < R, east = lane >= 64 - R;
+    if (west || east) {
+        T *q = stage + (west ? lane * RC : BAND + (63 - lane) * RC);
+#pragma unroll
+        for (int i = 0; i < RC; ++i) q[i] = u[i];
+    }
+    compiler_fence();
+#pragma unroll
+    for (int e0 = 0; e0 < 2 * BAND; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < 2 * BAND) st_coh(blk + e, stage[e]);
     }
     compiler_fence();
 }
@@ -248,11 +294,12 @@ __device__ __forceinline__ void wide_load(const gmem<T> *src, const WideTile &tl
 }
 
 // Stores the tile's valid cells (EDGE: only those within R of the tile's
-// valid edges, the cells its neighbours read).
-template <typename T, int R, int RC, bool EDGE, bool COH>
+// valid edges, the cells its neighbours read; ROWS: of those only the R top
+// and bottom rows, the side columns going through wide_cols_store).
+template <typename T, int R, int RC, bool EDGE, bool COH, bool ROWS = false>
 __device__ __forceinline__ void wide_store(gmem<T> *dst, const WideTile &tl, int nx, int lane, const T (&u)[RC]) {
     const bool lane_ok = lane < tl.wx;
-    const bool side = lane < R || lane >= tl.wx - R;
+    const bool side = !ROWS && (lane < R || lane >= tl.wx - R);
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
         bool ok = lane_ok && i < tl.hy;
@@ -281,6 +328,14 @@ struct WideOcc {
     static constexpr int value = RC <= 24 ? (sizeof(T) == 4 ? 6 : 5) : RC <= 32 ? 4 : RC <= 48 ? 3 : 2;
 };
 
+// Whether cached tiles exchange their side columns as contiguous blocks
+// (wide_cols_store). Off for FP64 radius 4, whose kernels it pushes further
+// past the register budget (measured slower there).
+template <typename T, int R>
+constexpr bool wide_cols_on() {
+    return !(sizeof(T) == 8 && R >= 4);
+}
+
 template <typename T, int R, bool BOX, int RC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WideOcc<T, RC>::value))) void
 stencil2d_wide(Wide2DParams<T, R> p) {
@@ -288,7 +343,8 @@ stencil2d_wide(Wide2DParams<T, R> p) {
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * WAVES + wave, nw = gridDim.x * WAVES;
     const int ntiles = p.ntx * p.nty;
-    T *cw = lds[wave].c[0], *ce = lds[wave].c[1];
+    constexpr int BAND2 = 2 * R * RC;   // one tile's edge-column block
+    T *cw = lds[wave].c[0], *ce = lds[wave].c[1];   // contiguous: cw also stages BAND2 elements
     GridSync gs;
     gs.init(p.sync);
     T u[RC];
@@ -303,10 +359,26 @@ stencil2d_wide(Wide2DParams<T, R> p) {
         for (int t = gw; t < ntiles; t += nw) {
             const WideTile tl = wide_tile_of<RC>(t, p.ntx, p.nx, p.ny, R);
             if (!p.cached) wide_load<T, RC>(src, tl, p.nx, p.ny, lane, u);
-            wide_halo<T, R, BOX, RC>(src, tl, p.nx, p.ny, lane, hr, cw, ce);
+            // cached tiles after the first step: side columns from the
+            // neighbours' blocks of the previous step (step 0 reads the
+            // caller's grid, which holds every cell)
+            const gmem<T> *cwb = nullptr, *ceb = nullptr;
+            if (wide_cols_on<T, R>() && p.cols && s > 0) {
+                const int tx = t % p.ntx;
+                const gmem<T> *blocks = p.cols + (size_t)(s & 1) * ntiles * BAND2;
+                if (tx > 0) cwb = blocks + (size_t)(t - 1) * BAND2 + R * RC;
+                if (tx < p.ntx - 1) ceb = blocks + (size_t)(t + 1) * BAND2;
+            }
+            wide_halo<T, R, BOX, RC>(src, tl, p.nx, p.ny, lane, hr, cw, ce, cwb, ceb);
             wide_rows<T, R, BOX, RC>(u, hr, cw, ce, p.W, tl.hy, lane < tl.wx);
-            if (p.cached) wide_store<T, R, RC, true, true>(dst, tl, p.nx, lane, u);
-            else wide_store<T, R, RC, false, true>(dst, tl, p.nx, lane, u);
+            if (wide_cols_on<T, R>() && p.cached && p.cols) {
+                wide_store<T, R, RC, true, true, true>(dst, tl, p.nx, lane, u);
+                wide_cols_store<T, R, RC>(p.cols + ((size_t)((s + 1) & 1) * ntiles + t) * BAND2, lane, u, cw);
+            } else if (p.cached) {
+                wide_store<T, R, RC, true, true>(dst, tl, p.nx, lane, u);
+            } else {
+                wide_store<T, R, RC, false, true>(dst, tl, p.nx, lane, u);
+            }
         }
         gs.sync();
     }
@@ -429,7 +501,13 @@ int run_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
     int rc = plan_wide<T, R, BOX>(s, tu, &pl);
     if (rc) return rc;
     const size_t cells = (size_t)s.nx * s.ny;
-    T *other = (T *)scratch(SLOT_WIDE, cells * sizeof(T));
+    // the second grid buffer, then (cached tiles) two step-parity copies of
+    // every tile's edge-column block of 2 R RC cells
+    const size_t cols_off = (cells * sizeof(T) + 255) & ~(size_t)255;
+    const bool cols = pl.cached && wide_cols_on<T, R>();
+    const size_t cols_bytes = cols ? (size_t)2 * pl.ntx * pl.nty * (2 * R * pl.rc) * sizeof(T) : 0;
+    char *ws = (char *)scratch(SLOT_WIDE, cols_off + cols_bytes);
+    T *other = (T *)ws;
     unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
     if (!other || !sync) return PERKS_E_NOMEM;
     // the second buffer needs the fixed ring (and, for streamed tiles, nothing
@@ -445,6 +523,7 @@ int run_wide(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
     p.ntx = pl.ntx;
     p.nty = pl.nty;
     p.cached = pl.cached;
+    p.cols = cols ? to_global((T *)(ws + cols_off)) : nullptr;
     fill_wide(p.W, coeffs);
     return launch_coop(pl.fn, pl.wgs, WW * 64, &p, st);
 }
