@@ -62,7 +62,8 @@ typedef struct {
 typedef struct perks_tuning {
     int32_t waves_per_wg;     /* wavefronts per workgroup (1..16)                      */
     int32_t wgs_per_cu;       /* co-resident workgroups per CU used by the plan        */
-    int32_t rows_per_lane;    /* cells each lane keeps in registers along y (3D: 4)   */
+    int32_t rows_per_lane;    /* cells each lane keeps in registers along y (3D: 4;
+                                 radius-2..4 kernels: 24, 32, 48 or 80)                */
     int32_t planes_per_lane;  /* 3D: column depth, planes per column (1..32; 0 auto)   */
     int32_t sync;             /* 0 auto, 1 grid barrier, 2 neighbour flags             */
     int32_t max_cached_tiles; /* <0: none cached (all tiles stream through HBM);
@@ -70,7 +71,7 @@ typedef struct perks_tuning {
                                  whose top planes stay in registers)                   */
     int32_t kernel;           /* 2D radius 1: 0 or 1 the radius-1 kernel (LDS rows,
                                  point-to-point halos); 2 the radius-2..4 kernel run at
-                                 radius 1 (grid barrier, 32/48/80 register rows)       */
+                                 radius 1 (grid barrier, 24/32/48/80 register rows)    */
     int32_t reserved;
 } perks_tuning;
 
