@@ -79,24 +79,51 @@ def interior(shape):
     return math.prod(s - 2 for s in shape)
 
 
-def cpu_baseline(target_s=15.0):
-    """The oracle (single thread) on a bounded sample of the 2d5pt 3072^2 FP64 case:
-    as many Jacobi steps as take about target_s (per-step time from a 4-step run,
-    which amortises the call's buffer set-up)."""
+def _host_cpu():
+    """(threads this process may run on, CPU model string)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline(target_s=10.0):
+    """The oracle on a bounded sample of the 2d5pt 3072^2 FP64 case, run twice:
+    single-threaded and with its rows shared by every host core this process
+    may use (same arithmetic).  Each leg runs as many Jacobi steps as take
+    about target_s (per-step time from a 2-step run).  The reported value is
+    the all-core leg."""
     import oracle
     import workloads
+    cores, model = _host_cpu()
     g = workloads.stencil_grid((3072, 3072), seed=0)
     w = workloads.stencil_weights("2d5pt")
-    t0 = time.perf_counter()
-    g = oracle.stencil(g, w, 4)
-    one = (time.perf_counter() - t0) / 4
-    k = max(1, min(1000, int(target_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.stencil(g, w, k)
-    dt = time.perf_counter() - t0
-    cells = interior((3072, 3072)) * k
-    return {"value": cells / dt / 1e9, "unit": "GCells/s", "cores": 1, "kind": "oracle",
-            "sample": f"2d5pt 3072^2 FP64, {k} Jacobi steps ({dt:.1f} s), single thread"}
+    legs = {}
+    for threads in (1, cores):
+        t0 = time.perf_counter()
+        oracle.stencil(g, w, 2, threads=threads)
+        one = (time.perf_counter() - t0) / 2
+        k = max(1, min(1000, int(target_s / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        oracle.stencil(g, w, k, threads=threads)
+        dt = time.perf_counter() - t0
+        legs[threads] = (interior((3072, 3072)) * k / dt / 1e9, k, dt)
+    v, k, dt = legs[cores]
+    v1, k1, dt1 = legs[1]
+    return {"value": v, "unit": "GCells/s", "cores": cores, "kind": "oracle",
+            "sample": f"2d5pt 3072^2 FP64, {k} Jacobi steps ({dt:.1f} s) on {cores} threads; "
+                      f"single thread {v1:.3f} GCells/s ({k1} steps, {dt1:.1f} s)",
+            "single_thread_value": v1, "cpu_model": model}
 
 
 def _time(fn, torch, reps):
@@ -153,6 +180,44 @@ def bench_cg(pk, torch, args):
                 f"{rec['baseline']['seconds']*1e3:.2f} ms ({rec['baseline']['iters']} it)  x{rec['speedup']:.2f}")
             out.append(rec)
     return out
+
+
+def bench_small(pk, torch, args):
+    """The 256^2 FP64 2d5pt case, 100 Jacobi steps (zero ring, U[0,1) seed 0):
+    latency-bound, so microseconds per step: the persistent kernel (untuned
+    plan: the radius-1 kernel with point-to-point halo words; and the
+    radius-2..4 family with its device barrier) vs one launch per step.
+    HIP events on the launch stream, median of repeated runs."""
+    import numpy as np
+    import workloads
+    steps, shape = 100, (256, 256)
+    w = workloads.stencil_weights("2d5pt")
+    g = torch.from_numpy(workloads.stencil_grid(shape, seed=0)).cuda()
+    stream = torch.cuda.current_stream()
+    reps = max(5, min(args.steps, 20))
+
+    def timed(fn):
+        fn()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1) * 1e3 / steps)
+        return float(np.median(out))
+
+    rec = {"workload": "2d5pt 256x256 FP64, 100 steps", "steps": steps,
+           "persistent_us_per_step": timed(lambda: pk.stencil_run(g, w, steps)),
+           "persistent_barrier_kernel_us_per_step": timed(lambda: pk.stencil_run(g, w, steps, tuning={"kernel": 2})),
+           "baseline_us_per_step": timed(lambda: pk.stencil_run_baseline(g, w, steps)),
+           "plan": pk.stencil_plan(shape, w, "float64")}
+    rec["speedup"] = rec["baseline_us_per_step"] / rec["persistent_us_per_step"]
+    log(f"2d5pt 256^2 FP64 100 steps: persistent {rec['persistent_us_per_step']:.2f} us/step "
+        f"(device-barrier kernel {rec['persistent_barrier_kernel_us_per_step']:.2f}), per-step launches "
+        f"{rec['baseline_us_per_step']:.2f} us/step  x{rec['speedup']:.2f}")
+    return rec
 
 
 WIDE_FLOPS = {"2ds9pt": 18, "2d13pt": 26, "2d17pt": 34, "2d25pt": 50,
@@ -374,6 +439,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default plans")
     ap.add_argument("--cases", default="all")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 256^2 100-step latency case")
     ap.add_argument("--no-wide", action="store_true", help="skip the radius-2..4 2D stencils")
     ap.add_argument("--no-cg-random", action="store_true", help="skip the n=1M random SPD system")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision CG")
@@ -455,12 +521,13 @@ def main():
     wall = time.perf_counter() - t_start
 
     results = []
-    total_cells, total_time = 0, 0.0
+    total_cells = {"float64": 0, "float32": 0}
+    total_time = {"float64": 0.0, "float32": 0.0}
     for i, (kind, shape, dt) in enumerate(cases):
         t = float(np.median(per_case[i]))
         cells = interior(shape) * STENCIL_STEPS
-        total_cells += cells * args.steps
-        total_time += sum(per_case[i])
+        total_cells[dt] += cells * args.steps
+        total_time[dt] += sum(per_case[i])
         plan = pk.stencil_plan(shape, weights[kind], dt, tuning=tuned.get((kind, shape, dt)))
         results.append({"case": f"{kind} {'x'.join(map(str, shape))} {dt}", "kind": kind, "dtype": dt,
                         "persistent_ms": t * 1e3, "persistent_gcells": cells / t / 1e9,
@@ -514,7 +581,10 @@ def main():
                         "algorithmic": f"Eq. 5: 2*{pl['cached_cells']} cached + 2*{STENCIL_STEPS}*{streamed} streamed "
                                        f"cells x {esz} B + {STENCIL_STEPS} x {pl['halo_bytes_per_step']} halo B"}
 
-    value = total_cells / total_time / 1e9 if total_time > 0 else None
+    def rate(dt):
+        return total_cells[dt] / total_time[dt] / 1e9 if total_time[dt] > 0 else None
+
+    value = rate("float64")
     out = {
         "metric": "stencil GCells/s + CG s-to-1e-8 resid: persistent vs per-step launch, 1 GPU",
         "value": value,
@@ -522,23 +592,36 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": total_time / args.steps * 1e3,
+        "ms_per_step": total_time["float64"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64",
         "data": "synthetic (seeded U[0,1) grids, zero Dirichlet ring)",
-        "config": {"workload": "stencil sweep: 2d5pt + 2d9pt-box 3072^2, 3d7pt 256^3; FP64 and FP32; "
-                               "1000 Jacobi steps per case, one persistent launch each (autotuned plans)",
+        "config": {"workload": "FP64 stencil sweep: 2d5pt + 2d9pt-box 3072^2, 3d7pt 256^3; 1000 Jacobi steps "
+                               "per case, one persistent launch each (autotuned plans)",
                    "stencil_steps": STENCIL_STEPS, "parallelism": "1 GPU"},
+        "fp32": {"value": rate("float32"), "unit": "GCells/s",
+                 "ms_per_step": total_time["float32"] / args.steps * 1e3,
+                 "workload": "the same sweep in FP32 (storage and arithmetic), timed in the same loop"},
         "cases": results,
         "roofline": roofline,
         "wall_s": wall,
     }
     if not args.no_baseline and results:
-        base_time = sum(r["baseline_ms"] for r in results) / 1e3
-        out["baseline_value"] = sum(interior(c[1]) * STENCIL_STEPS for c in cases) / base_time / 1e9
-        out["speedup_vs_per_step_launch"] = value / out["baseline_value"]
+        for dt, key in (("float64", "baseline_value"), ("float32", None)):
+            sel = [(r, c) for r, c in zip(results, cases) if c[2] == dt]
+            if not sel:
+                continue
+            base = sum(interior(c[1]) * STENCIL_STEPS for _, c in sel) / (sum(r["baseline_ms"] for r, _ in sel) / 1e3) / 1e9
+            if key:
+                out[key] = base
+                out["speedup_vs_per_step_launch"] = value / base if value else None
+            else:
+                out["fp32"]["baseline_value"] = base
+                out["fp32"]["speedup_vs_per_step_launch"] = out["fp32"]["value"] / base if out["fp32"]["value"] else None
+    if not args.no_small:
+        out["config_256"] = bench_small(pk, torch, args)
     if not args.no_wide:
         out["wide_stencils"] = bench_wide(pk, torch, args)
     if not args.no_cg:

@@ -69,9 +69,14 @@ typedef struct perks_tuning {
     int32_t max_cached_tiles; /* <0: none cached (all tiles stream through HBM);
                                  0: as many as fit; >0: at most this many (3D: columns
                                  whose top planes stay in registers)                   */
-    int32_t kernel;           /* 2D radius 1: 0 or 1 the radius-1 kernel (LDS rows,
-                                 point-to-point halos); 2 the radius-2..4 kernel run at
-                                 radius 1 (grid barrier, 24/32/48/80 register rows)    */
+    int32_t kernel;           /* 2D radius 1: 0 the library's choice, 1 the radius-1
+                                 kernel (LDS rows, point-to-point halos), 2 the
+                                 radius-2..4 kernel run at radius 1 (grid barrier,
+                                 24/32/48/80 register rows).  With every field of the
+                                 struct zero (or tune NULL) the library takes kernel 2
+                                 when the interior holds >= 2^20 cells and kernel 2
+                                 caches every tile, else kernel 1; any other nonzero
+                                 field selects kernel 1 unless kernel = 2.           */
     int32_t reserved;
 } perks_tuning;
 
@@ -382,6 +387,18 @@ int perks_nn_train(float *params, const float *x, const float *target, const flo
 int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
                     const float *nn_params, const double *logk, int32_t H, int32_t W, int32_t stall,
                     void *stream, perks_cg_result *out);
+
+/* perks_fcg_precondition -- the preconditioner of perks_fcg_solve applied
+ * once, by the same tile routine the FCG kernel runs in every iteration:
+ * z = dinv * r + rms(r) * net([r / rms(r), log k]) on the H x W grid
+ * (row y * W + x), rms(r) = sqrt(||r||^2 / (H W)); z = 0 when r = 0.
+ *   nn_params device, PERKS_NN_PARAMS floats (layout as perks_nn_forward).
+ *   r, logk, dinv  device, H * W doubles each (dinv: the Jacobi step's D^-1).
+ *   z         device, H * W doubles, written.
+ * Asynchronous on `stream`; uses the library's FCG scratch (calls that
+ * overlap in time with perks_fcg_solve on one device race). */
+int perks_fcg_precondition(const float *nn_params, const double *r, const double *logk, const double *dinv,
+                           int32_t H, int32_t W, double *z, void *stream);
 
 /* Device facts the planner uses (host struct, filled from the current device). */
 typedef struct {

@@ -28,7 +28,7 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 
 def build_oracle():
     """Compile the oracle's C library in place (gcc, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
 
 
@@ -42,6 +42,8 @@ def _load():
     lib.oracle_stencil.argtypes = [_f64p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int64, _f64p, ctypes.c_int, ctypes.c_int64]
     lib.oracle_stencil.restype = ctypes.c_int
+    lib.oracle_stencil_threads.argtypes = lib.oracle_stencil.argtypes + [ctypes.c_int]
+    lib.oracle_stencil_threads.restype = ctypes.c_int
     lib.oracle_dot.argtypes = [_f64p, _f64p, ctypes.c_int64]
     lib.oracle_dot.restype = ctypes.c_double
     lib.oracle_spmv.argtypes = [ctypes.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p]
@@ -67,12 +69,13 @@ def _ptr(a, t=_f64p):
     return a.ctypes.data_as(t)
 
 
-def stencil(grid, weights, steps):
+def stencil(grid, weights, steps, threads=1):
     """Return ``grid`` after ``steps`` Jacobi sweeps of the weight box.
 
     ``grid`` is 2D (ny, nx) or 3D (nz, ny, nx); ``weights`` is the dense
     (2r+1)^d box; the ring of width r stays fixed.  Computed in float64 on a
     float64 copy of ``grid`` (an FP32 input is first widened exactly).
+    ``threads`` host threads share each sweep's rows (same result).
     """
     g = _f64(grid).copy()
     w = _f64(weights)
@@ -81,7 +84,7 @@ def stencil(grid, weights, steps):
         raise ValueError("weights must be a (2r+1)^d box matching the grid's rank")
     r = w.shape[0] // 2
     nz, ny, nx = (g.shape if nd == 3 else (1,) + g.shape)
-    rc = _load().oracle_stencil(_ptr(g), nd, nx, ny, nz, _ptr(w), r, int(steps))
+    rc = _load().oracle_stencil_threads(_ptr(g), nd, nx, ny, nz, _ptr(w), r, int(steps), int(threads))
     if rc != 0:
         raise ValueError("oracle_stencil rejected its arguments")
     return g

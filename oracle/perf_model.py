@@ -5,7 +5,12 @@ paper.  One reading is needed: Eq. 9 prints T_PERKS = max(T_gm(D), T_sm), but
 the worked example (FP32 2d5pt, 3072^2, N = 1000, A100) arrives at 876.09
 GCells/s only when the halo time of the cached part is added to T_gm(D):
 3072^2 * 1000 / (9900.70 us + 871.22 us).  The model below therefore uses
-T_PERKS = max(T_gm(D) + T_gm(halo), T_sm).
+the global-memory side T_gm(D) + T_gm(halo).
+
+The shared-memory side of Eq. 9 (Eq. 7 for A_sm and Eq. 8 for T_sm) is not
+part of this model: the paper prints no value that would pin it (its worked
+example is global-memory bound), and Eq. 7 is garbled (N (L_sm + S_sm) is
+set equal to 2 (N - 1) D^sm_cache).
 """
 
 
@@ -19,19 +24,9 @@ def t_gm(accesses, elem_bytes, bw_bytes_per_s):
     return accesses * elem_bytes / bw_bytes_per_s
 
 
-def shared_accesses(n_steps, d_cache_sm):
-    """Eq. 7: A_sm = 2 (N - 1) D^sm_cache (elements)."""
-    return 2 * (n_steps - 1) * d_cache_sm
-
-
-def t_sm(a_sm_cache, a_sm_kernel, elem_bytes, bw_sm_bytes_per_s):
-    """Eq. 8: T_sm = (A_sm(D^sm_cache) + A_sm(KERNEL)) * S(type) / B_sm."""
-    return (a_sm_cache + a_sm_kernel) * elem_bytes / bw_sm_bytes_per_s
-
-
-def t_perks(t_gm_domain, t_gm_halo=0.0, t_sm_total=0.0):
-    """Eq. 9 with the halo term (see module docstring)."""
-    return max(t_gm_domain + t_gm_halo, t_sm_total)
+def t_perks(t_gm_domain, t_gm_halo=0.0):
+    """Eq. 9, global-memory side, with the halo term (see module docstring)."""
+    return t_gm_domain + t_gm_halo
 
 
 def projected_cells_per_s(domain_cells, n_steps, t):

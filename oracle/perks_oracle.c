@@ -28,11 +28,12 @@
  * Cells within distance r of the border form a fixed Dirichlet ring (the
  * paper does not state a boundary condition; this is the reading used).
  * Every interior cell becomes  sum over (dz,dy,dx) ascending of w*in[c+o].
+ * threads: host threads sharing each sweep's rows (1 = the plain loop).
  * Returns 0, or -1 on bad arguments / allocation failure.                   */
-int oracle_stencil(double *grid, int ndim, int64_t nx, int64_t ny, int64_t nz,
-                   const double *w, int r, int64_t steps)
+int oracle_stencil_threads(double *grid, int ndim, int64_t nx, int64_t ny, int64_t nz,
+                           const double *w, int r, int64_t steps, int threads)
 {
-    if (!grid || !w || r < 1 || steps < 0 || (ndim != 2 && ndim != 3)) return -1;
+    if (!grid || !w || r < 1 || steps < 0 || (ndim != 2 && ndim != 3) || threads < 1) return -1;
     if (ndim == 2) nz = 1;
     if (nx < 2 * r + 1 || ny < 2 * r + 1 || (ndim == 3 && nz < 2 * r + 1)) return -1;
     const int64_t plane = nx * ny, total = plane * nz;
@@ -43,22 +44,27 @@ int oracle_stencil(double *grid, int ndim, int64_t nx, int64_t ny, int64_t nz,
     if (!b) return -1;
     memcpy(b, a, (size_t)total * sizeof(double));          /* ring carried over */
     const int64_t z0 = (ndim == 3) ? r : 0, z1 = (ndim == 3) ? nz - r : 1;
+    const int64_t rows_per_plane = ny - 2 * r, rows = (z1 - z0) * rows_per_plane;
     for (int64_t t = 0; t < steps; ++t) {
-        for (int64_t z = z0; z < z1; ++z)
-            for (int64_t y = r; y < ny - r; ++y)
-                for (int64_t x = r; x < nx - r; ++x) {
-                    double acc = 0.0;
-                    for (int dz = 0; dz < nzw; ++dz)
-                        for (int dy = 0; dy < bw; ++dy)
-                            for (int dx = 0; dx < bw; ++dx) {
-                                double wt = w[(dz * bw + dy) * bw + dx];
-                                if (wt == 0.0) continue;
-                                int64_t zz = (ndim == 3) ? z + dz - r : 0;
-                                int64_t idx = zz * plane + (y + dy - r) * nx + (x + dx - r);
-                                acc = acc + wt * a[idx];
-                            }
-                    b[z * plane + y * nx + x] = acc;
-                }
+        /* interior rows (z, y) are independent within a sweep: with threads > 1
+         * they are shared among threads; every cell's sum is the same. */
+#pragma omp parallel for num_threads(threads) schedule(static)
+        for (int64_t zy = 0; zy < rows; ++zy) {
+            const int64_t z = z0 + zy / rows_per_plane, y = r + zy % rows_per_plane;
+            for (int64_t x = r; x < nx - r; ++x) {
+                double acc = 0.0;
+                for (int dz = 0; dz < nzw; ++dz)
+                    for (int dy = 0; dy < bw; ++dy)
+                        for (int dx = 0; dx < bw; ++dx) {
+                            double wt = w[(dz * bw + dy) * bw + dx];
+                            if (wt == 0.0) continue;
+                            int64_t zz = (ndim == 3) ? z + dz - r : 0;
+                            int64_t idx = zz * plane + (y + dy - r) * nx + (x + dx - r);
+                            acc = acc + wt * a[idx];
+                        }
+                b[z * plane + y * nx + x] = acc;
+            }
+        }
         double *tmp = a; a = b; b = tmp;
     }
     if (a != grid) {                       /* odd number of sweeps */
@@ -68,6 +74,12 @@ int oracle_stencil(double *grid, int ndim, int64_t nx, int64_t ny, int64_t nz,
         free(b);
     }
     return 0;
+}
+
+int oracle_stencil(double *grid, int ndim, int64_t nx, int64_t ny, int64_t nz,
+                   const double *w, int r, int64_t steps)
+{
+    return oracle_stencil_threads(grid, ndim, nx, ny, nz, w, r, steps, 1);
 }
 
 /* ------------------------------------------------------------------------ */

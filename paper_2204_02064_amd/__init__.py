@@ -108,7 +108,8 @@ def lib():
                                          ctypes.POINTER(CgResult)]
     L.perks_fcg_solve.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, vp, vp, i32, i32, i32, vp,
                                   ctypes.POINTER(CgResult)]
-    for name in ("perks_cg_solve_capture", "perks_fcg_solve"):
+    L.perks_fcg_precondition.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+    for name in ("perks_cg_solve_capture", "perks_fcg_solve", "perks_fcg_precondition"):
         getattr(L, name).restype = ctypes.c_int
     L.perks_nn_forward.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.perks_nn_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
@@ -566,3 +567,20 @@ def fcg_solve(A, b, x, H, W, params=None, logk=None, tol=1e-8, maxit=5000, stall
     d["fallbacks"] = d.pop("restarts")
     d["switched_at"] = None if res.reserved < 0 else int(res.reserved)
     return d
+
+
+def fcg_precondition(params, r, logk, dinv, H, W, z=None, stream=None):
+    """z = dinv * r + rms(r) * net([r / rms(r), log k]) on the H x W grid, by the
+    tile routine the FCG kernel applies (float64 device vectors of H * W)."""
+    import torch
+    n = int(H) * int(W)
+    _check_f32(params, NN_PARAMS, "params")
+    for t, nm in ((r, "r"), (logk, "logk"), (dinv, "dinv")):
+        _check_vec(t.reshape(-1), n, nm)
+    if z is None:
+        z = torch.empty(n, dtype=torch.float64, device=r.device)
+    _check_vec(z, n, "z")
+    _check(lib().perks_fcg_precondition(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                        ctypes.c_void_p(logk.data_ptr()), ctypes.c_void_p(dinv.data_ptr()), int(H),
+                                        int(W), ctypes.c_void_p(z.data_ptr()), _stream_handle(stream)))
+    return z

@@ -292,12 +292,69 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
     if (g == 0 && tid == 0) st_coh(p.ws + SYNC_EPOCH, gs.epoch);
 }
 
+// z = D^{-1} r + rms(r) * net(...) once, with the tile routine the FCG kernel
+// applies in every iteration: `rr` = ||r||^2 comes from fcg_rr, one
+// workgroup per 16 x 16 tile.
+__global__ __launch_bounds__(CG_THREADS) void fcg_rr(FcgParams p) {
+    double a[1] = {0.0};
+    for (int i = threadIdx.x; i < p.n; i += CG_THREADS) a[0] = __builtin_fma(p.r[i], p.r[i], a[0]);
+    block_sum<1>(a, cg_red_fcg);
+    if (threadIdx.x == 0) p.part[0] = a[0];
+}
+
+__global__ __launch_bounds__(CG_THREADS) void fcg_precond(FcgParams p) {
+    const double rr = p.part[0];
+    const int t = blockIdx.x;
+    if (rr > 0.0) {
+        const double rms = sqrt(rr / p.n);
+        net_tile(p, (t % p.ntx) * FT, (t / p.ntx) * FT, rms, 1.0 / rms);
+    } else {
+        // r = 0: the network input is undefined; z = D^{-1} r = 0
+        for (int e = threadIdx.x; e < FT * FT; e += CG_THREADS) {
+            const int gy = (t / p.ntx) * FT + e / FT, gx = (t % p.ntx) * FT + e % FT;
+            if (gy < p.H && gx < p.W) p.z[(size_t)gy * p.W + gx] = 0.0;
+        }
+    }
+}
+
 }  // namespace
 }  // namespace perks
 
 using namespace perks;
 
 extern "C" {
+
+int perks_fcg_precondition(const float *nn_params, const double *r, const double *logk, const double *dinv,
+                           int32_t H, int32_t W, double *z, void *stream) {
+    if (!nn_params || !r || !logk || !dinv || !z) return set_error(PERKS_E_INVAL, "NULL argument");
+    if (H < 1 || W < 1 || (int64_t)H * W > INT32_MAX) return set_error(PERKS_E_INVAL, "bad grid extents");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    FcgParams p{};
+    p.ntx = (W + FT - 1) / FT;
+    p.nty = (H + FT - 1) / FT;
+    const size_t frag = (size_t)NL * 5 * 64 * 8 * sizeof(unsigned short);
+    const size_t bytes = 64 * sizeof(double) + 2 * frag + NL * NC * sizeof(float) + 1024;
+    char *base = (char *)scratch(SLOT_FCG, bytes);
+    if (!base) return PERKS_E_NOMEM;
+    p.part = (double *)base;
+    unsigned short *wf = (unsigned short *)(p.part + 64);
+    unsigned short *wb = wf + frag / sizeof(unsigned short);   // backward fragments (unused here)
+    float *bias = (float *)(wb + frag / sizeof(unsigned short));
+    p.wf = wf;
+    p.bias = bias;
+    p.r = const_cast<double *>(r);
+    p.z = z;
+    p.dinv = const_cast<double *>(dinv);
+    p.logk = logk;
+    p.n = H * W;
+    p.H = H;
+    p.W = W;
+    hipLaunchKernelGGL(nn_pack, dim3((NL * 5 * 64 * 8 + 255) / 256), dim3(256), 0, st, nn_params, wf, wb, bias);
+    hipLaunchKernelGGL(fcg_rr, dim3(1), dim3(CG_THREADS), 0, st, p);
+    hipLaunchKernelGGL(fcg_precond, dim3(p.ntx * p.nty), dim3(CG_THREADS), 0, st, p);
+    PERKS_HIP_TRY(hipGetLastError());
+    return PERKS_OK;
+}
 
 int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit, const float *nn_params,
                     const double *logk, int32_t H, int32_t W, int32_t stall, void *stream, perks_cg_result *out) {

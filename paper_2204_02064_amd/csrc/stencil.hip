@@ -74,11 +74,36 @@ int classify(const double *c, const perks_shape &s, Kind *kind) {
     return PERKS_OK;
 }
 
+// True when the caller left every tuning field at zero (the library's choice).
+bool untuned(const perks_tuning *tu) {
+    return !tu || (tu->waves_per_wg == 0 && tu->wgs_per_cu == 0 && tu->rows_per_lane == 0 &&
+                   tu->planes_per_lane == 0 && tu->sync == 0 && tu->max_cached_tiles == 0 && tu->kernel == 0);
+}
+
+// Interior cells from which an untuned 2D radius-1 run takes the radius-2..4
+// kernel family.  Measured on MI355X: at 3072^2 that family (grid barrier,
+// one register-cached 64 x 24..48 tile per wave) beats the radius-1 kernel
+// (point-to-point halo words, LDS rows) in both precisions and both
+// patterns; on small grids, whose steps are a few microseconds, the
+// point-to-point kernel's neighbour-only waits are cheaper than a device
+// barrier.
+constexpr int64_t WIDE_FAMILY_MIN_CELLS = int64_t(1) << 20;
+
 // 2D radius-1 patterns may run on the radius-2..4 kernel family
-// (perks_tuning.kernel = 2); the per-step baseline always uses that family's
-// per-step kernel, the faster of the two per-step kernels.
-bool use_wide_family(Kind k, const perks_tuning *tu) {
-    return (k == K_2D5 || k == K_2D9) && tu && tu->kernel == 2;
+// (perks_tuning.kernel = 2, or untuned on a large grid whose tiles that
+// family caches all at once); the per-step baseline always uses that
+// family's per-step kernel, the faster of the two per-step kernels.
+bool use_wide_family(Kind k, const perks_shape &s, perks_dtype dt, const perks_tuning *tu) {
+    if (k != K_2D5 && k != K_2D9) return false;
+    if (tu && tu->kernel == 2) return true;
+    if (!untuned(tu)) return false;
+    const int64_t cells = (s.nx - 2) * (s.ny - 2);
+    if (cells < WIDE_FAMILY_MIN_CELLS) return false;
+    perks_stencil_plan pl{};
+    const bool box = k == K_2D9;
+    const int rc = dt == PERKS_F64 ? plan2d_wide_query<double>(s, 1, box, nullptr, &pl)
+                                   : plan2d_wide_query<float>(s, 1, box, nullptr, &pl);
+    return rc == PERKS_OK && pl.tiles > 0 && pl.cached_tiles == pl.tiles;
 }
 
 int check_tuning(const perks_tuning *tu) {
@@ -131,7 +156,7 @@ bool tuned_for(Kind kind, perks_dtype dt, const perks_shape &s, perks_tuning *ou
 
 int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int64_t steps, perks_dtype dt,
                  Kind kind, hipStream_t st, const perks_tuning *tune) {
-    if (is_wide(kind) || use_wide_family(kind, tune)) {
+    if (is_wide(kind) || use_wide_family(kind, shape, dt, tune)) {
         const int r = is_wide(kind) ? wide_radius(kind) : 1;
         const bool box = kind == K_W2B || kind == K_2D9;
         return dt == PERKS_F64 ? run2d_wide<double>((double *)grid, coeffs, shape, steps, r, box, st, tune)
@@ -207,7 +232,7 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
     rc = check_tuning(tune);
     if (rc) return rc;
     memset(plan, 0, sizeof(*plan));
-    if (is_wide(kind) || use_wide_family(kind, tune)) {
+    if (is_wide(kind) || use_wide_family(kind, shape, dt, tune)) {
         const int r = is_wide(kind) ? wide_radius(kind) : 1;
         const bool box = kind == K_W2B || kind == K_2D9;
         return dt == PERKS_F64 ? plan2d_wide_query<double>(shape, r, box, tune, plan)

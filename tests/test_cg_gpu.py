@@ -145,6 +145,15 @@ def test_full_size_poisson_128(pk):
     assert info["iters"] <= 1000
     xb, ib = _solve(pk, rp, ci, v, b, 1e-10, baseline=True)
     assert ib["status"] == "converged" and _iters_close(info["iters"], ib["iters"])
+    # the oracle's CG on the same system (about 540 iterations of a 14.6M
+    # nonzero SpMV in plain C: some seconds on the host)
+    xo, oi = oracle.cg(rp, ci, v, b, tol=1e-10, maxit=5000)
+    assert oi["status"] == "converged"
+    assert _iters_close(info["iters"], oi["iters"]), (info["iters"], oi["iters"])
+    # both iterates have relative residual <= 1e-10, so each is within
+    # kappa * 1e-10 of the solution (kappa = 12 / (12 sin^2(pi / 258)) ~ 6.7e3)
+    kappa = 1.0 / math.sin(math.pi / 258) ** 2
+    assert np.linalg.norm(x - xo) <= 2 * kappa * 1e-10 * np.linalg.norm(xo)
 
 
 def test_baseline_check_every_delays_stop_by_less_than_the_interval(pk):

@@ -134,6 +134,71 @@ def test_fcg_with_random_network_converges(pk, n, stall):
     assert _true_relres(rp, ci, v, f, x.cpu().numpy()) <= 1e-8 * 1.001
 
 
+def _random_layers(seed, bias=0.1):
+    """He-uniform weights on every tap and channel, nonzero biases."""
+    rng = np.random.default_rng(seed + 1000)
+    return [(w, rng.uniform(-bias, bias, b.shape).astype(np.float32)) for w, b in onn.init_params(seed=seed)]
+
+
+# Grids that are not multiples of the 16 x 16 tile (ragged last tiles in x and
+# y, a grid narrower than one tile, a single pixel) and one that is.
+NET_GRIDS = [(37, 45, 1), (16, 16, 2), (50, 20, 3), (7, 90, 4), (1, 1, 5), (33, 17, 6)]
+
+
+@pytest.mark.parametrize("H,W,seed", NET_GRIDS)
+def test_fcg_network_matches_oracle_elementwise(pk, H, W, seed):
+    """The FCG kernel's own network tile routine (all six layers of a tile
+    in LDS, halos recomputed, MFMA) against oracle.nn with the same bf16
+    rounding; bar as for perks_nn_forward: relative L2 error of the network
+    part <= 2e-3 and max error <= 2e-2 of its scale."""
+    layers = _random_layers(seed)
+    rng = np.random.default_rng(seed)
+    r = rng.standard_normal((H, W))
+    lk = rng.standard_normal((H, W))
+    dinv = rng.uniform(0.1, 1.0, (H, W))
+    params = to_dev(pk.nn_pack_params(layers))
+    z = pk.fcg_precondition(params, to_dev(r.ravel()), to_dev(lk.ravel()), to_dev(dinv.ravel()), H, W)
+    z = z.cpu().numpy().reshape(H, W)
+    ref = onn.apply_preconditioner(layers, r, lk, bf16=True, dinv=dinv)
+    net, net_ref = z - dinv * r, ref - dinv * r
+    assert np.abs(net_ref).max() > 0.05 * np.abs(dinv * r).max()      # the network part is not negligible
+    assert np.linalg.norm(net - net_ref) <= 2e-3 * np.linalg.norm(net_ref)
+    assert np.abs(net - net_ref).max() <= 2e-2 * np.abs(net_ref).max()
+
+
+def test_fcg_network_of_zero_residual_is_zero(pk):
+    layers = _random_layers(9)
+    H, W = 20, 21
+    zero = to_dev(np.zeros(H * W))
+    z = pk.fcg_precondition(to_dev(pk.nn_pack_params(layers)), zero, to_dev(np.ones(H * W)), to_dev(np.ones(H * W)),
+                            H, W)
+    np.testing.assert_array_equal(z.cpu().numpy(), 0.0)
+
+
+@pytest.mark.parametrize("n,seed", [(37, 1), (50, 2), (23, 3)])
+def test_first_fcg_step_follows_the_networks_direction(pk, n, seed):
+    """From x0 = 0 one FCG iteration gives x1 = alpha z0 with z0 = M(b): the
+    direction of x1 is the oracle's preconditioned residual (the network's
+    when <z0, b> > 0, else the Jacobi step), and alpha = <z0, b> / <z0, A z0>."""
+    rp, ci, v, lk, f = workloads.diffusion_problem(n, seed=seed)
+    layers = _random_layers(seed + 20)
+    dinv = 1.0 / _diag(rp, ci, v).reshape(n, n)
+    zref = onn.apply_preconditioner(layers, f.reshape(n, n), lk, bf16=True, dinv=dinv).ravel()
+    use_net = float(zref @ f) > 0.0
+    if not use_net:
+        zref = (dinv.ravel() * f)
+    A = pk.CsrMatrix(rp, ci, v)
+    x = to_dev(np.zeros(n * n))
+    info = pk.fcg_solve(A, to_dev(f), x, n, n, params=to_dev(pk.nn_pack_params(layers)), logk=to_dev(lk), tol=0.0,
+                        maxit=1, stall=50)
+    assert info["iters"] == 1 and info["fallbacks"] == (0 if use_net else 1)
+    x1 = x.cpu().numpy()
+    c = float(x1 @ zref) / float(zref @ zref)
+    assert np.linalg.norm(x1 - c * zref) <= 2e-3 * np.linalg.norm(x1)
+    Az = oracle.spmv(rp, ci, v, zref)
+    assert c == pytest.approx(float(zref @ f) / float(zref @ Az), rel=1e-2)
+
+
 def test_capture_equals_truncated_solve(pk):
     rp, ci, v, lk, f = workloads.diffusion_problem(40, seed=9)
     A = pk.CsrMatrix(rp, ci, v)

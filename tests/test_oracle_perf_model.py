@@ -24,9 +24,3 @@ def test_worked_example():
     # Eq. 9 read literally (max without the halo term) does not give the printed value
     P_literal = pm.projected_cells_per_s(i["domain_cells"], i["n_steps"], pm.t_perks(t_dom))
     assert abs(P_literal / 1e9 - p["gcells_per_s"]) > 50
-
-
-def test_shared_memory_terms():
-    assert pm.shared_accesses(1000, 10) == 2 * 999 * 10
-    assert pm.t_sm(100, 50, 8, 1e9) == pytest.approx(150 * 8 / 1e9)
-    assert pm.t_perks(1.0, 0.5, 2.0) == 2.0

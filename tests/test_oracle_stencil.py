@@ -158,3 +158,12 @@ def test_reflection_symmetry():
 def test_bad_arguments_raise():
     with pytest.raises(ValueError):
         oracle.stencil(np.zeros((2, 5)), workloads.stencil_weights("2d5pt"), 1)
+
+
+@pytest.mark.parametrize("kind,shape", [("2d9pt", (67, 130)), ("3d7pt", (9, 14, 33))])
+def test_threaded_sweeps_give_the_same_bits(kind, shape):
+    """Rows of one sweep are independent: sharing them among threads changes
+    no cell's sum (the CPU baseline's all-core leg)."""
+    g = workloads.stencil_grid(shape, seed=3)
+    w = workloads.stencil_weights(kind)
+    np.testing.assert_array_equal(oracle.stencil(g, w, 7, threads=4), oracle.stencil(g, w, 7))

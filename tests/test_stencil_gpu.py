@@ -158,9 +158,17 @@ def test_split_runs_compose_bitwise_and_zero_steps_is_identity(pk):
     np.testing.assert_array_equal(_run(pk, g, w, 0, torch.float64), g)
 
 
-@pytest.mark.parametrize("kind,shape,dtype", [("2d5pt", (3072, 3072), "float64"), ("2d9pt", (3072, 3072), "float32"),
-                                              ("3d7pt", (256, 256, 256), "float64")])
-def test_full_size_eigenmode_decay(pk, kind, shape, dtype):
+# The plans the benchmark times at 3072^2 (the radius-2..4 kernel family at
+# radius 1: 48 register rows per lane in FP64, 24 in FP32, every tile cached;
+# also the untuned default there) and the radius-1 kernel family.
+BENCH_TUNING = {"float64": {"kernel": 2, "rows_per_lane": 48}, "float32": {"kernel": 2, "rows_per_lane": 24}}
+EIGEN_CASES = [("2d5pt", (3072, 3072), "float64", {"kernel": 1}), ("2d9pt", (3072, 3072), "float32", {"kernel": 1}),
+               ("3d7pt", (256, 256, 256), "float64", None)]
+EIGEN_CASES += [(k, (3072, 3072), dt, BENCH_TUNING[dt]) for k in ("2d5pt", "2d9pt") for dt in ("float64", "float32")]
+
+
+@pytest.mark.parametrize("kind,shape,dtype,tuning", EIGEN_CASES)
+def test_full_size_eigenmode_decay(pk, kind, shape, dtype, tuning):
     # At the benchmark sizes the oracle cannot follow 1000 steps cell by cell;
     # a discrete sine mode must decay by its closed-form factor instead.  The
     # factor is evaluated with the weights the kernel multiplies by (FP32
@@ -190,7 +198,7 @@ def test_full_size_eigenmode_decay(pk, kind, shape, dtype):
         u[tuple(idx)] = 0
     tdt = getattr(torch, dtype)
     u = u.astype(np.float32).astype(np.float64) if dtype == "float32" else u
-    got = _run(pk, u, workloads.stencil_weights(kind), steps, tdt)
+    got = _run(pk, u, workloads.stencil_weights(kind), steps, tdt, tuning=tuning)
     err = rel_err(got, lam ** steps * u)
     print(f"{kind} {dtype} {shape}: relative error after {steps} steps {err:.2e}")
     # FP32: each step rounds npts partial sums, each bounded by max|u| (the
@@ -204,10 +212,40 @@ def test_full_size_eigenmode_decay(pk, kind, shape, dtype):
     assert err <= tol
 
 
+@pytest.mark.parametrize("kind", ["2d5pt", "2d9pt"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_full_size_bench_plans_match_oracle(pk, kind, dtype):
+    """3072^2 on exactly the plans the benchmark times: a few steps against
+    the oracle and bitwise against the per-step baseline; the untuned default
+    is the same plan, and it caches every tile."""
+    tu = BENCH_TUNING[dtype]
+    tdt = getattr(torch, dtype)
+    g = workloads.stencil_grid((3072, 3072), seed=0)
+    w = workloads.stencil_weights(kind)
+    if dtype == "float32":
+        g = g.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    got = _run(pk, g, w, 4, tdt, tuning=tu)
+    assert rel_err(got, oracle.stencil(g, w, 4)) <= (1e-12 if dtype == "float64" else 1e-5)
+    np.testing.assert_array_equal(got, _run(pk, g, w, 4, tdt, baseline=True))
+    np.testing.assert_array_equal(got, _run(pk, g, w, 4, tdt))
+    plan, default = pk.stencil_plan((3072, 3072), w, dtype, tuning=tu), pk.stencil_plan((3072, 3072), w, dtype)
+    assert plan == default
+    assert plan["rows_per_lane"] == tu["rows_per_lane"] and plan["cached_tiles"] == plan["tiles"] > 0
+
+
+def test_untuned_small_grids_keep_the_radius1_kernel(pk):
+    """Below 2^20 interior cells the untuned plan is the radius-1 kernel
+    (point-to-point halo words); the 256^2 100-step configuration runs on it."""
+    w = workloads.stencil_weights("2d5pt")
+    assert pk.stencil_plan((256, 256), w, "float64")["sync"] == 2
+    assert pk.stencil_plan((256, 256), w, "float64", tuning={"kernel": 2})["sync"] == 1
+
+
 def test_full_size_matches_oracle_for_a_few_steps(pk):
     g = workloads.stencil_grid((3072, 3072), seed=0)
     w = workloads.stencil_weights("2d5pt")
-    got = _run(pk, g, w, 6, torch.float64)
+    got = _run(pk, g, w, 6, torch.float64, tuning={"kernel": 1})
     assert rel_err(got, oracle.stencil(g, w, 6)) <= 1e-12
     base = _run(pk, g, w, 6, torch.float64, baseline=True)
     np.testing.assert_array_equal(got, base)
