@@ -184,7 +184,15 @@ typedef struct {
     double relres;            /* final recursive ||r|| / ||b||                        */
     double relres_true;       /* ||b - A x|| / ||b|| recomputed at exit               */
     double cached_nnz_frac;   /* share of A's nonzeros held on chip                   */
-    double reserved;
+    int32_t fallbacks;        /* flexible CG: iterations whose network step was
+                                 replaced by the Jacobi step (0 for plain CG)         */
+    int32_t switched_at;      /* flexible CG: iteration at which the solve continued
+                                 as Jacobi-PCG after the network stalled (-1: never;
+                                 -1 for plain CG)                                     */
+    int64_t barrier_cycles;   /* mean over the persistent grid's workgroups of the
+                                 shader-clock cycles spent inside device barriers
+                                 during the solve's last persistent launch (entry to
+                                 release; s_memtime); 0 for the host-looped baseline */
 } perks_cg_result;
 
 enum { PERKS_PRECOND_NONE = 0, PERKS_PRECOND_JACOBI = 1 };
@@ -363,6 +371,29 @@ int perks_nn_train(float *params, const float *x, const float *target, const flo
                    int32_t P, int32_t H, int32_t W, int32_t epochs, int32_t batch, float lr, uint64_t seed,
                    float *m, float *v, int32_t *step, double *losses, void *stream);
 
+/* perks_nn_make_pairs -- training pairs of the network from iterates that
+ * perks_cg_solve_capture recorded (Jacobi-PCG on the problem A x = f).  For
+ * capture j with iterate x_j and recursive residual r_j, rms_j =
+ * sqrt(||r_j||^2 / n) (summed in a fixed order) and, at grid point i (row i
+ * of A, pixel i of the H x W grid, row-major):
+ *   inputs[j][i]  = { r_j[i] / rms_j, logk[i] }
+ *   targets[j][i] = (xstar[i] - x_j[i] - r_j[i] / A_ii) / rms_j
+ * computed in FP64 and rounded to FP32: the part of the error e_j = x* - x_j
+ * that the Jacobi step D^-1 r_j leaves, which the network adds to that step
+ * inside perks_fcg_solve.
+ *   A         FP64 CSR (device arrays), n = H * W rows, diagonal present.
+ *   xstar, logk          device, n doubles (converged solution; log k).
+ *   cap_x, cap_r         device, ncap x n doubles (0 <= ncap <= 4096).
+ *   inputs    device, ncap x n x 2 floats; targets device, ncap x n floats:
+ *             written for j < *count.
+ *   count     host, out: the number of leading captures that form pairs
+ *             (the first capture whose residual has a non-finite entry or
+ *             rms 0, i.e. one the solve did not reach, ends the list).
+ * Synchronises `stream` (the count is read back). */
+int perks_nn_make_pairs(const perks_csr *A, const double *xstar, const double *logk, const double *cap_x,
+                        const double *cap_r, int32_t ncap, int32_t H, int32_t W, float *inputs, float *targets,
+                        int32_t *count, void *stream);
+
 /*
  * perks_fcg_solve -- flexible CG preconditioned by the network, one
  * persistent launch.  FCG(1): p = z - (<z, q_old> / <p_old, q_old>) p_old,
@@ -379,9 +410,10 @@ int perks_nn_train(float *params, const float *x, const float *target, const flo
  * the FCG kernel from the start.
  *   A       FP64 CSR on an H x W grid of unknowns (row y * W + x), n = H * W.
  *   logk    device, H * W doubles (the second network input).
- *   out     iters, status, restarts = iterations that fell back to Jacobi,
- *           reserved = iteration at which the solve switched to Jacobi-PCG
- *           (-1: never), relres / relres_true as for perks_cg_solve.
+ *   out     iters, status, fallbacks (iterations that took the Jacobi step),
+ *           switched_at (iteration at which the solve continued as Jacobi-PCG,
+ *           -1: never), relres / relres_true as for perks_cg_solve,
+ *           barrier_cycles of the FCG launch; restarts = 0.
  * Returns PERKS_OK when the true relative residual meets tol.
  */
 int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
@@ -399,6 +431,33 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
  * overlap in time with perks_fcg_solve on one device race). */
 int perks_fcg_precondition(const float *nn_params, const double *r, const double *logk, const double *dinv,
                            int32_t H, int32_t W, double *z, void *stream);
+
+/* perks_barrier_stats -- in-kernel timing of the device-wide barrier (the
+ * grid.sync() that replaces each relaunch, Sec. 3 / Listing 1) in the last
+ * persistent launch made by this library on the current device (stencil,
+ * CG, FCG or batched).  Every workgroup counts, with the scalar shader clock
+ * (s_memtime), the cycles from entering a barrier to leaving it, and the
+ * cycles from its start to its end; the kernel stores one record per
+ * workgroup.  This call synchronises `stream` (which must be the launch's
+ * stream or one ordered after it) and averages the records.
+ *   out  host, filled: wgs (grid size of that launch; 0 when no persistent
+ *        launch has been made), barriers (per workgroup), wait_cycles and
+ *        total_cycles (means over workgroups), max_wait_cycles, wait_share
+ *        (sum of waits / sum of totals: the share of the kernel's time spent
+ *        waiting in barriers, independent of the clock rate).
+ * Launches on the same device after the one of interest overwrite the
+ * records.  Returns PERKS_OK or an error. */
+typedef struct {
+    int32_t wgs;
+    int32_t reserved;
+    int64_t barriers;
+    double wait_cycles;
+    double max_wait_cycles;
+    double total_cycles;
+    double wait_share;
+} perks_barrier_stats_t;
+
+int perks_barrier_stats(void *stream, perks_barrier_stats_t *out);
 
 /* Device facts the planner uses (host struct, filled from the current device). */
 typedef struct {

@@ -149,6 +149,31 @@ def rms(v):
     return float(np.sqrt(np.mean(np.square(v))))
 
 
+def make_pairs(diag, xstar, log_k, xs, rs):
+    """Training pairs from iterates x_j with residuals r_j of a problem with
+    solution xstar (arrays of shape (N, N); diag: the operator's diagonal).
+    The preconditioner adds rms(r) * net(...) to the Jacobi step r / diag, so
+    the network's target is the rest of the error, scaled like its input:
+        input_j  = [r_j / rms(r_j), log k]
+        target_j = (xstar - x_j - r_j / diag) / rms(r_j).
+    Pairs stop at the first residual that is not finite or is zero.  Returns
+    (inputs [P, N, N, 2], targets [P, N, N]) in float64."""
+    ins, tgts = [], []
+    for x, r in zip(xs, rs):
+        r = np.asarray(r, dtype=np.float64)
+        if not np.all(np.isfinite(r)):
+            break
+        s = rms(r)
+        if s == 0.0:
+            break
+        ins.append(np.stack([r / s, np.asarray(log_k, dtype=np.float64)], axis=-1))
+        tgts.append((np.asarray(xstar, dtype=np.float64) - np.asarray(x, dtype=np.float64) - r / diag) / s)
+    n = np.shape(log_k)
+    if not ins:
+        return np.zeros((0,) + n + (2,)), np.zeros((0,) + n)
+    return np.stack(ins), np.stack(tgts)
+
+
 def apply_preconditioner(params, r, log_k, bf16=False, dinv=None):
     """z = rms(r) * net([r / rms(r), log k]) (+ dinv * r when dinv is given)
     for r, log_k (and dinv) of shape (N, N)."""

@@ -58,7 +58,14 @@ class Csr(ctypes.Structure):
 class CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("wgs", ctypes.c_int32), ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("cached_nnz_frac", ctypes.c_double), ("reserved", ctypes.c_double)]
+                ("cached_nnz_frac", ctypes.c_double), ("fallbacks", ctypes.c_int32),
+                ("switched_at", ctypes.c_int32), ("barrier_cycles", ctypes.c_int64)]
+
+
+class BarrierStats(ctypes.Structure):
+    _fields_ = [("wgs", ctypes.c_int32), ("reserved", ctypes.c_int32), ("barriers", ctypes.c_int64),
+                ("wait_cycles", ctypes.c_double), ("max_wait_cycles", ctypes.c_double),
+                ("total_cycles", ctypes.c_double), ("wait_share", ctypes.c_double)]
 
 
 class DeviceInfo(ctypes.Structure):
@@ -93,6 +100,8 @@ def lib():
     L.perks_strerror.argtypes = [ctypes.c_int]
     L.perks_last_error.restype = ctypes.c_char_p
     L.perks_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
+    L.perks_barrier_stats.argtypes = [vp, ctypes.POINTER(BarrierStats)]
+    L.perks_barrier_stats.restype = ctypes.c_int
     L.perks_cg_solve.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, i32, vp, ctypes.POINTER(CgResult)]
     L.perks_cg_solve_baseline.argtypes = [ctypes.POINTER(Csr), vp, vp, f64, i32, i32, i32, i32, vp,
                                           ctypes.POINTER(CgResult)]
@@ -118,7 +127,10 @@ def lib():
     L.perks_nn_energy_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.perks_nn_train.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
-    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad", "perks_nn_train"):
+    L.perks_nn_make_pairs.argtypes = [ctypes.POINTER(Csr), vp, vp, vp, vp, i32, i32, i32, vp, vp,
+                                      ctypes.POINTER(ctypes.c_int32), vp]
+    for name in ("perks_nn_forward", "perks_nn_loss_grad", "perks_nn_adam", "perks_nn_energy_grad", "perks_nn_train",
+                 "perks_nn_make_pairs"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("perks_stencil_run", "perks_stencil_run_baseline", "perks_stencil_plan_query",
                  "perks_device_query", "perks_cg_solve", "perks_cg_solve_baseline", "perks_cg_batch_create",
@@ -286,9 +298,18 @@ class CsrMatrix:
 
 def _cg_result(r, precision):
     d = {"iters": r.iters, "status": STATUS.get(r.status, str(r.status)), "wgs": r.wgs, "relres": r.relres,
-         "relres_true": r.relres_true, "cached_nnz_frac": r.cached_nnz_frac}
+         "relres_true": r.relres_true, "cached_nnz_frac": r.cached_nnz_frac, "barrier_cycles": r.barrier_cycles}
     d["outer" if PRECISION[precision] == 1 else "restarts"] = r.restarts
     return d
+
+
+def barrier_stats(stream=None):
+    """Barrier clock of the last persistent launch on the current device
+    (perks_barrier_stats): mean cycles per workgroup waiting in device barriers,
+    barriers per workgroup, and the share of the kernel's time spent waiting."""
+    st = BarrierStats()
+    _check(lib().perks_barrier_stats(_stream_handle(stream), ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in BarrierStats._fields_ if f != "reserved"}
 
 
 def _check_vec(v, n, name):
@@ -521,6 +542,34 @@ def nn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                                float(lr), float(beta1), float(beta2), float(eps), _stream_handle(stream)))
 
 
+def nn_make_pairs(A, xstar, logk, xcap, rcap, H, W, stream=None):
+    """Training pairs from captured iterates (perks_nn_make_pairs): returns
+    (inputs [m, H, W, 2] float32, targets [m, H, W] float32) device tensors for
+    the m leading captures the solve reached."""
+    import torch
+    n = int(H) * int(W)
+    if A.n != n:
+        raise ValueError("H * W must equal the matrix order")
+    _check_vec(xstar, n, "xstar")
+    _check_vec(logk.reshape(-1), n, "logk")
+    for t, nm in ((xcap, "xcap"), (rcap, "rcap")):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != n:
+            raise ValueError(f"{nm} must be a contiguous float64 device tensor [ncap, {n}]")
+    if xcap.shape != rcap.shape:
+        raise ValueError("xcap and rcap must have the same shape")
+    ncap = int(rcap.shape[0])
+    inputs = torch.empty((ncap, int(H), int(W), 2), dtype=torch.float32, device=rcap.device)
+    targets = torch.empty((ncap, int(H), int(W)), dtype=torch.float32, device=rcap.device)
+    cnt = ctypes.c_int32(0)
+    st = A._struct()
+    _check(lib().perks_nn_make_pairs(ctypes.byref(st), ctypes.c_void_p(xstar.data_ptr()),
+                                     ctypes.c_void_p(logk.data_ptr()), ctypes.c_void_p(xcap.data_ptr()),
+                                     ctypes.c_void_p(rcap.data_ptr()), ncap, int(H), int(W),
+                                     ctypes.c_void_p(inputs.data_ptr()), ctypes.c_void_p(targets.data_ptr()),
+                                     ctypes.byref(cnt), _stream_handle(stream)))
+    return inputs[:cnt.value], targets[:cnt.value]
+
+
 def cg_solve_capture(A, b, x, iters, tol=1e-10, maxit=5000, precond=None, stream=None):
     """Persistent FP64 CG that also returns x_k and r_k after each k in ``iters``.
 
@@ -564,8 +613,9 @@ def fcg_solve(A, b, x, H, W, params=None, logk=None, tol=1e-8, maxit=5000, stall
                                int(stall), _stream_handle(stream), ctypes.byref(res))
     _check(rc, allow_positive=True)
     d = _cg_result(res, None)
-    d["fallbacks"] = d.pop("restarts")
-    d["switched_at"] = None if res.reserved < 0 else int(res.reserved)
+    d.pop("restarts")
+    d["fallbacks"] = res.fallbacks
+    d["switched_at"] = None if res.switched_at < 0 else int(res.switched_at)
     return d
 
 

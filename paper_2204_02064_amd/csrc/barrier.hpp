@@ -23,6 +23,12 @@
 // starts from the epoch the previous launch left in SYNC_EPOCH and stores its
 // final epoch there before it ends, so no reset (and no memset) is needed
 // between launches, including hipGraph replays.
+//
+// Timing: every workgroup counts the shader-clock cycles (s_memtime) it spends
+// inside device barriers, from entering sync() to leaving it, and the cycles
+// from its first barrier set-up to its end; at the end it stores both, and
+// the number of barriers, in its own record of the SYNC_STATS area (read back
+// by perks_barrier_stats).  Two scalar clock reads per barrier.
 #pragma once
 
 #include "common.hpp"
@@ -59,13 +65,42 @@ __device__ __forceinline__ void wait_own_stores() {
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
+// Per-workgroup barrier clock (wave-uniform values, scalar registers).
+struct BarrierClock {
+    unsigned long long begin, wait;
+    unsigned count;
+
+    static __device__ __forceinline__ unsigned long long now() { return __builtin_amdgcn_s_memtime(); }
+    __device__ __forceinline__ void start() {
+        begin = now();
+        wait = 0;
+        count = 0;
+    }
+    __device__ __forceinline__ void add(unsigned long long t0) {
+        wait += now() - t0;
+        ++count;
+    }
+    // Stores {wait, total, count} in this workgroup's record.
+    __device__ __forceinline__ void publish(unsigned *ws) const {
+        if (threadIdx.x == 0) {
+            unsigned long long *rec = (unsigned long long *)(ws + SYNC_STATS) + SYNC_STATS_WORDS * blockIdx.x;
+            const unsigned long long total = now() - begin;
+            st_coh(rec + 0, wait);
+            st_coh(rec + 1, total);
+            st_coh(rec + 2, (unsigned long long)count);
+        }
+    }
+};
+
 struct GridSync {
     unsigned *ws;
     unsigned epoch;
+    BarrierClock clk;
 
     __device__ __forceinline__ void init(unsigned *w) {
         ws = w;
         epoch = ld_coh(ws + SYNC_EPOCH);
+        clk.start();
     }
 
     // All threads of all workgroups call this; returns when every workgroup
@@ -77,6 +112,7 @@ struct GridSync {
     // workgroup gather data written by others through the caches.
     template <bool acquire_caches = false>
     __device__ __forceinline__ void sync() {
+        const unsigned long long t0 = BarrierClock::now();
         const unsigned e = ++epoch;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         wait_own_stores();
@@ -93,13 +129,16 @@ struct GridSync {
         if (acquire_caches && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        clk.add(t0);
     }
 
     // Called once by every workgroup after its last sync(): records the epoch
-    // for the next launch.  Only workgroup 0 writes; every workgroup has read
-    // the start epoch before the first sync(), which precedes this write.
+    // for the next launch and this workgroup's barrier clock.  Only workgroup
+    // 0 writes the epoch; every workgroup has read the start epoch before the
+    // first sync(), which precedes this write.
     __device__ __forceinline__ void finish() {
         if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, epoch);
+        clk.publish(ws);
     }
 };
 
@@ -115,21 +154,25 @@ struct GroupSync {
     unsigned *gen;     // the group's generation word
     unsigned epoch;
     int rank, size;
+    BarrierClock *clk; // the workgroup's barrier clock (shared by the groups it joins)
 
-    __device__ __forceinline__ void init(unsigned *ws, int first, int group, int r, int n, unsigned epoch0) {
+    __device__ __forceinline__ void init(unsigned *ws, int first, int group, int r, int n, unsigned epoch0,
+                                         BarrierClock *c) {
         flags = ws + SYNC_FLAGS + first;
         gen = ws + SYNC_GROUP_GEN + group * SYNC_GROUP_STRIDE;
         rank = r;
         size = n;
         epoch = epoch0;
+        clk = c;
     }
     // The whole grid as one group, epochs continuing from the last launch.
-    __device__ __forceinline__ void init_grid(unsigned *ws) {
+    __device__ __forceinline__ void init_grid(unsigned *ws, BarrierClock *c) {
         flags = ws + SYNC_FLAGS;
         gen = ws + SYNC_GEN;
         rank = blockIdx.x;
         size = gridDim.x;
         epoch = ld_coh(ws + SYNC_EPOCH);
+        clk = c;
     }
 
     template <bool acquire_caches = false>
@@ -140,6 +183,7 @@ struct GroupSync {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             return;
         }
+        const unsigned long long t0 = BarrierClock::now();
         const unsigned e = ++epoch;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         wait_own_stores();
@@ -156,6 +200,7 @@ struct GroupSync {
         if (acquire_caches && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        clk->add(t0);
     }
 };
 

@@ -743,12 +743,15 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
 // One problem on the whole grid.
 template <bool JACOBI, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
+    BarrierClock clk;
+    clk.start();
     GroupSync gs;
-    gs.init_grid(ws);
+    gs.init_grid(ws, &clk);
     CInst *in = (CInst *)pin;
     if (MIXED) cg_mixed_body<JACOBI>(*in, gs, blockIdx.x, gridDim.x);
     else cg_f64_body<JACOBI>(in, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
+    clk.publish(ws);
 }
 
 // Many problems in one launch.  Workgroup g runs the tasks
@@ -775,22 +778,26 @@ struct CgBatch {
 template <bool JACOBI, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
     const int g = blockIdx.x;
+    BarrierClock clk;
+    clk.start();
     const unsigned e0 = ld_coh(bp.ws + SYNC_EPOCH);
     for (int t = bp.task_ptr[g]; t < bp.task_ptr[g + 1]; ++t) {
         const CgTask task = bp.tasks[t];
         GroupSync gs;
         // disjoint epoch ranges per group: a workgroup's flag left by an
         // earlier group can never match a later group's epochs
-        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span);
+        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span,
+                &clk);
         CInst *in = (CInst *)(bp.inst + task.inst);
         if (MIXED) cg_mixed_body<JACOBI>(*in, gs, task.rank, task.size);
         else cg_f64_body<JACOBI>(in, gs, task.rank, task.size);
     }
     GroupSync all;
-    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span);
+    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span, &clk);
     all.gen = bp.ws + SYNC_GEN;
     all.sync();
     if (g == 0 && threadIdx.x == 0) st_coh(bp.ws + SYNC_EPOCH, all.epoch);
+    clk.publish(bp.ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -1147,7 +1154,9 @@ void fill_result(perks_cg_result *out, int iters, int status, int restarts, int 
     out->relres = relres;
     out->relres_true = reltrue;
     out->cached_nnz_frac = frac;
-    out->reserved = 0;
+    out->fallbacks = 0;
+    out->switched_at = -1;
+    out->barrier_cycles = 0;
 }
 
 // Result words (iters, status, relres, relres_true, ||b||, restarts/outer)
@@ -1238,6 +1247,7 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     CgInst *pdev = reinterpret_cast<CgInst *>(p.result + 16);
     PERKS_HIP_TRY(hipMemcpyAsync(pdev, &p, sizeof(CgInst), hipMemcpyHostToDevice, st));
     void *args[] = {&pdev, &ws};
+    note_persistent_launch(G, nullptr);
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
     if (e != hipSuccess) return launch_error(e);
     double h[8] = {0};
@@ -1245,7 +1255,14 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     PERKS_HIP_TRY(hipStreamSynchronize(st));
     const double lds = mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ;
     const double cached = std::min<double>((double)A->nnz, lds * G);
-    return result_from_words(h, G, A->nnz ? cached / (double)A->nnz : 0.0, out);
+    const int status = result_from_words(h, G, A->nnz ? cached / (double)A->nnz : 0.0, out);
+    if (out) {
+        perks_barrier_stats_t bs;
+        rc = read_barrier_stats(G, nullptr, st, &bs);
+        if (rc) return rc;
+        out->barrier_cycles = (int64_t)bs.wait_cycles;
+    }
+    return status;
 }
 
 struct BaseShape {
@@ -1713,6 +1730,7 @@ int perks_cg_batch_run(perks_cg_batch *P, void *stream) {
                            (int)(SYNC_BYTES / 4));
         P->epochs_used = per_run;
     }
+    note_persistent_launch(P->G, P->ws);
     if (P->exec) {
         PERKS_HIP_TRY(hipGraphLaunch(P->exec, st));
     } else {
@@ -1731,9 +1749,13 @@ int perks_cg_batch_results(perks_cg_batch *P, perks_cg_result *outs, void *strea
     PERKS_HIP_TRY(hipMemcpyAsync(h.data(), P->results, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     PERKS_HIP_TRY(hipStreamSynchronize(st));
     int worst = PERKS_OK;
+    perks_barrier_stats_t bs;
+    const int rc = read_barrier_stats(P->G, P->ws, st, &bs);
+    if (rc) return rc;
     for (int i = 0; i < P->count; ++i) {
         perks_cg_result r;
         const int s = result_from_words(&h[8 * (size_t)i], P->wgs[i], P->cached_frac[i], &r);
+        r.barrier_cycles = (int64_t)bs.wait_cycles;   // the launch's mean over workgroups
         if (outs) outs[i] = r;
         if (s == PERKS_BREAKDOWN || (s == PERKS_NOT_CONVERGED && worst == PERKS_OK)) worst = s;
     }
@@ -1752,6 +1774,7 @@ int perks_cg_batch_destroy(perks_cg_batch *P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->mem) {
+        forget_persistent_launch(P->ws);
         (void)hipDeviceSynchronize();
         (void)hipFree(P->mem);
     }

@@ -39,6 +39,7 @@ enum ScratchSlot {
     SLOT_NN,            // network activations, gradients, packed weights
     SLOT_FCG,           // flexible-CG work vectors
     SLOT_WIDE,          // second grid buffer of the radius-2..4 persistent stencils
+    SLOT_NN_PAIRS,      // partial sums of training-pair formation
     SLOT_COUNT
 };
 // Returns a device pointer of at least `bytes`, or nullptr (error already set).
@@ -54,7 +55,12 @@ constexpr int SYNC_FLAGS = 1024;      // flags[wg]
 constexpr int SYNC_MAX_WGS = 8192;
 constexpr int SYNC_GROUP_GEN = SYNC_FLAGS + SYNC_MAX_WGS;   // generation word of workgroup group j
 constexpr int SYNC_GROUP_STRIDE = 16;                      // at SYNC_GROUP_GEN + j * stride (own 64 B)
-constexpr size_t SYNC_BYTES = (SYNC_GROUP_GEN + (size_t)SYNC_MAX_WGS * SYNC_GROUP_STRIDE) * 4 + 4096;
+// Barrier clock records, one per workgroup of the last persistent launch:
+// SYNC_STATS_WORDS 64-bit words each, {cycles waiting in barriers, cycles
+// from the first barrier set-up to the end, barriers taken, unused}.
+constexpr int SYNC_STATS = SYNC_GROUP_GEN + SYNC_MAX_WGS * SYNC_GROUP_STRIDE;
+constexpr int SYNC_STATS_WORDS = 4;
+constexpr size_t SYNC_BYTES = (SYNC_STATS + (size_t)SYNC_MAX_WGS * SYNC_STATS_WORDS * 2) * 4 + 4096;
 
 struct DeviceFacts {
     int device = -1;
@@ -68,8 +74,20 @@ struct DeviceFacts {
 int device_facts(DeviceFacts *out);
 
 // Cooperative launch of a persistent kernel taking one by-value parameter
-// struct; maps a too-large grid to PERKS_E_NOTCORESIDENT.
+// struct; maps a too-large grid to PERKS_E_NOTCORESIDENT.  Records the grid
+// size as the current device's last persistent launch (for its barrier clock
+// records).
 int launch_coop(const void *fn, int wgs, int threads, void *params, hipStream_t st);
+// Records `wgs` and its barrier words `ws` (NULL: the library's shared ones)
+// as the current device's last persistent launch (launches that do not go
+// through launch_coop).
+void note_persistent_launch(int wgs, unsigned *ws);
+// Drops that record if its barrier words are `ws` (about to be freed).
+void forget_persistent_launch(unsigned *ws);
+// Averages the barrier clock records of the first G workgroups in the barrier
+// words `ws` (NULL: the shared ones); synchronises `st` (see
+// perks_barrier_stats).
+int read_barrier_stats(int G, unsigned *ws, hipStream_t st, perks_barrier_stats_t *out);
 
 }  // namespace perks
 

@@ -132,8 +132,10 @@ __device__ __forceinline__ void net_tile(const FcgParams &p, int tx0, int ty0, d
 }
 
 __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
+    BarrierClock clk;
+    clk.start();
     GroupSync gs;
-    gs.init_grid(p.ws);
+    gs.init_grid(p.ws, &clk);
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const int ntiles = p.ntx * p.nty;
     const int own_tiles = g < ntiles ? (ntiles - 1 - g) / G + 1 : 0;
@@ -290,6 +292,7 @@ __global__ __launch_bounds__(CG_THREADS) void fcg_persistent(FcgParams p) {
         p.result[6] = switched;
     }
     if (g == 0 && tid == 0) st_coh(p.ws + SYNC_EPOCH, gs.epoch);
+    clk.publish(p.ws);
 }
 
 // z = D^{-1} r + rms(r) * net(...) once, with the tile routine the FCG kernel
@@ -417,6 +420,7 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     p.use_net = nn_params ? 1 : 0;
     p.tol = tol;
     void *args[] = {&p};
+    note_persistent_launch(G, nullptr);
     hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&fcg_persistent), dim3(G),
                                               dim3(CG_THREADS), args, 0, st);
     if (e != hipSuccess) {
@@ -427,6 +431,9 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     double h[8] = {0};
     PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
     PERKS_HIP_TRY(hipStreamSynchronize(st));
+    perks_barrier_stats_t bs;
+    int rcb = read_barrier_stats(G, nullptr, st, &bs);
+    if (rcb) return rcb;
     const int s = (int)h[1];
     int iters = (int)h[0];
     double relres = h[2], relres_true = h[3];
@@ -444,12 +451,14 @@ int perks_fcg_solve(const perks_csr *A, const void *b, void *x, double tol, int3
     if (out) {
         out->iters = iters;
         out->status = status;
-        out->restarts = (int)h[5];
+        out->restarts = 0;
         out->wgs = G;
         out->relres = relres;
         out->relres_true = relres_true;
         out->cached_nnz_frac = 0.0;
-        out->reserved = h[6];
+        out->fallbacks = (int)h[5];
+        out->switched_at = (int)h[6];
+        out->barrier_cycles = (int64_t)bs.wait_cycles;   // the FCG launch (not the Jacobi-PCG tail)
     }
     return status;
 }

@@ -598,3 +598,110 @@ int perks_nn_train(float *params, const float *x, const float *target, const flo
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Training pairs from captured CG iterates (the network's part of the error
+// that the Jacobi step leaves, scaled by the residual's RMS).
+namespace {
+
+constexpr int PAIR_BLOCKS = 256;   // partial sums per capture
+
+// part[j][b] = sum of r_j^2 over the grid-stride share of block b; a NaN
+// partial when any r_j entry in that share is not finite.
+__global__ __launch_bounds__(256) void pair_sumsq(const double *cap_r, int64_t n, double *part) {
+    const int j = blockIdx.y;
+    const double *r = cap_r + (size_t)j * n;
+    double s = 0.0;
+    bool finite = true;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = r[i];
+        finite = finite && isfinite(v);
+        s = __builtin_fma(v, v, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const bool all_finite = __all(finite);
+    __shared__ double red[4];
+    __shared__ int bad[4];
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = s;
+        bad[threadIdx.x >> 6] = !all_finite;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        part[(size_t)j * gridDim.x + blockIdx.x] = (bad[0] | bad[1] | bad[2] | bad[3]) ? NAN : t;
+    }
+}
+
+// rms[j] = sqrt(sum of the partials / n), summed in block order (NaN when a
+// partial is NaN).
+__global__ __launch_bounds__(64) void pair_rms(const double *part, int nb, int64_t n, double *rms) {
+    const int j = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[(size_t)j * nb + b];
+        rms[j] = sqrt(s / (double)n);
+    }
+}
+
+// For capture j and grid point i (row i of A): inputs[j][i] = {r/rms, logk},
+// targets[j][i] = (xstar - x_j - r / a_ii) / rms, computed in FP64 and
+// rounded to FP32.
+__global__ __launch_bounds__(256) void pair_form(const int *rowptr, const int *colind, const double *val,
+                                                 const double *xstar, const double *logk, const double *cap_x,
+                                                 const double *cap_r, const double *rms, int64_t n, float *inputs,
+                                                 float *targets) {
+    const int j = blockIdx.y;
+    const double s = rms[j];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double d = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (colind[k] == (int)i) d += val[k];
+        const double r = cap_r[(size_t)j * n + i];
+        const double x = cap_x[(size_t)j * n + i];
+        const size_t o = (size_t)j * n + i;
+        inputs[2 * o] = (float)(r / s);
+        inputs[2 * o + 1] = (float)logk[i];
+        targets[o] = (float)((xstar[i] - x - r / d) / s);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int perks_nn_make_pairs(const perks_csr *A, const double *xstar, const double *logk, const double *cap_x,
+                        const double *cap_r, int32_t ncap, int32_t H, int32_t W, float *inputs, float *targets,
+                        int32_t *count, void *stream) {
+    if (!A || !xstar || !logk || !cap_x || !cap_r || !inputs || !targets || !count)
+        return set_error(PERKS_E_INVAL, "NULL argument");
+    if (A->dt != PERKS_F64 || !A->rowptr || !A->colind || !A->val)
+        return set_error(PERKS_E_INVAL, "A must be an FP64 CSR matrix");
+    if (H < 1 || W < 1 || (int64_t)H * W != A->n) return set_error(PERKS_E_INVAL, "H * W must equal A's order");
+    if (ncap < 0 || ncap > 4096) return set_error(PERKS_E_INVAL, "ncap must be in [0, 4096]");
+    *count = 0;
+    if (ncap == 0) return PERKS_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    double *part = (double *)scratch(SLOT_NN_PAIRS, ((size_t)ncap * PAIR_BLOCKS + ncap) * sizeof(double));
+    if (!part) return PERKS_E_NOMEM;
+    double *rms = part + (size_t)ncap * PAIR_BLOCKS;
+    hipLaunchKernelGGL(pair_sumsq, dim3(PAIR_BLOCKS, ncap), dim3(256), 0, st, cap_r, n, part);
+    hipLaunchKernelGGL(pair_rms, dim3(ncap), dim3(64), 0, st, (const double *)part, PAIR_BLOCKS, n, rms);
+    std::vector<double> h(ncap);
+    PERKS_HIP_TRY(hipMemcpyAsync(h.data(), rms, ncap * sizeof(double), hipMemcpyDeviceToHost, st));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    int m = 0;
+    while (m < ncap && std::isfinite(h[m]) && h[m] > 0.0) ++m;
+    if (m > 0) {
+        const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(pair_form, dim3(nb, m), dim3(256), 0, st, (const int *)A->rowptr,
+                           (const int *)A->colind, (const double *)A->val, xstar, logk, cap_x, cap_r,
+                           (const double *)rms, n, inputs, targets);
+    }
+    PERKS_HIP_TRY(hipGetLastError());
+    *count = m;
+    return PERKS_OK;
+}
+
+}  // extern "C"

@@ -1,6 +1,8 @@
 // Host runtime of libperks: error strings, per-device scratch memory, device
 // facts.
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -93,7 +95,60 @@ int device_facts(DeviceFacts *out) {
     return PERKS_OK;
 }
 
+namespace {
+// grid size and barrier words (NULL: the shared ones) of the last persistent
+// launch per device
+int g_last_wgs[kMaxDevices];
+unsigned *g_last_ws[kMaxDevices];
+}
+
+void note_persistent_launch(int wgs, unsigned *ws) {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_last_wgs[dev] = wgs;
+        g_last_ws[dev] = ws;
+    }
+}
+
+void forget_persistent_launch(unsigned *ws) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (int d = 0; d < kMaxDevices; ++d)
+        if (g_last_ws[d] == ws) {
+            g_last_wgs[d] = 0;
+            g_last_ws[d] = nullptr;
+        }
+}
+
+int read_barrier_stats(int G, unsigned *ws, hipStream_t st, perks_barrier_stats_t *out) {
+    memset(out, 0, sizeof(*out));
+    if (G <= 0) return PERKS_OK;
+    if (G > SYNC_MAX_WGS) return set_error(PERKS_E_INVAL, "barrier stats: %d workgroups", G);
+    if (!ws) ws = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!ws) return PERKS_E_NOMEM;
+    std::vector<unsigned long long> rec((size_t)G * SYNC_STATS_WORDS);
+    PERKS_HIP_TRY(hipMemcpyAsync(rec.data(), ws + SYNC_STATS, rec.size() * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    double wait = 0, total = 0, count = 0, wmax = 0;
+    for (int g = 0; g < G; ++g) {
+        const unsigned long long *r = &rec[(size_t)g * SYNC_STATS_WORDS];
+        wait += (double)r[0];
+        total += (double)r[1];
+        count += (double)r[2];
+        wmax = std::max(wmax, (double)r[0]);
+    }
+    out->wgs = G;
+    out->barriers = (int64_t)(count / G + 0.5);
+    out->wait_cycles = wait / G;
+    out->max_wait_cycles = wmax;
+    out->total_cycles = total / G;
+    out->wait_share = total > 0 ? wait / total : 0.0;
+    return PERKS_OK;
+}
+
 int launch_coop(const void *fn, int wgs, int threads, void *params, hipStream_t st) {
+    note_persistent_launch(wgs, nullptr);
     void *args[] = {params};
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(wgs), dim3(threads), args, 0, st);
     if (e == hipErrorCooperativeLaunchTooLarge) {
@@ -140,6 +195,22 @@ int perks_device_query(perks_device_info *info) {
     info->hbm_bytes = (int64_t)f.hbm;
     snprintf(info->arch, sizeof(info->arch), "%s", f.arch);
     return PERKS_OK;
+}
+
+int perks_barrier_stats(void *stream, perks_barrier_stats_t *out) {
+    if (!out) return perks::set_error(PERKS_E_INVAL, "perks_barrier_stats: out is NULL");
+    memset(out, 0, sizeof(*out));
+    int dev = 0;
+    PERKS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= perks::kMaxDevices) return perks::set_error(PERKS_E_HIP, "device index out of range");
+    int G;
+    unsigned *ws;
+    {
+        std::lock_guard<std::mutex> lock(perks::g_mu);
+        G = perks::g_last_wgs[dev];
+        ws = perks::g_last_ws[dev];
+    }
+    return perks::read_barrier_stats(G, ws, (hipStream_t)stream, out);
 }
 
 }  // extern "C"

@@ -19,7 +19,7 @@ components a local network cannot represent nor by the scale of e.
 """
 import numpy as np
 
-from . import CsrMatrix, cg_solve, cg_solve_capture, nn_pack_params, nn_train
+from . import CsrMatrix, cg_solve, cg_solve_capture, nn_make_pairs, nn_pack_params, nn_train
 
 CAPTURE_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
 
@@ -28,30 +28,23 @@ def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000, with_fi
     """problems: iterable of (rowptr, colind, values, log_k [n, n], f) torch
     tensors on the device.  Returns (inputs [P, n, n, 2] float32, targets
     [P, n, n] float32) device tensors, and with ``with_field`` also the index
-    of each pair's problem (int64 [P])."""
+    of each pair's problem (int64 [P]).  Every step runs in the library: the
+    two Jacobi-PCG solves (x*, then the captured iterates) and the pair
+    formation (perks_nn_make_pairs); here only allocation and concatenation."""
     import torch
     xs, ts, fi = [], [], []
     for pid, (rp, ci, v, lk, f) in enumerate(problems):
         n = lk.shape[0]
         A = CsrMatrix(rp, ci, v)
-        rows = torch.repeat_interleave(torch.arange(rp.numel() - 1, device=rp.device), rp[1:] - rp[:-1])
-        diag = torch.zeros(rp.numel() - 1, dtype=v.dtype, device=v.device).index_add_(
-            0, rows, torch.where(ci.long() == rows, v, torch.zeros_like(v)))
         xstar = torch.zeros_like(f)
         cg_solve(A, f, xstar, tol=tol, maxit=maxit, precond="jacobi")
         x = torch.zeros_like(f)
         info, xc, rc = cg_solve_capture(A, f, x, iters, tol=tol, maxit=maxit, precond="jacobi")
-        for j in range(xc.shape[0]):
-            r = rc[j]
-            if not torch.isfinite(r).all():
-                break                                  # iteration count not reached
-            s = torch.sqrt(torch.mean(r * r))
-            if s <= 0:
-                break
-            xs.append(torch.stack([(r / s).reshape(n, n), lk], dim=-1).to(torch.float32))
-            ts.append(((xstar - xc[j] - r / diag) / s).reshape(n, n).to(torch.float32))
-            fi.append(pid)
-    X, T = torch.stack(xs), torch.stack(ts)
+        X, T = nn_make_pairs(A, xstar, lk.contiguous(), xc, rc, n, n)
+        xs.append(X)
+        ts.append(T)
+        fi.extend([pid] * X.shape[0])
+    X, T = torch.cat(xs), torch.cat(ts)
     if with_field:
         return X, T, torch.tensor(fi, dtype=torch.int64, device=X.device)
     return X, T

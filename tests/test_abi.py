@@ -124,3 +124,33 @@ def test_solver_arguments_are_rejected_before_any_device_call(L):
                             None) == -1
     assert L.perks_nn_train(fake, fake, fake, None, None, 4, 3, 4, 1, 2, 1e-3, 0, fake, fake, ctypes.byref(st), None,
                             None) == -5
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets (a host-only C program built with gcc prints them)."""
+    import shutil
+    import subprocess
+    import paper_2204_02064_amd as pk
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"perks_cg_result": pk.CgResult, "perks_barrier_stats_t": pk.BarrierStats, "perks_tuning": pk.Tuning,
+               "perks_stencil_plan": pk.StencilPlan, "perks_csr": pk.Csr, "perks_shape": pk.Shape,
+               "perks_device_info": pk.DeviceInfo}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)

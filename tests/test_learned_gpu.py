@@ -54,3 +54,32 @@ def test_energy_loss_training_reduces_the_a_norm_error(pk):
     first, last = np.mean(losses[:5]), np.mean(losses[-5:])
     print(f"energy loss {first:.4f} -> {last:.4f}", flush=True)
     assert last < first
+
+
+def test_pairs_match_the_oracle(pk):
+    """perks_nn_make_pairs against oracle.nn.make_pairs on the same captured
+    iterates (copied to the host): FP64 arithmetic rounded to FP32 on both
+    sides, rms summed in different orders (a relative difference of a few
+    FP64 ulps), so FP32 values agree to one FP32 rounding step."""
+    import oracle.nn as onn
+    n = 48
+    rp, ci, v, lk, f = workloads.diffusion_problem_torch(n, seed=5)
+    A = pk.CsrMatrix(rp, ci, v)
+    xstar = torch.zeros_like(f)
+    pk.cg_solve(A, f, xstar, tol=1e-12, maxit=20000, precond="jacobi")
+    x = torch.zeros_like(f)
+    iters = (1, 2, 4, 8, 16, 32, 64, 128, 100000)   # the last one is never reached
+    _, xc, rc = pk.cg_solve_capture(A, f, x, iters, tol=1e-12, maxit=20000, precond="jacobi")
+    X, T = pk.nn_make_pairs(A, xstar, lk.contiguous(), xc, rc, n, n)
+    rph, cih, vh = rp.cpu().numpy(), ci.cpu().numpy(), v.cpu().numpy()
+    diag = np.zeros(n * n)
+    for i in range(n * n):
+        for k in range(rph[i], rph[i + 1]):
+            if cih[k] == i:
+                diag[i] += vh[k]
+    xs = [a.reshape(n, n) for a in xc.cpu().numpy()]
+    rs = [a.reshape(n, n) for a in rc.cpu().numpy()]
+    oin, otg = onn.make_pairs(diag.reshape(n, n), xstar.cpu().numpy().reshape(n, n), lk.cpu().numpy(), xs, rs)
+    assert X.shape[0] == oin.shape[0] == len(iters) - 1
+    np.testing.assert_allclose(X.cpu().numpy(), oin.astype(np.float32), rtol=2 ** -22, atol=0)
+    np.testing.assert_allclose(T.cpu().numpy(), otg.astype(np.float32), rtol=2 ** -22, atol=1e-30)

@@ -295,3 +295,49 @@ def test_energy_loss_with_jacobi_term():
     # and the preconditioner applies the same step
     z = nn.apply_preconditioner(zero, x[0], x[1], dinv=1.0 / planes[2])
     np.testing.assert_allclose(z, zj, rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Training pairs (the error the Jacobi step leaves, scaled by rms(r)).
+
+def test_pairs_of_a_diagonal_operator_have_zero_target():
+    """For a diagonal operator the Jacobi step is the exact correction
+    (e = D^-1 r), so every target vanishes; the input's first channel has
+    unit rms and the second is log k unchanged."""
+    rng = np.random.default_rng(3)
+    n = 9
+    diag = rng.uniform(0.5, 3.0, (n, n))
+    lk = rng.standard_normal((n, n))
+    xstar = rng.standard_normal((n, n))
+    xs = [rng.standard_normal((n, n)) for _ in range(3)]
+    rs = [diag * (xstar - x) for x in xs]
+    ins, tg = nn.make_pairs(diag, xstar, lk, xs, rs)
+    assert ins.shape == (3, n, n, 2) and tg.shape == (3, n, n)
+    assert np.max(np.abs(tg)) <= 1e-14 * max(1.0, np.max(np.abs(xstar)))
+    for j in range(3):
+        assert abs(np.sqrt(np.mean(ins[j, ..., 0] ** 2)) - 1.0) <= 1e-14
+        np.testing.assert_array_equal(ins[j, ..., 1], lk)
+
+
+def test_pairs_are_scale_invariant_and_stop_at_unreached_captures():
+    """Scaling residual and error together by c leaves every pair unchanged
+    (both are divided by rms(r)); a NaN or zero residual ends the list."""
+    rng = np.random.default_rng(4)
+    n = 7
+    diag = rng.uniform(1.0, 2.0, (n, n))
+    lk = rng.standard_normal((n, n))
+    xstar = rng.standard_normal((n, n))
+    x = rng.standard_normal((n, n))
+    r = rng.standard_normal((n, n))
+    a_in, a_t = nn.make_pairs(diag, xstar, lk, [x], [r])
+    c = 2.0 ** -7
+    b_in, b_t = nn.make_pairs(diag, c * xstar, lk, [c * x], [c * r])
+    np.testing.assert_allclose(b_in, a_in, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(b_t, a_t, rtol=1e-13, atol=1e-15)
+    # the second capture was not reached (NaN) -> one pair; a zero residual too
+    nan = np.full((n, n), np.nan)
+    assert nn.make_pairs(diag, xstar, lk, [x, x, x], [r, nan, r])[0].shape[0] == 1
+    assert nn.make_pairs(diag, xstar, lk, [x, x], [np.zeros((n, n)), r])[0].shape[0] == 0
+    # direct evaluation at one pixel
+    s = np.sqrt(np.mean(r ** 2))
+    assert a_t[0, 2, 3] == pytest.approx((xstar[2, 3] - x[2, 3] - r[2, 3] / diag[2, 3]) / s, rel=1e-14)
