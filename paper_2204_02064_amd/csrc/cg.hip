@@ -23,782 +23,18 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <mutex>
 #include <vector>
 
-#include "barrier.hpp"
-#include "cg_common.hpp"
-#include "common.hpp"
+#include "cg_device.hpp"
 
 namespace perks {
+
+// The register-resident FP64 solver kernel (cg_reg.hip) and its launch
+// shape: threads per workgroup, rows per thread.
+const void *cg_reg_kernel(bool jacobi, int *threads, int *rows_per_thread);
+
 namespace {
-
-enum { PART_PQ = 0, PART_RZ = 1, PART_RR = 2, PART_BB = 3, PART_TRUE = 4, NPART = 5 };
-
-// One CG problem and its work vectors (device pointers).  FP64 solves use
-// r, z, q, p, dinv; mixed solves use r64 and the FP32 vectors.  part
-// holds NPART partial sums per workgroup of the problem's group; result
-// receives iters, status, relres, relres_true, ||b||, restarts or outer steps.
-struct CgInst {
-    const int *rowptr;
-    const int *colind;
-    const double *val;
-    const double *b;
-    double *x;
-    double *r, *z, *q, *p, *dinv;
-    float *val32;
-    double *r64;
-    float *r32, *z32, *q32, *p32, *d32, *dinv32;
-    double *part;
-    double *result;
-    double *sval64;          // sliced-ELL copy of A (FP64 solver), NULL: CSR only
-    float *sval32;           // sliced-ELL copy of A (mixed solver)
-    int *scol;               // its column indices
-    int *sperm;              // rows of each workgroup's slice in sliced-ELL order (n entries)
-    double *cap_x, *cap_r;   // FP64 solver: x and r after the iterations listed in cap_iters
-    const int *cap_iters;    // ascending iteration counts (device)
-    int ncap;
-    int n;
-    int nnz;
-    int maxit;
-    int max_outer;
-    double tol;
-    double inner_tol;
-};
-
-// The problem description as kernels read it: through the constant address
-// space (the host writes it before the launch, no kernel writes it), so that
-// the compiler takes every pointer loaded from it to address global memory
-// and emits global_* accesses instead of flat ones (which also count in
-// lgkmcnt, making every LDS wait of the SpMV wait for the gathers too).
-using CInst = const __attribute__((address_space(4))) CgInst;
-
-// The workgroup's LDS copy of (the first entries of) its slice of A: FP64
-// values for the FP64 solver, FP32 values for the mixed-precision solver.
-// Each kernel references only its own pair, so each gets only that pair.
-constexpr int CG_LDS_NNZ = 12032;     // 141 KiB of the 160 KiB LDS (12 B/nonzero)
-constexpr int CG_LDS_NNZ32 = 18048;   // 141 KiB (8 B/nonzero)
-__shared__ double cg_lval[CG_LDS_NNZ];
-__shared__ int cg_lcol[CG_LDS_NNZ];
-__shared__ float cg_lval32[CG_LDS_NNZ32];
-__shared__ int cg_lcol32[CG_LDS_NNZ32];
-
-template <typename T> struct LdsA;
-template <> struct LdsA<double> {
-    static constexpr int cap = CG_LDS_NNZ;
-    static __device__ __forceinline__ double &val(int k) { return cg_lval[k]; }
-    static __device__ __forceinline__ int &col(int k) { return cg_lcol[k]; }
-};
-template <> struct LdsA<float> {
-    static constexpr int cap = CG_LDS_NNZ32;
-    static __device__ __forceinline__ float &val(int k) { return cg_lval32[k]; }
-    static __device__ __forceinline__ int &col(int k) { return cg_lcol32[k]; }
-};
-
-// y_i for rows [r0, r1) with L lanes per row: sum_k a_k * v(col_k) in type T,
-// where v(j) is produced by `fetch`.  FROM_LDS: the rows lie wholly in the
-// LDS copy of the slice (entry k at index k - kbase); otherwise A is read from
-// `gval` in global memory.  Each lane group takes U rows per pass and issues
-// all their loads before any use (U times the memory-level parallelism of one
-// row at a time).  A row's sum is the lane-strided partial sums followed by
-// the group butterfly: its rounding depends neither on U nor on where A is
-// read from.
-template <int U, bool FROM_LDS, typename T, typename F, typename S>
-__device__ __forceinline__ void spmv_range(const int *rowptr, const int *colind, const T *gval, int r0, int r1,
-                                           int L, int kbase, F fetch, S sink) {
-    const int tid = threadIdx.x;
-    const int gl = tid & (L - 1);
-    const int rpp = CG_THREADS / L;
-    for (int row0 = r0; row0 < r1; row0 += rpp * U) {
-        int kb[U], ke[U];
-        T s[U];
-        int len = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = row0 + u * rpp + tid / L;
-            kb[u] = 0;
-            ke[u] = 0;
-            s[u] = T(0);
-            if (i < r1) {
-                kb[u] = rowptr[i] + gl;
-                ke[u] = rowptr[i + 1];
-            }
-            len = max(len, ke[u] - kb[u]);
-        }
-        for (int j = 0; j < len; j += L) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = kb[u] + j;
-                if (k < ke[u]) {
-                    T a;
-                    int c;
-                    if constexpr (FROM_LDS) {
-                        a = LdsA<T>::val(k - kbase);
-                        c = LdsA<T>::col(k - kbase);
-                    } else {
-                        a = gval[k];
-                        c = colind[k];
-                    }
-                    s[u] = fma_t(a, fetch(c), s[u]);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const T t = group_sum(s[u], L);
-            const int i = row0 + u * rpp + tid / L;
-            if (i < r1 && gl == 0) sink(i, t);
-        }
-    }
-}
-
-// Rows [r0, rc) come from the LDS copy, rows [rc, r1) from global memory.
-template <int U, typename T, typename F, typename S>
-__device__ __forceinline__ void spmv_rows(const int *rowptr, const int *colind, const T *gval, int r0, int rc,
-                                          int r1, int L, int kbase, F fetch, S sink) {
-    spmv_range<U, true>(rowptr, colind, gval, r0, rc, L, kbase, fetch, sink);
-    spmv_range<U, false>(rowptr, colind, gval, rc, r1, L, kbase, fetch, sink);
-}
-
-// First row of [r0, r1) that does not end within the first kc entries of the
-// slice starting at kbase (rows before it are wholly cached).
-__device__ __forceinline__ int cached_rows_end(const int *rowptr, int r0, int r1, int kbase, int kc) {
-    int lo = r0, hi = r1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (rowptr[mid + 1] - kbase <= kc) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-constexpr int CG_U = PERKS_CG_U;
-
-__shared__ double cg_red[4 * CG_WAVES];
-__shared__ double cg_bcast;
-
-// The workgroup's share of a problem solved by a group of G workgroups, of
-// which this one has rank g: rows [r0, r1) (merge-path split).
-//
-// Two layouts of the slice's rows:
-// * sliced ELL (when padding costs at most a quarter more entries): chunks of
-//   64 consecutive rows, one lane per row, the chunk's rows padded to its
-//   longest row and stored entry-major (entry j of the chunk's rows is 64
-//   consecutive values), built by the workgroup at kernel start in its own
-//   region of the packed arrays.  Loads are coalesced, no row pointers are
-//   read in the iterations, no lanes are reduced across.  Padding entries are
-//   0 * x[row].  Chunks [0, cc) are also held in LDS.
-// * CSR with L lanes per row otherwise (irregular row lengths): the first kc
-//   nonzeros in LDS, rows [r0, rc) wholly cached.
-// A row's sum is the same either way up to rounding order; its order depends
-// only on the layout, which depends only on the problem and G.
-constexpr int SELL_MAX_CHUNKS = 2048;
-__shared__ int cg_chunk_len[SELL_MAX_CHUNKS];
-__shared__ int cg_chunk_off[SELL_MAX_CHUNKS];
-__shared__ int cg_flag;
-
-struct Slice {
-    int r0, r1, rc, kbase, nnz, kc, L;
-    int sell, nch, cc, sbase;
-    const int *perm;   // sliced-ELL row order (rows sorted by length), or NULL: natural order
-};
-
-// Entries the packed arrays of one problem need for G workgroups.
-__host__ __device__ inline size_t sell_capacity(int64_t nnz, int G) {
-    return (size_t)(nnz + nnz / 4) + 64 * (size_t)G + 64;
-}
-
-template <typename T>
-__device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int *scol, int g, int G) {
-    Slice sl;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    sl.r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
-    sl.r1 = merge_split(p.rowptr, p.n, p.nnz, g + 1, G);
-    sl.kbase = p.rowptr[sl.r0];
-    sl.nnz = p.rowptr[sl.r1] - sl.kbase;
-    sl.L = pick_group(sl.r1 - sl.r0, sl.nnz);
-    sl.nch = (sl.r1 - sl.r0 + 63) / 64;
-    sl.sbase = (int)(sl.kbase + sl.kbase / 4) + 64 * g;
-    __syncthreads();   // the previous problem of this workgroup is done with LDS
-    // chunk lengths (longest row of each chunk), then their offsets
-    sl.sell = sval != nullptr && sl.nch <= SELL_MAX_CHUNKS;
-    if (sl.sell) {
-        for (int c = wave; c < sl.nch; c += CG_WAVES) {
-            const int i = sl.r0 + 64 * c + lane;
-            int len = i < sl.r1 ? p.rowptr[i + 1] - p.rowptr[i] : 0;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-            if (lane == 0) cg_chunk_len[c] = len;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int c = 0; c < sl.nch; ++c) {
-                cg_chunk_off[c] = acc;
-                acc += 64 * cg_chunk_len[c];
-            }
-            cg_flag = acc <= sl.nnz + sl.nnz / 4 + 64 ? acc : -1;
-        }
-        __syncthreads();
-        sl.sell = cg_flag >= 0;
-    }
-    sl.perm = nullptr;
-    const int nrows = sl.r1 - sl.r0;
-    if (!sl.sell && sval != nullptr && p.sperm != nullptr && sl.nch <= SELL_MAX_CHUNKS && nrows <= LdsA<T>::cap) {
-        // Irregular rows: sliced ELL over the slice's rows sorted by length,
-        // longest first (SELL-C-sigma with sigma = the slice), so that each
-        // chunk's rows have nearly equal lengths.  A stable counting sort on
-        // min(length, 255); its order depends only on the problem and G.
-        int *key = &LdsA<T>::col(0);
-        int *cnt = cg_chunk_off;   // 256 bucket counters, then starts
-        for (int r = tid; r < nrows; r += CG_THREADS) {
-            const int i = sl.r0 + r;
-            key[r] = 255 - min(p.rowptr[i + 1] - p.rowptr[i], 255);
-        }
-        for (int b = tid; b < 256; b += CG_THREADS) cnt[b] = 0;
-        __syncthreads();
-        for (int r = tid; r < nrows; r += CG_THREADS) atomicAdd(&cnt[key[r]], 1);
-        __syncthreads();
-        if (wave == 0) {
-            // exclusive prefix over the 256 buckets: 4 per lane, then a wave scan
-            int c4[4], tot = 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c4[u] = cnt[4 * lane + u];
-                tot += c4[u];
-            }
-            int incl = tot;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int t = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += t;
-            }
-            int run = incl - tot;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cnt[4 * lane + u] = run;
-                run += c4[u];
-            }
-            // stable scatter, 64 rows at a time: rank among equal keys from
-            // ballots over the key bits
-            const unsigned long long lt = (1ULL << lane) - 1ULL;
-            for (int base = 0; base < nrows; base += 64) {
-                const int r = base + lane;
-                const int k = r < nrows ? key[r] : 256;
-                unsigned long long same = __ballot(1);
-#pragma unroll
-                for (int bit = 0; bit < 9; ++bit) {
-                    const unsigned long long m = __ballot((k >> bit) & 1);
-                    same &= ((k >> bit) & 1) ? m : ~m;
-                }
-                const int rank = __popcll(same & lt);
-                if (r < nrows) {
-                    const int pos = cnt[k] + rank;
-                    st_coh(p.sperm + sl.r0 + pos, sl.r0 + r);
-                }
-                __builtin_amdgcn_wave_barrier();
-                if (r < nrows && rank == 0) cnt[k] += __popcll(same);
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        __syncthreads();
-        sl.perm = p.sperm + sl.r0;
-        for (int c = wave; c < sl.nch; c += CG_WAVES) {
-            const int r = 64 * c + lane;
-            const int i = r < nrows ? ld_coh(sl.perm + r) : sl.r0;
-            int len = r < nrows ? p.rowptr[i + 1] - p.rowptr[i] : 0;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-            if (lane == 0) cg_chunk_len[c] = len;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int c = 0; c < sl.nch; ++c) {
-                cg_chunk_off[c] = acc;
-                acc += 64 * cg_chunk_len[c];
-            }
-            cg_flag = acc <= sl.nnz + sl.nnz / 4 + 64 ? acc : -1;
-        }
-        __syncthreads();
-        sl.sell = cg_flag >= 0;
-        if (!sl.sell) sl.perm = nullptr;
-    }
-    if (sl.sell) {
-        // cached chunks: a prefix whose entries fit in LDS
-        int cc = 0;
-        while (cc < sl.nch && cg_chunk_off[cc] + 64 * cg_chunk_len[cc] <= LdsA<T>::cap) ++cc;
-        sl.cc = cc;
-        for (int c = wave; c < sl.nch; c += CG_WAVES) {
-            const int r = 64 * c + lane;
-            const int i = r < nrows ? (sl.perm ? ld_coh(sl.perm + r) : sl.r0 + r) : sl.r1;
-            const int len = cg_chunk_len[c], off = cg_chunk_off[c];
-            const int kb = i < sl.r1 ? p.rowptr[i] : 0;
-            const int kn = i < sl.r1 ? p.rowptr[i + 1] - kb : 0;
-            const int self = i < sl.r1 ? i : sl.r0;
-            for (int j = 0; j < len; ++j) {
-                const T a = j < kn ? val[kb + j] : T(0);
-                const int cidx = j < kn ? p.colind[kb + j] : self;
-                const int e = off + j * 64 + lane;
-                sval[sl.sbase + e] = a;
-                scol[sl.sbase + e] = cidx;
-                if (c < cc) {
-                    LdsA<T>::val(e) = a;
-                    LdsA<T>::col(e) = cidx;
-                }
-            }
-        }
-        sl.kc = 0;
-        sl.rc = sl.r0;
-    } else {
-        sl.cc = 0;
-        sl.kc = min(sl.nnz, LdsA<T>::cap);
-        for (int k = tid; k < sl.kc; k += CG_THREADS) {
-            LdsA<T>::val(k) = val[sl.kbase + k];
-            LdsA<T>::col(k) = p.colind[sl.kbase + k];
-        }
-        sl.rc = cached_rows_end(p.rowptr, sl.r0, sl.r1, sl.kbase, sl.kc);
-    }
-    __syncthreads();   // also publishes the packed arrays within the workgroup
-    return sl;
-}
-
-#ifndef PERKS_SELL_U
-#define PERKS_SELL_U 4
-#endif
-// Entries of a row whose loads and gathers are issued before their products.
-constexpr int SELL_U = PERKS_SELL_U;
-
-// y_i = sum_j a_j * v(col_j) over the sliced-ELL chunks [c0, c1), one lane
-// per row, entries in CSR order; FROM_LDS: the chunks are held in LDS.
-template <bool FROM_LDS, typename T, typename F, typename S>
-__device__ __forceinline__ void spmv_sell_range(const Slice &sl, const T *sval, const int *scol, int c0, int c1,
-                                                F fetch, S sink) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = c0 + wave; c < c1; c += CG_WAVES) {
-        const int len = cg_chunk_len[c], off = cg_chunk_off[c];
-        const int r = 64 * c + lane;
-        const int i = sl.perm ? (sl.r0 + r < sl.r1 ? sl.perm[r] : sl.r1) : sl.r0 + r;
-        T acc = T(0);
-        int j = 0;
-        for (; j + SELL_U <= len; j += SELL_U) {
-            T a[SELL_U];
-            int cidx[SELL_U];
-#pragma unroll
-            for (int u = 0; u < SELL_U; ++u) {
-                const int e = off + (j + u) * 64 + lane;
-                if constexpr (FROM_LDS) {
-                    a[u] = LdsA<T>::val(e);
-                    cidx[u] = LdsA<T>::col(e);
-                } else {
-                    a[u] = sval[sl.sbase + e];
-                    cidx[u] = scol[sl.sbase + e];
-                }
-            }
-            T xv[SELL_U];
-#pragma unroll
-            for (int u = 0; u < SELL_U; ++u) xv[u] = fetch(cidx[u]);
-#pragma unroll
-            for (int u = 0; u < SELL_U; ++u) acc = fma_t(a[u], xv[u], acc);
-        }
-        for (; j < len; ++j) {
-            const int e = off + j * 64 + lane;
-            T a;
-            int cidx;
-            if constexpr (FROM_LDS) {
-                a = LdsA<T>::val(e);
-                cidx = LdsA<T>::col(e);
-            } else {
-                a = sval[sl.sbase + e];
-                cidx = scol[sl.sbase + e];
-            }
-            acc = fma_t(a, fetch(cidx), acc);
-        }
-        if (i < sl.r1) sink(i, acc);
-    }
-}
-
-// SpMV over the workgroup's rows in whichever layout the slice uses.
-template <int U, typename T, typename F, typename S>
-__device__ __forceinline__ void spmv_slice(CInst &p, const Slice &sl, const T *val, const T *sval,
-                                           const int *scol, F fetch, S sink) {
-    if (sl.sell) {
-        spmv_sell_range<true>(sl, sval, scol, 0, sl.cc, fetch, sink);
-        spmv_sell_range<false>(sl, sval, scol, sl.cc, sl.nch, fetch, sink);
-    } else {
-        spmv_rows<U>(p.rowptr, p.colind, val, sl.r0, sl.rc, sl.r1, sl.L, sl.kbase, fetch, sink);
-    }
-}
-
-// FP64 persistent CG of one problem by a group of G workgroups (this one of
-// rank g) synchronised by `gs`.  Per iteration: phase 1 q = A p and p.q,
-// phase 2 x, r, z updates and r.z, r.r, each followed by a group barrier and
-// a fixed-order all-reduce; before phase 1, phase P updates p in place on
-// own rows and a third barrier publishes it.  When the
-// recursive residual meets tol the true residual is recomputed; if it fails,
-// CG restarts from the current x while iterations remain.
-template <bool JACOBI, class Sync>
-__device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, const int G) {
-    // The problem is read from global memory through a pointer laundered at
-    // every phase: its fields are reloaded (scalar loads) instead of being
-    // kept live in scalar registers across the whole solve.
-    CInst *pp = opaque(pin);
-    const int tid = threadIdx.x;
-    const Slice sl = load_slice(*pp, pp->val, pp->sval64, pp->scol, g, G);
-    const int r0 = sl.r0, r1 = sl.r1;
-    if (JACOBI) {
-        for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            double dg = 0.0;
-            for (int k = pp->rowptr[i]; k < pp->rowptr[i + 1]; ++k)
-                if (pp->colind[k] == i) dg += pp->val[k];
-            pp->dinv[i] = 1.0 / dg;
-        }
-    }
-    const double *zsrc = JACOBI ? pp->z : pp->r;
-    int k = 0, status = 1, restarts = 0, k_cycle = -1, cap = 0;
-    while (cap < pp->ncap && pp->cap_iters[cap] <= 0) ++cap;
-    double bnorm = 0.0, rr = 0.0, tt = 0.0;
-    for (;;) {
-        pp = opaque(pin);
-        // phase 0: r = b - A x, z, p_{-1} = 0, partials b.b, r.z, r.r
-        double acc0[3] = {0.0, 0.0, 0.0};
-        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
-                        [&](int i, double s) { pp->q[i] = s; });
-        __syncthreads();
-        for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            const double bi = pp->b[i];
-            const double ri = bi - pp->q[i];
-            const double zi = JACOBI ? pp->dinv[i] * ri : ri;
-            if (JACOBI) {
-                pp->r[i] = ri;            // read back only by this thread
-                st_coh(pp->z + i, zi);    // gathered by other workgroups
-            } else {
-                st_coh(pp->r + i, ri);
-            }
-            st_coh(pp->p + i, 0.0);
-            acc0[0] = __builtin_fma(bi, bi, acc0[0]);
-            acc0[1] = __builtin_fma(ri, zi, acc0[1]);
-            acc0[2] = __builtin_fma(ri, ri, acc0[2]);
-        }
-        block_sum<3>(acc0, cg_red);
-        if (tid == 0) {
-            st_coh(pp->part + (size_t)PART_BB * G + g, acc0[0]);
-            st_coh(pp->part + (size_t)PART_RZ * G + g, acc0[1]);
-            st_coh(pp->part + (size_t)PART_RR * G + g, acc0[2]);
-        }
-        gs.template sync<true>();
-        bnorm = sqrt(grid_total(pp->part, PART_BB, G, &cg_bcast));
-        double rho = grid_total(pp->part, PART_RZ, G, &cg_bcast);
-        rr = grid_total(pp->part, PART_RR, G, &cg_bcast);
-        if (bnorm == 0.0) {
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pp->x + i, 0.0);
-            status = 0;
-            tt = 0.0;
-            break;
-        }
-        double beta = 0.0;
-        while (true) {
-            if (sqrt(rr) <= pp->tol * bnorm) break;
-            if (k >= pp->maxit) break;
-            pp = opaque(pin);
-            double acc1[1] = {0.0};
-            double *pn = pp->p;
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
-            gs.template sync<true>();
-            spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
-                            [&](int i, double s) {
-                                pp->q[i] = s;
-                                acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
-                            });
-            block_sum<1>(acc1, cg_red);
-            if (tid == 0) st_coh(pp->part + (size_t)PART_PQ * G + g, acc1[0]);
-            gs.template sync<true>();
-            const double pq = grid_total(pp->part, PART_PQ, G, &cg_bcast);
-            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
-            const double alpha = rho / pq;
-            pp = opaque(pin);
-            // phase 2: x, r, z updates on own rows
-            double acc2[2] = {0.0, 0.0};
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-                const double pi = pn[i], qi = pp->q[i], xi = pp->x[i], ro = pp->r[i];
-                st_coh(pp->x + i, __builtin_fma(alpha, pi, xi));   // read by others at exit
-                const double ri = __builtin_fma(-alpha, qi, ro);
-                double zi = ri;
-                if (JACOBI) {
-                    pp->r[i] = ri;
-                    zi = pp->dinv[i] * ri;
-                    st_coh(pp->z + i, zi);
-                } else {
-                    st_coh(pp->r + i, ri);
-                }
-                acc2[0] = __builtin_fma(ri, zi, acc2[0]);
-                acc2[1] = __builtin_fma(ri, ri, acc2[1]);
-            }
-            block_sum<2>(acc2, cg_red);
-            if (tid == 0) {
-                st_coh(pp->part + (size_t)PART_RZ * G + g, acc2[0]);
-                st_coh(pp->part + (size_t)PART_RR * G + g, acc2[1]);
-            }
-            gs.template sync<true>();
-            const double rho_new = grid_total(pp->part, PART_RZ, G, &cg_bcast);
-            rr = grid_total(pp->part, PART_RR, G, &cg_bcast);
-            ++k;
-            if (cap < pp->ncap && k == pp->cap_iters[cap]) {
-                // snapshot of the iterate and its residual (own rows, same
-                // thread-to-row mapping as phase 2)
-                for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-                    pp->cap_x[(size_t)cap * pp->n + i] = pp->x[i];
-                    pp->cap_r[(size_t)cap * pp->n + i] = pp->r[i];
-                }
-                ++cap;
-            }
-            if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
-            beta = rho_new / rho;
-            rho = rho_new;
-        }
-        // true residual ||b - A x|| (x of other workgroups read after the barrier)
-        pp = opaque(pin);
-        double acc3[1] = {0.0};
-        gs.template sync<true>();
-        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
-                        [&](int i, double s) {
-                            const double d = pp->b[i] - s;
-                            acc3[0] = __builtin_fma(d, d, acc3[0]);
-                        });
-        block_sum<1>(acc3, cg_red);
-        if (tid == 0) st_coh(pp->part + (size_t)PART_TRUE * G + g, acc3[0]);
-        gs.template sync<true>();
-        tt = grid_total(pp->part, PART_TRUE, G, &cg_bcast);
-        if (status == 2) break;
-        if (sqrt(tt) <= pp->tol * bnorm) { status = 0; break; }
-        // restart from x (recursive residual converged but the true one did
-        // not) unless the iteration budget is spent or the last cycle made no
-        // iteration (the two residuals differ only in rounding order there)
-        if (k >= pp->maxit || k == k_cycle) { status = 1; break; }
-        k_cycle = k;
-        ++restarts;
-    }
-    if (g == 0 && tid == 0) {
-        pp->result[0] = k;
-        pp->result[1] = status;
-        pp->result[2] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
-        pp->result[3] = bnorm > 0.0 ? sqrt(tt) / bnorm : 0.0;
-        pp->result[4] = bnorm;
-        pp->result[5] = restarts;
-    }
-}
-
-// Mixed precision: FP64 iterative refinement around an FP32 CG.  Outer step
-// (FP64): r = b - A x with the FP64 matrix; stop when ||r|| <= tol ||b||;
-// otherwise run CG in FP32 on A32 d = s r (A32 = float(A), s a power of two
-// near 1/||r||, so the scaling is exact), with FP32 vectors, SpMV and AXPYs
-// and FP64 dot products, alpha and beta, until its recursive residual has
-// fallen by inner_tol; then x += d / s.  An outer step that does not halve
-// ||r|| ends the solve (FP32 cannot resolve the system).  The FP32 copy of
-// each workgroup's slice of A is made by the workgroup itself (global copy +
-// LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
-// nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
-template <bool JACOBI, class Sync>
-__device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, const int G) {
-    const int tid = threadIdx.x;
-    {
-        // FP32 copy of this workgroup's slice (only this workgroup reads it)
-        const int s0 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g, G)];
-        const int s1 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g + 1, G)];
-        for (int k = s0 + tid; k < s1; k += CG_THREADS) p.val32[k] = (float)p.val[k];
-    }
-    const Slice sl = load_slice(p, (const float *)p.val32, p.sval32, p.scol, g, G);   // its barriers publish val32
-    const int r0 = sl.r0, r1 = sl.r1, kbase = sl.kbase, L = sl.L;
-    double accb[1] = {0.0};
-    for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-        if (JACOBI) {
-            double dg = 0.0;
-            for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k)
-                if (p.colind[k] == i) dg += p.val[k];
-            p.dinv32[i] = (float)(1.0 / dg);
-        }
-        const double bi = p.b[i];
-        accb[0] = __builtin_fma(bi, bi, accb[0]);
-    }
-    block_sum<1>(accb, cg_red);
-    if (tid == 0) st_coh(p.part + (size_t)PART_BB * G + g, accb[0]);
-
-    const float *zsrc = JACOBI ? p.z32 : p.r32;
-    double bnorm = -1.0, rn = 0.0, prev = INFINITY;
-    int k = 0, outer = 0, status = 1;
-    for (;;) {
-        gs.template sync<true>();   // x (and, the first time, the b.b partials) complete
-        if (bnorm < 0.0) bnorm = sqrt(grid_total(p.part, PART_BB, G, &cg_bcast));
-        if (bnorm == 0.0) {
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, 0.0);
-            status = 0;
-            rn = 0.0;
-            break;
-        }
-        // outer residual in FP64 (A from global memory in FP64)
-        double accr[1] = {0.0};
-        spmv_range<CG_U, false>(p.rowptr, p.colind, p.val, r0, r1, L, kbase, [&](int c) { return p.x[c]; },
-                                [&](int i, double sv) {
-                                    const double ri = p.b[i] - sv;
-                                    p.r64[i] = ri;
-                                    accr[0] = __builtin_fma(ri, ri, accr[0]);
-                                });
-        block_sum<1>(accr, cg_red);
-        if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, accr[0]);
-        gs.template sync<true>();
-        rn = sqrt(grid_total(p.part, PART_TRUE, G, &cg_bcast));
-        if (status == 2) break;
-        if (rn <= p.tol * bnorm) { status = 0; break; }
-        if (k >= p.maxit || outer >= p.max_outer || !(rn <= 0.5 * prev)) break;
-        prev = rn;
-        int ex;
-        (void)frexp(rn, &ex);
-        const double sc = ldexp(1.0, 1 - ex);   // 2^-floor(log2 rn)
-        // inner start: r32 = float(s r), z32, p_{-1} = 0, d = 0
-        double acc0[2] = {0.0, 0.0};
-        for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            const float ri = (float)(p.r64[i] * sc);
-            const float zi = JACOBI ? p.dinv32[i] * ri : ri;
-            if (JACOBI) {
-                p.r32[i] = ri;
-                st_coh(p.z32 + i, zi);
-            } else {
-                st_coh(p.r32 + i, ri);
-            }
-            st_coh(p.p32 + i, 0.0f);
-            p.d32[i] = 0.0f;
-            acc0[0] = __builtin_fma((double)ri, (double)zi, acc0[0]);
-            acc0[1] = __builtin_fma((double)ri, (double)ri, acc0[1]);
-        }
-        block_sum<2>(acc0, cg_red);
-        if (tid == 0) {
-            st_coh(p.part + (size_t)PART_RZ * G + g, acc0[0]);
-            st_coh(p.part + (size_t)PART_RR * G + g, acc0[1]);
-        }
-        gs.template sync<true>();
-        double rho = grid_total(p.part, PART_RZ, G, &cg_bcast);
-        double rr = grid_total(p.part, PART_RR, G, &cg_bcast);
-        const double stop = p.inner_tol * sqrt(rr);
-        double beta = 0.0;
-        for (int j = 0; sqrt(rr) > stop && k < p.maxit; ++j) {
-            const float bf = (float)beta;
-            double acc1[1] = {0.0};
-            float *pn = p.p32;
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
-            gs.template sync<true>();
-            spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
-                            [&](int c) { return pn[c]; },
-                            [&](int i, float sv) {
-                                p.q32[i] = sv;
-                                acc1[0] = __builtin_fma((double)pn[i], (double)sv, acc1[0]);
-                            });
-            block_sum<1>(acc1, cg_red);
-            if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
-            gs.template sync<true>();
-            const double pq = grid_total(p.part, PART_PQ, G, &cg_bcast);
-            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
-            const float af = (float)(rho / pq);
-            double acc2[2] = {0.0, 0.0};
-            for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-                const float pi = pn[i];
-                p.d32[i] = __builtin_fmaf(af, pi, p.d32[i]);
-                const float ri = __builtin_fmaf(-af, p.q32[i], p.r32[i]);
-                float zi = ri;
-                if (JACOBI) {
-                    p.r32[i] = ri;
-                    zi = p.dinv32[i] * ri;
-                    st_coh(p.z32 + i, zi);
-                } else {
-                    st_coh(p.r32 + i, ri);
-                }
-                acc2[0] = __builtin_fma((double)ri, (double)zi, acc2[0]);
-                acc2[1] = __builtin_fma((double)ri, (double)ri, acc2[1]);
-            }
-            block_sum<2>(acc2, cg_red);
-            if (tid == 0) {
-                st_coh(p.part + (size_t)PART_RZ * G + g, acc2[0]);
-                st_coh(p.part + (size_t)PART_RR * G + g, acc2[1]);
-            }
-            gs.template sync<true>();
-            const double rho_new = grid_total(p.part, PART_RZ, G, &cg_bcast);
-            rr = grid_total(p.part, PART_RR, G, &cg_bcast);
-            ++k;
-            if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
-            beta = rho_new / rho;
-            rho = rho_new;
-        }
-        // x += d / s on own rows (read by every workgroup in the next residual)
-        for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, p.x[i] + (double)p.d32[i] / sc);
-        ++outer;
-    }
-    if (g == 0 && tid == 0) {
-        p.result[0] = k;
-        p.result[1] = status;
-        p.result[2] = bnorm > 0.0 ? rn / bnorm : 0.0;
-        p.result[3] = bnorm > 0.0 ? rn / bnorm : 0.0;
-        p.result[4] = bnorm;
-        p.result[5] = outer;
-    }
-}
-
-// One problem on the whole grid.
-template <bool JACOBI, bool MIXED>
-__global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
-    BarrierClock clk;
-    clk.start();
-    GroupSync gs;
-    gs.init_grid(ws, &clk);
-    CInst *in = (CInst *)pin;
-    if (MIXED) cg_mixed_body<JACOBI>(*in, gs, blockIdx.x, gridDim.x);
-    else cg_f64_body<JACOBI>(in, gs, blockIdx.x, gridDim.x);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
-    clk.publish(ws);
-}
-
-// Many problems in one launch.  Workgroup g runs the tasks
-// tasks[task_ptr[g] .. task_ptr[g+1]) in order; a task is (problem, rank,
-// group size, group id).  A problem given to several workgroups is the first
-// task of each of them (a contiguous range of workgroups, synchronised by the
-// group's own barrier); the other problems are solved by one workgroup each,
-// one after another.  Every workgroup takes its tasks in the same phase
-// order, so no wait can be circular.  A final barrier of the whole grid
-// precedes the hand-over of the epoch to the next launch.
-struct CgTask {
-    int inst, rank, size, group;
-};
-
-struct CgBatch {
-    const CgInst *inst;
-    const CgTask *tasks;
-    const int *task_ptr;
-    unsigned *ws;
-    unsigned epoch_span;   // > barriers any group takes: group j uses epochs start + j*span + 1 ..
-    int ngroups;           // groups of two or more workgroups (ids 0 .. ngroups-1)
-};
-
-template <bool JACOBI, bool MIXED>
-__global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
-    const int g = blockIdx.x;
-    BarrierClock clk;
-    clk.start();
-    const unsigned e0 = ld_coh(bp.ws + SYNC_EPOCH);
-    for (int t = bp.task_ptr[g]; t < bp.task_ptr[g + 1]; ++t) {
-        const CgTask task = bp.tasks[t];
-        GroupSync gs;
-        // disjoint epoch ranges per group: a workgroup's flag left by an
-        // earlier group can never match a later group's epochs
-        gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span,
-                &clk);
-        CInst *in = (CInst *)(bp.inst + task.inst);
-        if (MIXED) cg_mixed_body<JACOBI>(*in, gs, task.rank, task.size);
-        else cg_f64_body<JACOBI>(in, gs, task.rank, task.size);
-    }
-    GroupSync all;
-    all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span, &clk);
-    all.gen = bp.ws + SYNC_GEN;
-    all.sync();
-    if (g == 0 && threadIdx.x == 0) st_coh(bp.ws + SYNC_EPOCH, all.epoch);
-    clk.publish(bp.ws);
-}
 
 // ---------------------------------------------------------------------------
 // Baseline kernels (one launch each per iteration).
@@ -1208,6 +444,37 @@ int cg_group_size(int cap, int64_t n) {
     return g;
 }
 
+// Matrices (by their device arrays, order, nonzeros and grid size) whose
+// slices the register-resident solver could not take: later solves of the
+// same matrix go straight to the memory-resident solver.  Only a hint: the
+// solver checks eligibility itself.
+struct NoregKey {
+    const void *rowptr, *colind;
+    int64_t n, nnz;
+    int G, device;
+};
+std::mutex g_noreg_mu;
+std::vector<NoregKey> g_noreg;
+
+bool noreg_known(const perks_csr *A, int G) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(g_noreg_mu);
+    for (const NoregKey &k : g_noreg)
+        if (k.rowptr == A->rowptr && k.colind == A->colind && k.n == A->n && k.nnz == A->nnz && k.G == G &&
+            k.device == dev)
+            return true;
+    return false;
+}
+
+void noreg_remember(const perks_csr *A, int G) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(g_noreg_mu);
+    if (g_noreg.size() >= 256) g_noreg.erase(g_noreg.begin());
+    g_noreg.push_back({A->rowptr, A->colind, A->n, A->nnz, G, dev});
+}
+
 struct Capture {
     const int *iters = nullptr;
     int n = 0;
@@ -1248,11 +515,27 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     PERKS_HIP_TRY(hipMemcpyAsync(pdev, &p, sizeof(CgInst), hipMemcpyHostToDevice, st));
     void *args[] = {&pdev, &ws};
     note_persistent_launch(G, nullptr);
-    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
-    if (e != hipSuccess) return launch_error(e);
     double h[8] = {0};
-    PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
-    PERKS_HIP_TRY(hipStreamSynchronize(st));
+    // FP64: first the solver with register-resident own rows when the rows
+    // per workgroup suggest they fit (it reports CG_STATUS_NOREG and leaves
+    // after its set-up when a slice does not)
+    bool done = false;
+    int reg_threads = 0, reg_rows = 0;
+    const void *fr = mixed ? nullptr : cg_reg_kernel(jac, &reg_threads, &reg_rows);
+    if (fr && (double)A->n / G <= 0.95 * reg_threads * reg_rows && !noreg_known(A, G)) {
+        hipError_t e = hipLaunchCooperativeKernel(fr, dim3(G), dim3(reg_threads), args, 0, st);
+        if (e != hipSuccess) return launch_error(e);
+        PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+        done = (int)h[1] != CG_STATUS_NOREG;
+        if (!done) noreg_remember(A, G);
+    }
+    if (!done) {
+        hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CG_THREADS), args, 0, st);
+        if (e != hipSuccess) return launch_error(e);
+        PERKS_HIP_TRY(hipMemcpyAsync(h, p.result, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+        PERKS_HIP_TRY(hipStreamSynchronize(st));
+    }
     const double lds = mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ;
     const double cached = std::min<double>((double)A->nnz, lds * G);
     const int status = result_from_words(h, G, A->nnz ? cached / (double)A->nnz : 0.0, out);

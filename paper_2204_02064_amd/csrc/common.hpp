@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
+#include <utility>
 
 #include "../../include/perks.h"
 
@@ -201,6 +203,16 @@ template <typename T, int N>
 __device__ __forceinline__ void settle(T (&a)[N]) {
 #pragma unroll
     for (int i = 0; i < N; ++i) asm volatile("" : "+v"(a[i]));
+}
+
+// Calls f(integral_constant<int, I>) for I = B .. E-1 (a compile-time loop:
+// every register-array index stays constant, whatever the unroller decides).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 // Keeps the compiler from moving memory operations across this point.  LDS

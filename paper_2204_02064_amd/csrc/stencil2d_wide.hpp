@@ -36,16 +36,6 @@
 
 namespace perks {
 
-// Calls f(integral_constant<int, I>) for I = B .. E-1 (a compile-time loop:
-// every register-array index stays constant, whatever the unroller decides).
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 template <typename T, int R>
 struct WideW {
     T w[(2 * R + 1) * (2 * R + 1)];   // [dy + R][dx + R]
