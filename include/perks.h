@@ -123,6 +123,25 @@ typedef struct {
 int perks_stencil_run(void *grid, const double *coeffs, perks_shape shape, int64_t steps,
                       perks_dtype dt, void *stream, const perks_tuning *tune);
 
+/*
+ * perks_stencil_run_noalloc -- perks_stencil_run for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The persistent radius-1 2D kernel
+ * (2d5pt or 2d9pt weights, any radius-1 2D pattern; the plan perks_stencil_run
+ * takes with tuning.kernel = 1: register and LDS rows, point-to-point halo
+ * words) runs with its barrier words and halo buffers in a fixed library
+ * array of 32 MiB per device (held until the process ends) instead of
+ * library-allocated scratch; the call makes no hipMalloc / hipFree.
+ *   Arguments as for perks_stencil_run (no tuning).
+ *   The first call on a device looks the array up and clears it (a fill
+ *   kernel on `stream`); later calls continue from the epochs it holds.
+ *   Calls that overlap in time on one device share the array and race.
+ * Returns PERKS_OK, PERKS_E_UNSUPPORTED for other patterns, 3D grids or a
+ * grid whose halo buffers do not fit the array (e.g. FP64 beyond about
+ * 3500 x 3500), or another error as perks_stencil_run. */
+int perks_stencil_run_noalloc(void *grid, const double *coeffs, perks_shape shape, int64_t steps, perks_dtype dt,
+                              void *stream);
+
 /* Same computation, host-looped: one kernel launch per step over ping-pong
  * buffers (the per-step-launch baseline the paper compares against, Sec. 3,
  * fig:exemodel left).  Bitwise identical result to perks_stencil_run. */

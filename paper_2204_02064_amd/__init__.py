@@ -89,6 +89,8 @@ def lib():
     dp = ctypes.POINTER(ctypes.c_double)
     L.perks_stencil_run.argtypes = [vp, dp, Shape, i64, i32, vp, ctypes.POINTER(Tuning)]
     L.perks_stencil_run_baseline.argtypes = [vp, dp, Shape, i64, i32, vp]
+    L.perks_stencil_run_noalloc.argtypes = [vp, dp, Shape, i64, i32, vp]
+    L.perks_stencil_run_noalloc.restype = ctypes.c_int
     L.perks_stencil_plan_query.argtypes = [dp, Shape, i32, ctypes.POINTER(Tuning), ctypes.POINTER(StencilPlan)]
     L.perks_stencil_autotune.argtypes = [dp, Shape, i32, i64, i32, vp, ctypes.POINTER(Tuning),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -207,6 +209,18 @@ def stencil_run(grid, weights, steps, tuning=None, stream=None):
     rc = lib().perks_stencil_run(ctypes.c_void_p(grid.data_ptr()), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  _shape_of(grid, r), int(steps), _dtype_code(grid), _stream_handle(stream),
                                  _tuning(tuning))
+    _check(rc)
+    return grid
+
+
+def stencil_run_noalloc(grid, weights, steps, stream=None):
+    """stencil_run of a 2D radius-1 pattern with no device allocation
+    (perks_stencil_run_noalloc: the library's fixed per-device array)."""
+    _check_grid(grid)
+    w, r = _coeff_array(weights, grid.dim())
+    rc = lib().perks_stencil_run_noalloc(ctypes.c_void_p(grid.data_ptr()),
+                                         w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _shape_of(grid, r),
+                                         int(steps), _dtype_code(grid), _stream_handle(stream))
     _check(rc)
     return grid
 

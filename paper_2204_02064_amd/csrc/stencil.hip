@@ -10,8 +10,56 @@
 #include "common.hpp"
 #include "stencil_api.hpp"
 
+// Scratch of perks_stencil_run_noalloc (barrier words, then face buffers):
+// one copy per device, alive until the process ends.  In host code this name
+// is a stand-in, not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.  It has external
+// linkage (in its own namespace): the runtime resolves only exported device
+// symbols, and an internal-linkage array is reported as an invalid symbol.
+// No kernel names it, so `used` keeps the device compiler from dropping it;
+// 256 spare bytes let the host round its address up to 256 bytes whatever
+// alignment the code object gives it.
+constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
+namespace perks_noalloc {
+__device__ __attribute__((used)) __align__(256) unsigned char scratch[NOALLOC_BYTES + 256];
+}
+
 namespace perks {
 namespace {
+
+// Zero fill of n 32-bit words (a kernel, not hipMemsetAsync: stream-ordered
+// and safe under graph capture).
+__global__ __launch_bounds__(256) void fill_zero_words(unsigned *w, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = 0u;
+}
+
+// Per-device address of `scratch`, looked up on the first call on a device
+// (with that device current), when the whole array is also cleared on the
+// caller's stream: the barrier and halo words then start at epoch 0, and
+// every later call continues the epochs the previous one left there.
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[64];
+
+int noalloc_scratch(hipStream_t st, void **out) {
+    int dev = -1;
+    PERKS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(PERKS_E_HIP, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(perks_noalloc::scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return set_error(PERKS_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        ptr = (void *)(((uintptr_t)ptr + 255) & ~(uintptr_t)255);
+        hipLaunchKernelGGL(fill_zero_words, dim3(1024), dim3(256), 0, st, (unsigned *)ptr, NOALLOC_BYTES / 4);
+        PERKS_HIP_TRY(hipGetLastError());
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return PERKS_OK;
+}
 
 // Patterns: radius 1 (2D 5-point star, 2D 9-point box, 3D 7-point star),
 // the radius-2..4 2D stars and radius-2 2D box, and the radius-2 3D star.
@@ -195,6 +243,25 @@ int perks_stencil_run(void *grid, const double *coeffs, perks_shape shape, int64
     perks_tuning remembered;
     if (!tune && tuned_for(kind, dt, shape, &remembered)) tune = &remembered;
     return run_dispatch(grid, coeffs, shape, steps, dt, kind, as_stream(stream), tune);
+}
+
+int perks_stencil_run_noalloc(void *grid, const double *coeffs, perks_shape shape, int64_t steps, perks_dtype dt,
+                              void *stream) {
+    int rc = check_common(grid, coeffs, shape, steps, dt);
+    if (rc) return rc;
+    Kind kind;
+    rc = classify(coeffs, shape, &kind);
+    if (rc) return rc;
+    if (shape.ndim != 2 || (kind != K_2D5 && kind != K_2D9))
+        return set_error(PERKS_E_UNSUPPORTED, "perks_stencil_run_noalloc runs 2D radius-1 patterns only");
+    if (steps == 0) return PERKS_OK;
+    hipStream_t st = as_stream(stream);
+    void *mem = nullptr;
+    rc = noalloc_scratch(st, &mem);
+    if (rc) return rc;
+    const bool box = kind == K_2D9;
+    return dt == PERKS_F64 ? run2d_in<double>((double *)grid, coeffs, shape, steps, box, st, mem, NOALLOC_BYTES)
+                           : run2d_in<float>((float *)grid, coeffs, shape, steps, box, st, mem, NOALLOC_BYTES);
 }
 
 int perks_stencil_run_baseline(void *grid, const double *coeffs, perks_shape shape, int64_t steps, perks_dtype dt,

@@ -840,12 +840,21 @@ void fill_weights(Weights2D<T> &W, const double *c) {
     for (int i = 0; i < 9; ++i) W.w[i] = (T)c[i];
 }
 
+// Bytes of face buffers (and whether they hold epoch-tagged words) that plan
+// `pl` needs for extents s.
 template <typename T>
-int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
-          const perks_tuning *tu) {
-    Plan2D pl;
-    int rc = plan2d<T>(s, box, tu, &pl);
-    if (rc) return rc;
+size_t faces2d_bytes(const perks_shape &s, const Plan2D &pl) {
+    // LL words double the footprint of a face element (data + epoch)
+    const size_t mult = pl.ll ? 2 : 1;
+    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx * mult, cb = (size_t)2 * (2 * pl.ntx + 2) * s.ny * mult;
+    return (rb + cb) * sizeof(T);
+}
+
+// Launches plan `pl` with the given face buffers (faces2d_bytes of them) and
+// barrier words (SYNC_BYTES); allocates nothing.
+template <typename T>
+int run2d_planned(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, const Plan2D &pl, T *faces,
+                  unsigned *sync, hipStream_t st) {
     Stencil2DParams<T> p{};
     p.grid = to_global(grid);
     p.nx = (int)s.nx;
@@ -860,18 +869,46 @@ int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bo
     p.cached = pl.cached;
     p.steps = steps;
     fill_weights(p.W, coeffs);
-    // LL words double the footprint of a face element (data + epoch)
     const size_t mult = pl.ll ? 2 : 1;
-    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx * mult, cb = (size_t)2 * (2 * pl.ntx + 2) * s.ny * mult;
-    // LL words and raw values never share a buffer (a raw value read as an
-    // LL word could carry any epoch)
-    T *faces = (T *)scratch(pl.ll ? SLOT_FACES_LL : SLOT_FACES, (rb + cb) * sizeof(T));
-    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
-    if (!faces || !sync) return PERKS_E_NOMEM;
+    const size_t rb = (size_t)2 * (2 * pl.nty + 2) * s.nx * mult;
     p.rowbuf = to_global(faces);
     p.colbuf = to_global(faces + rb);
     p.sync = sync;
     return launch_coop(pl.fn, pl.wgs, W2 * 64, &p, st);
+}
+
+template <typename T>
+int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+          const perks_tuning *tu) {
+    Plan2D pl;
+    int rc = plan2d<T>(s, box, tu, &pl);
+    if (rc) return rc;
+    // LL words and raw values never share a buffer (a raw value read as an
+    // LL word could carry any epoch)
+    T *faces = (T *)scratch(pl.ll ? SLOT_FACES_LL : SLOT_FACES, faces2d_bytes<T>(s, pl));
+    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!faces || !sync) return PERKS_E_NOMEM;
+    return run2d_planned<T>(grid, coeffs, s, steps, pl, faces, sync, st);
+}
+
+// run2d with the default plan (point-to-point halo words) in caller-provided
+// memory: `mem` (device) holds the barrier words (SYNC_BYTES, first) and the
+// face buffers; nothing is allocated.  PERKS_E_UNSUPPORTED when the plan
+// needs more than `cap` bytes.
+template <typename T>
+int run2d_in(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+             void *mem, size_t cap) {
+    Plan2D pl;
+    int rc = plan2d<T>(s, box, nullptr, &pl);
+    if (rc) return rc;
+    const size_t need = SYNC_BYTES + faces2d_bytes<T>(s, pl);
+    if (need > cap)
+        return set_error(PERKS_E_UNSUPPORTED, "the grid needs %zu bytes of scratch, more than the %zu available", need,
+                         cap);
+    unsigned *sync = (unsigned *)mem;
+    rc = run2d_planned<T>(grid, coeffs, s, steps, pl, (T *)((char *)mem + SYNC_BYTES), sync, st);
+    if (rc == PERKS_OK) note_persistent_launch(pl.wgs, sync);   // its barrier clock records are in mem
+    return rc;
 }
 
 // Many 2D grids in one launch: one tile height for all grids (the smallest

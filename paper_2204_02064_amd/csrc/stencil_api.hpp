@@ -11,6 +11,11 @@ int run2d(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bo
           const perks_tuning *tu);
 template <typename T>
 int plan2d_query(const perks_shape &shape, bool box, const perks_tuning *tune, perks_stencil_plan *plan);
+// run2d with the default plan, barrier words and face buffers in `mem` (cap
+// bytes, device); allocates nothing.
+template <typename T>
+int run2d_in(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+             void *mem, size_t cap);
 
 template <typename T>
 int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
