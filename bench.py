@@ -41,11 +41,30 @@ PEAK_HBM_GBS = 8000.0
 # from: a changed source reports null until measured again.
 MEASURED_TRAFFIC = {
     ("3d7pt", (256, 256, 256), "float64"): {
-        "bytes": 210.88e9,   # profiles/stencil3d_column_f64_256cubed.md
+        "bytes": 210.87e9,   # profiles/stencil3d_column_f64_256cubed.md
         "sources": ["paper_2204_02064_amd/csrc/stencil3d.hpp", "paper_2204_02064_amd/csrc/barrier.hpp",
                     "paper_2204_02064_amd/csrc/common.hpp", "paper_2204_02064_amd/csrc/stencil3d_f64.hip"],
-        "sha256": "2811941ef9a61ae29e316e1b3f98efdca5df4979459b3b1a221e40b906eea2d2",
+        "sha256": "ee20ecef5c24ecef834194060f5158fbebdda83634407ef87ea2ff5a27a5deea",
     },
+}
+
+
+# Fabric bytes per Jacobi step (FETCH_SIZE x2 + WRITE_SIZE x1, rocprofv3
+# --pmc) of the persistent launch and of the per-step baseline, default plans
+# (profiles/stencil_hbm_traffic_persistent_vs_per_step.md); reported while the
+# kernels' sources are unchanged (null otherwise).
+_CSRC = "paper_2204_02064_amd/csrc/"
+_SRC2 = [_CSRC + "stencil2d_wide.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
+_SRC3 = [_CSRC + "stencil3d.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
+STEP_TRAFFIC = {
+    ("2d5pt", "float64"): {"persistent": 11.5e6, "per_step": 174.3e6, "sources": _SRC2 + [_CSRC + "stencil2d_wide_f64.hip"],
+                           "sha256": "0a71b1a0543ebc2039c18b098c649fc32268b7e6b05941b2f56df643f68cd481"},
+    ("2d5pt", "float32"): {"persistent": 10.0e6, "per_step": 92.8e6, "sources": _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
+                           "sha256": "afddb6fcfb378bd24c0575ddf0acb6ec65fed5c67fcdab4ac1aea67cc9c11a53"},
+    ("3d7pt", "float64"): {"persistent": 210.9e6, "per_step": 407.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
+                           "sha256": "ee20ecef5c24ecef834194060f5158fbebdda83634407ef87ea2ff5a27a5deea"},
+    ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
+                           "sha256": "f3f7ebad3ad411f0756ee4300bab44ace441fdc793bc0b845e13a216f32479dd"},
 }
 
 
@@ -69,6 +88,22 @@ def measured_traffic(case):
     except OSError:
         return None
     return m["bytes"] if digest == m["sha256"] else None
+
+
+def step_traffic():
+    """Measured fabric bytes per Jacobi step, persistent vs per-step launch
+    (STEP_TRAFFIC), for the cases whose kernel sources are unchanged."""
+    out = {}
+    for (kind, dt), m in STEP_TRAFFIC.items():
+        try:
+            ok = sources_digest(m["sources"]) == m["sha256"]
+        except OSError:
+            ok = False
+        key = f"{kind} {dt}"
+        out[key] = ({"persistent_bytes": m["persistent"], "per_step_bytes": m["per_step"],
+                     "reduction": m["per_step"] / m["persistent"]} if ok else None)
+    return {"unit": "fabric bytes per Jacobi step (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)", "cases": out,
+            "source": "profiles/stencil_hbm_traffic_persistent_vs_per_step.md"}
 
 
 def log(*a):
@@ -174,6 +209,11 @@ def bench_cg(pk, torch, args):
                 rec[label] = {"seconds": t, "iters": info["iters"], "us_per_iter": t / max(1, info["iters"]) * 1e6,
                               "relres_true": info["relres_true"], "status": info["status"],
                               "outer": info.get("outer")}
+                if label == "persistent":
+                    bs = pk.barrier_stats()
+                    rec[label]["barrier"] = {"wait_share": bs["wait_share"],
+                                             "barriers_per_workgroup": bs["barriers"],
+                                             "wait_cycles_per_barrier": bs["wait_cycles"] / max(1, bs["barriers"])}
             rec["speedup"] = rec["baseline"]["seconds"] / rec["persistent"]["seconds"]
             log(f"CG {name} {rec['precision']} tol {tol:.0e}: persistent {rec['persistent']['seconds']*1e3:.2f} ms "
                 f"({rec['persistent']['iters']} it, {rec['persistent']['us_per_iter']:.1f} us/it)  baseline "
@@ -543,6 +583,13 @@ def main():
             r["baseline_gcells"] = cells / tb / 1e9
             r["speedup"] = r["persistent_gcells"] / r["baseline_gcells"]
 
+    # barrier clock of each persistent launch (one more untimed run per case)
+    for i, r in enumerate(results):
+        run_case(i)
+        bs = pk.barrier_stats()
+        r["barrier"] = {"wait_share": bs["wait_share"], "barriers_per_workgroup": bs["barriers"],
+                        "wait_cycles_per_barrier": bs["wait_cycles"] / max(1, bs["barriers"])}
+
     for r in results:
         log(f"{r['case']:28s} persistent {r['persistent_gcells']:8.1f} GCells/s"
             + (f"  baseline {r['baseline_gcells']:8.1f} GCells/s  x{r['speedup']:.2f}" if "speedup" in r else "")
@@ -620,6 +667,7 @@ def main():
             else:
                 out["fp32"]["baseline_value"] = base
                 out["fp32"]["speedup_vs_per_step_launch"] = out["fp32"]["value"] / base if out["fp32"]["value"] else None
+    out["traffic_per_step"] = step_traffic()
     if not args.no_small:
         out["config_256"] = bench_small(pk, torch, args)
     if not args.no_wide:
