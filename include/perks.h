@@ -185,14 +185,26 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
 
 /* Sparse matrix in CSR form (0-based, 32-bit indices, column indices of a row
  * in any order).  rowptr, colind, val are device pointers; val holds float or
- * double per `dt`. */
+ * double per `dt`.
+ * spmv selects the SpMV layout of the persistent solvers (the per-matrix
+ * choice of what to keep on chip, Sec. 4.3.2):
+ *   0  the library's choice: sliced ELL when each 64-row chunk's padding to
+ *      its longest row costs at most a quarter more entries, then the solver
+ *      with each workgroup's r, p, q in registers (when its rows fit) and the
+ *      first part of its slice of A in LDS; irregular rows: sliced ELL over
+ *      the rows sorted by length, else CSR; A's slice prefix in LDS;
+ *   1  the same without the register-resident solver;
+ *   2  merge-path SpMV (Merrill and Garland's merge-based CSR SpMV, the one
+ *      the paper's CG uses, Sec. 4.3.1): each workgroup's rows and nonzeros
+ *      split into chunks of 8 path items, the chunk starts searched once and
+ *      kept, A's slice prefix in LDS. */
 typedef struct {
     int64_t n, nnz;
     const int32_t *rowptr;
     const int32_t *colind;
     const void *val;
     perks_dtype dt;
-    int32_t reserved;
+    int32_t spmv;
 } perks_csr;
 
 typedef struct {

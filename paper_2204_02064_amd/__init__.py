@@ -52,7 +52,7 @@ class StencilPlan(ctypes.Structure):
 class Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dt", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("spmv", ctypes.c_int32)]
 
 
 class CgResult(ctypes.Structure):
@@ -289,10 +289,16 @@ def device_info():
             "hbm_bytes": d.hbm_bytes, "arch": d.arch.decode()}
 
 
-class CsrMatrix:
-    """Device CSR matrix (int32 rowptr/colind, float64 values) as torch tensors."""
+SPMV = {None: 0, "auto": 0, "sell": 1, "merge": 2}
 
-    def __init__(self, rowptr, colind, values, device="cuda"):
+
+class CsrMatrix:
+    """Device CSR matrix (int32 rowptr/colind, float64 values) as torch tensors.
+    ``spmv`` picks the persistent solvers' SpMV layout (perks_csr.spmv):
+    "auto" (the library's choice), "sell" (sliced ELL / CSR, vectors in
+    memory) or "merge" (merge-path SpMV)."""
+
+    def __init__(self, rowptr, colind, values, device="cuda", spmv="auto"):
         import torch
 
         def dev(a, npt, tt):
@@ -304,10 +310,13 @@ class CsrMatrix:
         self.values = dev(values, np.float64, torch.float64)
         self.n = self.rowptr.numel() - 1
         self.nnz = self.colind.numel()
+        if spmv not in SPMV:
+            raise ValueError(f"spmv must be one of {sorted(k for k in SPMV if k)}")
+        self.spmv = spmv
 
     def _struct(self):
         return Csr(self.n, self.nnz, self.rowptr.data_ptr(), self.colind.data_ptr(), self.values.data_ptr(),
-                   PERKS_F64 if self.values.dtype.itemsize == 8 else PERKS_F32, 0)
+                   PERKS_F64 if self.values.dtype.itemsize == 8 else PERKS_F32, SPMV[self.spmv])
 
 
 def _cg_result(r, precision):

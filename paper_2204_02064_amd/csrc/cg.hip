@@ -306,6 +306,7 @@ int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int 
     if (A->n >= (int64_t(1) << 31) - 1 || A->nnz >= (int64_t(1) << 31) - 1)
         return set_error(PERKS_E_INVAL, "32-bit CSR indices limit n and nnz to < 2^31");
     if (A->dt != PERKS_F64) return set_error(PERKS_E_UNSUPPORTED, "this entry point solves FP64 matrices");
+    if (A->spmv < 0 || A->spmv > 2) return set_error(PERKS_E_INVAL, "spmv must be 0, 1 or 2 (got %d)", A->spmv);
     if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(PERKS_E_INVAL, "tol must be finite and >= 0");
     if (maxit < 0) return set_error(PERKS_E_INVAL, "maxit must be >= 0");
     if (precond != PERKS_PRECOND_NONE && precond != PERKS_PRECOND_JACOBI)
@@ -410,11 +411,18 @@ int launch_error(hipError_t e) {
                      hipGetErrorString(e));
 }
 
-const void *persistent_fn(bool jac, bool mixed) {
-    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_persistent<true, true>)
-                          : reinterpret_cast<const void *>(&cg_persistent<false, true>);
-    return jac ? reinterpret_cast<const void *>(&cg_persistent<true, false>)
-               : reinterpret_cast<const void *>(&cg_persistent<false, false>);
+template <bool MERGE>
+const void *persistent_fn_t(bool jac, bool mixed) {
+    if (mixed) return jac ? reinterpret_cast<const void *>(&cg_persistent<true, true, MERGE>)
+                          : reinterpret_cast<const void *>(&cg_persistent<false, true, MERGE>);
+    return jac ? reinterpret_cast<const void *>(&cg_persistent<true, false, MERGE>)
+               : reinterpret_cast<const void *>(&cg_persistent<false, false, MERGE>);
+}
+
+// The persistent solver kernel; the merge-path SpMV is built into separate
+// instances, so the other layouts do not carry its registers.
+const void *persistent_fn(bool jac, bool mixed, bool merge = false) {
+    return merge ? persistent_fn_t<true>(jac, mixed) : persistent_fn_t<false>(jac, mixed);
 }
 
 const void *batched_fn(bool jac, bool mixed) {
@@ -483,7 +491,7 @@ struct Capture {
 
 int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, bool mixed,
                         hipStream_t st, perks_cg_result *out, const Capture &capture = Capture()) {
-    const void *fn = persistent_fn(jac, mixed);
+    const void *fn = persistent_fn(jac, mixed, A->spmv == 2);
     int cap = 0;
     int rc = cg_capacity(fn, &cap);
     if (rc) return rc;
@@ -495,6 +503,7 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     if (!ws) return PERKS_E_NOMEM;
     p.rowptr = A->rowptr;
     p.colind = A->colind;
+    p.spmv = A->spmv;
     p.val = (const double *)A->val;
     p.b = (const double *)b;
     p.x = (double *)x;
@@ -521,7 +530,7 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     // after its set-up when a slice does not)
     bool done = false;
     int reg_threads = 0, reg_rows = 0;
-    const void *fr = mixed ? nullptr : cg_reg_kernel(jac, &reg_threads, &reg_rows);
+    const void *fr = (mixed || A->spmv != 0) ? nullptr : cg_reg_kernel(jac, &reg_threads, &reg_rows);
     if (fr && (double)A->n / G <= 0.95 * reg_threads * reg_rows && !noreg_known(A, G)) {
         hipError_t e = hipLaunchCooperativeKernel(fr, dim3(G), dim3(reg_threads), args, 0, st);
         if (e != hipSuccess) return launch_error(e);
@@ -927,6 +936,7 @@ int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *cons
             p.result = (double *)(base + o_res) + 8 * (size_t)i;
             p.rowptr = As[i].rowptr;
             p.colind = As[i].colind;
+            p.spmv = As[i].spmv;
             p.val = (const double *)As[i].val;
             p.b = (const double *)bs[i];
             p.x = (double *)xs[i];

@@ -42,6 +42,7 @@ struct CgInst {
     double *cap_x, *cap_r;   // FP64 solver: x and r after the iterations listed in cap_iters
     const int *cap_iters;    // ascending iteration counts (device)
     int ncap;
+    int spmv;                // SpMV layout requested: 0 the library's choice, 1 sliced ELL / CSR, 2 merge path
     int n;
     int nnz;
     int maxit;
@@ -185,14 +186,26 @@ struct Slice {
     int r0, r1, rc, kbase, nnz, kc, L;
     int sell, nch, cc, sbase;
     const int *perm;   // sliced-ELL row order (rows sorted by length), or NULL: natural order
+    int merge;         // merge-path layout (see spmv_merge)
+    int nchunks;       // merge path: chunks of MERGE_IPT items
+    const int *mrow;   // merge path: first row (slice-relative) of chunk c, c = 0 .. nchunks
 };
+
+// Merge-path SpMV (Merrill and Garland's merge-based CSR SpMV, the SpMV the
+// paper's CG uses, Sec. 4.3.1): the slice's row ends and nonzeros form one
+// path of nrows + nnz items, cut into chunks of MERGE_IPT consecutive items,
+// one chunk per thread per tile of CG_THREADS chunks.  Each chunk's start
+// (row, nonzero) is found by a binary search on the merge diagonal once, at
+// kernel start, and kept in memory for every later SpMV (A is static, so the
+// search results are too: Sec. 4.3.2).
+constexpr int MERGE_IPT = 8;
 
 // Entries the packed arrays of one problem need for G workgroups.
 __host__ __device__ inline size_t sell_capacity(int64_t nnz, int G) {
     return (size_t)(nnz + nnz / 4) + 64 * (size_t)G + 64;
 }
 
-template <typename T>
+template <typename T, bool MERGE = false>
 __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int *scol, int g, int G) {
     Slice sl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -204,8 +217,11 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
     sl.nch = (sl.r1 - sl.r0 + 63) / 64;
     sl.sbase = (int)(sl.kbase + sl.kbase / 4) + 64 * g;
     __syncthreads();   // the previous problem of this workgroup is done with LDS
+    sl.merge = MERGE && p.spmv == 2 && scol != nullptr;
+    sl.nchunks = 0;
+    sl.mrow = nullptr;
     // chunk lengths (longest row of each chunk), then their offsets
-    sl.sell = sval != nullptr && sl.nch <= SELL_MAX_CHUNKS;
+    sl.sell = !sl.merge && sval != nullptr && sl.nch <= SELL_MAX_CHUNKS;
     if (sl.sell) {
         for (int c = wave; c < sl.nch; c += CG_WAVES) {
             const int i = sl.r0 + 64 * c + lane;
@@ -228,7 +244,8 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
     }
     sl.perm = nullptr;
     const int nrows = sl.r1 - sl.r0;
-    if (!sl.sell && sval != nullptr && p.sperm != nullptr && sl.nch <= SELL_MAX_CHUNKS && nrows <= LdsA<T>::cap) {
+    if (!sl.merge && !sl.sell && sval != nullptr && p.sperm != nullptr && sl.nch <= SELL_MAX_CHUNKS &&
+        nrows <= LdsA<T>::cap) {
         // Irregular rows: sliced ELL over the slice's rows sorted by length,
         // longest first (SELL-C-sigma with sigma = the slice), so that each
         // chunk's rows have nearly equal lengths.  A stable counting sort on
@@ -342,6 +359,27 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
             LdsA<T>::col(k) = p.colind[sl.kbase + k];
         }
         sl.rc = cached_rows_end(p.rowptr, sl.r0, sl.r1, sl.kbase, sl.kc);
+        if (sl.merge) {
+            // chunk c starts on merge diagonal d = c * MERGE_IPT: its first row is
+            // the number of rows whose end comes before item d, the smallest i
+            // with end(i) + i >= d (end(i) = rowptr[r0 + i + 1] - kbase).  Stored
+            // in this problem's otherwise unused sliced-ELL index array, at an
+            // offset no other workgroup's chunks reach.
+            const long long lw = (long long)nrows + sl.nnz;
+            sl.nchunks = (int)((lw + MERGE_IPT - 1) / MERGE_IPT);
+            int *mrow = scol + (size_t)(((long long)sl.r0 + sl.kbase) / MERGE_IPT) + 2 * (size_t)g;
+            for (int c = tid; c <= sl.nchunks; c += CG_THREADS) {
+                const long long d = std::min((long long)c * MERGE_IPT, lw);
+                int lo = 0, hi = nrows;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((long long)(p.rowptr[sl.r0 + mid + 1] - sl.kbase) + mid < d) lo = mid + 1;
+                    else hi = mid;
+                }
+                mrow[c] = lo;
+            }
+            sl.mrow = mrow;
+        }
     }
     __syncthreads();   // also publishes the packed arrays within the workgroup
     return sl;
@@ -612,11 +650,120 @@ __device__ __forceinline__ void block_sum_ref(double (&v)[CG_VT][K]) {
     __syncthreads();
 }
 
+__shared__ double cg_merge_f[CG_WAVES];
+__shared__ double cg_merge_s[CG_WAVES];
+
+// y_i for the slice's rows by the merge path.  Per tile, thread t takes chunk
+// c = tile + t: it loads the chunk's nonzeros (at most MERGE_IPT; from the LDS
+// copy of A for entries below kc) and their gathers at once, then walks the
+// chunk's items in path order: a nonzero adds a * v(col) to the running sum,
+// a row end completes that row.  A row that began in an earlier chunk gets
+// that chunk's partial sum through a segmented scan over the tile's chunks in
+// thread order (the carry of the chunk before the first row end, plus the
+// carries of the chunks before it that completed no row) and the tile's carry
+// from the tile before; rows completed inside a chunk go straight to sink.
+// Every sum's order depends only on the matrix and the chunk size.
+template <typename T, typename F, typename S>
+__device__ __forceinline__ void spmv_merge(CInst &p, const Slice &sl, const T *val, F fetch, S sink) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nrows = sl.r1 - sl.r0;
+    const long long lw = (long long)nrows + sl.nnz;
+    const int *rowend = p.rowptr + sl.r0 + 1;   // rowend[i] - kbase: end of row i within the slice
+    T tile_carry = T(0);
+    for (int c0 = 0; c0 < sl.nchunks; c0 += CG_THREADS) {
+        const int c = c0 + tid;
+        int i = 0, i1 = 0, j = 0, j1 = 0;
+        if (c < sl.nchunks) {
+            i = sl.mrow[c];
+            i1 = sl.mrow[c + 1];
+            j = (int)((long long)c * MERGE_IPT - i);
+            j1 = (int)(std::min((long long)(c + 1) * MERGE_IPT, lw) - i1);
+        }
+        T a[MERGE_IPT], xv[MERGE_IPT];
+        int cidx[MERGE_IPT];
+#pragma unroll
+        for (int k = 0; k < MERGE_IPT; ++k) {
+            a[k] = T(0);
+            cidx[k] = 0;
+            const int e = j + k;
+            if (e < j1) {
+                if (e < sl.kc) {
+                    a[k] = LdsA<T>::val(e);
+                    cidx[k] = LdsA<T>::col(e);
+                } else {
+                    a[k] = val[sl.kbase + e];
+                    cidx[k] = p.colind[sl.kbase + e];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MERGE_IPT; ++k) xv[k] = j + k < j1 ? fetch(cidx[k]) : T(0);
+        T acc = T(0), first_val = T(0);
+        int first_row = -1;
+        int iend = i < i1 ? rowend[i] - sl.kbase : 0x7fffffff;
+        auto complete = [&](int r) {
+            if (first_row < 0) {
+                first_row = r;
+                first_val = acc;
+            } else {
+                sink(sl.r0 + r, acc);
+            }
+            acc = T(0);
+        };
+#pragma unroll
+        for (int k = 0; k < MERGE_IPT; ++k) {
+            if (j + k < j1) {
+                while (i < i1 && iend <= j + k) {
+                    complete(i);
+                    ++i;
+                    iend = i < i1 ? rowend[i] - sl.kbase : 0x7fffffff;
+                }
+                acc = fma_t(a[k], xv[k], acc);
+            }
+        }
+        while (i < i1) {   // rows ending after the chunk's last nonzero
+            complete(i);
+            ++i;
+        }
+        // segmented scan of (completed a row, carry) over the tile's chunks
+        bool f = first_row >= 0;
+        T sc = acc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T su = __shfl_up(sc, off, 64);
+            const int fu = __shfl_up((int)f, off, 64);
+            if (lane >= off) {
+                if (!f) sc = su + sc;
+                f = f || fu;
+            }
+        }
+        // exclusive value within the wave
+        T ex_s = __shfl_up(sc, 1, 64);
+        bool ex_f = __shfl_up((int)f, 1, 64) != 0;
+        if (lane == 63) {
+            cg_merge_f[wave] = f ? 1.0 : 0.0;
+            cg_merge_s[wave] = (double)sc;
+        }
+        __syncthreads();
+        // carry entering this wave: the tile carry, then waves 0 .. wave-1
+        T pre = tile_carry;
+        for (int w = 0; w < wave; ++w) pre = cg_merge_f[w] != 0.0 ? (T)cg_merge_s[w] : pre + (T)cg_merge_s[w];
+        T all = pre;
+        for (int w = wave; w < CG_WAVES; ++w) all = cg_merge_f[w] != 0.0 ? (T)cg_merge_s[w] : all + (T)cg_merge_s[w];
+        const T incoming = lane == 0 ? pre : (ex_f ? ex_s : pre + ex_s);
+        if (first_row >= 0) sink(sl.r0 + first_row, incoming + first_val);
+        tile_carry = all;
+        __syncthreads();   // the wave sums are read before the next tile writes them
+    }
+}
+
 // SpMV over the workgroup's rows in whichever layout the slice uses.
-template <int U, typename T, typename F, typename S>
+template <int U, bool MERGE, typename T, typename F, typename S>
 __device__ __forceinline__ void spmv_slice(CInst &p, const Slice &sl, const T *val, const T *sval,
                                            const int *scol, F fetch, S sink) {
-    if (sl.sell) {
+    if (MERGE && sl.merge) {
+        if constexpr (MERGE) spmv_merge(p, sl, val, fetch, sink);
+    } else if (sl.sell) {
         // chunk c on wave c % CG_WAVES, whether it is held in LDS or not: in
         // natural order thread tid computes rows r0 + tid + CG_THREADS * j
         const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -831,14 +978,14 @@ __device__ __forceinline__ void cg_f64_reg(CInst *pin, Sync &gs, const int g, co
 // own rows and a third barrier publishes it.  When the
 // recursive residual meets tol the true residual is recomputed; if it fails,
 // CG restarts from the current x while iterations remain.
-template <bool JACOBI, class Sync>
+template <bool JACOBI, bool MERGE, class Sync>
 __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, const int G) {
     // The problem is read from global memory through a pointer laundered at
     // every phase: its fields are reloaded (scalar loads) instead of being
     // kept live in scalar registers across the whole solve.
     CInst *pp = opaque(pin);
     const int tid = threadIdx.x;
-    const Slice sl = load_slice(*pp, pp->val, pp->sval64, pp->scol, g, G);
+    const Slice sl = load_slice<double, MERGE>(*pp, pp->val, pp->sval64, pp->scol, g, G);
     const int r0 = sl.r0, r1 = sl.r1;
     if (JACOBI) {
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
@@ -856,7 +1003,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
         pp = opaque(pin);
         // phase 0: r = b - A x, z, p_{-1} = 0, partials b.b, r.z, r.r
         double acc0[3] = {0.0, 0.0, 0.0};
-        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
+        spmv_slice<CG_U, MERGE>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
                         [&](int i, double s) { pp->q[i] = s; });
         __syncthreads();
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
@@ -899,7 +1046,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
             double *pn = pp->p;
             for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fma(beta, pn[i], zsrc[i]));
             gs.template sync<true>();
-            spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
+            spmv_slice<CG_U, MERGE>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pn[c]; },
                             [&](int i, double s) {
                                 pp->q[i] = s;
                                 acc1[0] = __builtin_fma(pn[i], s, acc1[0]);
@@ -954,7 +1101,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
         pp = opaque(pin);
         double acc3[1] = {0.0};
         gs.template sync<true>();
-        spmv_slice<CG_U>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
+        spmv_slice<CG_U, MERGE>(*pp, sl, pp->val, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
                         [&](int i, double s) {
                             const double d = pp->b[i] - s;
                             acc3[0] = __builtin_fma(d, d, acc3[0]);
@@ -992,7 +1139,7 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
 // each workgroup's slice of A is made by the workgroup itself (global copy +
 // LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
 // nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
-template <bool JACOBI, class Sync>
+template <bool JACOBI, bool MERGE, class Sync>
 __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, const int G) {
     const int tid = threadIdx.x;
     {
@@ -1001,7 +1148,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
         const int s1 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g + 1, G)];
         for (int k = s0 + tid; k < s1; k += CG_THREADS) p.val32[k] = (float)p.val[k];
     }
-    const Slice sl = load_slice(p, (const float *)p.val32, p.sval32, p.scol, g, G);   // its barriers publish val32
+    const Slice sl = load_slice<float, MERGE>(p, (const float *)p.val32, p.sval32, p.scol, g, G);   // its barriers publish val32
     const int r0 = sl.r0, r1 = sl.r1, kbase = sl.kbase, L = sl.L;
     double accb[1] = {0.0};
     for (int i = r0 + tid; i < r1; i += CG_THREADS) {
@@ -1080,7 +1227,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             float *pn = p.p32;
             for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pn + i, __builtin_fmaf(bf, pn[i], zsrc[i]));
             gs.template sync<true>();
-            spmv_slice<CG_U>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
+            spmv_slice<CG_U, MERGE>(p, sl, (const float *)p.val32, (const float *)p.sval32, p.scol,
                             [&](int c) { return pn[c]; },
                             [&](int i, float sv) {
                                 p.q32[i] = sv;
@@ -1136,15 +1283,15 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
 }
 
 // One problem on the whole grid.
-template <bool JACOBI, bool MIXED>
+template <bool JACOBI, bool MIXED, bool MERGE>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
     BarrierClock clk;
     clk.start();
     GroupSync gs;
     gs.init_grid(ws, &clk);
     CInst *in = (CInst *)pin;
-    if (MIXED) cg_mixed_body<JACOBI>(*in, gs, blockIdx.x, gridDim.x);
-    else cg_f64_body<JACOBI>(in, gs, blockIdx.x, gridDim.x);
+    if (MIXED) cg_mixed_body<JACOBI, MERGE>(*in, gs, blockIdx.x, gridDim.x);
+    else cg_f64_body<JACOBI, MERGE>(in, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
     clk.publish(ws);
 }
@@ -1198,8 +1345,8 @@ __global__ __launch_bounds__(CG_THREADS) void cg_batched(CgBatch bp) {
         gs.init(bp.ws, g - task.rank, task.group, task.rank, task.size, e0 + (unsigned)task.group * bp.epoch_span,
                 &clk);
         CInst *in = (CInst *)(bp.inst + task.inst);
-        if (MIXED) cg_mixed_body<JACOBI>(*in, gs, task.rank, task.size);
-        else cg_f64_body<JACOBI>(in, gs, task.rank, task.size);
+        if (MIXED) cg_mixed_body<JACOBI, false>(*in, gs, task.rank, task.size);
+        else cg_f64_body<JACOBI, false>(in, gs, task.rank, task.size);
     }
     GroupSync all;
     all.init(bp.ws, 0, 0, g, gridDim.x, e0 + (unsigned)bp.ngroups * bp.epoch_span, &clk);

@@ -50,8 +50,8 @@ def _true_relres(rp, ci, v, b, x):
     return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
 
 
-def _solve(pk, rp, ci, v, b, tol, maxit=5000, precond=None, baseline=False, x0=None):
-    A = pk.CsrMatrix(rp, ci, v)
+def _solve(pk, rp, ci, v, b, tol, maxit=5000, precond=None, baseline=False, x0=None, spmv="auto"):
+    A = pk.CsrMatrix(rp, ci, v, spmv=spmv)
     bd = to_dev(b)
     xd = to_dev(np.zeros_like(b) if x0 is None else x0)
     fn = pk.cg_solve_baseline if baseline else pk.cg_solve
@@ -188,3 +188,63 @@ def test_random_spd_one_million_rows_jacobi(pk, baseline):
     assert info["status"] == "converged" and oinfo["status"] == "converged"
     assert _true_relres(rp, ci, v, b, x) <= 1e-10
     assert _iters_close(info["iters"], oinfo["iters"]), (info["iters"], oinfo["iters"])
+
+
+# ---------------------------------------------------------------------------
+# Merge-path SpMV (perks_csr.spmv = 2) and the vectors-in-memory sliced ELL
+# (spmv = 1): the same parity bar.  Sizes give every workgroup several tiles of
+# merge-path chunks (the random matrix: about 1,000 rows and 21,000 nonzeros
+# per workgroup, 1024 threads x 8 items per tile) and rows that span chunks,
+# threads and tiles (the longest random rows have up to 200 entries).
+
+@pytest.mark.parametrize("spmv", ["merge", "sell"])
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d", "random", "random_big"])
+def test_spmv_layouts_match_oracle(pk, spmv, precond, case):
+    if case == "poisson2d":
+        rp, ci, v = workloads.poisson_csr(90, 2)
+    elif case == "poisson3d":
+        rp, ci, v = workloads.poisson_csr(24, 3)
+    elif case == "random":
+        rp, ci, v = workloads.random_spd_csr(30000, seed=1)
+    else:
+        rp, ci, v = workloads.random_spd_csr(100000, seed=2)
+    if case == "random_big" and precond is None:
+        precond = "jacobi"   # unpreconditioned CG needs thousands of iterations here
+    n = rp.size - 1
+    b = workloads.rhs_uniform(n, seed=0)
+    print(f"spmv {spmv} {case} precond {precond}", flush=True)
+    x, info = _solve(pk, rp, ci, v, b, 1e-10, precond=precond, spmv=spmv)
+    xo, oinfo = oracle.cg(rp, ci, v, b, tol=1e-10, maxit=5000, precond=precond)
+    assert info["status"] == "converged" and oinfo["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, x) <= 1e-10
+    assert _iters_close(info["iters"], oinfo["iters"]), (info["iters"], oinfo["iters"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_merge_path_spmv_single_iteration_is_the_product(pk):
+    """One CG iteration from x0 = 0 on a diagonal-dominant random matrix
+    gives x1 = alpha r0 with alpha = (r.r) / (r.Ar): the merge-path SpMV's A r
+    enters only through alpha, so x1 matches the oracle's product-based value
+    to rounding; the rows include ones longer than a chunk and a tile."""
+    rp, ci, v = workloads.random_spd_csr(50000, seed=3, max_degree=200)
+    n = rp.size - 1
+    b = workloads.rhs_uniform(n, seed=1)
+    x, info = _solve(pk, rp, ci, v, b, 1e-30, maxit=1, spmv="merge")
+    assert info["iters"] == 1
+    Ab = oracle.spmv(rp, ci, v, b)
+    alpha = float(np.dot(b, b) / np.dot(b, Ab))
+    np.testing.assert_allclose(x, alpha * b, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+def test_merge_path_mixed_precision(pk, precond):
+    rp, ci, v = workloads.random_spd_csr(30000, seed=1)
+    n = rp.size - 1
+    b = workloads.rhs_uniform(n, seed=0)
+    A = pk.CsrMatrix(rp, ci, v, spmv="merge")
+    bd, xd = to_dev(b), to_dev(np.zeros(n))
+    info = pk.cg_solve(A, bd, xd, tol=1e-8, maxit=5000, precond=precond, precision="mixed")
+    torch.cuda.synchronize()
+    assert info["status"] == "converged"
+    assert _true_relres(rp, ci, v, b, xd.cpu().numpy()) <= 1e-8
