@@ -127,6 +127,39 @@ def test_grid_barrier_and_point_to_point_sync_agree_bitwise(pk, kind, shape):
     assert rel_err(a, oracle.stencil(g, w, 21)) <= 1e-12
 
 
+_XCD_OFF = ("halo words within one XCD's L2 (sync 3) are not in the library: a build of that mode (8 workgroups "
+            "launched per working one, words moved with L1-bypassing loads and stores) did not finish on 2d5pt "
+            "256^2 FP64 with 16 working workgroups, twice; the cause was not found and the mode was taken out")
+
+
+@pytest.mark.skip(reason=_XCD_OFF)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("kind,shape", [("2d5pt", (256, 256)), ("2d9pt", (130, 389)), ("2d5pt", (70, 1000)),
+                                        ("2d9pt", (5, 3))])
+def test_xcd_local_halo_words_agree_bitwise(pk, dtype, kind, shape):
+    # sync=3: the point-to-point halo words kept in one XCD's L2 (8 workgroups
+    # launched per working one); the same arithmetic as sync=2
+    g = workloads.stencil_grid(shape, seed=12).astype(dtype)
+    w = workloads.stencil_weights(kind)
+    tt = getattr(torch, dtype)
+    print(f"xcd-local {kind} {shape} {dtype}", flush=True)
+    assert pk.stencil_plan(shape, w, dtype, tuning={"sync": 3})["sync"] == 3
+    for steps in (1, 2, 37):
+        a = _run(pk, g, w, steps, tt, tuning={"sync": 3})
+        b = _run(pk, g, w, steps, tt, tuning={"sync": 2})
+        np.testing.assert_array_equal(a, b, err_msg=f"steps {steps}")
+    gd = g.astype(np.float64)
+    wd = w.astype(np.float32).astype(np.float64) if dtype == "float32" else w
+    assert rel_err(a, oracle.stencil(gd, wd, 37)) <= (1e-12 if dtype == "float64" else 1e-5)
+
+
+def test_xcd_local_mode_is_refused(pk):
+    # sync 3 is not a mode of this library: the plan must refuse it
+    w = workloads.stencil_weights("2d5pt")
+    with pytest.raises(RuntimeError):
+        pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 3})
+
+
 def test_repeated_launches_reuse_epochs_safely(pk):
     # consecutive persistent launches on different shapes share the face
     # buffers; stale words must never be taken for current ones
@@ -239,6 +272,7 @@ def test_untuned_small_grids_keep_the_radius1_kernel(pk):
     (point-to-point halo words); the 256^2 100-step configuration runs on it."""
     w = workloads.stencil_weights("2d5pt")
     assert pk.stencil_plan((256, 256), w, "float64")["sync"] == 2
+    assert pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 2})["sync"] == 2
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"kernel": 2})["sync"] == 1
 
 
