@@ -129,17 +129,21 @@ def cg(rowptr, colind, values, b, x0=None, tol=1e-10, maxit=5000, precond=None):
                "restarts": int(out[3]), "status": CG_STATUS[st]}
 
 
-MIXED_INNER_TOL = 1e-4   # default inner (FP32) relative reduction per outer step
-MIXED_MAX_OUTER = 30
+MIXED_UPDATE_TOL = 0.3   # fall of the FP32 recursive residual that triggers an FP64 replacement
+MIXED_MAX_OUTER = 100    # replacements allowed (after the first residual)
+MIXED_STALL = 3          # replacements in a row without a new smallest true residual
 
 
 def cg_mixed(rowptr, colind, values, b, x0=None, tol=1e-8, maxit=5000, precond=None,
-             inner_tol=MIXED_INNER_TOL, max_outer=MIXED_MAX_OUTER):
-    """Mixed-precision CG: FP64 iterative refinement around an FP32 CG.
+             update_tol=MIXED_UPDATE_TOL, max_outer=MIXED_MAX_OUTER):
+    """Mixed-precision CG: one FP32 CG recurrence whose residual is replaced
+    by the true FP64 residual of an FP64 iterate whenever it has fallen by
+    ``update_tol`` (the direction is kept across replacements).
 
-    Returns ``(x, info)`` with ``info = {iters (total inner), relres_true,
-    outer, status, history}``; ``history[j]`` is the true relative residual
-    before outer step j.
+    Returns ``(x, info)`` with ``info = {iters (FP32 iterations),
+    relres_true, outer (replacements after the first residual), status,
+    history}``; ``history[j]`` is the true relative residual at the j-th
+    residual computation (``history[0]`` that of x0).
     """
     rp = np.ascontiguousarray(rowptr, dtype=np.int32)
     ci = np.ascontiguousarray(colind, dtype=np.int32)
@@ -150,7 +154,7 @@ def cg_mixed(rowptr, colind, values, b, x0=None, tol=1e-8, maxit=5000, precond=N
     hist = np.full(max_outer + 1, np.nan)
     pc = {None: 0, "none": 0, "jacobi": 1}[precond]
     st = _load().oracle_cg_mixed(n, _ptr(rp, _i32p), _ptr(ci, _i32p), _ptr(v), _ptr(b), _ptr(x),
-                                 float(tol), int(maxit), pc, float(inner_tol), int(max_outer),
+                                 float(tol), int(maxit), pc, float(update_tol), int(max_outer),
                                  _ptr(out), _ptr(hist))
     if st < 0:
         raise ValueError("oracle_cg_mixed rejected its arguments")

@@ -229,31 +229,49 @@ int oracle_chol_solve(int64_t n, const double *A, const double *b, double *x)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Mixed-precision conjugate gradient with FP64 iterative refinement.  The
+/* Mixed-precision conjugate gradient with FP64 residual replacement.  The
  * paper computes CG in one precision; this is the mixed-precision extension
- * of its CG solver, so every choice below is a reading, not the paper's:
+ * of its CG solver, so every choice below is a reading, not the paper's.
+ * One CG recurrence runs in FP32; at chosen points its recursive residual is
+ * replaced by the true residual computed in FP64 from an FP64 iterate
+ * ("reliable updates": Sleijpen and van der Vorst 1996; van der Vorst and
+ * Ye 2000), and the search direction is kept across the replacement, so the
+ * Krylov space built so far is not thrown away:
  *
- *   outer (FP64):  r = b - A x;  stop when ||r|| <= tol ||b||;
- *                  solve A d = r approximately in FP32;  x = x + d.
- *   inner (FP32):  CG on A32 d = r32 with A32 = float(A), r32 = float(s r)
- *                  for a power-of-two s ~ 1/||r|| (exact scaling, keeps FP32
- *                  far from under/overflow); vectors and SpMV / AXPY in
- *                  FP32 arithmetic; dot products, alpha and beta in FP64
- *                  (a product of two floats is exact in double); the
- *                  inner loop stops when its recursive residual has fallen
- *                  by inner_tol, or when the total iteration budget is spent.
- *   stagnation:    an outer step that does not halve ||r|| ends the solve as
- *                  not converged (FP32 cannot resolve the system), as does
- *                  reaching max_outer outer steps.
+ *   replacement (FP64):  x = x + d / s;  r = b - A x;  stop when
+ *                        ||r|| <= tol ||b||;  new scale s' = 2^-floor(log2
+ *                        ||r||) (exact, keeps FP32 far from under/overflow);
+ *                        r32 = float(s' r), z32 = M r32, d = 0, the
+ *                        direction p32 multiplied by s'/s (exact), and
+ *                        beta = (r32, z32) / (rho s'^2 / s^2), rho being the
+ *                        last (r32, z32) of the recurrence before the
+ *                        replacement (rescaled to the new units); the first
+ *                        replacement starts the recurrence (p = z, beta 0).
+ *   iteration (FP32):    p = z + beta p;  q = A32 p;  alpha = rho / (p, q);
+ *                        d += alpha p;  r32 -= alpha q;  z32 = M r32, with
+ *                        A32 = float(A), FP32 vectors and arithmetic, and
+ *                        dot products, alpha and beta in FP64 (a product of
+ *                        two floats is exact in double).
+ *   trigger:             a replacement follows the iteration after which
+ *                        ||r32|| <= update_tol * (largest ||r32|| since the
+ *                        last replacement), or ||r32|| / s <= tol ||b|| (the
+ *                        recursion claims convergence), or the iteration
+ *                        budget is spent, or the recurrence broke down.
+ *   stagnation:          MIXED_STALL replacements in a row whose true
+ *                        residual is not below every earlier one end the
+ *                        solve as not converged (FP32 cannot resolve the
+ *                        system), as does reaching max_outer replacements.
  *
  * The Jacobi preconditioner, when asked for, is z = dinv32 * r in FP32 with
  * dinv32 = float(1 / diag).
  *
- * out[0] : total inner iterations, out[1] : last outer ||r||/||b|| (this is
- * the true FP64 residual), out[2] : same as out[1], out[3] : outer steps.
- * hist   : if not NULL, hist[j] = ||r_j||/||b|| before outer step j
- *          (max_outer + 1 entries).
+ * out[0] : total FP32 iterations, out[1] : last ||r||/||b|| (the true FP64
+ * residual), out[2] : same as out[1], out[3] : replacements after the first
+ * residual (the FP32 segments run).
+ * hist   : if not NULL, hist[j] = ||r_j||/||b|| at the j-th residual
+ *          computation, the first one included (max_outer + 1 entries).
  * Returns 0 converged, 1 not converged, 2 breakdown, -1 bad arguments.     */
+#define MIXED_STALL 3
 
 /* pairwise FP64 sum of double(x_i) * double(y_i) for float vectors */
 static double dot32_rec(const float *x, const float *y, int64_t n)
@@ -274,10 +292,10 @@ static double dot32(const float *x, const float *y, int64_t n)
 
 int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
                     const double *b, double *x, double tol, int maxit, int precond,
-                    double inner_tol, int max_outer, double *out, double *hist)
+                    double update_tol, int max_outer, double *out, double *hist)
 {
     if (n < 0 || !rowptr || !b || !x || !out || maxit < 0 || !(tol >= 0.0) ||
-        !(inner_tol > 0.0) || max_outer < 1) return -1;
+        !(update_tol > 0.0) || max_outer < 1) return -1;
     out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0;
     if (n == 0) return 0;
     const int64_t nnz = rowptr[n];
@@ -290,7 +308,7 @@ int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, con
     float *q = malloc((size_t)n * sizeof(float));
     float *d = malloc((size_t)n * sizeof(float));
     float *dinv = malloc((size_t)n * sizeof(float));
-    int status = 1, k = 0, outer = 0;
+    int status = 1, k = 0, outer = 0, stall = 0, broke = 0;
     double rel = 0.0;
     if (!a32 || !r || !ax || !rr || !z || !p || !q || !d || !dinv) { status = -1; goto done; }
     for (int64_t e = 0; e < nnz; ++e) a32[e] = (float)val[e];
@@ -298,6 +316,8 @@ int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, con
         double dd = 0.0;
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) if (colind[e] == i) dd = dd + val[e];
         dinv[i] = (float)(1.0 / dd);
+        d[i] = 0.0f;
+        p[i] = 0.0f;
     }
     const double bnorm = sqrt(oracle_dot(b, b, n));
     if (bnorm == 0.0) {
@@ -305,36 +325,45 @@ int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, con
         status = 0;
         goto done;
     }
-    double prev = INFINITY;
+    double s = 1.0, rho = 0.0, best = INFINITY;
     for (;;) {
-        /* outer residual in FP64 */
+        /* replacement: fold the FP32 correction into x, true residual in FP64 */
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + (double)d[i] / s;
         oracle_spmv(n, rowptr, colind, val, x, ax);
         for (int64_t i = 0; i < n; ++i) r[i] = b[i] - ax[i];
         const double rn = sqrt(oracle_dot(r, r, n));
         rel = rn / bnorm;
         if (hist) hist[outer] = rel;
         if (rn <= tol * bnorm) { status = 0; break; }
-        if (k >= maxit || outer >= max_outer || !(rn <= 0.5 * prev)) { status = 1; break; }
-        prev = rn;
-        /* inner FP32 CG on A d = s r, d0 = 0 */
-        const double s = ldexp(1.0, -ilogb(rn));
+        if (broke) { status = 2; break; }
+        if (rn < best) { best = rn; stall = 0; }
+        else if (++stall >= MIXED_STALL) { status = 1; break; }
+        if (k >= maxit || outer >= max_outer) { status = 1; break; }
+        /* restart the recurrence's residual from r, keep its direction */
+        const double s_new = ldexp(1.0, -ilogb(rn));
+        const double ratio = outer == 0 ? 1.0 : s_new / s;   /* first: p is 0 */
         for (int64_t i = 0; i < n; ++i) {
-            rr[i] = (float)(r[i] * s);
+            rr[i] = (float)(r[i] * s_new);
             z[i] = precond ? dinv[i] * rr[i] : rr[i];
-            p[i] = z[i];
             d[i] = 0.0f;
+            p[i] = p[i] * (float)ratio;
         }
-        double rho = dot32(rr, z, n);
-        double rr2 = dot32(rr, rr, n);
-        const double rr0 = rr2;
-        while (k < maxit && sqrt(rr2) > inner_tol * sqrt(rr0)) {
+        const double rho_r = dot32(rr, z, n);
+        double beta = outer == 0 ? 0.0 : rho_r / (rho * ratio * ratio);
+        rho = rho_r;
+        s = s_new;
+        double rmax = sqrt(dot32(rr, rr, n));
+        /* FP32 iterations until the next replacement */
+        for (;;) {
+            const float bf = (float)beta;
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + bf * p[i];
             for (int64_t i = 0; i < n; ++i) {
                 float t = 0.0f;
                 for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) t = t + a32[e] * p[colind[e]];
                 q[i] = t;
             }
             const double pq = dot32(p, q, n);
-            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
+            if (!(pq > 0.0) || !isfinite(pq)) { broke = 1; break; }
             const float af = (float)(rho / pq);
             for (int64_t i = 0; i < n; ++i) {
                 d[i] = d[i] + af * p[i];
@@ -342,22 +371,15 @@ int oracle_cg_mixed(int64_t n, const int32_t *rowptr, const int32_t *colind, con
                 z[i] = precond ? dinv[i] * rr[i] : rr[i];
             }
             const double rho_new = dot32(rr, z, n);
-            rr2 = dot32(rr, rr, n);
+            const double rnorm = sqrt(dot32(rr, rr, n));
             ++k;
-            if (precond && !(rho_new > 0.0) && rr2 > 0.0) { status = 2; break; }
-            const float bf = (float)(rho_new / rho);
-            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + bf * p[i];
+            if (precond && !(rho_new > 0.0) && rnorm > 0.0) { broke = 1; break; }
+            if (rnorm > rmax) rmax = rnorm;
+            if (rnorm <= update_tol * rmax || rnorm <= tol * bnorm * s || k >= maxit) break;
+            beta = rho_new / rho;
             rho = rho_new;
         }
-        /* x = x + d / s (exact rescaling by a power of two) */
-        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + (double)d[i] / s;
         ++outer;
-        if (status == 2) {
-            oracle_spmv(n, rowptr, colind, val, x, ax);
-            for (int64_t i = 0; i < n; ++i) r[i] = b[i] - ax[i];
-            rel = sqrt(oracle_dot(r, r, n)) / bnorm;
-            break;
-        }
     }
 done:
     out[0] = k; out[1] = rel; out[2] = rel; out[3] = outer;

@@ -1,11 +1,15 @@
-"""Pins of the mixed-precision CG oracle (FP64 refinement around FP32 CG; no GPU).
+"""Pins of the mixed-precision CG oracle (one FP32 CG recurrence with FP64
+residual replacement; no GPU).
 
 The mixed solver is pinned to a dense Cholesky solve on small SPD systems, to
-the FP32 accuracy floor of a single refinement step (which an all-FP64 inner
-solve would beat by orders of magnitude), to the contraction per refinement
-step that iterative-refinement theory predicts, to one inner step on a
-Poisson eigenvector, to exact invariance under power-of-two scaling of b, and
-to its edge cases.
+the FP32 accuracy floor of a single FP32 segment (which an all-FP64 recurrence
+would beat by orders of magnitude), to the FP64 CG oracle's iteration count
+(a recurrence that keeps its direction across replacements follows FP64 CG;
+one restarted at every replacement, or with a wrongly scaled beta, needs far
+more iterations), to a true residual that falls at every replacement on
+Poisson systems, to one step on a Poisson eigenvector, to exact invariance
+under power-of-two scaling of b, to the stagnation rule, and to its edge
+cases.
 """
 import math
 
@@ -54,28 +58,53 @@ def test_single_step_stops_at_the_fp32_floor():
     """One refinement step cannot beat FP32 (kappa * u32 level); refinement can."""
     rp, ci, v = workloads.poisson_csr(64, 2)
     b = workloads.rhs_uniform(rp.size - 1, seed=3)
-    _, one = oracle.cg_mixed(rp, ci, v, b, tol=1e-14, maxit=3000, inner_tol=1e-14, max_outer=1)
+    _, one = oracle.cg_mixed(rp, ci, v, b, tol=1e-14, maxit=3000, update_tol=1e-14, max_outer=1)
     assert one["outer"] == 1 and one["status"] == "not_converged"
     assert 1e-9 < one["relres_true"] < 1e-4
     _, full = oracle.cg_mixed(rp, ci, v, b, tol=1e-12, maxit=3000)
     assert full["status"] == "converged" and full["relres_true"] <= 1e-12
 
 
-@pytest.mark.parametrize("side,inner_tol", [(32, 1e-4), (64, 1e-4), (64, 1e-3)])
-def test_refinement_contraction_per_outer_step(side, inner_tol):
-    """||r_{j+1}|| / ||r_j|| <= 10 * max(inner_tol, kappa * u32) above the FP64 floor."""
-    rp, ci, v = workloads.poisson_csr(side, 2)
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d", "random_jacobi"])
+def test_replacements_keep_the_krylov_space(case):
+    """Total FP32 iterations within 15% (+2) of FP64 CG's on the same system.
+
+    FP32 recurrences lose orthogonality a little faster than FP64 ones (on 2D
+    Poisson the count ranges from equal to about 9% more, depending on where
+    the replacements fall); restarting the recurrence at every replacement
+    costs 1.5-2x."""
+    precond = None
+    if case == "poisson2d":
+        rp, ci, v = workloads.poisson_csr(48, 2)
+    elif case == "poisson3d":
+        rp, ci, v = workloads.poisson_csr(16, 3)
+    else:
+        rp, ci, v = workloads.random_spd_csr(3000, seed=4)
+        precond = "jacobi"
+    b = workloads.rhs_uniform(rp.size - 1, seed=2)
+    _, ref = oracle.cg(rp, ci, v, b, tol=1e-10, maxit=5000, precond=precond)
+    _, mix = oracle.cg_mixed(rp, ci, v, b, tol=1e-10, maxit=5000, precond=precond)
+    assert ref["status"] == "converged" and mix["status"] == "converged"
+    assert abs(mix["iters"] - ref["iters"]) <= 0.15 * ref["iters"] + 2, (mix["iters"], ref["iters"])
+    # replacements happen: the FP32 recursion alone would stop at the FP32 floor
+    assert mix["outer"] >= 2
+
+
+@pytest.mark.parametrize("side,dim", [(40, 2), (12, 3)])
+def test_true_residual_falls_at_every_replacement(side, dim):
+    rp, ci, v = workloads.poisson_csr(side, dim)
     n = rp.size - 1
     b = workloads.rhs_uniform(n, seed=side)
-    th = math.pi / (side + 1)
-    kappa = (8 - 4 * math.cos(side * th)) / (4 - 4 * math.cos(th))   # 2D Dirichlet Laplacian
-    _, info = oracle.cg_mixed(rp, ci, v, b, tol=1e-13, maxit=20000, inner_tol=inner_tol)
+    x, info = oracle.cg_mixed(rp, ci, v, b, tol=1e-12, maxit=5000)
     h = info["history"]
-    assert info["status"] == "converged" and len(h) >= 3
-    above = h[1:] >= 100 * kappa * 2.0 ** -53     # steps not limited by FP64 residual accuracy
-    ratios = (h[1:] / h[:-1])[above]
-    assert ratios.size >= 2
-    assert np.all(ratios <= 10 * max(inner_tol, kappa * U32)), ratios
+    assert info["status"] == "converged" and h.size == info["outer"] + 1
+    assert np.all(np.diff(h) < 0), h
+    # the last entry is the true residual of the returned x
+    import scipy.sparse as sp
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    true = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert abs(h[-1] - true) <= 1e-6 * true
+    assert h[-1] <= 1e-12
 
 
 def test_one_inner_step_on_poisson_eigenvector():
@@ -105,10 +134,10 @@ def test_inner_solve_uses_fp32_matrix():
     A = np.diag([1.0, 2.0, 3.0]) + 1e-9 * np.ones((3, 3))
     rp, ci, v = _dense_to_csr(A)
     b = np.array([1.0, -2.0, 0.5])
-    x, info = oracle.cg_mixed(rp, ci, v, b, tol=1e-14, maxit=100)
+    x, info = oracle.cg_mixed(rp, ci, v, b, tol=1e-14, maxit=100, update_tol=1e-6)
     assert info["status"] == "converged"
     np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-13)
-    # the first FP32 step solves diag(1,2,3) (the 1e-9 part rounds away in
+    # the first FP32 segment solves float(A) (the 1e-9 part rounds away in
     # sum with the diagonal only at FP32 precision): history[1] ~ 1e-9 level
     assert 1e-11 < info["history"][1] < 1e-6
 
@@ -135,3 +164,9 @@ def test_mixed_reports_stagnation_when_fp32_cannot_resolve():
     _, info = oracle.cg_mixed(rp, ci, v, b, tol=1e-10, maxit=20000)
     assert info["status"] in ("not_converged", "breakdown")
     assert info["outer"] < oracle.MIXED_MAX_OUTER
+    if info["status"] == "not_converged":
+        # ended by the stagnation rule: the last MIXED_STALL replacements set
+        # no new smallest true residual
+        h = info["history"]
+        k = oracle.MIXED_STALL
+        assert h.size > k and np.all(h[-k:] >= h[:-k].min())
