@@ -230,20 +230,29 @@ enum { PERKS_PRECOND_NONE = 0, PERKS_PRECOND_JACOBI = 1 };
 
 /* Arithmetic of a CG solve.
  *   PERKS_PREC_F64    FP64 throughout.
- *   PERKS_PREC_MIXED  FP64 iterative refinement around an FP32 CG: each outer
- *                     step forms r = b - A x in FP64 and, unless
- *                     ||r|| <= tol ||b||, solves A d = r approximately with CG
- *                     in FP32 (FP32 copy of A's values, FP32 vectors, SpMV and
- *                     AXPYs; FP64 dot products, alpha and beta; the right-hand
- *                     side scaled by an exact power of two near 1/||r||) until
- *                     the inner recursive residual has fallen by
- *                     PERKS_MIXED_INNER_TOL, then x += d.  An outer step that
- *                     does not halve ||r||, or PERKS_MIXED_MAX_OUTER outer
- *                     steps, end the solve as PERKS_NOT_CONVERGED.  The paper's
- *                     CG runs in one precision; this mode is an extension. */
+ *   PERKS_PREC_MIXED  one CG recurrence in FP32 (FP32 copy of A's values, FP32
+ *                     vectors, SpMV and AXPYs; FP64 dot products, alpha and
+ *                     beta) whose recursive residual is replaced, from time
+ *                     to time, by the true residual r = b - A x computed in
+ *                     FP64 from an FP64 iterate x (residual replacement, the
+ *                     "reliable updates" of Sleijpen and van der Vorst).  A
+ *                     replacement follows the iteration after which the FP32
+ *                     residual has fallen to PERKS_MIXED_UPDATE_TOL times its
+ *                     largest value since the last one, or claims
+ *                     convergence, or the budget is spent; it adds the FP32
+ *                     correction d to x, forms r, stops if ||r|| <= tol ||b||,
+ *                     and restarts the recurrence's residual from float(s r)
+ *                     (s an exact power of two near 1/||r||) while keeping
+ *                     its search direction (rescaled by the same power of
+ *                     two), so the Krylov space is not discarded.
+ *                     PERKS_MIXED_STALL replacements in a row without a new
+ *                     smallest ||r||, or PERKS_MIXED_MAX_OUTER replacements,
+ *                     end the solve as PERKS_NOT_CONVERGED.  The paper's CG
+ *                     runs in one precision; this mode is an extension. */
 enum { PERKS_PREC_F64 = 0, PERKS_PREC_MIXED = 1 };
-#define PERKS_MIXED_INNER_TOL 1e-4
-#define PERKS_MIXED_MAX_OUTER 30
+#define PERKS_MIXED_UPDATE_TOL 0.3
+#define PERKS_MIXED_MAX_OUTER 100
+#define PERKS_MIXED_STALL 3
 
 /*
  * perks_cg_solve -- conjugate gradient for SPD A (Sec. 2.2.2, Sec. 4.3).
@@ -256,16 +265,18 @@ enum { PERKS_PREC_F64 = 0, PERKS_PREC_MIXED = 1 };
  * fixed-order all-reduce inside the kernel) and AXPYs are fused, the first
  * part of each workgroup's slice of the matrix is cached in LDS, and
  * workgroups synchronise with a device-wide barrier.
- * PERKS_PREC_MIXED: the refinement loop above, all outer and inner steps in
- * ONE persistent launch; the stopping test is on the true FP64 residual.
+ * PERKS_PREC_MIXED: the replacement scheme above, every FP32 iteration and
+ * every FP64 replacement in ONE persistent launch; the stopping test is on
+ * the true FP64 residual.
  *   A         host struct describing device CSR arrays (values FP64).
  *   b         device, n doubles.      x  device, n doubles: initial guess in,
  *             solution out.
- *   maxit     CG iterations allowed (mixed: inner iterations, all outer steps).
+ *   maxit     CG iterations allowed (mixed: FP32 iterations).
  *   precond   PERKS_PRECOND_NONE or PERKS_PRECOND_JACOBI (z = D^{-1} r).
  *   precision PERKS_PREC_F64 or PERKS_PREC_MIXED.
  *   out       host, filled on return (may be NULL); `restarts` counts
- *             restarts (F64) or outer refinement steps (MIXED).
+ *             restarts (F64) or residual replacements after the first
+ *             residual (MIXED).
  * Returns PERKS_OK, PERKS_NOT_CONVERGED, PERKS_BREAKDOWN or an error.
  */
 int perks_cg_solve(const perks_csr *A, const void *b, void *x, double tol, int32_t maxit,
@@ -284,7 +295,8 @@ int perks_cg_solve_capture(const perks_csr *A, const void *b, void *x, double to
  * AXPYs) launched every iteration, scalars kept on the device, and the host
  * reading the residual norm back every `check_every` iterations (>= 1) to
  * decide convergence -- the multi-kernel structure the paper fuses (Sec. 3.1,
- * "Practicality of PERKS").  MIXED: the host also runs the outer loop. */
+ * "Practicality of PERKS").  MIXED: the host also decides every residual
+ * replacement (the trigger test then runs every check_every iterations). */
 int perks_cg_solve_baseline(const perks_csr *A, const void *b, void *x, double tol,
                             int32_t maxit, int32_t precond, int32_t precision,
                             int32_t check_every, void *stream, perks_cg_result *out);

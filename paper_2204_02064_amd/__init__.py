@@ -344,8 +344,9 @@ def _check_vec(v, n, name):
 def cg_solve(A, b, x, tol=1e-10, maxit=5000, precond=None, precision=None, stream=None):
     """Persistent-kernel CG: solves A x = b in place in ``x``; returns an info dict.
 
-    ``precision``: None / "f64" (FP64 throughout) or "mixed" (FP64 iterative
-    refinement around an FP32 CG, one launch).
+    ``precision``: None / "f64" (FP64 throughout) or "mixed" (one FP32 CG
+    recurrence with FP64 residual replacement, one launch; ``outer`` counts
+    the replacements).
     """
     _check_vec(b, A.n, "b")
     _check_vec(x, A.n, "x")

@@ -181,10 +181,11 @@ __global__ __launch_bounds__(256) void base_resid(int n, const double *b, const 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// r32 = float(sc r64), z32, p32 = z32, d32 = 0; partial r.z and r.r in FP64.
-__global__ __launch_bounds__(256) void base_mixed_init(int n, const double *r64, double sc, float *r, float *z,
-                                                       float *pv, float *d, const float *dinv, double *part_rz,
-                                                       double *part_rr) {
+// Residual replacement: r32 = float(sc r64), z32, d32 = 0, the direction
+// p32 multiplied by ratio (a power of two: exact); partial r.z and r.r in FP64.
+__global__ __launch_bounds__(256) void base_mixed_replace(int n, const double *r64, double sc, float ratio, float *r,
+                                                          float *z, float *pv, float *d, const float *dinv,
+                                                          double *part_rz, double *part_rr) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     double a = 0.0, c = 0.0;
     if (i < n) {
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void base_mixed_init(int n, const double *r64,
         r[i] = ri;
         const float zi = dinv ? dinv[i] * ri : ri;
         if (dinv) z[i] = zi;
-        pv[i] = zi;
+        pv[i] = pv[i] * ratio;
         d[i] = 0.0f;
         a = (double)ri * (double)zi;
         c = (double)ri * (double)ri;
@@ -209,6 +210,15 @@ __global__ __launch_bounds__(256) void base_mixed_init(int n, const double *r64,
         part_rz[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
         part_rr[blockIdx.x] = red[4] + red[5] + red[6] + red[7];
     }
+}
+
+// beta after a replacement: rho_new is the new residual's r.z, rho the last
+// r.z of the recurrence (in the old units: ratio2 = (s'/s)^2); the first
+// replacement starts the recurrence (beta 0).
+__global__ void base_replace_beta(BaseScalars *s, double ratio2, int first) {
+    s->beta = first ? 0.0 : s->rho_new / (s->rho * ratio2);
+    s->rho = s->rho_new;
+    s->status = 1.0;
 }
 
 __global__ __launch_bounds__(256) void base_xupdate(int n, double *x, const float *d, double sc) {
@@ -512,7 +522,7 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     p.maxit = maxit;
     p.max_outer = PERKS_MIXED_MAX_OUTER;
     p.tol = tol;
-    p.inner_tol = PERKS_MIXED_INNER_TOL;
+    p.update_tol = PERKS_MIXED_UPDATE_TOL;
     p.cap_iters = capture.iters;
     p.ncap = capture.n;
     p.cap_x = capture.x;
@@ -685,9 +695,10 @@ int cg_baseline_f64(const perks_csr *A, const void *b, void *x, double tol, int 
     return status;
 }
 
-// Host-looped mixed-precision solve: the same algorithm as cg_mixed_persistent
-// with one kernel per step and the host deciding every outer step and, every
-// check_every inner iterations, the inner stop.
+// Host-looped mixed-precision solve: the same algorithm as the persistent one
+// (residual replacement around one FP32 recurrence) with one kernel per step,
+// the host deciding every replacement and, every check_every iterations,
+// whether the recursive residual has fallen enough for the next one.
 int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, int maxit, bool jac, int check_every,
                       hipStream_t st, perks_cg_result *out) {
     CgWork w;
@@ -704,6 +715,8 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
     if (A->nnz > 0) hipLaunchKernelGGL(to_f32, dim3(nbv), dim3(256), 0, st, (int64_t)A->nnz, val, w.val32);
     if (jac)
         hipLaunchKernelGGL(invert_diagonal32, dim3(nb), dim3(256), 0, st, A->rowptr, A->colind, val, n, w.dinv32);
+    PERKS_HIP_TRY(hipMemsetAsync(w.p32, 0, (size_t)n * sizeof(float), st));
+    PERKS_HIP_TRY(hipMemsetAsync(w.d32, 0, (size_t)n * sizeof(float), st));
     double hs[8];
     // ||b||
     hipLaunchKernelGGL(base_resid, dim3(nb), dim3(256), 0, st, n, (const double *)b, (const double *)nullptr,
@@ -718,11 +731,12 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
         fill_result(out, 0, PERKS_OK, 0, 0, 0.0, 0.0, 0.0);
         return PERKS_OK;
     }
-    int total = 0, outer = 0, status = PERKS_NOT_CONVERGED;
-    double rn = 0.0, prev = INFINITY;
+    int k = 0, outer = 0, stall = 0, status = PERKS_NOT_CONVERGED;
+    double rn = 0.0, best = INFINITY, sc = 1.0;
     bool broke = false;
     for (;;) {
-        // outer residual in FP64: r64 = b - A x  (A x lands in r64 first)
+        // replacement: x += d / s, then r64 = b - A x in FP64 (A x lands in r64 first)
+        if (outer > 0) hipLaunchKernelGGL(base_xupdate, dim3(nb), dim3(256), 0, st, n, xd, (const float *)w.d32, sc);
         hipLaunchKernelGGL(base_spmv<double>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind, val, n, L,
                            (const double *)xd, w.r64, (const double *)nullptr, (double *)nullptr);
         hipLaunchKernelGGL(base_resid, dim3(nb), dim3(256), 0, st, n, (const double *)b, (const double *)w.r64,
@@ -731,34 +745,37 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
         PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
         PERKS_HIP_TRY(hipStreamSynchronize(st));
         rn = std::sqrt(hs[4]);
-        if (broke) {
-            status = PERKS_BREAKDOWN;
-            break;
-        }
         if (rn <= tol * bnorm) {
             status = PERKS_OK;
             break;
         }
-        if (total >= maxit || outer >= PERKS_MIXED_MAX_OUTER || !(rn <= 0.5 * prev)) {
-            status = PERKS_NOT_CONVERGED;
+        if (broke) {
+            status = PERKS_BREAKDOWN;
             break;
         }
-        prev = rn;
+        if (rn < best) {
+            best = rn;
+            stall = 0;
+        } else if (++stall >= PERKS_MIXED_STALL) {
+            break;
+        }
+        if (k >= maxit || outer >= PERKS_MIXED_MAX_OUTER) break;
         int ex;
         (void)std::frexp(rn, &ex);
-        const double sc = std::ldexp(1.0, 1 - ex);
-        hipLaunchKernelGGL(base_mixed_init, dim3(nb), dim3(256), 0, st, n, (const double *)w.r64, sc, w.r32, w.z32,
-                           w.p32, w.d32, dinv, B.part_b, B.part_c);
-        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho);
+        const double sc_new = std::ldexp(1.0, 1 - ex);
+        const double ratio = outer == 0 ? 1.0 : sc_new / sc;   // first: p is 0
+        hipLaunchKernelGGL(base_mixed_replace, dim3(nb), dim3(256), 0, st, n, (const double *)w.r64, sc_new,
+                           (float)ratio, w.r32, w.z32, w.p32, w.d32, dinv, B.part_b, B.part_c);
+        hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
         hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
+        hipLaunchKernelGGL(base_replace_beta, dim3(1), dim3(1), 0, st, S, ratio * ratio, outer == 0 ? 1 : 0);
         PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
         PERKS_HIP_TRY(hipStreamSynchronize(st));
-        const double stop = PERKS_MIXED_INNER_TOL * std::sqrt(hs[4]);
-        hs[7] = 1.0;
-        PERKS_HIP_TRY(hipMemcpyAsync(&S->status, &hs[7], sizeof(double), hipMemcpyHostToDevice, st));
-        bool done = !(std::sqrt(hs[4]) > stop);
-        int k = 0;
-        while (!done && total + k < maxit) {
+        sc = sc_new;
+        double rmax = std::sqrt(hs[4]);
+        int j = 0;
+        for (;;) {
+            hipLaunchKernelGGL(base_pupdate<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)z, w.p32);
             hipLaunchKernelGGL(base_spmv<float>, dim3(nbs), dim3(256), 0, st, A->rowptr, A->colind,
                                (const float *)w.val32, n, L, (const float *)w.p32, w.q32, (const float *)w.p32,
                                B.part_a);
@@ -768,26 +785,26 @@ int cg_baseline_mixed(const perks_csr *A, const void *b, void *x, double tol, in
                                (const float *)w.q32, w.d32, w.r32, w.z32, dinv, B.part_b, B.part_c);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_b, nb, &S->rho_new);
             hipLaunchKernelGGL(base_reduce, dim3(1), dim3(1024), 0, st, B.part_c, nb, &S->rr);
-            hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
-            hipLaunchKernelGGL(base_pupdate<float>, dim3(nb), dim3(256), 0, st, n, S, (const float *)z, w.p32);
             ++k;
-            if (k % check_every == 0 || total + k >= maxit) {
+            ++j;
+            if (j % check_every == 0 || k >= maxit) {
                 PERKS_HIP_TRY(hipMemcpyAsync(hs, S, sizeof(BaseScalars), hipMemcpyDeviceToHost, st));
                 PERKS_HIP_TRY(hipStreamSynchronize(st));
-                if (hs[7] != 1.0) {
+                const double rnorm = std::sqrt(hs[4]);
+                if (hs[7] != 1.0 || (jac && !(hs[6] > 0.0) && rnorm > 0.0)) {
                     broke = true;
                     break;
                 }
-                done = !(std::sqrt(hs[4]) > stop);
+                rmax = std::max(rmax, rnorm);
+                if (rnorm <= PERKS_MIXED_UPDATE_TOL * rmax || rnorm <= tol * bnorm * sc || k >= maxit) break;
             }
+            hipLaunchKernelGGL(base_beta, dim3(1), dim3(1), 0, st, S);
         }
         PERKS_HIP_TRY(hipGetLastError());
-        total += k;
-        hipLaunchKernelGGL(base_xupdate, dim3(nb), dim3(256), 0, st, n, xd, (const float *)w.d32, sc);
         ++outer;
     }
     PERKS_HIP_TRY(hipGetLastError());
-    fill_result(out, total, status, outer, 0, rn / bnorm, rn / bnorm, 0.0);
+    fill_result(out, k, status, outer, 0, rn / bnorm, rn / bnorm, 0.0);
     return status;
 }
 
@@ -945,7 +962,7 @@ int perks_cg_batch_create(const perks_csr *As, const void *const *bs, void *cons
             p.maxit = maxit;
             p.max_outer = PERKS_MIXED_MAX_OUTER;
             p.tol = tol;
-            p.inner_tol = PERKS_MIXED_INNER_TOL;
+            p.update_tol = PERKS_MIXED_UPDATE_TOL;
             const double lds = mixed ? CG_LDS_NNZ32 : CG_LDS_NNZ;
             if (nnz[i] > 0) P->cached_frac[i] = std::min<double>((double)nnz[i], lds * S.wgs[i]) / (double)nnz[i];
         }

@@ -48,7 +48,7 @@ struct CgInst {
     int maxit;
     int max_outer;
     double tol;
-    double inner_tol;
+    double update_tol;
 };
 
 // The problem description as kernels read it: through the constant address
@@ -1129,16 +1129,24 @@ __device__ __forceinline__ void cg_f64_body(CInst *pin, Sync &gs, const int g, c
     }
 }
 
-// Mixed precision: FP64 iterative refinement around an FP32 CG.  Outer step
-// (FP64): r = b - A x with the FP64 matrix; stop when ||r|| <= tol ||b||;
-// otherwise run CG in FP32 on A32 d = s r (A32 = float(A), s a power of two
-// near 1/||r||, so the scaling is exact), with FP32 vectors, SpMV and AXPYs
-// and FP64 dot products, alpha and beta, until its recursive residual has
-// fallen by inner_tol; then x += d / s.  An outer step that does not halve
-// ||r|| ends the solve (FP32 cannot resolve the system).  The FP32 copy of
-// each workgroup's slice of A is made by the workgroup itself (global copy +
-// LDS cache of its first CG_LDS_NNZ32 entries): 8 instead of 12 bytes per
-// nonzero in the inner iterations, and 1.5x the nonzeros held on chip.
+// Mixed precision: one FP32 CG recurrence whose recursive residual is
+// replaced, from time to time, by the true residual of an FP64 iterate
+// (residual replacement, "reliable updates"), the search direction being kept
+// across each replacement so that the Krylov space built so far survives.
+//   replacement (FP64): x += d / s on own rows; r = b - A x with the FP64
+//     matrix; stop when ||r|| <= tol ||b||; new exact scale s' = 2^-floor(
+//     log2 ||r||); r32 = float(s' r), z32, d = 0, p32 *= s'/s (exact), and
+//     beta = (r32, z32) / (rho (s'/s)^2) (the first replacement: p = z).
+//   iteration (FP32 vectors, SpMV and AXPYs; FP64 dots, alpha, beta), until
+//     ||r32|| <= update_tol * (its largest value since the replacement), or
+//     ||r32|| / s <= tol ||b||, or the budget is spent, or a breakdown.
+//   stagnation: PERKS_MIXED_STALL replacements in a row without a new
+//     smallest true residual end the solve (FP32 cannot resolve the system).
+// Barriers: three per iteration (as the FP64 solver) and three per
+// replacement.  The FP32 copy of each workgroup's slice of A is made by the
+// workgroup itself (global copy + LDS cache of its first CG_LDS_NNZ32
+// entries): 8 instead of 12 bytes per nonzero in the FP32 iterations, and
+// 1.5x the nonzeros held on chip.
 template <bool JACOBI, bool MERGE, class Sync>
 __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, const int G) {
     const int tid = threadIdx.x;
@@ -1160,14 +1168,20 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
         }
         const double bi = p.b[i];
         accb[0] = __builtin_fma(bi, bi, accb[0]);
+        p.d32[i] = 0.0f;
+        p.p32[i] = 0.0f;
     }
     block_sum<1>(accb, cg_red);
     if (tid == 0) st_coh(p.part + (size_t)PART_BB * G + g, accb[0]);
 
     const float *zsrc = JACOBI ? p.z32 : p.r32;
-    double bnorm = -1.0, rn = 0.0, prev = INFINITY;
-    int k = 0, outer = 0, status = 1;
+    double bnorm = -1.0, rn = 0.0, best = INFINITY, sc = 1.0, rho = 0.0;
+    int k = 0, outer = 0, status = 1, stall = 0;
+    bool broke = false;
     for (;;) {
+        // replacement: fold the FP32 correction into x (own rows; every
+        // workgroup reads x in the residual below)
+        for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, p.x[i] + (double)p.d32[i] / sc);
         gs.template sync<true>();   // x (and, the first time, the b.b partials) complete
         if (bnorm < 0.0) bnorm = sqrt(grid_total(p.part, PART_BB, G, &cg_bcast));
         if (bnorm == 0.0) {
@@ -1176,7 +1190,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             rn = 0.0;
             break;
         }
-        // outer residual in FP64 (A from global memory in FP64)
+        // true residual in FP64 (A from global memory in FP64)
         double accr[1] = {0.0};
         spmv_range<CG_U, false>(p.rowptr, p.colind, p.val, r0, r1, L, kbase, [&](int c) { return p.x[c]; },
                                 [&](int i, double sv) {
@@ -1188,17 +1202,24 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
         if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, accr[0]);
         gs.template sync<true>();
         rn = sqrt(grid_total(p.part, PART_TRUE, G, &cg_bcast));
-        if (status == 2) break;
         if (rn <= p.tol * bnorm) { status = 0; break; }
-        if (k >= p.maxit || outer >= p.max_outer || !(rn <= 0.5 * prev)) break;
-        prev = rn;
+        if (broke) { status = 2; break; }
+        if (rn < best) {
+            best = rn;
+            stall = 0;
+        } else if (++stall >= PERKS_MIXED_STALL) {
+            break;
+        }
+        if (k >= p.maxit || outer >= p.max_outer) break;
+        // restart the recurrence's residual from r, keep its direction
         int ex;
         (void)frexp(rn, &ex);
-        const double sc = ldexp(1.0, 1 - ex);   // 2^-floor(log2 rn)
-        // inner start: r32 = float(s r), z32, p_{-1} = 0, d = 0
+        const double sc_new = ldexp(1.0, 1 - ex);   // 2^-floor(log2 rn)
+        const double ratio = outer == 0 ? 1.0 : sc_new / sc;   // first: p is 0
+        const float ratio_f = (float)ratio;
         double acc0[2] = {0.0, 0.0};
         for (int i = r0 + tid; i < r1; i += CG_THREADS) {
-            const float ri = (float)(p.r64[i] * sc);
+            const float ri = (float)(p.r64[i] * sc_new);
             const float zi = JACOBI ? p.dinv32[i] * ri : ri;
             if (JACOBI) {
                 p.r32[i] = ri;
@@ -1206,7 +1227,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             } else {
                 st_coh(p.r32 + i, ri);
             }
-            st_coh(p.p32 + i, 0.0f);
+            p.p32[i] = p.p32[i] * ratio_f;   // own rows, read back by this thread in phase P
             p.d32[i] = 0.0f;
             acc0[0] = __builtin_fma((double)ri, (double)zi, acc0[0]);
             acc0[1] = __builtin_fma((double)ri, (double)ri, acc0[1]);
@@ -1217,11 +1238,13 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             st_coh(p.part + (size_t)PART_RR * G + g, acc0[1]);
         }
         gs.template sync<true>();
-        double rho = grid_total(p.part, PART_RZ, G, &cg_bcast);
-        double rr = grid_total(p.part, PART_RR, G, &cg_bcast);
-        const double stop = p.inner_tol * sqrt(rr);
-        double beta = 0.0;
-        for (int j = 0; sqrt(rr) > stop && k < p.maxit; ++j) {
+        const double rho_r = grid_total(p.part, PART_RZ, G, &cg_bcast);
+        double beta = outer == 0 ? 0.0 : rho_r / (rho * ratio * ratio);
+        rho = rho_r;
+        sc = sc_new;
+        double rmax = sqrt(grid_total(p.part, PART_RR, G, &cg_bcast));
+        // FP32 iterations until the next replacement
+        for (;;) {
             const float bf = (float)beta;
             double acc1[1] = {0.0};
             float *pn = p.p32;
@@ -1237,7 +1260,7 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             if (tid == 0) st_coh(p.part + (size_t)PART_PQ * G + g, acc1[0]);
             gs.template sync<true>();
             const double pq = grid_total(p.part, PART_PQ, G, &cg_bcast);
-            if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }
+            if (!(pq > 0.0) || !isfinite(pq)) { broke = true; break; }
             const float af = (float)(rho / pq);
             double acc2[2] = {0.0, 0.0};
             for (int i = r0 + tid; i < r1; i += CG_THREADS) {
@@ -1262,14 +1285,14 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             }
             gs.template sync<true>();
             const double rho_new = grid_total(p.part, PART_RZ, G, &cg_bcast);
-            rr = grid_total(p.part, PART_RR, G, &cg_bcast);
+            const double rnorm = sqrt(grid_total(p.part, PART_RR, G, &cg_bcast));
             ++k;
-            if (JACOBI && !(rho_new > 0.0) && rr > 0.0) { status = 2; break; }
+            if (JACOBI && !(rho_new > 0.0) && rnorm > 0.0) { broke = true; break; }
+            rmax = fmax(rmax, rnorm);
+            if (rnorm <= p.update_tol * rmax || rnorm <= p.tol * bnorm * sc || k >= p.maxit) break;
             beta = rho_new / rho;
             rho = rho_new;
         }
-        // x += d / s on own rows (read by every workgroup in the next residual)
-        for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(p.x + i, p.x[i] + (double)p.d32[i] / sc);
         ++outer;
     }
     if (g == 0 && tid == 0) {

@@ -1,14 +1,18 @@
-"""GPU parity of the mixed-precision CG (FP64 refinement around FP32 CG).
+"""GPU parity of the mixed-precision CG (one FP32 CG recurrence with FP64
+residual replacement).
 
-The oracle runs the same refinement algorithm in plain C (FP32 storage and
-arithmetic for the inner solve, FP64 dots and outer residual).  Rounding
+The oracle runs the same algorithm in plain C (FP32 storage and arithmetic
+for the recurrence, FP64 dots, iterate and replaced residual).  Rounding
 orders differ, so parity is: the same status, the true FP64 relative
 residual (recomputed on the host from the returned x) within tol, x equal to
-the FP64 oracle solution within kappa * tol, the same number of outer steps
-(+-1) and a total inner iteration count within max(5, 10%) of the oracle's:
-the GPU's FP32 recurrences use fused multiply-adds and the oracle's do not,
-and FP32 CG loses orthogonality early, so the inner Krylov sequences drift
-apart by a few iterations per outer step.
+the FP64 oracle solution within kappa * tol, a replacement count within
+max(2, 20%) and a total FP32 iteration count within max(5, 15%) of the
+oracle's: the GPU's FP32 recurrences use fused multiply-adds and the
+oracle's do not, so the replacement points move and FP32 CG's loss of
+orthogonality (which can cost up to about a tenth of the iterations on 2D
+Poisson, depending on where replacements fall) differs between the two.  And
+the property the scheme exists for: the FP32 iteration count stays within
+15% of the FP64 oracle CG's (the Krylov space survives the replacements).
 """
 import math
 
@@ -79,28 +83,31 @@ def test_mixed_matches_oracle(pk, baseline, precond, case, tol):
     assert rt <= tol * 1.001 and abs(info["relres_true"] - rt) <= 1e-3 * tol + 1e-15
     xs, _ = oracle.cg(rp, ci, v, b, tol=1e-13, maxit=20000, precond=precond)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * tol
-    assert abs(info["outer"] - oinfo["outer"]) <= 1
-    assert abs(info["iters"] - oinfo["iters"]) <= max(5, math.ceil(0.10 * oinfo["iters"]))
+    assert abs(info["outer"] - oinfo["outer"]) <= max(2, math.ceil(0.2 * oinfo["outer"]))
+    assert abs(info["iters"] - oinfo["iters"]) <= max(5, math.ceil(0.15 * oinfo["iters"]))
+    _, finfo = oracle.cg(rp, ci, v, b, tol=tol, maxit=20000, precond=precond)
+    assert info["iters"] <= 1.15 * finfo["iters"] + 2, (info["iters"], finfo["iters"])
 
 
 def test_persistent_and_baseline_agree(pk):
     rp, ci, v, b, _ = _case("poisson2d")
     x1, i1 = _solve(pk, rp, ci, v, b, 1e-10)
     x2, i2 = _solve(pk, rp, ci, v, b, 1e-10, baseline=True)
-    assert i1["outer"] == i2["outer"]
-    assert abs(i1["iters"] - i2["iters"]) <= max(2, math.ceil(0.02 * i2["iters"]))
+    assert abs(i1["outer"] - i2["outer"]) <= 1
+    assert abs(i1["iters"] - i2["iters"]) <= max(2, math.ceil(0.05 * i2["iters"]))
     assert np.linalg.norm(x1 - x2) / np.linalg.norm(x2) <= 1e-7
 
 
-def test_check_every_only_delays_the_inner_stop(pk):
-    """The host reads the inner residual every 8 iterations: each inner solve
-    may run up to 7 iterations longer (deeper reduction per outer step, so
-    possibly fewer outer steps); the answer still meets tol."""
+def test_check_every_only_delays_the_replacements(pk):
+    """The host reads the FP32 residual every 8 iterations: each replacement
+    may come up to 7 iterations later (a deeper fall per replacement, so
+    usually fewer of them); the answer still meets tol."""
     rp, ci, v, b, _ = _case("poisson3d")
     x1, i1 = _solve(pk, rp, ci, v, b, 1e-9, baseline=True, check_every=1)
     x8, i8 = _solve(pk, rp, ci, v, b, 1e-9, baseline=True, check_every=8)
     assert i8["status"] == "converged" and i1["status"] == "converged"
-    assert i8["outer"] <= i1["outer"]
+    assert i8["outer"] <= i1["outer"] + 1
+    assert abs(i8["iters"] - i1["iters"]) <= max(8, math.ceil(0.15 * i1["iters"]))
     assert _true_relres(rp, ci, v, b, x8) <= 1e-9 * 1.001
 
 
@@ -129,7 +136,7 @@ def test_mixed_edge_cases(pk, baseline):
 
 
 def test_stagnation_is_reported_not_hidden(pk):
-    """kappa * u32 >> 1: refinement cannot converge; the solver must say so."""
+    """kappa * u32 >> 1: FP32 cannot resolve the system; the solver must say so."""
     n = 32
     rng = np.random.default_rng(11)
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
