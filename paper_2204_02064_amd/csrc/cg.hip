@@ -32,7 +32,7 @@ namespace perks {
 
 // The register-resident FP64 solver kernel (cg_reg.hip) and its launch
 // shape: threads per workgroup, rows per thread.
-const void *cg_reg_kernel(bool jacobi, int *threads, int *rows_per_thread);
+const void *cg_reg_kernel(bool jacobi, bool mixed, int *threads, int *rows_per_thread);
 
 namespace {
 
@@ -328,9 +328,10 @@ int check_csr(const perks_csr *A, const void *b, const void *x, double tol, int 
 
 // Work area of one problem: the partial-sum table (NPART per workgroup) and
 // 64 result words, then the vectors.  FP64 solver: r, z, q, p, dinv (n
-// doubles each).  Mixed solver: r64 (n doubles); r, z, q, p, d, dinv (n
-// floats each); the FP32 copy of A's values (nnz floats).  Every vector starts
-// on a 256-byte boundary.
+// doubles each), the sliced-ELL values and indices.  Mixed solver: r64 (n
+// doubles); r, z, q, p, d, dinv (n floats each); the FP32 copy of A's values
+// (nnz floats); the sliced-ELL FP32 values and indices, and the FP64 values of
+// the same layout.  Every vector starts on a 256-byte boundary.
 size_t vec_len(int64_t n) { return ((size_t)n + 63) / 64 * 64 + 64; }
 
 size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
@@ -340,7 +341,7 @@ size_t inst_bytes(int64_t n, int64_t nnz, int parts, bool mixed) {
     size_t bytes = (np + 64) * sizeof(double);
     if (mixed)
         bytes += nv * sizeof(double) + 6 * nv * sizeof(float) + (((size_t)nnz + 63) / 64 * 64) * sizeof(float) +
-                 ns * (sizeof(float) + sizeof(int));
+                 ns * (sizeof(float) + sizeof(int) + sizeof(double));
     else
         bytes += 5 * nv * sizeof(double) + ns * (sizeof(double) + sizeof(int));
     bytes += nv * sizeof(int);   // sperm
@@ -367,6 +368,7 @@ void carve(char *base, int64_t n, int64_t nnz, int parts, bool mixed, CgInst *w)
         w->sval32 = w->val32 + ((size_t)nnz + 63) / 64 * 64;
         w->scol = (int *)(w->sval32 + ns);
         w->sperm = w->scol + ns;
+        w->sval64 = (double *)(w->sperm + nv);   // FP64 values of the sliced-ELL layout
     } else {
         double *d = (double *)v;
         w->r = d;
@@ -535,12 +537,12 @@ int cg_persistent_solve(const perks_csr *A, const void *b, void *x, double tol, 
     void *args[] = {&pdev, &ws};
     note_persistent_launch(G, nullptr);
     double h[8] = {0};
-    // FP64: first the solver with register-resident own rows when the rows
-    // per workgroup suggest they fit (it reports CG_STATUS_NOREG and leaves
-    // after its set-up when a slice does not)
+    // first the solver with register-resident own rows when the rows per
+    // workgroup suggest they fit (it reports CG_STATUS_NOREG and leaves after
+    // its set-up when a slice does not)
     bool done = false;
     int reg_threads = 0, reg_rows = 0;
-    const void *fr = (mixed || A->spmv != 0) ? nullptr : cg_reg_kernel(jac, &reg_threads, &reg_rows);
+    const void *fr = A->spmv != 0 ? nullptr : cg_reg_kernel(jac, mixed, &reg_threads, &reg_rows);
     if (fr && (double)A->n / G <= 0.95 * reg_threads * reg_rows && !noreg_known(A, G)) {
         hipError_t e = hipLaunchCooperativeKernel(fr, dim3(G), dim3(reg_threads), args, 0, st);
         if (e != hipSuccess) return launch_error(e);

@@ -205,8 +205,11 @@ __host__ __device__ inline size_t sell_capacity(int64_t nnz, int G) {
     return (size_t)(nnz + nnz / 4) + 64 * (size_t)G + 64;
 }
 
+// sval64, when given (mixed-precision solvers), also receives the FP64 values
+// of the sliced-ELL layout (from p.val), for the FP64 residual replacements.
 template <typename T, bool MERGE = false>
-__device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int *scol, int g, int G) {
+__device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int *scol, int g, int G,
+                                            double *sval64 = nullptr) {
     Slice sl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     sl.r0 = merge_split(p.rowptr, p.n, p.nnz, g, G);
@@ -343,6 +346,7 @@ __device__ __forceinline__ Slice load_slice(CInst &p, const T *val, T *sval, int
                 const int e = off + j * 64 + lane;
                 sval[sl.sbase + e] = a;
                 scol[sl.sbase + e] = cidx;
+                if (sval64) sval64[sl.sbase + e] = j < kn ? p.val[kb + j] : 0.0;
                 if (c < cc) {
                     LdsA<T>::val(e) = a;
                     LdsA<T>::col(e) = cidx;
@@ -1156,8 +1160,11 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
         const int s1 = p.rowptr[merge_split(p.rowptr, p.n, p.nnz, g + 1, G)];
         for (int k = s0 + tid; k < s1; k += CG_THREADS) p.val32[k] = (float)p.val[k];
     }
-    const Slice sl = load_slice<float, MERGE>(p, (const float *)p.val32, p.sval32, p.scol, g, G);   // its barriers publish val32
+    // its barriers publish val32
+    const Slice sl = load_slice<float, MERGE>(p, (const float *)p.val32, p.sval32, p.scol, g, G, p.sval64);
     const int r0 = sl.r0, r1 = sl.r1, kbase = sl.kbase, L = sl.L;
+    Slice s64 = sl;
+    s64.cc = 0;   // the FP64 sliced-ELL values are read from global memory only
     double accb[1] = {0.0};
     for (int i = r0 + tid; i < r1; i += CG_THREADS) {
         if (JACOBI) {
@@ -1190,14 +1197,19 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
             rn = 0.0;
             break;
         }
-        // true residual in FP64 (A from global memory in FP64)
+        // true residual in FP64 (A from global memory in FP64: its sliced-ELL
+        // copy when the slice has that layout, else CSR)
         double accr[1] = {0.0};
-        spmv_range<CG_U, false>(p.rowptr, p.colind, p.val, r0, r1, L, kbase, [&](int c) { return p.x[c]; },
-                                [&](int i, double sv) {
-                                    const double ri = p.b[i] - sv;
-                                    p.r64[i] = ri;
-                                    accr[0] = __builtin_fma(ri, ri, accr[0]);
-                                });
+        {
+            auto fx = [&](int c) { return p.x[c]; };
+            auto sink = [&](int i, double sv) {
+                const double ri = p.b[i] - sv;
+                p.r64[i] = ri;
+                accr[0] = __builtin_fma(ri, ri, accr[0]);
+            };
+            if (sl.sell) spmv_slice<CG_U, false>(p, s64, p.val, (const double *)p.sval64, p.scol, fx, sink);
+            else spmv_range<CG_U, false>(p.rowptr, p.colind, p.val, r0, r1, L, kbase, fx, sink);
+        }
         block_sum<1>(accr, cg_red);
         if (tid == 0) st_coh(p.part + (size_t)PART_TRUE * G + g, accr[0]);
         gs.template sync<true>();
@@ -1305,6 +1317,218 @@ __device__ __forceinline__ void cg_mixed_body(CInst &p, Sync &gs, const int g, c
     }
 }
 
+// Mixed-precision persistent CG with register-resident own rows: the FP32
+// r, p, q, d (and D^{-1}) of the thread's rows stay in registers for the whole
+// solve (see CG_REF_WAVES for the row mapping), so an FP32 iteration moves
+// A's values beyond the LDS copy, p once published and once gathered, and
+// nothing else; x and the FP64 residual are touched only at replacements.
+// The arithmetic and its order are those of cg_mixed_body, row for row and
+// sum for sum, so both give the same bits.  The same eligibility rule as
+// cg_f64_reg (CG_STATUS_NOREG when a slice does not allow it).
+template <bool JACOBI, class Sync>
+__device__ __forceinline__ void cg_mixed_reg(CInst *pin, Sync &gs, const int g, const int G) {
+    constexpr int M = CG_VT * CG_RV;
+    CInst *pp = opaque(pin);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    {
+        const int s0 = pp->rowptr[merge_split(pp->rowptr, pp->n, pp->nnz, g, G)];
+        const int s1 = pp->rowptr[merge_split(pp->rowptr, pp->n, pp->nnz, g + 1, G)];
+        for (int k = s0 + tid; k < s1; k += CG_THREADS) pp->val32[k] = (float)pp->val[k];
+    }
+    const Slice sl = load_slice<float>(*pp, (const float *)pp->val32, pp->sval32, pp->scol, g, G, pp->sval64);
+    const int r0 = sl.r0, r1 = sl.r1;
+    Slice s64 = sl;
+    s64.cc = 0;
+    float rv[M], pv[M], qv[M], dv[M], wv[M];
+    double accb[CG_VT][1] = {};
+    {
+        const int lb = launder_v(lane);
+        static_for<0, M>([&](auto mc) {
+            constexpr int m = decltype(mc)::value, h = m / CG_RV;
+            const int i = reg_row(r0, wave, lb, m);
+            rv[m] = pv[m] = qv[m] = dv[m] = 0.0f;
+            wv[m] = 1.0f;
+            if (i < r1) {
+                if (JACOBI) {
+                    double dg = 0.0;
+                    for (int k = pp->rowptr[i]; k < pp->rowptr[i + 1]; ++k)
+                        if (pp->colind[k] == i) dg += pp->val[k];
+                    wv[m] = (float)(1.0 / dg);
+                }
+                const double bi = pp->b[i];
+                accb[h][0] = __builtin_fma(bi, bi, accb[h][0]);
+            }
+        });
+    }
+    block_sum_ref<1>(accb);
+    {
+        const bool fits = sl.sell && !sl.perm && sl.nch <= CG_REF_WAVES * CG_RV;
+        if (tid == 0) {
+            st_coh(pp->part + (size_t)PART_TRUE * G + g, fits ? 1.0 : 0.0);
+            st_coh(pp->part + (size_t)PART_BB * G + g, accb[0][0]);
+        }
+        gs.template sync<true>();
+        if (grid_total(pp->part, PART_TRUE, G, &cg_bcast) != (double)G) {
+            if (g == 0 && tid == 0) {
+                pp->result[0] = 0;
+                pp->result[1] = CG_STATUS_NOREG;
+            }
+            return;
+        }
+    }
+    const double bnorm = sqrt(grid_total(pp->part, PART_BB, G, &cg_bcast));
+    double rn = 0.0, best = INFINITY, sc = 1.0, rho = 0.0;
+    int k = 0, outer = 0, status = 1, stall = 0;
+    bool broke = false;
+    for (;;) {
+        pp = opaque(pin);
+        // replacement: fold the FP32 correction into x (own rows)
+        {
+            const int lb = launder_v(lane);
+            static_for<0, M>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                const int i = reg_row(r0, wave, lb, m);
+                if (i < r1) st_coh(pp->x + i, pp->x[i] + (double)dv[m] / sc);
+            });
+        }
+        gs.template sync<true>();
+        if (bnorm == 0.0) {
+            for (int i = r0 + tid; i < r1; i += CG_THREADS) st_coh(pp->x + i, 0.0);
+            status = 0;
+            rn = 0.0;
+            break;
+        }
+        // true residual in FP64 (sliced-ELL FP64 values from global memory);
+        // r64 of own rows kept in memory until the new scale is known
+        double accr[CG_VT][1] = {};
+        spmv_sell_reg(s64, (const double *)pp->sval64, pp->scol, [&](int c) { return pp->x[c]; },
+                      [&](auto mc, int i, double sv) {
+                          constexpr int h = decltype(mc)::value / CG_RV;
+                          const double ri = pp->b[i] - sv;
+                          pp->r64[i] = ri;
+                          accr[h][0] = __builtin_fma(ri, ri, accr[h][0]);
+                      });
+        block_sum_ref<1>(accr);
+        if (tid == 0) st_coh(pp->part + (size_t)PART_TRUE * G + g, accr[0][0]);
+        gs.template sync<true>();
+        rn = sqrt(grid_total(pp->part, PART_TRUE, G, &cg_bcast));
+        if (rn <= pp->tol * bnorm) { status = 0; break; }
+        if (broke) { status = 2; break; }
+        if (rn < best) {
+            best = rn;
+            stall = 0;
+        } else if (++stall >= PERKS_MIXED_STALL) {
+            break;
+        }
+        if (k >= pp->maxit || outer >= pp->max_outer) break;
+        int ex;
+        (void)frexp(rn, &ex);
+        const double sc_new = ldexp(1.0, 1 - ex);   // 2^-floor(log2 rn)
+        const double ratio = outer == 0 ? 1.0 : sc_new / sc;   // first: p is 0
+        const float ratio_f = (float)ratio;
+        double acc0[CG_VT][2] = {};
+        {
+            const int lb = launder_v(lane);
+            static_for<0, M>([&](auto mc) {
+                constexpr int m = decltype(mc)::value, h = m / CG_RV;
+                const int i = reg_row(r0, wave, lb, m);
+                if (i < r1) {
+                    const float ri = (float)(pp->r64[i] * sc_new);
+                    const float zi = JACOBI ? wv[m] * ri : ri;
+                    rv[m] = ri;
+                    pv[m] = pv[m] * ratio_f;
+                    dv[m] = 0.0f;
+                    acc0[h][0] = __builtin_fma((double)ri, (double)zi, acc0[h][0]);
+                    acc0[h][1] = __builtin_fma((double)ri, (double)ri, acc0[h][1]);
+                }
+            });
+        }
+        block_sum_ref<2>(acc0);
+        if (tid == 0) {
+            st_coh(pp->part + (size_t)PART_RZ * G + g, acc0[0][0]);
+            st_coh(pp->part + (size_t)PART_RR * G + g, acc0[0][1]);
+        }
+        gs.template sync<true>();
+        const double rho_r = grid_total(pp->part, PART_RZ, G, &cg_bcast);
+        double beta = outer == 0 ? 0.0 : rho_r / (rho * ratio * ratio);
+        rho = rho_r;
+        sc = sc_new;
+        double rmax = sqrt(grid_total(pp->part, PART_RR, G, &cg_bcast));
+        for (;;) {
+            pp = opaque(pin);
+            // phase P: p = z + beta p on own rows, published for the gathers
+            const float bf = (float)beta;
+            float *pn = pp->p32;
+            {
+                const int lb = launder_v(lane);
+                static_for<0, M>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    const int i = reg_row(r0, wave, lb, m);
+                    const float zi = JACOBI ? wv[m] * rv[m] : rv[m];
+                    pv[m] = __builtin_fmaf(bf, pv[m], zi);
+                    if (i < r1) st_coh(pn + i, pv[m]);
+                });
+            }
+            gs.template sync<true>();
+            // phase 1: q = A p (FP32), partial p.q in FP64
+            double acc1[CG_VT][1] = {};
+            spmv_sell_reg(sl, (const float *)pp->sval32, pp->scol, [&](int c) { return pn[c]; },
+                          [&](auto mc, int i, float sv) {
+                              constexpr int m = decltype(mc)::value, h = m / CG_RV;
+                              qv[m] = sv;
+                              acc1[h][0] = __builtin_fma((double)pv[m], (double)sv, acc1[h][0]);
+                          });
+            block_sum_ref<1>(acc1);
+            if (tid == 0) st_coh(pp->part + (size_t)PART_PQ * G + g, acc1[0][0]);
+            gs.template sync<true>();
+            const double pq = grid_total(pp->part, PART_PQ, G, &cg_bcast);
+            if (!(pq > 0.0) || !isfinite(pq)) { broke = true; break; }
+            const float af = (float)(rho / pq);
+            // phase 2: d, r updates on own rows, partials r.z, r.r in FP64
+            double acc2[CG_VT][2] = {};
+            {
+                const int lb = launder_v(lane);
+                static_for<0, M>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value, h = m / CG_RV;
+                    const int i = reg_row(r0, wave, lb, m);
+                    if (i < r1) {
+                        dv[m] = __builtin_fmaf(af, pv[m], dv[m]);
+                        const float ri = __builtin_fmaf(-af, qv[m], rv[m]);
+                        rv[m] = ri;
+                        const float zi = JACOBI ? wv[m] * ri : ri;
+                        acc2[h][0] = __builtin_fma((double)ri, (double)zi, acc2[h][0]);
+                        acc2[h][1] = __builtin_fma((double)ri, (double)ri, acc2[h][1]);
+                    }
+                });
+            }
+            block_sum_ref<2>(acc2);
+            if (tid == 0) {
+                st_coh(pp->part + (size_t)PART_RZ * G + g, acc2[0][0]);
+                st_coh(pp->part + (size_t)PART_RR * G + g, acc2[0][1]);
+            }
+            gs.template sync<true>();
+            const double rho_new = grid_total(pp->part, PART_RZ, G, &cg_bcast);
+            const double rnorm = sqrt(grid_total(pp->part, PART_RR, G, &cg_bcast));
+            ++k;
+            if (JACOBI && !(rho_new > 0.0) && rnorm > 0.0) { broke = true; break; }
+            rmax = fmax(rmax, rnorm);
+            if (rnorm <= pp->update_tol * rmax || rnorm <= pp->tol * bnorm * sc || k >= pp->maxit) break;
+            beta = rho_new / rho;
+            rho = rho_new;
+        }
+        ++outer;
+    }
+    if (g == 0 && tid == 0) {
+        pp->result[0] = k;
+        pp->result[1] = status;
+        pp->result[2] = bnorm > 0.0 ? rn / bnorm : 0.0;
+        pp->result[3] = bnorm > 0.0 ? rn / bnorm : 0.0;
+        pp->result[4] = bnorm;
+        pp->result[5] = outer;
+    }
+}
+
 // One problem on the whole grid.
 template <bool JACOBI, bool MIXED, bool MERGE>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, unsigned *ws) {
@@ -1319,16 +1543,17 @@ __global__ __launch_bounds__(CG_THREADS) void cg_persistent(const CgInst *pin, u
     clk.publish(ws);
 }
 
-// One problem on the whole grid, own rows in registers (FP64; status
-// CG_STATUS_NOREG when a slice does not allow it).  Instantiated by
-// cg_reg.hip only.
-template <bool JACOBI>
+// One problem on the whole grid, own rows in registers (FP64 or mixed
+// precision; status CG_STATUS_NOREG when a slice does not allow it).
+// Instantiated by cg_reg.hip only.
+template <bool JACOBI, bool MIXED>
 __global__ __launch_bounds__(CG_THREADS) void cg_persistent_reg(const CgInst *pin, unsigned *ws) {
     BarrierClock clk;
     clk.start();
     GroupSync gs;
     gs.init_grid(ws, &clk);
-    cg_f64_reg<JACOBI>((CInst *)pin, gs, blockIdx.x, gridDim.x);
+    if (MIXED) cg_mixed_reg<JACOBI>((CInst *)pin, gs, blockIdx.x, gridDim.x);
+    else cg_f64_reg<JACOBI>((CInst *)pin, gs, blockIdx.x, gridDim.x);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(ws + SYNC_EPOCH, gs.epoch);
     clk.publish(ws);
 }

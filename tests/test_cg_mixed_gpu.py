@@ -89,6 +89,27 @@ def test_mixed_matches_oracle(pk, baseline, precond, case, tol):
     assert info["iters"] <= 1.15 * finfo["iters"] + 2, (info["iters"], finfo["iters"])
 
 
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d", "random"])
+def test_register_resident_solver_is_bitwise_the_memory_resident_one(pk, precond, case):
+    """The library's choice runs the solver with register-resident own rows
+    when every slice allows it; it reproduces the memory-resident solver's
+    arithmetic (spmv="sell" forces that one) bit for bit."""
+    rp, ci, v, b, _ = _case(case)
+    print(f"mixed CG registers vs memory {case} precond={precond}", flush=True)
+    out = []
+    for spmv in ("auto", "sell"):
+        A = pk.CsrMatrix(rp, ci, v, spmv=spmv)
+        bd, xd = to_dev(b), to_dev(np.zeros_like(b))
+        info = pk.cg_solve(A, bd, xd, tol=1e-10, maxit=5000, precond=precond, precision="mixed")
+        torch.cuda.synchronize()
+        out.append((xd.cpu().numpy(), info))
+    (x1, i1), (x2, i2) = out
+    assert i1["status"] == i2["status"] == "converged"
+    assert (i1["iters"], i1["outer"]) == (i2["iters"], i2["outer"])
+    np.testing.assert_array_equal(x1, x2)
+
+
 def test_persistent_and_baseline_agree(pk):
     rp, ci, v, b, _ = _case("poisson2d")
     x1, i1 = _solve(pk, rp, ci, v, b, 1e-10)
