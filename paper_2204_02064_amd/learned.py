@@ -1,9 +1,9 @@
 """Training of the learned preconditioner from pairs the persistent CG produces.
 
 Pairs: for a diffusion problem A x = f with log-permeability log k, the
-persistent Jacobi-preconditioned CG is run to a tight tolerance for x*, then
-run again with snapshots of its iterate x_k and residual r_k after
-k = 1, 2, 4, 8, ... iterations; each snapshot gives the network input
+persistent Jacobi-preconditioned CG is run to a tight tolerance, with
+snapshots of its iterate x_k and residual r_k after k = 1, 2, 4, 8, ...
+iterations; its final iterate is x*; each snapshot gives the network input
 [r_k / rms(r_k), log k] and the target (x* - x_k - D^-1 r_k) / rms(r_k): the
 preconditioner returns D^-1 r + rms(r) net(...), so the network's part of the
 error e_k = x* - x_k is what the Jacobi step leaves of it.
@@ -19,7 +19,7 @@ components a local network cannot represent nor by the scale of e.
 """
 import numpy as np
 
-from . import CsrMatrix, cg_solve, cg_solve_capture, nn_make_pairs, nn_pack_params, nn_train
+from . import CsrMatrix, cg_solve_capture, nn_make_pairs, nn_pack_params, nn_train
 
 CAPTURE_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
 
@@ -29,17 +29,16 @@ def harvest_pairs(problems, iters=CAPTURE_ITERS, tol=1e-12, maxit=20000, with_fi
     tensors on the device.  Returns (inputs [P, n, n, 2] float32, targets
     [P, n, n] float32) device tensors, and with ``with_field`` also the index
     of each pair's problem (int64 [P]).  Every step runs in the library: the
-    two Jacobi-PCG solves (x*, then the captured iterates) and the pair
-    formation (perks_nn_make_pairs); here only allocation and concatenation."""
+    Jacobi-PCG solve with captured iterates (its final iterate is x*) and the
+    pair formation (perks_nn_make_pairs); here only allocation and
+    concatenation."""
     import torch
     xs, ts, fi = [], [], []
     for pid, (rp, ci, v, lk, f) in enumerate(problems):
         n = lk.shape[0]
         A = CsrMatrix(rp, ci, v)
         xstar = torch.zeros_like(f)
-        cg_solve(A, f, xstar, tol=tol, maxit=maxit, precond="jacobi")
-        x = torch.zeros_like(f)
-        info, xc, rc = cg_solve_capture(A, f, x, iters, tol=tol, maxit=maxit, precond="jacobi")
+        info, xc, rc = cg_solve_capture(A, f, xstar, iters, tol=tol, maxit=maxit, precond="jacobi")
         X, T = nn_make_pairs(A, xstar, lk.contiguous(), xc, rc, n, n)
         xs.append(X)
         ts.append(T)
