@@ -72,12 +72,18 @@ typedef struct perks_tuning {
     int32_t kernel;           /* 2D radius 1: 0 the library's choice, 1 the radius-1
                                  kernel (LDS rows, point-to-point halos), 2 the
                                  radius-2..4 kernel run at radius 1 (grid barrier,
-                                 24/32/48/80 register rows).  With every field of the
-                                 struct zero (or tune NULL) the library takes kernel 2
-                                 when the interior holds >= 2^20 cells and kernel 2
-                                 caches every tile, else kernel 1; any other nonzero
-                                 field selects kernel 1 unless kernel = 2.           */
-    int32_t reserved;
+                                 24/32/48/80 register rows), 3 the temporally blocked
+                                 kernel (tiles of 64 - 2K columns x rows_per_lane (8
+                                 or 16) rows, each wave taking K steps on its tile and
+                                 a K-wide ghost ring in registers between grid
+                                 barriers; K = steps_per_sync).  With every field of
+                                 the struct zero (or tune NULL) the library takes
+                                 kernel 2 when the interior holds >= 2^20 cells and
+                                 kernel 2 caches every tile, else kernel 1; any other
+                                 nonzero field selects kernel 1 unless kernel = 2
+                                 or 3.                                                */
+    int32_t steps_per_sync;   /* kernel 3: K, steps between exchanges (2, 4 or 8; 0
+                                 means 4)                                             */
 } perks_tuning;
 
 /* Plan a call would use (for reporting and for the performance model). */
@@ -91,7 +97,10 @@ typedef struct {
     int64_t cached_cells;     /* interior cells held on chip                          */
     int64_t interior_cells;
     int64_t halo_bytes_per_step;  /* face traffic written + read per step             */
-    int32_t sync;             /* 1 grid barrier per step, 2 point-to-point halo words */
+    int32_t sync;             /* 1 grid barrier per step, 2 point-to-point halo words,
+                                 3 a grid barrier every steps_per_sync steps (kernel
+                                 3; halo_bytes_per_step then counts the tiles' block
+                                 reads and writes per step)                           */
     int32_t lds_rows_per_lane;/* rows of each cached tile held in LDS (PERKS_MIX)     */
 } perks_stencil_plan;
 

@@ -37,7 +37,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_wg", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("planes_per_lane", ctypes.c_int32),
                 ("sync", ctypes.c_int32), ("max_cached_tiles", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32)]
 
 
 class StencilPlan(ctypes.Structure):
@@ -279,7 +279,7 @@ def stencil_autotune(shape, weights, dtype="float64", probe_steps=50, remember=T
     _check(lib().perks_stencil_autotune(w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sh, dt, int(probe_steps),
                                         1 if remember else 0, _stream_handle(stream), ctypes.byref(t),
                                         ctypes.byref(rate)))
-    return {f: getattr(t, f) for f, _ in Tuning._fields_ if f != "reserved"}, rate.value
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}, rate.value
 
 
 def device_info():

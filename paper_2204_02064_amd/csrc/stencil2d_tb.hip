@@ -1,0 +1,257 @@
+// 2D radius-1 Jacobi stencils (Eq. 2, the 5-point star and the 9-point box of
+// tab:domain), temporally blocked persistent kernel for small grids.
+//
+// On a small grid a step costs a few microseconds, almost all of it the
+// latency of the halo exchange between CUs (a store that other CUs must see,
+// then their loads), so the persistent kernel exchanges only every K steps:
+// each wavefront owns a tile of OW = 64 - 2K columns x H rows and holds the
+// tile plus a ring of K ghost columns and rows in registers (lane l keeps
+// column x0 - K + l, rows y0 - K .. y0 + H + K - 1); it then takes K Jacobi
+// steps on that block with no exchange at all (neighbours along y in the
+// lane's registers, along x by DPP lane shifts).  Each step leaves the cells
+// one row and one column further in from the block's edge exact, so after K
+// steps the owned tile is exact: the ghost ring is recomputed instead of
+// exchanged (overlapped temporal blocking).  The tile is then stored into
+// the other of two grid buffers, and one device-wide barrier precedes the
+// next block's loads.  The grid lives in the two buffers between blocks (on
+// a small grid, in the caches); the paper's register cache holds each block
+// for K steps.
+//
+// Every cell is summed in ascending (dy, dx) order, one multiply then FMAs,
+// as the per-step baseline does, so the two agree bit for bit.  Ring cells
+// and clamped copies outside the grid are never updated.
+#include <algorithm>
+
+#include "barrier.hpp"
+#include "common.hpp"
+#include "stencil_api.hpp"
+
+namespace perks {
+namespace {
+
+constexpr int TBW = 4;   // waves per workgroup
+
+template <typename T>
+struct TB2DParams {
+    gmem<T> *buf0;   // the caller's grid
+    gmem<T> *buf1;   // second buffer of the same extents (ring copied in)
+    unsigned *sync;
+    int64_t steps;
+    int nx, ny;
+    int ntx, nty;    // tiles along x (OW columns) and y (H rows)
+    T w[9];          // [dy + 1][dx + 1]
+};
+
+// One Jacobi step of a block of RB rows x 64 lanes, in place.  Rows 0 and
+// RB - 1 lack a neighbour row and lanes 0 and 63 a neighbour column: their
+// new values are not exact and are never used (they lie outside the region
+// that is still exact after this step).
+template <typename T, bool BOX, int RB>
+__device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
+    T pv = u[0], pw = from_west(pv, pv), pe = from_east(pv, pv);
+    T cv = u[1], cw = from_west(cv, cv), ce = from_east(cv, cv);
+#pragma unroll
+    for (int i = 1; i < RB - 1; ++i) {
+        const T nv = u[i + 1];
+        const T nw = from_west(nv, nv), ne = from_east(nv, nv);
+        T acc;
+        if constexpr (BOX) {
+            acc = w[0] * pw;
+            acc = fma_t(w[1], pv, acc);
+            acc = fma_t(w[2], pe, acc);
+            acc = fma_t(w[3], cw, acc);
+            acc = fma_t(w[4], cv, acc);
+            acc = fma_t(w[5], ce, acc);
+            acc = fma_t(w[6], nw, acc);
+            acc = fma_t(w[7], nv, acc);
+            acc = fma_t(w[8], ne, acc);
+        } else {
+            acc = w[1] * pv;
+            acc = fma_t(w[3], cw, acc);
+            acc = fma_t(w[4], cv, acc);
+            acc = fma_t(w[5], ce, acc);
+            acc = fma_t(w[7], nv, acc);
+        }
+        const int y = y0 + i;
+        u[i] = (lane_in && y >= 1 && y <= ny - 2) ? acc : cv;
+        pv = cv;
+        pw = cw;
+        pe = ce;
+        cv = nv;
+        cw = nw;
+        ce = ne;
+    }
+}
+
+template <typename T, bool BOX, int K, int H>
+__global__ __launch_bounds__(TBW * 64) void stencil2d_tb(TB2DParams<T> p) {
+    constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = blockIdx.x * TBW + wave, nw = gridDim.x * TBW;
+    const int ntiles = p.ntx * p.nty;
+    T w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = p.w[k];
+    GridSync gs;
+    gs.init(p.sync);
+    int64_t blk = 0;
+    for (int64_t s0 = 0; s0 < p.steps; s0 += K, ++blk) {
+        const int kk = (int)std::min<int64_t>(K, p.steps - s0);
+        const gmem<T> *src = opaque((blk & 1) ? p.buf1 : p.buf0);
+        gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
+        for (int t = gw; t < ntiles; t += nw) {
+            const int tx = t % p.ntx, ty = t / p.ntx;
+            const int xg = 1 + OW * tx - K + lane;   // this lane's column
+            const int y0 = 1 + H * ty - K;           // the block's first row
+            const int xc = min(max(xg, 0), p.nx - 1);
+            T u[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int yc = min(max(y0 + i, 0), p.ny - 1);
+                u[i] = ld_coh(src + (size_t)yc * p.nx + xc);
+            }
+            const bool lane_in = xg >= 1 && xg <= p.nx - 2;
+            for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB>(u, w, lane_in, y0, p.ny);
+            const bool own = lane_in && lane >= K && lane < K + OW;
+#pragma unroll
+            for (int i = K; i < K + H; ++i) {
+                const int y = y0 + i;
+                if (own && y >= 1 && y <= p.ny - 2) st_coh(dst + (size_t)y * p.nx + xg, u[i]);
+            }
+        }
+        gs.sync();
+    }
+    if (blk & 1) {
+        // the result is in the second buffer: each wave copies back the cells
+        // it stored there in the last block
+        for (int t = gw; t < ntiles; t += nw) {
+            const int tx = t % p.ntx, ty = t / p.ntx;
+            const int xg = 1 + OW * tx - K + lane;
+            const int y0 = 1 + H * ty - K;
+            const bool own = xg >= 1 && xg <= p.nx - 2 && lane >= K && lane < K + OW;
+            for (int i = K; i < K + H; ++i) {
+                const int y = y0 + i;
+                if (own && y >= 1 && y <= p.ny - 2) {
+                    const size_t e = (size_t)y * p.nx + xg;
+                    p.buf0[e] = ld_coh(p.buf1 + e);
+                }
+            }
+        }
+    }
+    gs.finish();
+}
+
+template <typename T, bool BOX, int K>
+const void *pick_tb_h(int h) {
+    switch (h) {
+        case 8: return reinterpret_cast<const void *>(&stencil2d_tb<T, BOX, K, 8>);
+        case 16: return reinterpret_cast<const void *>(&stencil2d_tb<T, BOX, K, 16>);
+        default: return nullptr;
+    }
+}
+
+template <typename T, bool BOX>
+const void *pick_tb(int k, int h) {
+    switch (k) {
+        case 2: return pick_tb_h<T, BOX, 2>(h);
+        case 4: return pick_tb_h<T, BOX, 4>(h);
+        case 8: return pick_tb_h<T, BOX, 8>(h);
+        default: return nullptr;
+    }
+}
+
+struct PlanTB {
+    int k = 0, h = 0, ntx = 0, nty = 0, wgs = 0;
+    const void *fn = nullptr;
+};
+
+template <typename T>
+int plan_tb(const perks_shape &s, bool box, const perks_tuning *tu, PlanTB *pl) {
+    if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel is 2D");
+    // defaults measured on MI355X (2d5pt, 100 steps): K = 8 up to 2^18
+    // interior cells (256^2: 1.57 us per step FP64, 512^2: 1.66), K = 4 above
+    // (1024^2: 2.75); 8-row tiles (more waves, shorter blocks) throughout
+    const int64_t interior = (s.nx - 2) * (s.ny - 2);
+    pl->k = (tu && tu->steps_per_sync > 0) ? tu->steps_per_sync : (interior <= (int64_t(1) << 18) ? 8 : 4);
+    pl->h = (tu && tu->rows_per_lane > 0) ? tu->rows_per_lane : 8;
+    if (tu && tu->waves_per_wg != 0 && tu->waves_per_wg != TBW)
+        return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel uses %d waves per workgroup", TBW);
+    if (tu && tu->sync != 0 && tu->sync != 1)
+        return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel synchronises with a grid barrier");
+    pl->fn = box ? pick_tb<T, true>(pl->k, pl->h) : pick_tb<T, false>(pl->k, pl->h);
+    if (!pl->fn)
+        return set_error(PERKS_E_UNSUPPORTED, "temporal blocking takes steps_per_sync 2, 4 or 8 and rows_per_lane 8 "
+                                              "or 16 (got %d, %d)", pl->k, pl->h);
+    const int ow = 64 - 2 * pl->k;
+    pl->ntx = (int)((s.nx - 2 + ow - 1) / ow);
+    pl->nty = (int)((s.ny - 2 + pl->h - 1) / pl->h);
+    const int64_t tiles = (int64_t)pl->ntx * pl->nty;
+    if (tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "grid too large for this kernel");
+    DeviceFacts f;
+    int rc = device_facts(&f);
+    if (rc) return rc;
+    int occ = 0;
+    PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl->fn, TBW * 64, 0));
+    if (occ < 1) return set_error(PERKS_E_NOTCORESIDENT, "temporally blocked kernel does not fit a CU");
+    const int wpc = (tu && tu->wgs_per_cu > 0) ? std::min(tu->wgs_per_cu, occ) : occ;
+    pl->wgs = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + TBW - 1) / TBW, (int64_t)f.cus * wpc));
+    return PERKS_OK;
+}
+
+}  // namespace
+
+template <typename T>
+int run2d_tb(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+             const perks_tuning *tu) {
+    PlanTB pl;
+    int rc = plan_tb<T>(s, box, tu, &pl);
+    if (rc) return rc;
+    const size_t cells = (size_t)s.nx * s.ny;
+    T *other = (T *)scratch(SLOT_WIDE, cells * sizeof(T));
+    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!other || !sync) return PERKS_E_NOMEM;
+    // the second buffer needs the fixed ring: copy the whole grid once
+    PERKS_HIP_TRY(hipMemcpyAsync(other, grid, cells * sizeof(T), hipMemcpyDeviceToDevice, st));
+    TB2DParams<T> p{};
+    p.buf0 = to_global(grid);
+    p.buf1 = to_global(other);
+    p.sync = sync;
+    p.steps = steps;
+    p.nx = (int)s.nx;
+    p.ny = (int)s.ny;
+    p.ntx = pl.ntx;
+    p.nty = pl.nty;
+    for (int k = 0; k < 9; ++k) p.w[k] = (T)coeffs[k];
+    return launch_coop(pl.fn, pl.wgs, TBW * 64, &p, st);
+}
+
+template <typename T>
+int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perks_stencil_plan *plan) {
+    PlanTB pl;
+    int rc = plan_tb<T>(s, box, tu, &pl);
+    if (rc) return rc;
+    const int64_t tiles = (int64_t)pl.ntx * pl.nty;
+    const int64_t rb = pl.h + 2 * pl.k, ow = 64 - 2 * pl.k;
+    plan->wgs = pl.wgs;
+    plan->waves_per_wg = TBW;
+    plan->rows_per_lane = pl.h;
+    plan->planes_per_lane = 1;
+    plan->tiles = tiles;
+    plan->cached_tiles = 0;    // between blocks the grid lives in its two buffers
+    plan->cached_cells = 0;
+    plan->interior_cells = (s.nx - 2) * (s.ny - 2);
+    // per step: each tile's block read and its owned cells written, once per K steps
+    plan->halo_bytes_per_step = tiles * (64 * rb + ow * pl.h) * (int64_t)sizeof(T) / pl.k;
+    plan->sync = 3;
+    plan->lds_rows_per_lane = 0;
+    return PERKS_OK;
+}
+
+template int run2d_tb<float>(float *, const double *, const perks_shape &, int64_t, bool, hipStream_t,
+                             const perks_tuning *);
+template int run2d_tb<double>(double *, const double *, const perks_shape &, int64_t, bool, hipStream_t,
+                              const perks_tuning *);
+template int plan2d_tb_query<float>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
+template int plan2d_tb_query<double>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
+
+}  // namespace perks

@@ -17,6 +17,13 @@ template <typename T>
 int run2d_in(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
              void *mem, size_t cap);
 
+// Temporally blocked 2D radius-1 kernel (perks_tuning.kernel = 3).
+template <typename T>
+int run2d_tb(T *grid, const double *coeffs, const perks_shape &s, int64_t steps, bool box, hipStream_t st,
+             const perks_tuning *tu);
+template <typename T>
+int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perks_stencil_plan *plan);
+
 template <typename T>
 int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
                   bool box, hipStream_t st);

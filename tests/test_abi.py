@@ -69,7 +69,10 @@ def test_invalid_arguments_are_rejected(L):
     assert L.perks_stencil_run_batched((ctypes.c_void_p * 1)(fake), (pk.Shape * 1)(pk.Shape(2, 2, 64, 64, 1)), 1,
                                        w25p, 1, 1, None) == -5
     tu = pk.Tuning()
-    tu.kernel = 3          # only 0, 1, 2
+    tu.kernel = 4          # only 0, 1, 2, 3
+    assert L.perks_stencil_run(fake, wp, pk.Shape(2, 0, 8, 8, 1), 1, 1, None, ctypes.byref(tu)) == -1
+    tu = pk.Tuning()
+    tu.steps_per_sync = 4  # for kernel 3 only
     assert L.perks_stencil_run(fake, wp, pk.Shape(2, 0, 8, 8, 1), 1, 1, None, ctypes.byref(tu)) == -1
     wn = np.full(9, np.nan)
     assert L.perks_stencil_run(fake, wn.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

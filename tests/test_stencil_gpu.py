@@ -160,6 +160,37 @@ def test_xcd_local_mode_is_refused(pk):
         pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 3})
 
 
+@pytest.mark.parametrize("k,h", [(2, 8), (4, 16), (8, 8), (8, 16)])
+@pytest.mark.parametrize("shape", [(256, 256), (130, 389), (70, 1000), (5, 3)])
+@pytest.mark.parametrize("kind", ["2d5pt", "2d9pt"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_temporally_blocked_kernel_is_bitwise_the_per_step_baseline(pk, dtype, kind, shape, k, h):
+    """kernel 3: K steps per exchange on tiles of 64 - 2K columns x h rows with
+    a K-wide ghost ring; step counts below, at and past K, ragged tiles and a
+    grid smaller than one tile."""
+    g = workloads.stencil_grid(shape, seed=21).astype(dtype)
+    w = workloads.stencil_weights(kind)
+    tt = getattr(torch, dtype)
+    tu = {"kernel": 3, "steps_per_sync": k, "rows_per_lane": h}
+    print(f"temporal blocking {kind} {shape} {dtype} K={k} H={h}", flush=True)
+    plan = pk.stencil_plan(shape, w, dtype, tuning=tu)
+    assert plan["sync"] == 3 and plan["rows_per_lane"] == h
+    for steps in sorted({1, k - 1, k, 2 * k + 1, 37} - {0}):
+        a = _run(pk, g, w, steps, tt, tuning=tu)
+        b = _run(pk, g, w, steps, tt, baseline=True)
+        np.testing.assert_array_equal(a, b, err_msg=f"steps {steps}")
+    gd = g.astype(np.float64)
+    wd = w.astype(np.float32).astype(np.float64) if dtype == "float32" else w
+    assert rel_err(a, oracle.stencil(gd, wd, 37)) <= (1e-12 if dtype == "float64" else 1e-5)
+
+
+def test_temporally_blocked_kernel_rejects_other_shapes(pk):
+    w = workloads.stencil_weights("2d5pt")
+    for tu in ({"kernel": 3, "steps_per_sync": 3}, {"kernel": 3, "rows_per_lane": 12}, {"steps_per_sync": 4}):
+        with pytest.raises(RuntimeError):
+            pk.stencil_plan((256, 256), w, "float64", tuning=tu)
+
+
 def test_repeated_launches_reuse_epochs_safely(pk):
     # consecutive persistent launches on different shapes share the face
     # buffers; stale words must never be taken for current ones
@@ -267,13 +298,20 @@ def test_full_size_bench_plans_match_oracle(pk, kind, dtype):
     assert plan["rows_per_lane"] == tu["rows_per_lane"] and plan["cached_tiles"] == plan["tiles"] > 0
 
 
-def test_untuned_small_grids_keep_the_radius1_kernel(pk):
-    """Below 2^20 interior cells the untuned plan is the radius-1 kernel
-    (point-to-point halo words); the 256^2 100-step configuration runs on it."""
+def test_untuned_small_grids_take_temporal_blocking(pk):
+    """Below 2^20 interior cells the untuned plan is the temporally blocked
+    kernel (8 steps per exchange up to 2^18 cells, 4 above, 8-row tiles); the
+    256^2 100-step configuration runs on it, and matches the oracle."""
     w = workloads.stencil_weights("2d5pt")
-    assert pk.stencil_plan((256, 256), w, "float64")["sync"] == 2
+    pl = pk.stencil_plan((256, 256), w, "float64")
+    assert pl["sync"] == 3 and pl["rows_per_lane"] == 8
+    assert pk.stencil_plan((1024, 1024), w, "float32")["sync"] == 3
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 2})["sync"] == 2
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"kernel": 2})["sync"] == 1
+    g = workloads.stencil_grid((256, 256), seed=0)
+    got = _run(pk, g, w, 100, torch.float64)
+    assert rel_err(got, oracle.stencil(g, w, 100)) <= 1e-12
+    np.testing.assert_array_equal(got, _run(pk, g, w, 100, torch.float64, baseline=True))
 
 
 def test_full_size_matches_oracle_for_a_few_steps(pk):
