@@ -167,11 +167,13 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
  *   grids   host array of `count` device pointers, each updated in place.
  *   shapes  host array of `count` extents (2D, radius 1 only; sizes may differ).
  *   coeffs  one weight box for all grids (as for perks_stencil_run).
- * The tiles of all grids share the launch's waves (one tile height for all
- * grids); each grid keeps its own halo buffers and point-to-point halo
- * synchronisation, so no grid waits on another.  Results are bitwise those of
- * perks_stencil_run on each grid.  Synchronises `stream` before it uploads
- * the grid table (host memory is not retained).
+ * The tiles of all grids (48 columns x 16 rows) share the launch's waves;
+ * each wave takes 8 steps of a tile and its 8-wide ghost ring in registers
+ * between device-wide barriers (the temporal blocking of perks_tuning.kernel
+ * 3), each grid ping-ponging between itself and a second buffer from the
+ * library's scratch.  Results are bitwise those of perks_stencil_run (and of
+ * the per-step baseline) on each grid.  Synchronises `stream` before it
+ * uploads the grid table (host memory is not retained).
  */
 int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int32_t count,
                               const double *coeffs, int64_t steps, perks_dtype dt, void *stream);

@@ -357,8 +357,9 @@ int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int
     const bool box = kind == K_2D9;
     hipStream_t st = as_stream(stream);
     return dt == PERKS_F64
-               ? run2d_batched<double>(reinterpret_cast<double *const *>(grids), shapes, count, coeffs, steps, box, st)
-               : run2d_batched<float>(reinterpret_cast<float *const *>(grids), shapes, count, coeffs, steps, box, st);
+               ? run2d_tb_batched<double>(reinterpret_cast<double *const *>(grids), shapes, count, coeffs, steps, box,
+                                          st)
+               : run2d_tb_batched<float>(reinterpret_cast<float *const *>(grids), shapes, count, coeffs, steps, box, st);
 }
 
 int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype dt, int64_t probe_steps,

@@ -1,5 +1,5 @@
 // 2D radius-1 Jacobi stencils (Eq. 2 and the 2d9pt box of tab:domain) on
-// gfx950: the tile arithmetic, the persistent kernel and the batched kernel.
+// gfx950: the tile arithmetic and the persistent kernel.
 // (Their per-step baseline is the radius-2..4 family's per-step kernel run at
 // radius 1, which sums the same terms in the same order.)
 //
@@ -619,111 +619,6 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2
     gs.finish();
 }
 
-// Many grids in one persistent launch (point-to-point halo synchronisation).
-// The tiles of all grids form one list (grid i owns global tiles
-// tile_base[i] .. tile_base[i+1]-1); global tiles below `cached` are kept on
-// chip by wave t, the rest are streamed round-robin, exactly as in
-// stencil2d_persistent.  Each grid has its own face buffers, so the grids
-// never wait for each other; all share the launch's epochs.
-template <typename T>
-struct Batch2DParams {
-    const Stencil2DParams<T> *inst;
-    const int *tile_base;
-    unsigned *sync;
-    long long steps;
-    int count;
-    int ntiles;
-    int cached;
-};
-
-__device__ __forceinline__ int locate_grid(const int *base, int count, int t) {
-    int lo = 0, hi = count - 1;   // the last i with base[i] <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (base[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <typename T, int R, bool BOX, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void stencil2d_batched(
-    Batch2DParams<T> bp) {
-    constexpr int HMAX = R + LdsRows<T>::value;
-    __shared__ T lds[WAVES][4][HMAX + 2];
-    __shared__ T ltile[WAVES][LdsRows<T>::value * 64];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int gw = blockIdx.x * WAVES + wave;
-    const int nwaves = gridDim.x * WAVES;
-    T *lw = lds[wave][0];
-    T *le = lds[wave][1];
-    T *ow = lds[wave][2];
-    T *oe = lds[wave][3];
-    T *lt = ltile[wave];
-    GridSync gs;
-    gs.init(bp.sync);
-    const unsigned base = ld_coh(bp.sync + SYNC_LL_EPOCH);
-    const unsigned ering = base + 1u, epoch0 = base + 2u;
-    auto grid_params = [&](int i) {
-        Stencil2DParams<T> q = bp.inst[i];
-        q.ering = ering;
-        q.epoch0 = epoch0;
-        return q;
-    };
-    for (int i = 0; i < bp.count; ++i) init_ring_faces_ll(grid_params(i));
-    for (int t = gw; t < bp.ntiles; t += nwaves) {
-        const int i = locate_grid(bp.tile_base, bp.count, t);
-        const Stencil2DParams<T> q = grid_params(i);
-        publish_initial_ll(q, tile_of(q, t - bp.tile_base[i]), lane);
-    }
-    gs.sync();
-
-    const bool has_cached = gw < bp.cached;
-    const int ci = has_cached ? locate_grid(bp.tile_base, bp.count, gw) : 0;
-    T v[R];
-    Tile2D ct{};
-    if (has_cached) {
-        const Stencil2DParams<T> q = grid_params(ci);
-        ct = tile_of(q, gw - bp.tile_base[ci]);
-        const int xl = min(ct.x0 + lane, q.nx - 1);
-#pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = (i < ct.hy) ? q.grid[(size_t)(ct.y0 + i) * q.nx + xl] : T(0);
-        for (int i = R; i < ct.hy; ++i) lt[(i - R) * 64 + lane] = q.grid[(size_t)(ct.y0 + i) * q.nx + xl];
-    }
-    settle(v);   // the initial loads complete before the time loop
-    for (long long s = 0; s < bp.steps; ++s) {
-        const int par = (int)(s & 1);
-        const unsigned e_in = epoch0 + (unsigned)s;
-        if (has_cached) {
-            Stencil2DParams<T> q = grid_params(ci);
-            q.grid = opaque(q.grid);
-            q.rowbuf = opaque(q.rowbuf);
-            q.colbuf = opaque(q.colbuf);
-            step_cached<T, R, BOX, true>(q, ct, par, e_in, lane, v, lt, lw, le, ow, oe);
-        }
-        for (int t = bp.cached + gw; t < bp.ntiles; t += nwaves) {
-            const int i = locate_grid(bp.tile_base, bp.count, t);
-            Stencil2DParams<T> q = grid_params(i);
-            q.grid = opaque(q.grid);
-            q.rowbuf = opaque(q.rowbuf);
-            q.colbuf = opaque(q.colbuf);
-            step_streamed<T, 8, BOX, true>(q, tile_of(q, t - bp.tile_base[i]), par, e_in, lane, lw, le, ow, oe);
-        }
-    }
-    if (has_cached) {
-        const Stencil2DParams<T> q = grid_params(ci);
-        if (lane < ct.wx) {
-#pragma unroll
-            for (int i = 0; i < R; ++i)
-                if (i < ct.hy) q.grid[(size_t)(ct.y0 + i) * q.nx + ct.x0 + lane] = v[i];
-            for (int i = R; i < ct.hy; ++i) q.grid[(size_t)(ct.y0 + i) * q.nx + ct.x0 + lane] = lt[(i - R) * 64 + lane];
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st_coh(bp.sync + SYNC_LL_EPOCH, epoch0 + (unsigned)bp.steps);
-    gs.finish();
-}
-
 // ---------------------------------------------------------------------------
 // Host planning / launch (2D).
 constexpr int W2 = 8;       // wavefronts per workgroup of the persistent kernel
@@ -736,21 +631,6 @@ template <typename T, int R, bool BOX>
 const void *persist2d_fn(bool ll) {
     return ll ? reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2, true>)
               : reinterpret_cast<const void *>(&stencil2d_persistent<T, R, BOX, W2, false>);
-}
-
-template <typename T, bool BOX>
-const void *pick2d_batched(int R) {
-    switch (R) {
-        case 8: return reinterpret_cast<const void *>(&stencil2d_batched<T, 8, BOX, W2>);
-        case 16: return reinterpret_cast<const void *>(&stencil2d_batched<T, 16, BOX, W2>);
-        case 32: return reinterpret_cast<const void *>(&stencil2d_batched<T, 32, BOX, W2>);
-        case 48: return reinterpret_cast<const void *>(&stencil2d_batched<T, 48, BOX, W2>);
-        default: break;
-    }
-    if constexpr (std::is_same<T, float>::value) {
-        if (R == 64) return reinterpret_cast<const void *>(&stencil2d_batched<T, 64, BOX, W2>);
-    }
-    return nullptr;
 }
 
 template <typename T, bool BOX>
@@ -909,97 +789,6 @@ int run2d_in(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
     rc = run2d_planned<T>(grid, coeffs, s, steps, pl, (T *)((char *)mem + SYNC_BYTES), sync, st);
     if (rc == PERKS_OK) note_persistent_launch(pl.wgs, sync);   // its barrier clock records are in mem
     return rc;
-}
-
-// Many 2D grids in one launch: one tile height for all grids (the smallest
-// register depth, or the deepest plus LDS rows, with which every tile of every
-// grid is cached, else the deepest tiles with the most LDS rows), per-grid face
-// buffers carved from one scratch block.
-template <typename T>
-int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
-                  bool box, hipStream_t st) {
-    DeviceFacts f;
-    int rc = device_facts(&f);
-    if (rc) return rc;
-    const long long cap = (long long)f.cus * W2;
-    auto total_tiles = [&](int H) {
-        long long t = 0;
-        for (int i = 0; i < count; ++i)
-            t += (long long)((shapes[i].nx - 2 + 63) / 64) * ((shapes[i].ny - 2 + H - 1) / H);
-        return t;
-    };
-    int R = 0, RL = 0, deepest = 0;
-    for (int r : RList<T>::v) {
-        const void *fn = box ? pick2d_batched<T, true>(r) : pick2d_batched<T, false>(r);
-        int occ = 0;
-        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, W2 * 64, 0) != hipSuccess || occ < 1)
-            continue;
-        deepest = r;
-        if (!R && total_tiles(r) <= cap) R = r;
-    }
-    if (!deepest) return set_error(PERKS_E_UNSUPPORTED, "no batched 2D kernel fits the device");
-    if (!R) {
-        R = deepest;
-        RL = LdsRows<T>::value;
-        for (int rl = 1; rl <= LdsRows<T>::value; ++rl)
-            if (total_tiles(deepest + rl) <= cap) {
-                RL = rl;
-                break;
-            }
-    }
-    const int H = R + RL;
-    std::vector<Stencil2DParams<T>> inst(count);
-    std::vector<int> base(count + 1, 0);
-    size_t face_elems = 0;
-    for (int i = 0; i < count; ++i) {
-        Stencil2DParams<T> &p = inst[i];
-        p = Stencil2DParams<T>{};
-        p.grid = to_global(grids[i]);
-        p.nx = (int)shapes[i].nx;
-        p.ny = (int)shapes[i].ny;
-        const int nxi = p.nx - 2, nyi = p.ny - 2;
-        p.ntx = (nxi + 63) / 64;
-        p.nty = (nyi + H - 1) / H;
-        p.R = H;
-        p.RL = RL;
-        p.last_w = nxi - 64 * (p.ntx - 1);
-        p.last_h = nyi - H * (p.nty - 1);
-        p.ntiles = p.ntx * p.nty;
-        p.steps = steps;
-        fill_weights(p.W, coeffs);
-        base[i + 1] = base[i] + p.ntiles;
-        face_elems += 2 * ((size_t)2 * (2 * p.nty + 2) * p.nx + (size_t)2 * (2 * p.ntx + 2) * p.ny);
-    }
-    const size_t meta = ((sizeof(Stencil2DParams<T>) * count + sizeof(int) * (count + 1)) + 255) / 256 * 256;
-    char *blk = (char *)scratch(SLOT_FACES_LL, meta + face_elems * sizeof(T));
-    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
-    if (!blk || !sync) return PERKS_E_NOMEM;
-    T *faces = (T *)(blk + meta);
-    for (int i = 0; i < count; ++i) {
-        Stencil2DParams<T> &p = inst[i];
-        const size_t rb = (size_t)2 * (2 * p.nty + 2) * p.nx * 2, cb = (size_t)2 * (2 * p.ntx + 2) * p.ny * 2;
-        p.rowbuf = to_global(faces);
-        p.colbuf = to_global(faces + rb);
-        p.sync = sync;
-        faces += rb + cb;
-    }
-    Stencil2DParams<T> *dinst = (Stencil2DParams<T> *)blk;
-    int *dbase = (int *)(blk + sizeof(Stencil2DParams<T>) * count);
-    PERKS_HIP_TRY(hipStreamSynchronize(st));   // the block may still be read by an earlier launch
-    PERKS_HIP_TRY(hipMemcpy(dinst, inst.data(), sizeof(Stencil2DParams<T>) * count, hipMemcpyHostToDevice));
-    PERKS_HIP_TRY(hipMemcpy(dbase, base.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice));
-    Batch2DParams<T> bp{};
-    bp.inst = dinst;
-    bp.tile_base = dbase;
-    bp.sync = sync;
-    bp.steps = steps;
-    bp.count = count;
-    bp.ntiles = base[count];
-    bp.cached = (int)std::min<long long>(bp.ntiles, cap);
-    const long long waves = std::min<long long>(bp.ntiles, cap);
-    const int wgs = (int)((waves + W2 - 1) / W2);
-    const void *fn = box ? pick2d_batched<T, true>(R) : pick2d_batched<T, false>(R);
-    return launch_coop(fn, wgs, W2 * 64, &bp, st);
 }
 
 template <typename T>

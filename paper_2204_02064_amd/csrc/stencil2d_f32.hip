@@ -6,6 +6,4 @@ namespace perks {
 template int run2d_in<float>(float *, const double *, const perks_shape &, int64_t, bool, hipStream_t, void *, size_t);
 template int run2d<float>(float *, const double *, const perks_shape &, int64_t, bool, hipStream_t, const perks_tuning *);
 template int plan2d_query<float>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
-template int run2d_batched<float>(float *const *, const perks_shape *, int, const double *, int64_t, bool,
-                                  hipStream_t);
 }  // namespace perks

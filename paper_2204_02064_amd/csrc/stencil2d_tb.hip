@@ -21,6 +21,7 @@
 // as the per-step baseline does, so the two agree bit for bit.  Ring cells
 // and clamped copies outside the grid are never updated.
 #include <algorithm>
+#include <vector>
 
 #include "barrier.hpp"
 #include "common.hpp"
@@ -83,9 +84,53 @@ __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_i
     }
 }
 
+// One block of K (kk <= K) steps of tile t of a grid: load the tile and its
+// ghost ring from src, step, store the owned cells into dst.
+template <typename T, bool BOX, int K, int H>
+__device__ __forceinline__ void tb_tile(const gmem<T> *src, gmem<T> *dst, int nx, int ny, int ntx, int t, int kk,
+                                        int lane, const T (&w)[9]) {
+    constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
+    const int tx = t % ntx, ty = t / ntx;
+    const int xg = 1 + OW * tx - K + lane;   // this lane's column
+    const int y0 = 1 + H * ty - K;           // the block's first row
+    const int xc = min(max(xg, 0), nx - 1);
+    T u[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int yc = min(max(y0 + i, 0), ny - 1);
+        u[i] = ld_coh(src + (size_t)yc * nx + xc);
+    }
+    const bool lane_in = xg >= 1 && xg <= nx - 2;
+    for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB>(u, w, lane_in, y0, ny);
+    const bool own = lane_in && lane >= K && lane < K + OW;
+#pragma unroll
+    for (int i = K; i < K + H; ++i) {
+        const int y = y0 + i;
+        if (own && y >= 1 && y <= ny - 2) st_coh(dst + (size_t)y * nx + xg, u[i]);
+    }
+}
+
+// The owned cells of tile t from the second buffer back into the grid (the
+// same wave stored them there).
+template <int K, int H, typename T>
+__device__ __forceinline__ void tb_copy_back(gmem<T> *buf0, const gmem<T> *buf1, int nx, int ny, int ntx, int t,
+                                             int lane) {
+    constexpr int OW = 64 - 2 * K;
+    const int tx = t % ntx, ty = t / ntx;
+    const int xg = 1 + OW * tx - K + lane;
+    const int y0 = 1 + H * ty - K;
+    const bool own = xg >= 1 && xg <= nx - 2 && lane >= K && lane < K + OW;
+    for (int i = K; i < K + H; ++i) {
+        const int y = y0 + i;
+        if (own && y >= 1 && y <= ny - 2) {
+            const size_t e = (size_t)y * nx + xg;
+            buf0[e] = ld_coh(buf1 + e);
+        }
+    }
+}
+
 template <typename T, bool BOX, int K, int H>
 __global__ __launch_bounds__(TBW * 64) void stencil2d_tb(TB2DParams<T> p) {
-    constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * TBW + wave, nw = gridDim.x * TBW;
     const int ntiles = p.ntx * p.nty;
@@ -99,43 +144,68 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tb(TB2DParams<T> p) {
         const int kk = (int)std::min<int64_t>(K, p.steps - s0);
         const gmem<T> *src = opaque((blk & 1) ? p.buf1 : p.buf0);
         gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
-        for (int t = gw; t < ntiles; t += nw) {
-            const int tx = t % p.ntx, ty = t / p.ntx;
-            const int xg = 1 + OW * tx - K + lane;   // this lane's column
-            const int y0 = 1 + H * ty - K;           // the block's first row
-            const int xc = min(max(xg, 0), p.nx - 1);
-            T u[RB];
+        for (int t = gw; t < ntiles; t += nw) tb_tile<T, BOX, K, H>(src, dst, p.nx, p.ny, p.ntx, t, kk, lane, w);
+        gs.sync();
+    }
+    if (blk & 1)   // the result is in the second buffer
+        for (int t = gw; t < ntiles; t += nw) tb_copy_back<K, H>(p.buf0, p.buf1, p.nx, p.ny, p.ntx, t, lane);
+    gs.finish();
+}
+
+// Many grids in one launch: the tiles of every grid form one range (grid i's
+// tiles start at tile_base[i]), taken by the waves in turn; one barrier per
+// block for all of them.
+template <typename T>
+struct TBGrid {
+    gmem<T> *buf0, *buf1;
+    int nx, ny, ntx, tile_base;
+};
+
+template <typename T>
+struct TBBatchParams {
+    const TBGrid<T> *grids;
+    int count, ntiles;
+    unsigned *sync;
+    int64_t steps;
+    T w[9];
+};
+
+// Grid of global tile t: the last i with grids[i].tile_base <= t.
+template <typename T>
+__device__ __forceinline__ int tb_locate(const TBGrid<T> *g, int count, int t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g[mid].tile_base <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, bool BOX, int K, int H>
+__global__ __launch_bounds__(TBW * 64) void stencil2d_tb_batched(TBBatchParams<T> p) {
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = blockIdx.x * TBW + wave, nw = gridDim.x * TBW;
+    T w[9];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int yc = min(max(y0 + i, 0), p.ny - 1);
-                u[i] = ld_coh(src + (size_t)yc * p.nx + xc);
-            }
-            const bool lane_in = xg >= 1 && xg <= p.nx - 2;
-            for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB>(u, w, lane_in, y0, p.ny);
-            const bool own = lane_in && lane >= K && lane < K + OW;
-#pragma unroll
-            for (int i = K; i < K + H; ++i) {
-                const int y = y0 + i;
-                if (own && y >= 1 && y <= p.ny - 2) st_coh(dst + (size_t)y * p.nx + xg, u[i]);
-            }
+    for (int k = 0; k < 9; ++k) w[k] = p.w[k];
+    GridSync gs;
+    gs.init(p.sync);
+    int64_t blk = 0;
+    for (int64_t s0 = 0; s0 < p.steps; s0 += K, ++blk) {
+        const int kk = (int)std::min<int64_t>(K, p.steps - s0);
+        for (int t = gw; t < p.ntiles; t += nw) {
+            const TBGrid<T> g = p.grids[tb_locate(p.grids, p.count, t)];
+            const gmem<T> *src = opaque((blk & 1) ? g.buf1 : g.buf0);
+            gmem<T> *dst = opaque((blk & 1) ? g.buf0 : g.buf1);
+            tb_tile<T, BOX, K, H>(src, dst, g.nx, g.ny, g.ntx, t - g.tile_base, kk, lane, w);
         }
         gs.sync();
     }
     if (blk & 1) {
-        // the result is in the second buffer: each wave copies back the cells
-        // it stored there in the last block
-        for (int t = gw; t < ntiles; t += nw) {
-            const int tx = t % p.ntx, ty = t / p.ntx;
-            const int xg = 1 + OW * tx - K + lane;
-            const int y0 = 1 + H * ty - K;
-            const bool own = xg >= 1 && xg <= p.nx - 2 && lane >= K && lane < K + OW;
-            for (int i = K; i < K + H; ++i) {
-                const int y = y0 + i;
-                if (own && y >= 1 && y <= p.ny - 2) {
-                    const size_t e = (size_t)y * p.nx + xg;
-                    p.buf0[e] = ld_coh(p.buf1 + e);
-                }
-            }
+        for (int t = gw; t < p.ntiles; t += nw) {
+            const TBGrid<T> g = p.grids[tb_locate(p.grids, p.count, t)];
+            tb_copy_back<K, H>(g.buf0, g.buf1, g.nx, g.ny, g.ntx, t - g.tile_base, lane);
         }
     }
     gs.finish();
@@ -158,6 +228,13 @@ const void *pick_tb(int k, int h) {
         case 8: return pick_tb_h<T, BOX, 8>(h);
         default: return nullptr;
     }
+}
+
+template <typename T, bool BOX>
+const void *pick_tb_batched(int k, int h) {
+    if (k == 4 && h == 16) return reinterpret_cast<const void *>(&stencil2d_tb_batched<T, BOX, 4, 16>);
+    if (k == 8 && h == 16) return reinterpret_cast<const void *>(&stencil2d_tb_batched<T, BOX, 8, 16>);
+    return nullptr;
 }
 
 struct PlanTB {
@@ -225,6 +302,62 @@ int run2d_tb(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
     return launch_coop(pl.fn, pl.wgs, TBW * 64, &p, st);
 }
 
+// Batched grids (perks_stencil_run_batched): K steps per exchange and
+// 16-row tiles (throughput: the fewest bytes per step, the blocks' reads and
+// writes spread over every grid's tiles).
+constexpr int TB_BATCH_K = 8, TB_BATCH_H = 16;
+
+template <typename T>
+int run2d_tb_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                     bool box, hipStream_t st) {
+    const void *fn = box ? pick_tb_batched<T, true>(TB_BATCH_K, TB_BATCH_H)
+                         : pick_tb_batched<T, false>(TB_BATCH_K, TB_BATCH_H);
+    DeviceFacts f;
+    int rc = device_facts(&f);
+    if (rc) return rc;
+    int occ = 0;
+    PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, TBW * 64, 0));
+    if (occ < 1) return set_error(PERKS_E_NOTCORESIDENT, "batched temporally blocked kernel does not fit a CU");
+    constexpr int OW = 64 - 2 * TB_BATCH_K;
+    std::vector<TBGrid<T>> g(count);
+    int64_t tiles = 0;
+    size_t cells = 0;
+    for (int i = 0; i < count; ++i) {
+        g[i].nx = (int)shapes[i].nx;
+        g[i].ny = (int)shapes[i].ny;
+        g[i].ntx = (int)((shapes[i].nx - 2 + OW - 1) / OW);
+        const int nty = (int)((shapes[i].ny - 2 + TB_BATCH_H - 1) / TB_BATCH_H);
+        g[i].tile_base = (int)tiles;
+        tiles += (int64_t)g[i].ntx * nty;
+        cells += ((size_t)shapes[i].nx * shapes[i].ny + 63) / 64 * 64;
+        if (tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "batch too large for this kernel");
+    }
+    const size_t meta = (sizeof(TBGrid<T>) * count + 255) / 256 * 256;
+    char *blk = (char *)scratch(SLOT_WIDE, meta + cells * sizeof(T));
+    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!blk || !sync) return PERKS_E_NOMEM;
+    T *other = (T *)(blk + meta);
+    PERKS_HIP_TRY(hipStreamSynchronize(st));   // the block may still be read by an earlier launch
+    for (int i = 0; i < count; ++i) {
+        const size_t c = (size_t)shapes[i].nx * shapes[i].ny;
+        g[i].buf0 = to_global(grids[i]);
+        g[i].buf1 = to_global(other);
+        // the second buffer needs the fixed ring: copy the whole grid once
+        PERKS_HIP_TRY(hipMemcpyAsync(other, grids[i], c * sizeof(T), hipMemcpyDeviceToDevice, st));
+        other += (c + 63) / 64 * 64;
+    }
+    PERKS_HIP_TRY(hipMemcpy(blk, g.data(), sizeof(TBGrid<T>) * count, hipMemcpyHostToDevice));
+    TBBatchParams<T> p{};
+    p.grids = (const TBGrid<T> *)blk;
+    p.count = count;
+    p.ntiles = (int)tiles;
+    p.sync = sync;
+    p.steps = steps;
+    for (int k = 0; k < 9; ++k) p.w[k] = (T)coeffs[k];
+    const int wgs = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + TBW - 1) / TBW, (int64_t)f.cus * occ));
+    return launch_coop(fn, wgs, TBW * 64, &p, st);
+}
+
 template <typename T>
 int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perks_stencil_plan *plan) {
     PlanTB pl;
@@ -252,6 +385,10 @@ template int run2d_tb<float>(float *, const double *, const perks_shape &, int64
 template int run2d_tb<double>(double *, const double *, const perks_shape &, int64_t, bool, hipStream_t,
                               const perks_tuning *);
 template int plan2d_tb_query<float>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
+template int run2d_tb_batched<float>(float *const *, const perks_shape *, int, const double *, int64_t, bool,
+                                     hipStream_t);
+template int run2d_tb_batched<double>(double *const *, const perks_shape *, int, const double *, int64_t, bool,
+                                      hipStream_t);
 template int plan2d_tb_query<double>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
 
 }  // namespace perks

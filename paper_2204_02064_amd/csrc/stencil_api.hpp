@@ -23,10 +23,10 @@ int run2d_tb(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
              const perks_tuning *tu);
 template <typename T>
 int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perks_stencil_plan *plan);
-
 template <typename T>
-int run2d_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
-                  bool box, hipStream_t st);
+int run2d_tb_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                     bool box, hipStream_t st);
+
 // Radius-2..4 2D stencils: `radius` 2..4 with `box` false (stars) or radius
 // 2 with `box` true.
 template <typename T>
