@@ -321,8 +321,9 @@ def bench_wide(pk, torch, args):
 
 def bench_batched_stencil(pk, torch, args):
     """512 2D 5-point FP64 grids, sides round(exp(U[ln 64, ln 1024])), 100 Jacobi
-    steps each: one batched persistent launch vs one persistent launch per grid
-    vs one launch per step per grid (HIP events on the current stream)."""
+    steps each: one batched persistent launch (the one-shot call, and the same
+    launch as a reusable plan) vs one persistent launch per grid vs one launch
+    per step per grid (HIP events on the current stream)."""
     import numpy as np
 
     import workloads
@@ -344,13 +345,19 @@ def bench_batched_stencil(pk, torch, args):
         return e0.elapsed_time(e1) / 1e3
 
     t_batch = timed(lambda: pk.stencil_run_batched(grids, w, steps))
+    plan = pk.StencilBatch(grids, w, steps)    # the same launch as a reusable plan (graph launch)
+    t_plan = timed(plan.run)
+    graph = plan.has_graph()
+    plan.close()
     t_seq = timed(lambda: [pk.stencil_run(g, w, steps) for g in grids])
     t_base = timed(lambda: [pk.stencil_run_baseline(g, w, steps) for g in grids])
     log(f"batched stencil: {count} 2d5pt FP64 grids ({cells / steps / 1e6:.1f}M cells), {steps} steps: one launch "
-        f"{t_batch * 1e3:.2f} ms ({cells / t_batch / 1e9:.1f} GCells/s) | per-grid persistent {t_seq * 1e3:.2f} ms "
+        f"{t_batch * 1e3:.2f} ms ({cells / t_batch / 1e9:.1f} GCells/s; as a plan {t_plan * 1e3:.2f} ms, graph "
+        f"{graph}) | per-grid persistent {t_seq * 1e3:.2f} ms "
         f"(x{t_seq / t_batch:.2f}) | per-step launches {t_base * 1e3:.2f} ms (x{t_base / t_batch:.2f})")
     return {"grids": count, "steps": steps, "cells": int(cells // steps), "batched_ms": t_batch * 1e3,
-            "batched_gcells": cells / t_batch / 1e9, "per_grid_persistent_ms": t_seq * 1e3,
+            "batched_gcells": cells / t_batch / 1e9, "plan_run_ms": t_plan * 1e3, "plan_graph": graph,
+            "per_grid_persistent_ms": t_seq * 1e3,
             "per_step_launch_ms": t_base * 1e3, "speedup_vs_per_grid": t_seq / t_batch,
             "speedup_vs_per_step": t_base / t_batch}
 

@@ -179,6 +179,37 @@ int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int
                               const double *coeffs, int64_t steps, perks_dtype dt, void *stream);
 
 /*
+ * Batched stencils as a reusable plan, launched without host synchronisation
+ * (an extension, as perks_stencil_run_batched):
+ * perks_stencil_batch_create   validates, allocates (device memory owned by
+ *                              the plan: barrier words, grid table, second
+ *                              buffers; synchronous) and builds the launch.
+ *                              grids[i] (count device pointers) stay bound to
+ *                              the plan: refill them between runs (ring
+ *                              included), do not free them before destroy.
+ * perks_stencil_batch_run      enqueues `steps` sweeps of every grid on
+ *                              `stream`: one kernel launch (a one-node HIP
+ *                              graph with the cooperative attribute when the
+ *                              runtime accepts it); nothing else runs on the
+ *                              host or the stream, so the call may be made
+ *                              during stream capture.  Results as for
+ *                              perks_stencil_run_batched.
+ * perks_stencil_batch_graph    the plan's hipGraph_t (as void *), for use as a
+ *                              child graph; PERKS_E_UNSUPPORTED without one.
+ *                              Owned by the plan.
+ * perks_stencil_batch_destroy  synchronises the device and frees the plan.
+ * Runs of one plan must not overlap in time (they share its barrier words).
+ */
+typedef struct perks_stencil_batch perks_stencil_batch;
+
+int perks_stencil_batch_create(void *const *grids, const perks_shape *shapes, int32_t count,
+                               const double *coeffs, int64_t steps, perks_dtype dt,
+                               perks_stencil_batch **plan);
+int perks_stencil_batch_run(perks_stencil_batch *plan, void *stream);
+int perks_stencil_batch_graph(perks_stencil_batch *plan, void **graph);
+int perks_stencil_batch_destroy(perks_stencil_batch *plan);
+
+/*
  * perks_stencil_autotune -- pick the launch plan by measurement.
  *
  * Times `probe_steps` sweeps of each candidate plan (the planner's own choice

@@ -98,6 +98,14 @@ def lib():
     L.perks_stencil_run_batched.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Shape), i32, dp, i64,
                                             i32, vp]
     L.perks_stencil_run_batched.restype = ctypes.c_int
+    L.perks_stencil_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Shape), i32, dp, i64,
+                                             i32, ctypes.POINTER(ctypes.c_void_p)]
+    L.perks_stencil_batch_run.argtypes = [vp, vp]
+    L.perks_stencil_batch_graph.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
+    L.perks_stencil_batch_destroy.argtypes = [vp]
+    for name in ("perks_stencil_batch_create", "perks_stencil_batch_run", "perks_stencil_batch_graph",
+                 "perks_stencil_batch_destroy"):
+        getattr(L, name).restype = ctypes.c_int
     L.perks_strerror.restype = ctypes.c_char_p
     L.perks_strerror.argtypes = [ctypes.c_int]
     L.perks_last_error.restype = ctypes.c_char_p
@@ -264,6 +272,45 @@ def stencil_run_batched(grids, weights, steps, stream=None):
     _check(lib().perks_stencil_run_batched(ptrs, shapes, m, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            int(steps), _dtype_code(grids[0]), _stream_handle(stream)))
     return grids
+
+
+class StencilBatch:
+    """A batched-stencil plan: device memory and the launch made once, run many
+    times.  ``run()`` enqueues one launch (a HIP graph node when available)
+    without synchronising; refill the grids in place between runs."""
+
+    def __init__(self, grids, weights, steps):
+        self._keep = list(grids)
+        m = len(grids)
+        for g in grids:
+            _check_grid(g)
+            if g.dim() != 2 or g.dtype != grids[0].dtype:
+                raise ValueError("batched grids must be 2D and of one dtype")
+        w, r = _coeff_array(weights, 2)
+        ptrs = (ctypes.c_void_p * max(m, 1))(*[g.data_ptr() for g in grids])
+        shapes = (Shape * max(m, 1))(*[_shape_of(g, r) for g in grids])
+        self._h = ctypes.c_void_p()
+        dt = _dtype_code(grids[0]) if m else 1
+        _check(lib().perks_stencil_batch_create(ptrs, shapes, m, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                int(steps), dt, ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(lib().perks_stencil_batch_run(self._h, _stream_handle(stream)))
+
+    def has_graph(self):
+        g = ctypes.c_void_p()
+        return lib().perks_stencil_batch_graph(self._h, ctypes.byref(g)) == 0
+
+    def close(self):
+        if self._h:
+            lib().perks_stencil_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stencil_autotune(shape, weights, dtype="float64", probe_steps=50, remember=True, stream=None):

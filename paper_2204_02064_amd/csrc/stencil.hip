@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <new>
 #include <vector>
 
 #include "common.hpp"
@@ -242,6 +243,24 @@ int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int
                            : run3d<float>((float *)grid, coeffs, shape, steps, st, tune);
 }
 
+// Checks a batch (2D radius-1 grids of one pattern); box: the 9-point box.
+int check_batch(void *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                perks_dtype dt, bool *box) {
+    if (count < 0) return set_error(PERKS_E_INVAL, "count must be >= 0");
+    if (count > 0 && (!grids || !shapes)) return set_error(PERKS_E_INVAL, "grids and shapes must not be NULL");
+    Kind kind = K_2D5;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_common(grids[i], coeffs, shapes[i], steps, dt);
+        if (rc) return set_error(rc, "grid %d: %s", i, last_error());
+        if (shapes[i].ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "batched stencils are 2D");
+        if (radius_of(shapes[i]) != 1) return set_error(PERKS_E_UNSUPPORTED, "batched stencils have radius 1");
+        rc = classify(coeffs, shapes[i], &kind);
+        if (rc) return rc;
+    }
+    *box = kind == K_2D9;
+    return PERKS_OK;
+}
+
 }  // namespace
 }  // namespace perks
 
@@ -341,25 +360,68 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
 
 int perks_stencil_run_batched(void *const *grids, const perks_shape *shapes, int32_t count, const double *coeffs,
                               int64_t steps, perks_dtype dt, void *stream) {
-    if (count < 0) return set_error(PERKS_E_INVAL, "count must be >= 0");
-    if (count == 0) return PERKS_OK;
-    if (!grids || !shapes) return set_error(PERKS_E_INVAL, "grids and shapes must not be NULL");
-    Kind kind = K_2D5;
-    for (int i = 0; i < count; ++i) {
-        int rc = check_common(grids[i], coeffs, shapes[i], steps, dt);
-        if (rc) return set_error(rc, "grid %d: %s", i, last_error());
-        if (shapes[i].ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "batched stencils are 2D");
-        if (radius_of(shapes[i]) != 1) return set_error(PERKS_E_UNSUPPORTED, "batched stencils have radius 1");
-        rc = classify(coeffs, shapes[i], &kind);
-        if (rc) return rc;
-    }
-    if (steps == 0) return PERKS_OK;
-    const bool box = kind == K_2D9;
+    bool box = false;
+    int rc = check_batch(grids, shapes, count, coeffs, steps, dt, &box);
+    if (rc) return rc;
+    if (count == 0 || steps == 0) return PERKS_OK;
     hipStream_t st = as_stream(stream);
     return dt == PERKS_F64
                ? run2d_tb_batched<double>(reinterpret_cast<double *const *>(grids), shapes, count, coeffs, steps, box,
                                           st)
                : run2d_tb_batched<float>(reinterpret_cast<float *const *>(grids), shapes, count, coeffs, steps, box, st);
+}
+
+// The plan behind perks_stencil_batch: the batched kernel's plan and the
+// device it was made on.
+struct perks_stencil_batch {
+    perks::StencilBatchPlan *plan = nullptr;
+    int device = -1;
+};
+
+int perks_stencil_batch_create(void *const *grids, const perks_shape *shapes, int32_t count, const double *coeffs,
+                               int64_t steps, perks_dtype dt, perks_stencil_batch **plan) {
+    if (!plan) return set_error(PERKS_E_INVAL, "plan must not be NULL");
+    *plan = nullptr;
+    bool box = false;
+    int rc = check_batch(grids, shapes, count, coeffs, steps, dt, &box);
+    if (rc) return rc;
+    auto *B = new (std::nothrow) perks_stencil_batch();
+    if (!B) return set_error(PERKS_E_NOMEM, "plan allocation failed");
+    (void)hipGetDevice(&B->device);
+    if (count > 0) {
+        rc = dt == PERKS_F64
+                 ? tb_batch_create<double>(reinterpret_cast<double *const *>(grids), shapes, count, coeffs, steps, box,
+                                           &B->plan)
+                 : tb_batch_create<float>(reinterpret_cast<float *const *>(grids), shapes, count, coeffs, steps, box,
+                                          &B->plan);
+        if (rc) {
+            delete B;
+            return rc;
+        }
+    }
+    *plan = B;
+    return PERKS_OK;
+}
+
+int perks_stencil_batch_run(perks_stencil_batch *plan, void *stream) {
+    if (!plan) return set_error(PERKS_E_INVAL, "plan must not be NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+        return set_error(PERKS_E_INVAL, "the plan belongs to device %d", plan->device);
+    return plan->plan ? tb_batch_run(plan->plan, as_stream(stream)) : PERKS_OK;
+}
+
+int perks_stencil_batch_graph(perks_stencil_batch *plan, void **graph) {
+    if (!plan || !graph) return set_error(PERKS_E_INVAL, "plan and graph must not be NULL");
+    if (!plan->plan) return set_error(PERKS_E_UNSUPPORTED, "an empty batch has no graph");
+    return tb_batch_graph(plan->plan, graph);
+}
+
+int perks_stencil_batch_destroy(perks_stencil_batch *plan) {
+    if (!plan) return PERKS_OK;
+    tb_batch_destroy(plan->plan);
+    delete plan;
+    return PERKS_OK;
 }
 
 int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype dt, int64_t probe_steps,

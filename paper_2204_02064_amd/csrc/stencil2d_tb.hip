@@ -21,6 +21,7 @@
 // as the per-step baseline does, so the two agree bit for bit.  Ring cells
 // and clamped copies outside the grid are never updated.
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "barrier.hpp"
@@ -182,6 +183,24 @@ __device__ __forceinline__ int tb_locate(const TBGrid<T> *g, int count, int t) {
     return lo;
 }
 
+// The fixed ring of grid g into its second buffer (by one wave; the first
+// block writes only interior cells there, and the second, the first to read
+// the second buffer, follows a device barrier).
+template <typename T>
+__device__ __forceinline__ void tb_copy_ring(const TBGrid<T> &g, int lane) {
+    const int nx = g.nx, ny = g.ny;
+    const size_t last = (size_t)(ny - 1) * nx;
+    for (int x = lane; x < nx; x += 64) {
+        st_coh(g.buf1 + x, g.buf0[x]);
+        st_coh(g.buf1 + last + x, g.buf0[last + x]);
+    }
+    for (int y = 1 + lane; y < ny - 1; y += 64) {
+        const size_t r = (size_t)y * nx;
+        st_coh(g.buf1 + r, g.buf0[r]);
+        st_coh(g.buf1 + r + nx - 1, g.buf0[r + nx - 1]);
+    }
+}
+
 template <typename T, bool BOX, int K, int H>
 __global__ __launch_bounds__(TBW * 64) void stencil2d_tb_batched(TBBatchParams<T> p) {
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -191,6 +210,11 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tb_batched(TBBatchParams<T
     for (int k = 0; k < 9; ++k) w[k] = p.w[k];
     GridSync gs;
     gs.init(p.sync);
+    // each grid's ring goes to its second buffer with the wave of its first tile
+    for (int t = gw; t < p.ntiles; t += nw) {
+        const TBGrid<T> g = p.grids[tb_locate(p.grids, p.count, t)];
+        if (t == g.tile_base) tb_copy_ring(g, lane);
+    }
     int64_t blk = 0;
     for (int64_t s0 = 0; s0 < p.steps; s0 += K, ++blk) {
         const int kk = (int)std::min<int64_t>(K, p.steps - s0);
@@ -302,60 +326,229 @@ int run2d_tb(T *grid, const double *coeffs, const perks_shape &s, int64_t steps,
     return launch_coop(pl.fn, pl.wgs, TBW * 64, &p, st);
 }
 
-// Batched grids (perks_stencil_run_batched): K steps per exchange and
-// 16-row tiles (throughput: the fewest bytes per step, the blocks' reads and
-// writes spread over every grid's tiles).
+namespace {
+
+// Batched grids: K steps per exchange and 16-row tiles (throughput: the
+// fewest bytes per step, the blocks' reads and writes spread over every
+// grid's tiles).
 constexpr int TB_BATCH_K = 8, TB_BATCH_H = 16;
 
+// The grid table of a batch (second buffers carved from `other`, 64-element
+// aligned), the kernel, its grid size and the bytes of second buffers.
 template <typename T>
-int run2d_tb_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
-                     bool box, hipStream_t st) {
-    const void *fn = box ? pick_tb_batched<T, true>(TB_BATCH_K, TB_BATCH_H)
-                         : pick_tb_batched<T, false>(TB_BATCH_K, TB_BATCH_H);
+struct TBBatchShape {
+    std::vector<TBGrid<T>> g;
+    int64_t tiles = 0;
+    size_t cells = 0;   // elements of the second buffers
+    const void *fn = nullptr;
+    int wgs = 0;
+};
+
+template <typename T>
+int tb_batch_shape(T *const *grids, const perks_shape *shapes, int count, bool box, TBBatchShape<T> *b) {
+    b->fn = box ? pick_tb_batched<T, true>(TB_BATCH_K, TB_BATCH_H) : pick_tb_batched<T, false>(TB_BATCH_K, TB_BATCH_H);
     DeviceFacts f;
     int rc = device_facts(&f);
     if (rc) return rc;
     int occ = 0;
-    PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, TBW * 64, 0));
+    PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->fn, TBW * 64, 0));
     if (occ < 1) return set_error(PERKS_E_NOTCORESIDENT, "batched temporally blocked kernel does not fit a CU");
     constexpr int OW = 64 - 2 * TB_BATCH_K;
-    std::vector<TBGrid<T>> g(count);
-    int64_t tiles = 0;
-    size_t cells = 0;
+    b->g.assign(count, TBGrid<T>{});
     for (int i = 0; i < count; ++i) {
-        g[i].nx = (int)shapes[i].nx;
-        g[i].ny = (int)shapes[i].ny;
-        g[i].ntx = (int)((shapes[i].nx - 2 + OW - 1) / OW);
+        TBGrid<T> &g = b->g[i];
+        g.nx = (int)shapes[i].nx;
+        g.ny = (int)shapes[i].ny;
+        g.ntx = (int)((shapes[i].nx - 2 + OW - 1) / OW);
         const int nty = (int)((shapes[i].ny - 2 + TB_BATCH_H - 1) / TB_BATCH_H);
-        g[i].tile_base = (int)tiles;
-        tiles += (int64_t)g[i].ntx * nty;
-        cells += ((size_t)shapes[i].nx * shapes[i].ny + 63) / 64 * 64;
-        if (tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "batch too large for this kernel");
+        g.tile_base = (int)b->tiles;
+        g.buf0 = to_global(grids[i]);
+        b->tiles += (int64_t)g.ntx * nty;
+        b->cells += ((size_t)shapes[i].nx * shapes[i].ny + 63) / 64 * 64;
+        if (b->tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "batch too large for this kernel");
     }
-    const size_t meta = (sizeof(TBGrid<T>) * count + 255) / 256 * 256;
-    char *blk = (char *)scratch(SLOT_WIDE, meta + cells * sizeof(T));
-    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
-    if (!blk || !sync) return PERKS_E_NOMEM;
-    T *other = (T *)(blk + meta);
-    PERKS_HIP_TRY(hipStreamSynchronize(st));   // the block may still be read by an earlier launch
-    for (int i = 0; i < count; ++i) {
-        const size_t c = (size_t)shapes[i].nx * shapes[i].ny;
-        g[i].buf0 = to_global(grids[i]);
-        g[i].buf1 = to_global(other);
-        // the second buffer needs the fixed ring: copy the whole grid once
-        PERKS_HIP_TRY(hipMemcpyAsync(other, grids[i], c * sizeof(T), hipMemcpyDeviceToDevice, st));
-        other += (c + 63) / 64 * 64;
+    b->wgs = (int)std::max<int64_t>(1, std::min<int64_t>((b->tiles + TBW - 1) / TBW, (int64_t)f.cus * occ));
+    return PERKS_OK;
+}
+
+template <typename T>
+void tb_batch_carve(TBBatchShape<T> *b, T *other) {
+    for (TBGrid<T> &g : b->g) {
+        g.buf1 = to_global(other);
+        other += ((size_t)g.nx * g.ny + 63) / 64 * 64;
     }
-    PERKS_HIP_TRY(hipMemcpy(blk, g.data(), sizeof(TBGrid<T>) * count, hipMemcpyHostToDevice));
+}
+
+template <typename T>
+TBBatchParams<T> tb_batch_params(const TBBatchShape<T> &b, const TBGrid<T> *table, unsigned *sync, int64_t steps,
+                                 const double *coeffs) {
     TBBatchParams<T> p{};
-    p.grids = (const TBGrid<T> *)blk;
-    p.count = count;
-    p.ntiles = (int)tiles;
+    p.grids = table;
+    p.count = (int)b.g.size();
+    p.ntiles = (int)b.tiles;
     p.sync = sync;
     p.steps = steps;
     for (int k = 0; k < 9; ++k) p.w[k] = (T)coeffs[k];
-    const int wgs = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + TBW - 1) / TBW, (int64_t)f.cus * occ));
-    return launch_coop(fn, wgs, TBW * 64, &p, st);
+    return p;
+}
+
+__global__ __launch_bounds__(256) void tb_zero_words(unsigned *w, int m) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) w[i] = 0u;
+}
+
+}  // namespace
+
+template <typename T>
+int run2d_tb_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                     bool box, hipStream_t st) {
+    TBBatchShape<T> b;
+    int rc = tb_batch_shape(grids, shapes, count, box, &b);
+    if (rc) return rc;
+    const size_t meta = (sizeof(TBGrid<T>) * count + 255) / 256 * 256;
+    char *blk = (char *)scratch(SLOT_WIDE, meta + b.cells * sizeof(T));
+    unsigned *sync = (unsigned *)scratch(SLOT_SYNC, SYNC_BYTES);
+    if (!blk || !sync) return PERKS_E_NOMEM;
+    tb_batch_carve(&b, (T *)(blk + meta));
+    PERKS_HIP_TRY(hipStreamSynchronize(st));   // the block may still be read by an earlier launch
+    PERKS_HIP_TRY(hipMemcpy(blk, b.g.data(), sizeof(TBGrid<T>) * count, hipMemcpyHostToDevice));
+    TBBatchParams<T> p = tb_batch_params(b, (const TBGrid<T> *)blk, sync, steps, coeffs);
+    return launch_coop(b.fn, b.wgs, TBW * 64, &p, st);
+}
+
+
+// A batch plan: its own device block (barrier words, grid table, second
+// buffers) and its launch as a one-node HIP graph with the cooperative
+// attribute (or a direct cooperative launch where the runtime refuses one).
+struct StencilBatchPlan {
+    int device = -1;
+    bool f64 = false;
+    void *mem = nullptr;
+    unsigned *sync = nullptr;
+    const void *fn = nullptr;
+    int wgs = 0, count = 0;
+    int64_t steps = 0;
+    uint64_t epochs_used = 0;
+    TBBatchParams<float> pf{};
+    TBBatchParams<double> pd{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+template <typename T>
+int tb_batch_create(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                    bool box, StencilBatchPlan **out) {
+    *out = nullptr;
+    TBBatchShape<T> b;
+    int rc = tb_batch_shape(grids, shapes, count, box, &b);
+    if (rc) return rc;
+    auto *P = new (std::nothrow) StencilBatchPlan();
+    if (!P) return set_error(PERKS_E_NOMEM, "plan allocation failed");
+    (void)hipGetDevice(&P->device);
+    P->f64 = sizeof(T) == 8;
+    P->fn = b.fn;
+    P->wgs = b.wgs;
+    P->count = count;
+    P->steps = steps;
+    const size_t meta = (sizeof(TBGrid<T>) * count + 255) / 256 * 256;
+    const size_t bytes = SYNC_BYTES + meta + b.cells * sizeof(T);
+    do {
+        if (hipMalloc(&P->mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            P->mem = nullptr;
+            rc = set_error(PERKS_E_NOMEM, "batch plan: hipMalloc of %zu bytes failed", bytes);
+            break;
+        }
+        char *base = (char *)P->mem;
+        P->sync = (unsigned *)base;
+        tb_batch_carve(&b, (T *)(base + SYNC_BYTES + meta));
+        if (hipMemset(P->mem, 0, SYNC_BYTES) != hipSuccess ||
+            hipMemcpy(base + SYNC_BYTES, b.g.data(), sizeof(TBGrid<T>) * count, hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(PERKS_E_HIP, "batch plan: uploading the grid table failed");
+            break;
+        }
+        const TBBatchParams<T> p = tb_batch_params(b, (const TBGrid<T> *)(base + SYNC_BYTES), P->sync, steps, coeffs);
+        void *args[1];
+        if constexpr (sizeof(T) == 8) {
+            P->pd = p;
+            args[0] = &P->pd;
+        } else {
+            P->pf = p;
+            args[0] = &P->pf;
+        }
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(P->fn);
+        kp.gridDim = dim3(P->wgs);
+        kp.blockDim = dim3(TBW * 64);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipLaunchAttributeValue v{};
+        v.cooperative = 1;
+        if (hipGraphCreate(&P->graph, 0) != hipSuccess ||
+            hipGraphAddKernelNode(&node, P->graph, nullptr, 0, &kp) != hipSuccess ||
+            hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) != hipSuccess ||
+            hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (P->exec) (void)hipGraphExecDestroy(P->exec);
+            if (P->graph) (void)hipGraphDestroy(P->graph);
+            P->exec = nullptr;
+            P->graph = nullptr;
+        }
+    } while (false);
+    if (rc) {
+        tb_batch_destroy(P);
+        return rc;
+    }
+    *out = P;
+    return PERKS_OK;
+}
+
+int tb_batch_run(StencilBatchPlan *P, hipStream_t st) {
+    if (P->count == 0 || P->steps == 0) return PERKS_OK;
+    // barrier epochs are 32-bit: start again from zeroed words well before
+    // they could wrap (a fill kernel, so the reset is stream-ordered)
+    const uint64_t per_run = (uint64_t)(P->steps / TB_BATCH_K + 2);
+    P->epochs_used += per_run;
+    if (P->epochs_used > (uint64_t(1) << 31)) {
+        hipLaunchKernelGGL(tb_zero_words, dim3((SYNC_BYTES / 4 + 255) / 256), dim3(256), 0, st, P->sync,
+                           (int)(SYNC_BYTES / 4));
+        P->epochs_used = per_run;
+    }
+    note_persistent_launch(P->wgs, P->sync);
+    if (P->exec) {
+        PERKS_HIP_TRY(hipGraphLaunch(P->exec, st));
+        return PERKS_OK;
+    }
+    void *args[1] = {P->f64 ? (void *)&P->pd : (void *)&P->pf};
+    const hipError_t e = hipLaunchCooperativeKernel(P->fn, dim3(P->wgs), dim3(TBW * 64), args, 0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(e == hipErrorCooperativeLaunchTooLarge ? PERKS_E_NOTCORESIDENT : PERKS_E_HIP,
+                         "batched stencil launch: %s", hipGetErrorString(e));
+    }
+    return PERKS_OK;
+}
+
+int tb_batch_graph(StencilBatchPlan *P, void **graph) {
+    if (!P->graph) return set_error(PERKS_E_UNSUPPORTED, "the runtime refused a cooperative graph node");
+    *graph = (void *)P->graph;
+    return PERKS_OK;
+}
+
+void tb_batch_destroy(StencilBatchPlan *P) {
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->mem) {
+        forget_persistent_launch(P->sync);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(P->mem);
+    }
+    delete P;
 }
 
 template <typename T>
@@ -387,6 +580,10 @@ template int run2d_tb<double>(double *, const double *, const perks_shape &, int
 template int plan2d_tb_query<float>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);
 template int run2d_tb_batched<float>(float *const *, const perks_shape *, int, const double *, int64_t, bool,
                                      hipStream_t);
+template int tb_batch_create<float>(float *const *, const perks_shape *, int, const double *, int64_t, bool,
+                                    StencilBatchPlan **);
+template int tb_batch_create<double>(double *const *, const perks_shape *, int, const double *, int64_t, bool,
+                                     StencilBatchPlan **);
 template int run2d_tb_batched<double>(double *const *, const perks_shape *, int, const double *, int64_t, bool,
                                       hipStream_t);
 template int plan2d_tb_query<double>(const perks_shape &, bool, const perks_tuning *, perks_stencil_plan *);

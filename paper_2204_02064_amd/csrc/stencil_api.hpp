@@ -26,6 +26,15 @@ int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perk
 template <typename T>
 int run2d_tb_batched(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
                      bool box, hipStream_t st);
+// A batched-stencil plan (perks_stencil_batch_*): its own device memory and
+// its launch as a one-node HIP graph.
+struct StencilBatchPlan;
+template <typename T>
+int tb_batch_create(T *const *grids, const perks_shape *shapes, int count, const double *coeffs, int64_t steps,
+                    bool box, StencilBatchPlan **out);
+int tb_batch_run(StencilBatchPlan *P, hipStream_t st);
+int tb_batch_graph(StencilBatchPlan *P, void **graph);
+void tb_batch_destroy(StencilBatchPlan *P);
 
 // Radius-2..4 2D stencils: `radius` 2..4 with `box` false (stars) or radius
 // 2 with `box` true.

@@ -419,6 +419,29 @@ def test_batched_grids_equal_single_runs_bitwise(pk, kind, dtype):
         assert rel_err(got, oracle.stencil(g, w, 17)) <= (1e-12 if dtype == "float64" else 1e-5)
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batched_plan_reruns_bitwise(pk, dtype):
+    """perks_stencil_batch_*: one plan, three runs (its HIP graph when the
+    runtime gives one), the grids refilled in place between runs (new values,
+    new rings); every run bitwise the single-grid runs of the same input."""
+    shapes = [(66, 130), (5, 7), (257, 190), (129, 300)]
+    w = workloads.stencil_weights("2d9pt")
+    tdt = getattr(torch, dtype)
+    devs = [to_dev(np.zeros(sh), tdt) for sh in shapes]
+    plan = pk.StencilBatch(devs, w, 19)
+    print(f"batched plan {dtype}: graph {plan.has_graph()}", flush=True)
+    for rep in range(3):
+        inputs = [workloads.stencil_grid(sh, seed=100 * rep + j, ring_value=0.1 * (j + rep)).astype(dtype)
+                  for j, sh in enumerate(shapes)]
+        for d, g in zip(devs, inputs):
+            d.copy_(torch.from_numpy(g))
+        plan.run()
+        torch.cuda.synchronize()
+        for d, g in zip(devs, inputs):
+            np.testing.assert_array_equal(d.cpu().double().numpy(), _run(pk, g, w, 19, tdt, baseline=True))
+    plan.close()
+
+
 def test_batched_many_small_grids(pk):
     sides = workloads.lognormal_sides(64, lo=16, hi=96, seed=5)
     w = workloads.stencil_weights("2d5pt")
