@@ -210,6 +210,19 @@ int perks_stencil_batch_graph(perks_stencil_batch *plan, void **graph);
 int perks_stencil_batch_destroy(perks_stencil_batch *plan);
 
 /*
+ * The tunings perks_stencil_autotune remembers (per pattern, dtype and
+ * extents, per device) as a text file, so that a later process can use them
+ * without measuring again (an extension: the paper tunes per run).
+ * perks_tuning_save  writes the current device's entries to `path`.
+ * perks_tuning_load  reads `path` and adds its entries to the current
+ *                    device's table (replacing entries of the same key);
+ *                    PERKS_E_INVAL, and nothing loaded, for a file that is not
+ *                    a tuning file of this library.
+ */
+int perks_tuning_save(const char *path);
+int perks_tuning_load(const char *path);
+
+/*
  * perks_stencil_autotune -- pick the launch plan by measurement.
  *
  * Times `probe_steps` sweeps of each candidate plan (the planner's own choice

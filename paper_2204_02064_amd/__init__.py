@@ -103,8 +103,10 @@ def lib():
     L.perks_stencil_batch_run.argtypes = [vp, vp]
     L.perks_stencil_batch_graph.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
     L.perks_stencil_batch_destroy.argtypes = [vp]
+    L.perks_tuning_save.argtypes = [ctypes.c_char_p]
+    L.perks_tuning_load.argtypes = [ctypes.c_char_p]
     for name in ("perks_stencil_batch_create", "perks_stencil_batch_run", "perks_stencil_batch_graph",
-                 "perks_stencil_batch_destroy"):
+                 "perks_stencil_batch_destroy", "perks_tuning_save", "perks_tuning_load"):
         getattr(L, name).restype = ctypes.c_int
     L.perks_strerror.restype = ctypes.c_char_p
     L.perks_strerror.argtypes = [ctypes.c_int]
@@ -311,6 +313,16 @@ class StencilBatch:
             self.close()
         except Exception:
             pass
+
+
+def tuning_save(path):
+    """Write the remembered autotuner choices of the current device to ``path``."""
+    _check(lib().perks_tuning_save(os.fsencode(path)))
+
+
+def tuning_load(path):
+    """Add the tunings in ``path`` (written by tuning_save) to the current device's table."""
+    _check(lib().perks_tuning_load(os.fsencode(path)))
 
 
 def stencil_autotune(shape, weights, dtype="float64", probe_steps=50, remember=True, stream=None):

@@ -2,6 +2,8 @@
 // (tile depth, grid size, cached vs streamed tiles) and kernel dispatch.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -421,6 +423,67 @@ int perks_stencil_batch_destroy(perks_stencil_batch *plan) {
     if (!plan) return PERKS_OK;
     tb_batch_destroy(plan->plan);
     delete plan;
+    return PERKS_OK;
+}
+
+// The tuning table as text: a header line, then one line per entry of the
+// current device: kind dtype nx ny nz and the eight perks_tuning fields.
+int perks_tuning_save(const char *path) {
+    if (!path) return set_error(PERKS_E_INVAL, "path must not be NULL");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    (void)hipGetLastError();
+    std::vector<std::pair<TuneKey, perks_tuning>> rows;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_tuned)
+            if (std::get<0>(kv.first) == dev) rows.push_back(kv);
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) return set_error(PERKS_E_INVAL, "cannot open %s for writing", path);
+    fprintf(f, "perks-tuning 1\n");
+    for (const auto &kv : rows) {
+        const perks_tuning &t = kv.second;
+        fprintf(f, "%d %d %lld %lld %lld %d %d %d %d %d %d %d %d\n", std::get<1>(kv.first), std::get<2>(kv.first),
+                (long long)std::get<3>(kv.first), (long long)std::get<4>(kv.first), (long long)std::get<5>(kv.first),
+                t.waves_per_wg, t.wgs_per_cu, t.rows_per_lane, t.planes_per_lane, t.sync, t.max_cached_tiles,
+                t.kernel, t.steps_per_sync);
+    }
+    const bool ok = !ferror(f);
+    if (fclose(f) != 0 || !ok) return set_error(PERKS_E_INVAL, "writing %s failed", path);
+    return PERKS_OK;
+}
+
+int perks_tuning_load(const char *path) {
+    if (!path) return set_error(PERKS_E_INVAL, "path must not be NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return set_error(PERKS_E_INVAL, "cannot open %s", path);
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    (void)hipGetLastError();
+    char head[32] = {0};
+    int version = 0;
+    std::vector<std::pair<TuneKey, perks_tuning>> rows;
+    bool ok = fscanf(f, "%31s %d", head, &version) == 2 && strcmp(head, "perks-tuning") == 0 && version == 1;
+    while (ok) {
+        int kind, dt;
+        long long nx, ny, nz;
+        perks_tuning t{};
+        const int n = fscanf(f, "%d %d %lld %lld %lld %d %d %d %d %d %d %d %d", &kind, &dt, &nx, &ny, &nz,
+                             &t.waves_per_wg, &t.wgs_per_cu, &t.rows_per_lane, &t.planes_per_lane, &t.sync,
+                             &t.max_cached_tiles, &t.kernel, &t.steps_per_sync);
+        if (n == EOF) break;
+        if (n != 13 || kind < K_2D5 || kind > K_3S2 || (dt != PERKS_F32 && dt != PERKS_F64) || nx < 1 || ny < 1 ||
+            nz < 1 || check_tuning(&t) != PERKS_OK) {
+            ok = false;
+            break;
+        }
+        rows.emplace_back(TuneKey(dev, kind, dt, nx, ny, nz), t);
+    }
+    fclose(f);
+    if (!ok) return set_error(PERKS_E_INVAL, "%s is not a tuning file of this library (nothing loaded)", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : rows) g_tuned[kv.first] = kv.second;
     return PERKS_OK;
 }
 
