@@ -126,9 +126,10 @@ constexpr int C3_WAVES = 8;   // waves per workgroup (two per SIMD)
 constexpr int C3_DZMAX = 32;  // deepest column (LDS staging of its faces)
 constexpr int C3_SC = 2;      // planes per streamed chunk
 // planes of each workgroup's first column kept in LDS (streaming kernel
-// only): FP64 3 planes of 8 waves x 4 rows x 64 lanes = 48 KiB; FP32 none (its
+// only): FP64 4 planes of 8 waves x 4 rows x 64 lanes = 64 KiB, which with
+// the 96 KiB of face staging fills the 160 KiB of LDS; FP32 none (its
 // register planes already cover the deepest column)
-template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 3 : 0; };
+template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 4 : 0; };
 template <typename T> using LdsPlane = T[C3_WAVES][C3_RY][64];
 // register-cached planes per lane: NC * RY values of 128 VGPRs
 template <typename T> struct C3Cache { static constexpr int NC = sizeof(T) == 8 ? 12 : 32; };
