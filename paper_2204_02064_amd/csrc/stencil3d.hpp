@@ -126,10 +126,10 @@ constexpr int C3_WAVES = 8;   // waves per workgroup (two per SIMD)
 constexpr int C3_DZMAX = 32;  // deepest column (LDS staging of its faces)
 constexpr int C3_SC = 2;      // planes per streamed chunk
 // planes of each workgroup's first column kept in LDS (streaming kernel
-// only): FP64 4 planes of 8 waves x 4 rows x 64 lanes = 64 KiB, which with
-// the 96 KiB of face staging fills the 160 KiB of LDS; FP32 none (its
-// register planes already cover the deepest column)
-template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 4 : 0; };
+// only): FP64 5 planes of 8 waves x 4 rows x 64 lanes = 80 KiB, which with
+// the 80 KiB of face staging and row exchange fills the 160 KiB of LDS; FP32
+// none (its register planes already cover the deepest column)
+template <typename T> struct C3Lds { static constexpr int L = sizeof(T) == 8 ? 5 : 0; };
 template <typename T> using LdsPlane = T[C3_WAVES][C3_RY][64];
 // register-cached planes per lane: NC * RY values of 128 VGPRs
 template <typename T> struct C3Cache { static constexpr int NC = sizeof(T) == 8 ? 12 : 32; };
@@ -211,7 +211,6 @@ struct ColShared {
     T xs[C3_WAVES][2][C3_DZMAX][C3_RY];   // west / east face of each wave's rows, per plane
     T ysf[2][C3_DZMAX][64];               // south / north face of the column, per plane
     T ex[2][2][C3_WAVES][2][64];          // exchange [slot][plane of the pair][wave]: bottom / top row
-    T sink[C3_WAVES][64][C3_RY];          // edge writes of the lanes that hold no edge
 };
 
 // The fixed ring (both parities) from the grid.
@@ -343,19 +342,17 @@ __device__ __forceinline__ void plane_work(const Col3DParams<T> &p, const Col3D 
     // The column's new west / east edges and south / north boundary rows go
     // to the LDS slots just consumed (xs[w], ysf), published to global memory
     // in one batch after the last plane; only the bottom and top planes are
-    // stored here.  Every lane writes its rows, unconditionally: lane 0 into
-    // the west slot, lane wx-1 into the east one, the others into a private
-    // sink (no exec-mask changes in the plane loop); rows beyond hy are
-    // never published.  With wx == 1 lane 0 holds both edges.
-    {
-        const bool edge = lane == 0 || lane == c.wx - 1;
-        T *dst = edge ? &sh.xs[w][lane == 0 ? 0 : 1][iz][0] : &sh.sink[w][lane][0];
+    // stored here.  Lane 0 writes its rows into the west slot, lane wx-1
+    // into the east one (with wx == 1 lane 0 holds both edges); rows beyond
+    // hy are never published.
+    if (lane == 0 || lane == c.wx - 1) {
+        T *dst = &sh.xs[w][lane == 0 ? 0 : 1][iz][0];
 #pragma unroll
         for (int iy = 0; iy < RY; ++iy) dst[iy] = cur[iy];
-        if (c.wx == 1 && lane == 0) {
+    }
+    if (c.wx == 1 && lane == 0) {
 #pragma unroll
-            for (int iy = 0; iy < RY; ++iy) sh.xs[w][1][iz][iy] = cur[iy];
-        }
+        for (int iy = 0; iy < RY; ++iy) sh.xs[w][1][iz][iy] = cur[iy];
     }
     if (wr.first) sh.ysf[0][iz][lane] = cur[0];
     if (wr.last) sh.ysf[1][iz][lane] = last;
