@@ -73,17 +73,26 @@ typedef struct perks_tuning {
                                  kernel (LDS rows, point-to-point halos), 2 the
                                  radius-2..4 kernel run at radius 1 (grid barrier,
                                  24/32/48/80 register rows), 3 the temporally blocked
-                                 kernel (tiles of 64 - 2K columns x rows_per_lane (8
-                                 or 16) rows, each wave taking K steps on its tile and
-                                 a K-wide ghost ring in registers between grid
-                                 barriers; K = steps_per_sync).  With every field of
-                                 the struct zero (or tune NULL) the library takes
-                                 kernel 2 when the interior holds >= 2^20 cells and
-                                 kernel 2 caches every tile, else kernel 1; any other
+                                 kernel (tiles of 64 - 2K columns x rows_per_lane (8,
+                                 16, 32 or 56) rows, each wave taking K steps on its
+                                 tile and a K-wide ghost ring in registers between
+                                 grid barriers; K = steps_per_sync).  When every tile
+                                 has a wave of its own the blocks stay in registers
+                                 for the whole run and each exchange moves only the
+                                 K-wide bands (32 and 56 rows exist only so);
+                                 otherwise (or with max_cached_tiles < 0) each block
+                                 is loaded from and stored to the grid's two buffers.
+                                 With every field of the struct zero (or tune NULL)
+                                 the library takes kernel 3 when the interior holds
+                                 < 2^20 cells, or when its default plan (K = 4, 56
+                                 rows) keeps every tile in registers, else kernel 2
+                                 when it caches every tile, else kernel 1; any other
                                  nonzero field selects kernel 1 unless kernel = 2
                                  or 3.                                                */
     int32_t steps_per_sync;   /* kernel 3: K, steps between exchanges (2, 4 or 8; 0
-                                 means 4)                                             */
+                                 means 8 up to 2^18 interior cells, else 4); its
+                                 rows_per_lane 0 means 8, 16 (up to 2^20 cells) or
+                                 56                                                   */
 } perks_tuning;
 
 /* Plan a call would use (for reporting and for the performance model). */

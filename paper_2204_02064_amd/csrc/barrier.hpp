@@ -2,10 +2,10 @@
 // paper's Listing 1 / Listing 2), built for gfx950.
 //
 // Design (measured on MI355X, 256 workgroups of 512 threads):
-//   * One packed arrival word per workgroup; a single master wavefront
-//     (workgroup 0, wave 0) polls all of them, eight independent loads per
-//     lane per round, and then publishes a generation word that the other
-//     workgroups poll.  No
+//   * One packed arrival word per workgroup; the master workgroup
+//     (workgroup 0) polls all of them, each of its waves a share of 512-word
+//     chunks with eight independent loads per lane per round, and then
+//     publishes a generation word that the other workgroups poll.  No
 //     read-modify-write atomics: a shared counter serialises arrivals at the
 //     memory side (~70 ns each).
 //   * Only workgroup-scope fences.  All data that crosses workgroups is moved
@@ -35,15 +35,20 @@
 
 namespace perks {
 
-// Called by the 64 lanes of one wavefront: returns once flags[0 .. G) all
-// equal e.  Each lane issues up to 8 independent flag loads per round, so one
-// memory round trip covers 512 workgroups (a poll of G flags costs G / 512
-// round trips, not G / 64).
-__device__ __forceinline__ void wait_flags(const unsigned *flags, unsigned G, unsigned e) {
+// Called by the 64 lanes of wave `wave` of the `nwaves` waves that share the
+// poll: returns once flags[0 .. G) of its chunks all equal e.  The flags are
+// cut into chunks of 512; wave w polls chunks w, w + nwaves, ...  Each lane
+// issues 8 independent flag loads per chunk, so one memory round trip covers
+// a chunk, and with one chunk per wave the whole poll is one round trip (the
+// waves' polls run side by side; sequential chunks would cost one round trip
+// each).
+__device__ __forceinline__ void wait_flags(const unsigned *flags, unsigned G, unsigned e, unsigned wave,
+                                           unsigned nwaves) {
     const unsigned lane = threadIdx.x & 63;
+    const unsigned first = 512u * __builtin_amdgcn_readfirstlane(wave);
     while (true) {
         bool ok = true;
-        for (unsigned base = 0; base < G; base += 512) {
+        for (unsigned base = first; base < G; base += 512 * nwaves) {
             // lanes past the last workgroup load its flag again (no branch,
             // so the eight loads stay in flight together) and ignore it
             unsigned v[8];
@@ -119,10 +124,10 @@ struct GridSync {
         __syncthreads();
         if (threadIdx.x == 0) st_coh(ws + SYNC_FLAGS + blockIdx.x, e);
         if (blockIdx.x == 0) {
-            if (threadIdx.x < 64) {
-                wait_flags(ws + SYNC_FLAGS, gridDim.x, e);
-                if (threadIdx.x == 0) st_coh(ws + SYNC_GEN, e);
-            }
+            // every wave polls its chunks; the workgroup barrier joins them
+            wait_flags(ws + SYNC_FLAGS, gridDim.x, e, threadIdx.x >> 6, blockDim.x >> 6);
+            __syncthreads();
+            if (threadIdx.x == 0) st_coh(ws + SYNC_GEN, e);
         } else if (threadIdx.x == 0) {
             while (ld_coh(ws + SYNC_GEN) != e) __builtin_amdgcn_s_sleep(1);
         }
@@ -190,10 +195,9 @@ struct GroupSync {
         __syncthreads();
         if (threadIdx.x == 0) st_coh(flags + rank, e);
         if (rank == 0) {
-            if (threadIdx.x < 64) {
-                wait_flags(flags, (unsigned)size, e);
-                if (threadIdx.x == 0) st_coh(gen, e);
-            }
+            wait_flags(flags, (unsigned)size, e, threadIdx.x >> 6, blockDim.x >> 6);
+            __syncthreads();
+            if (threadIdx.x == 0) st_coh(gen, e);
         } else if (threadIdx.x == 0) {
             while (ld_coh(gen) != e) __builtin_amdgcn_s_sleep(1);
         }

@@ -168,12 +168,21 @@ int check_tuning(const perks_tuning *tu) {
 
 // The temporally blocked kernel (2D radius-1 patterns): kernel = 3, and the
 // library's choice below WIDE_FAMILY_MIN_CELLS interior cells (measured on
-// MI355X at 256^2 .. 1024^2 FP64 and FP32: 1.6-2.8 us per step against 3.1-4.8
-// for the point-to-point kernel and 3.4-5.1 for one launch per step).
-bool use_tb(Kind k, const perks_shape &s, const perks_tuning *tu) {
+// MI355X at 256^2 .. 1024^2 FP64 and FP32: 1.3-2.6 us per step against 3.1-4.8
+// for the point-to-point kernel and 3.4-5.1 for one launch per step), and
+// above it when its default plan keeps every tile in registers (3072^2 FP32:
+// 6.4 us per step against 7.3 for the radius-2..4 family; 3072^2 FP64 does
+// not fit and keeps that family).
+bool use_tb(Kind k, const perks_shape &s, perks_dtype dt, const perks_tuning *tu) {
     if (k != K_2D5 && k != K_2D9) return false;
     if (tu && tu->kernel == 3) return true;
-    return untuned(tu) && (s.nx - 2) * (s.ny - 2) < WIDE_FAMILY_MIN_CELLS;
+    if (!untuned(tu)) return false;
+    if ((s.nx - 2) * (s.ny - 2) < WIDE_FAMILY_MIN_CELLS) return true;
+    perks_stencil_plan pl{};
+    const bool box = k == K_2D9;
+    const int rc = dt == PERKS_F64 ? plan2d_tb_query<double>(s, box, nullptr, &pl)
+                                   : plan2d_tb_query<float>(s, box, nullptr, &pl);
+    return rc == PERKS_OK && pl.tiles > 0 && pl.cached_tiles == pl.tiles;
 }
 
 int check_common(const void *grid, const double *coeffs, const perks_shape &s, int64_t steps, perks_dtype dt) {
@@ -221,7 +230,7 @@ bool tuned_for(Kind kind, perks_dtype dt, const perks_shape &s, perks_tuning *ou
 
 int run_dispatch(void *grid, const double *coeffs, const perks_shape &shape, int64_t steps, perks_dtype dt,
                  Kind kind, hipStream_t st, const perks_tuning *tune) {
-    if (use_tb(kind, shape, tune)) {
+    if (use_tb(kind, shape, dt, tune)) {
         const bool box = kind == K_2D9;
         return dt == PERKS_F64 ? run2d_tb<double>((double *)grid, coeffs, shape, steps, box, st, tune)
                                : run2d_tb<float>((float *)grid, coeffs, shape, steps, box, st, tune);
@@ -339,7 +348,7 @@ int perks_stencil_plan_query(const double *coeffs, perks_shape shape, perks_dtyp
     rc = check_tuning(tune);
     if (rc) return rc;
     memset(plan, 0, sizeof(*plan));
-    if (use_tb(kind, shape, tune)) {
+    if (use_tb(kind, shape, dt, tune)) {
         const bool box = kind == K_2D9;
         return dt == PERKS_F64 ? plan2d_tb_query<double>(shape, box, tune, plan)
                                : plan2d_tb_query<float>(shape, box, tune, plan);
@@ -523,10 +532,23 @@ int perks_stencil_autotune(const double *coeffs, perks_shape shape, perks_dtype 
         // the radius-2..4 kernel family at radius 1
         add(0, 0, 1, 2);
         for (int r : {24, 32, 48, 80}) add(r, 0, 1, 2);
-        // temporal blocking (small grids: a block's K steps per exchange)
+        // temporal blocking (a block's K steps per exchange): on small grids
+        // the short tiles; on any grid the tall ones when every tile stays in
+        // registers (their blocks would stream otherwise)
         if ((shape.nx - 2) * (shape.ny - 2) < WIDE_FAMILY_MIN_CELLS)
             for (int k : {2, 4, 8})
                 for (int h : {8, 16}) add(h, 0, 0, 3, k);
+        for (int k : {2, 4})
+            for (int h : {32, 56}) {
+                perks_tuning t{};
+                t.rows_per_lane = h;
+                t.kernel = 3;
+                t.steps_per_sync = k;
+                perks_stencil_plan pl;
+                if (perks_stencil_plan_query(coeffs, shape, dt, &t, &pl) == PERKS_OK && pl.tiles > 0 &&
+                    pl.cached_tiles == pl.tiles)
+                    cands.push_back(t);
+            }
     } else {
         add(0, 0, 0);
         for (int pz : {8, 16, 24, 32}) add(0, pz, 0);   // column depths

@@ -48,7 +48,9 @@ struct TB2DParams {
 // RB - 1 lack a neighbour row and lanes 0 and 63 a neighbour column: their
 // new values are not exact and are never used (they lie outside the region
 // that is still exact after this step).
-template <typename T, bool BOX, int RB>
+// PIN: each row is finished before the next one's shifts are issued (a
+// scheduling barrier per row), which bounds the registers a tall block needs.
+template <typename T, bool BOX, int RB, bool PIN = false>
 __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
     T pv = u[0], pw = from_west(pv, pv), pe = from_east(pv, pv);
     T cv = u[1], cw = from_west(cv, cv), ce = from_east(cv, cv);
@@ -82,6 +84,7 @@ __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_i
         cv = nv;
         cw = nw;
         ce = ne;
+        if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -150,6 +153,90 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tb(TB2DParams<T> p) {
     }
     if (blk & 1)   // the result is in the second buffer
         for (int t = gw; t < ntiles; t += nw) tb_copy_back<K, H>(p.buf0, p.buf1, p.nx, p.ny, p.ntx, t, lane);
+    gs.finish();
+}
+
+// Register-resident variant, for grids whose tiles all have a wave of their
+// own (the plan checks it): each wave keeps its block in registers for the
+// whole run.  After a block of K steps it stores only the band of owned
+// cells within K of its tile's edge (into the other buffer), and after the
+// barrier loads only its ghost ring back from there (the neighbours' bands);
+// the last block stores the whole owned tile.  The cells and their
+// arithmetic are those of stencil2d_tb, so the two agree bit for bit, but a
+// block moves the band and the ring instead of the whole block and tile.
+// Element e of a wave-uniform row start: a scalar base plus a 32-bit vector
+// offset (a 64-bit vector address per row would cost two registers a row).
+template <typename T>
+__device__ __forceinline__ gmem<T> *row_at(gmem<T> *row, int e) {
+    return (gmem<T> *)((gmem<char> *)row + (unsigned)e * (unsigned)sizeof(T));
+}
+
+template <typename T, bool BOX, int K, int H>
+__global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
+    constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = blockIdx.x * TBW + wave;
+    const bool has = t < p.ntx * p.nty;   // waves past the last tile only join the barriers
+    T w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = p.w[k];
+    GridSync gs;
+    gs.init(p.sync);
+    const int tx = t % p.ntx, ty = t / p.ntx;
+    const int xg = 1 + OW * tx - K + lane;   // this lane's column
+    const int y0 = 1 + H * ty - K;           // the block's first row
+    const int xc = min(max(xg, 0), p.nx - 1);
+    const bool lane_in = xg >= 1 && xg <= p.nx - 2;
+    const bool own = lane_in && lane >= K && lane < K + OW;
+    const bool side = lane < 2 * K || lane >= OW;       // (owned lanes) within K of the west / east edge
+    const bool ring_lane = lane < K || lane >= K + OW;  // ghost columns
+    T u[RB];
+    if (has) {
+        gmem<T> *src = opaque(p.buf0);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int yc = min(max(y0 + i, 0), p.ny - 1);
+            u[i] = ld_coh(row_at(src + (size_t)yc * p.nx, xc));
+        }
+    }
+    int64_t blk = 0;
+    for (int64_t s0 = 0; s0 < p.steps; s0 += K, ++blk) {
+        const int kk = (int)std::min<int64_t>(K, p.steps - s0);
+        const bool last = s0 + K >= p.steps;
+        gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
+        if (has) {
+            for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB, true>(u, w, lane_in, y0, p.ny);
+            // owned rows are K .. K+H-1: the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes
+#pragma unroll
+            for (int i = K; i < K + H; ++i) {
+                const int y = y0 + i;
+                const bool band = last || side || i < 2 * K || i >= H;
+                if (own && band && y >= 1 && y <= p.ny - 2) st_coh(row_at(dst + (size_t)y * p.nx, xg), u[i]);
+            }
+        }
+        gs.sync();
+        if (has && !last) {
+            // the ghost rows in every lane, then the ghost columns' owned
+            // rows in their lanes only (a branch: each load then writes its
+            // row's register in place)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                if (i < K || i >= K + H) {
+                    const int yc = min(max(y0 + i, 0), p.ny - 1);
+                    u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
+                }
+            }
+            if (ring_lane) {
+#pragma unroll
+                for (int i = K; i < K + H; ++i) {
+                    const int yc = min(max(y0 + i, 0), p.ny - 1);
+                    u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
+                }
+            }
+        }
+    }
+    if ((blk & 1) && has)   // the result is in the second buffer
+        tb_copy_back<K, H>(p.buf0, p.buf1, p.nx, p.ny, p.ntx, t, lane);
     gs.finish();
 }
 
@@ -254,6 +341,18 @@ const void *pick_tb(int k, int h) {
     }
 }
 
+// Register-resident instantiations: the small-grid tiles, and 32- and
+// 56-row tiles for large grids (whose tiles must all be co-resident).
+template <typename T, bool BOX>
+const void *pick_tbr(int k, int h) {
+#define PERKS_TBR(K_, H_) \
+    if (k == K_ && h == H_) return reinterpret_cast<const void *>(&stencil2d_tbr<T, BOX, K_, H_>);
+    PERKS_TBR(2, 8) PERKS_TBR(4, 8) PERKS_TBR(8, 8) PERKS_TBR(2, 16) PERKS_TBR(4, 16) PERKS_TBR(8, 16)
+    PERKS_TBR(2, 32) PERKS_TBR(4, 32) PERKS_TBR(2, 56) PERKS_TBR(4, 56)
+#undef PERKS_TBR
+    return nullptr;
+}
+
 template <typename T, bool BOX>
 const void *pick_tb_batched(int k, int h) {
     if (k == 4 && h == 16) return reinterpret_cast<const void *>(&stencil2d_tb_batched<T, BOX, 4, 16>);
@@ -263,35 +362,66 @@ const void *pick_tb_batched(int k, int h) {
 
 struct PlanTB {
     int k = 0, h = 0, ntx = 0, nty = 0, wgs = 0;
+    bool resident = false;   // stencil2d_tbr: every tile in its own wave's registers
     const void *fn = nullptr;
 };
 
 template <typename T>
 int plan_tb(const perks_shape &s, bool box, const perks_tuning *tu, PlanTB *pl) {
     if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel is 2D");
-    // defaults measured on MI355X (2d5pt, 100 steps): K = 8 up to 2^18
-    // interior cells (256^2: 1.57 us per step FP64, 512^2: 1.66), K = 4 above
-    // (1024^2: 2.75); 8-row tiles (more waves, shorter blocks) throughout
+    // defaults measured on MI355X (2d5pt and 2d9pt, FP64 and FP32, register
+    // resident): up to 2^18 interior cells K = 8 on 8-row tiles (256^2: 1.5 us
+    // per step FP64), up to 2^20 K = 4 on 16-row tiles (1024^2: 2.6 us FP64,
+    // 2.0 FP32), above that K = 4 on 56-row tiles, which only the resident
+    // kernel has (3072^2 FP32: 6.4 us per step; FP64 3072^2 does not fit and
+    // takes 8-row streamed tiles when asked for temporal blocking)
     const int64_t interior = (s.nx - 2) * (s.ny - 2);
+    const bool hdef = !(tu && tu->rows_per_lane > 0);
     pl->k = (tu && tu->steps_per_sync > 0) ? tu->steps_per_sync : (interior <= (int64_t(1) << 18) ? 8 : 4);
-    pl->h = (tu && tu->rows_per_lane > 0) ? tu->rows_per_lane : 8;
+    pl->h = !hdef ? tu->rows_per_lane
+                  : interior <= (int64_t(1) << 18) ? 8 : interior < (int64_t(1) << 20) ? 16 : 56;
+    // max_cached_tiles < 0 keeps the grid in its buffers (streamed blocks);
+    // a positive cap below the tile count does too
+    const int64_t cap_tiles = (tu && tu->max_cached_tiles != 0) ? tu->max_cached_tiles : INT64_MAX;
     if (tu && tu->waves_per_wg != 0 && tu->waves_per_wg != TBW)
         return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel uses %d waves per workgroup", TBW);
     if (tu && tu->sync != 0 && tu->sync != 1)
         return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel synchronises with a grid barrier");
-    pl->fn = box ? pick_tb<T, true>(pl->k, pl->h) : pick_tb<T, false>(pl->k, pl->h);
-    if (!pl->fn)
-        return set_error(PERKS_E_UNSUPPORTED, "temporal blocking takes steps_per_sync 2, 4 or 8 and rows_per_lane 8 "
-                                              "or 16 (got %d, %d)", pl->k, pl->h);
     const int ow = 64 - 2 * pl->k;
     pl->ntx = (int)((s.nx - 2 + ow - 1) / ow);
     pl->nty = (int)((s.ny - 2 + pl->h - 1) / pl->h);
-    const int64_t tiles = (int64_t)pl->ntx * pl->nty;
+    int64_t tiles = (int64_t)pl->ntx * pl->nty;
     if (tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "grid too large for this kernel");
     DeviceFacts f;
     int rc = device_facts(&f);
     if (rc) return rc;
     int occ = 0;
+    // the register-resident kernel when every tile gets a wave of its own
+    const void *fr = box ? pick_tbr<T, true>(pl->k, pl->h) : pick_tbr<T, false>(pl->k, pl->h);
+    if (fr && tiles <= cap_tiles) {
+        PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fr, TBW * 64, 0));
+        const int wpc = (tu && tu->wgs_per_cu > 0) ? std::min(tu->wgs_per_cu, occ) : occ;
+        if (occ >= 1 && tiles <= (int64_t)f.cus * wpc * TBW) {
+            pl->resident = true;
+            pl->fn = fr;
+            pl->wgs = (int)((tiles + TBW - 1) / TBW);
+            return PERKS_OK;
+        }
+    }
+    pl->fn = box ? pick_tb<T, true>(pl->k, pl->h) : pick_tb<T, false>(pl->k, pl->h);
+    if (!pl->fn && hdef) {   // the default depth is resident only: stream 8-row tiles instead
+        pl->h = 8;
+        pl->nty = (int)((s.ny - 2 + pl->h - 1) / pl->h);
+        tiles = (int64_t)pl->ntx * pl->nty;
+        if (tiles > INT32_MAX) return set_error(PERKS_E_UNSUPPORTED, "grid too large for this kernel");
+        pl->fn = box ? pick_tb<T, true>(pl->k, pl->h) : pick_tb<T, false>(pl->k, pl->h);
+    }
+    if (!pl->fn)
+        return set_error(PERKS_E_UNSUPPORTED, fr ? "temporal blocking with %d rows per lane needs every tile "
+                                                   "co-resident (steps_per_sync %d)"
+                                                 : "temporal blocking takes steps_per_sync 2, 4 or 8 and "
+                                                   "rows_per_lane 8, 16, 32 or 56 (got %d, %d)",
+                         fr ? pl->h : pl->k, fr ? pl->k : pl->h);
     PERKS_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl->fn, TBW * 64, 0));
     if (occ < 1) return set_error(PERKS_E_NOTCORESIDENT, "temporally blocked kernel does not fit a CU");
     const int wpc = (tu && tu->wgs_per_cu > 0) ? std::min(tu->wgs_per_cu, occ) : occ;
@@ -563,11 +693,21 @@ int plan2d_tb_query(const perks_shape &s, bool box, const perks_tuning *tu, perk
     plan->rows_per_lane = pl.h;
     plan->planes_per_lane = 1;
     plan->tiles = tiles;
-    plan->cached_tiles = 0;    // between blocks the grid lives in its two buffers
-    plan->cached_cells = 0;
     plan->interior_cells = (s.nx - 2) * (s.ny - 2);
-    // per step: each tile's block read and its owned cells written, once per K steps
-    plan->halo_bytes_per_step = tiles * (64 * rb + ow * pl.h) * (int64_t)sizeof(T) / pl.k;
+    if (pl.resident) {
+        // every tile in registers; per block its band stored and its ghost ring loaded
+        plan->cached_tiles = tiles;
+        plan->cached_cells = plan->interior_cells;
+        const int64_t k2 = 2 * pl.k;
+        plan->halo_bytes_per_step =
+            tiles * (k2 * ow + k2 * (pl.h - k2) + k2 * 64 + k2 * pl.h) * (int64_t)sizeof(T) / pl.k;
+    } else {
+        // between blocks the grid lives in its two buffers: each tile's block
+        // read and its owned cells written, once per K steps
+        plan->cached_tiles = 0;
+        plan->cached_cells = 0;
+        plan->halo_bytes_per_step = tiles * (64 * rb + ow * pl.h) * (int64_t)sizeof(T) / pl.k;
+    }
     plan->sync = 3;
     plan->lds_rows_per_lane = 0;
     return PERKS_OK;

@@ -160,21 +160,28 @@ def test_xcd_local_mode_is_refused(pk):
         pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 3})
 
 
-@pytest.mark.parametrize("k,h", [(2, 8), (4, 16), (8, 8), (8, 16)])
+@pytest.mark.parametrize("k,h,resident", [(2, 8, True), (4, 16, True), (8, 8, True), (8, 16, True),
+                                          (2, 32, True), (4, 56, True),
+                                          (2, 8, False), (4, 16, False), (8, 8, False), (8, 16, False)])
 @pytest.mark.parametrize("shape", [(256, 256), (130, 389), (70, 1000), (5, 3)])
 @pytest.mark.parametrize("kind", ["2d5pt", "2d9pt"])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_temporally_blocked_kernel_is_bitwise_the_per_step_baseline(pk, dtype, kind, shape, k, h):
+def test_temporally_blocked_kernel_is_bitwise_the_per_step_baseline(pk, dtype, kind, shape, k, h, resident):
     """kernel 3: K steps per exchange on tiles of 64 - 2K columns x h rows with
     a K-wide ghost ring; step counts below, at and past K, ragged tiles and a
-    grid smaller than one tile."""
+    grid smaller than one tile.  Resident: every block stays in registers and
+    only the bands move; otherwise (max_cached_tiles -1) every block is loaded
+    and stored whole."""
     g = workloads.stencil_grid(shape, seed=21).astype(dtype)
     w = workloads.stencil_weights(kind)
     tt = getattr(torch, dtype)
     tu = {"kernel": 3, "steps_per_sync": k, "rows_per_lane": h}
-    print(f"temporal blocking {kind} {shape} {dtype} K={k} H={h}", flush=True)
+    if not resident:
+        tu["max_cached_tiles"] = -1
+    print(f"temporal blocking {kind} {shape} {dtype} K={k} H={h} resident={resident}", flush=True)
     plan = pk.stencil_plan(shape, w, dtype, tuning=tu)
     assert plan["sync"] == 3 and plan["rows_per_lane"] == h
+    assert plan["cached_tiles"] == (plan["tiles"] if resident else 0)
     for steps in sorted({1, k - 1, k, 2 * k + 1, 37} - {0}):
         a = _run(pk, g, w, steps, tt, tuning=tu)
         b = _run(pk, g, w, steps, tt, baseline=True)
@@ -186,9 +193,13 @@ def test_temporally_blocked_kernel_is_bitwise_the_per_step_baseline(pk, dtype, k
 
 def test_temporally_blocked_kernel_rejects_other_shapes(pk):
     w = workloads.stencil_weights("2d5pt")
-    for tu in ({"kernel": 3, "steps_per_sync": 3}, {"kernel": 3, "rows_per_lane": 12}, {"steps_per_sync": 4}):
+    for tu in ({"kernel": 3, "steps_per_sync": 3}, {"kernel": 3, "rows_per_lane": 12}, {"steps_per_sync": 4},
+               {"kernel": 3, "rows_per_lane": 56, "max_cached_tiles": -1}):
         with pytest.raises(RuntimeError):
             pk.stencil_plan((256, 256), w, "float64", tuning=tu)
+    # 56-row tiles exist only register resident: FP64 3072^2 has too many
+    with pytest.raises(RuntimeError):
+        pk.stencil_plan((3072, 3072), w, "float64", tuning={"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56})
 
 
 def test_repeated_launches_reuse_epochs_safely(pk):
@@ -225,7 +236,8 @@ def test_split_runs_compose_bitwise_and_zero_steps_is_identity(pk):
 # The plans the benchmark times at 3072^2 (the radius-2..4 kernel family at
 # radius 1: 48 register rows per lane in FP64, 24 in FP32, every tile cached;
 # also the untuned default there) and the radius-1 kernel family.
-BENCH_TUNING = {"float64": {"kernel": 2, "rows_per_lane": 48}, "float32": {"kernel": 2, "rows_per_lane": 24}}
+BENCH_TUNING = {"float64": {"kernel": 2, "rows_per_lane": 48},
+                "float32": {"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56}}
 EIGEN_CASES = [("2d5pt", (3072, 3072), "float64", {"kernel": 1}), ("2d9pt", (3072, 3072), "float32", {"kernel": 1}),
                ("3d7pt", (256, 256, 256), "float64", None)]
 EIGEN_CASES += [(k, (3072, 3072), dt, BENCH_TUNING[dt]) for k in ("2d5pt", "2d9pt") for dt in ("float64", "float32")]
@@ -289,10 +301,11 @@ def test_full_size_bench_plans_match_oracle(pk, kind, dtype):
     if dtype == "float32":
         g = g.astype(np.float32).astype(np.float64)
         w = w.astype(np.float32).astype(np.float64)
-    got = _run(pk, g, w, 4, tdt, tuning=tu)
-    assert rel_err(got, oracle.stencil(g, w, 4)) <= (1e-12 if dtype == "float64" else 1e-5)
-    np.testing.assert_array_equal(got, _run(pk, g, w, 4, tdt, baseline=True))
-    np.testing.assert_array_equal(got, _run(pk, g, w, 4, tdt))
+    # six steps: with K = 4 one block exchanges its bands, the second is short
+    got = _run(pk, g, w, 6, tdt, tuning=tu)
+    assert rel_err(got, oracle.stencil(g, w, 6)) <= (1e-12 if dtype == "float64" else 1e-5)
+    np.testing.assert_array_equal(got, _run(pk, g, w, 6, tdt, baseline=True))
+    np.testing.assert_array_equal(got, _run(pk, g, w, 6, tdt))
     plan, default = pk.stencil_plan((3072, 3072), w, dtype, tuning=tu), pk.stencil_plan((3072, 3072), w, dtype)
     assert plan == default
     assert plan["rows_per_lane"] == tu["rows_per_lane"] and plan["cached_tiles"] == plan["tiles"] > 0
@@ -300,12 +313,19 @@ def test_full_size_bench_plans_match_oracle(pk, kind, dtype):
 
 def test_untuned_small_grids_take_temporal_blocking(pk):
     """Below 2^20 interior cells the untuned plan is the temporally blocked
-    kernel (8 steps per exchange up to 2^18 cells, 4 above, 8-row tiles); the
-    256^2 100-step configuration runs on it, and matches the oracle."""
+    kernel (8 steps per exchange on 8-row tiles up to 2^18 cells, 4 steps on
+    16-row tiles above), every tile in registers; above 2^20 it is too when 56-row
+    tiles all fit (FP32 3072^2), else the radius-2..4 family (FP64 3072^2).
+    The 256^2 100-step configuration runs on it, and matches the oracle."""
     w = workloads.stencil_weights("2d5pt")
     pl = pk.stencil_plan((256, 256), w, "float64")
-    assert pl["sync"] == 3 and pl["rows_per_lane"] == 8
-    assert pk.stencil_plan((1024, 1024), w, "float32")["sync"] == 3
+    assert pl["sync"] == 3 and pl["rows_per_lane"] == 8 and pl["cached_tiles"] == pl["tiles"]
+    pl = pk.stencil_plan((1024, 1024), w, "float32")
+    assert pl["sync"] == 3 and pl["rows_per_lane"] == 16 and pl["cached_tiles"] == pl["tiles"]
+    pl = pk.stencil_plan((3072, 3072), w, "float32")
+    assert pl["sync"] == 3 and pl["rows_per_lane"] == 56 and pl["cached_tiles"] == pl["tiles"]
+    pl = pk.stencil_plan((3072, 3072), w, "float64")
+    assert pl["sync"] == 1 and pl["rows_per_lane"] == 48 and pl["cached_tiles"] == pl["tiles"]
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 2})["sync"] == 2
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"kernel": 2})["sync"] == 1
     g = workloads.stencil_grid((256, 256), seed=0)
