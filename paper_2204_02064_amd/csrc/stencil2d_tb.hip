@@ -175,8 +175,9 @@ template <typename T, bool BOX, int K, int H>
 __global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
     constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // waves past the last tile (ty >= nty) step a block of clamped copies and
+    // store nothing: their owned rows lie past the grid
     const int t = blockIdx.x * TBW + wave;
-    const bool has = t < p.ntx * p.nty;   // waves past the last tile only join the barriers
     T w[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = p.w[k];
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
     const bool side = lane < 2 * K || lane >= OW;       // (owned lanes) within K of the west / east edge
     const bool ring_lane = lane < K || lane >= K + OW;  // ghost columns
     T u[RB];
-    if (has) {
+    {
         gmem<T> *src = opaque(p.buf0);
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
@@ -199,43 +200,42 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
             u[i] = ld_coh(row_at(src + (size_t)yc * p.nx, xc));
         }
     }
+    settle(u);   // the loads land here, in the registers the steps use
+    // Every block ends with the ring loads, the last one too (its values go
+    // unused): no branch around them, so each load writes its row's register.
     int64_t blk = 0;
     for (int64_t s0 = 0; s0 < p.steps; s0 += K, ++blk) {
         const int kk = (int)std::min<int64_t>(K, p.steps - s0);
         const bool last = s0 + K >= p.steps;
         gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
-        if (has) {
-            for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB, true>(u, w, lane_in, y0, p.ny);
-            // owned rows are K .. K+H-1: the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes
+        for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB, true>(u, w, lane_in, y0, p.ny);
+        // owned rows are K .. K+H-1: the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes
 #pragma unroll
-            for (int i = K; i < K + H; ++i) {
-                const int y = y0 + i;
-                const bool band = last || side || i < 2 * K || i >= H;
-                if (own && band && y >= 1 && y <= p.ny - 2) st_coh(row_at(dst + (size_t)y * p.nx, xg), u[i]);
-            }
+        for (int i = K; i < K + H; ++i) {
+            const int y = y0 + i;
+            const bool band = last || side || i < 2 * K || i >= H;
+            if (own && band && y >= 1 && y <= p.ny - 2) st_coh(row_at(dst + (size_t)y * p.nx, xg), u[i]);
         }
         gs.sync();
-        if (has && !last) {
-            // the ghost rows in every lane, then the ghost columns' owned
-            // rows in their lanes only (a branch: each load then writes its
-            // row's register in place)
+        // the ghost rows in every lane, then the ghost columns' owned rows in
+        // their lanes only
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                if (i < K || i >= K + H) {
-                    const int yc = min(max(y0 + i, 0), p.ny - 1);
-                    u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
-                }
-            }
-            if (ring_lane) {
-#pragma unroll
-                for (int i = K; i < K + H; ++i) {
-                    const int yc = min(max(y0 + i, 0), p.ny - 1);
-                    u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
-                }
+        for (int i = 0; i < RB; ++i) {
+            if (i < K || i >= K + H) {
+                const int yc = min(max(y0 + i, 0), p.ny - 1);
+                u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
             }
         }
+        if (ring_lane) {
+#pragma unroll
+            for (int i = K; i < K + H; ++i) {
+                const int yc = min(max(y0 + i, 0), p.ny - 1);
+                u[i] = ld_coh(row_at(dst + (size_t)yc * p.nx, xc));
+            }
+        }
+        settle(u);
     }
-    if ((blk & 1) && has)   // the result is in the second buffer
+    if (blk & 1)   // the result is in the second buffer
         tb_copy_back<K, H>(p.buf0, p.buf1, p.nx, p.ny, p.ntx, t, lane);
     gs.finish();
 }
