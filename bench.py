@@ -41,10 +41,10 @@ PEAK_HBM_GBS = 8000.0
 # from: a changed source reports null until measured again.
 MEASURED_TRAFFIC = {
     ("3d7pt", (256, 256, 256), "float64"): {
-        "bytes": 189.80e9,   # profiles/stencil3d_column_f64_256cubed.md
+        "bytes": 190.31e9,   # profiles/stencil3d_column_f64_256cubed.md
         "sources": ["paper_2204_02064_amd/csrc/stencil3d.hpp", "paper_2204_02064_amd/csrc/barrier.hpp",
                     "paper_2204_02064_amd/csrc/common.hpp", "paper_2204_02064_amd/csrc/stencil3d_f64.hip"],
-        "sha256": "8dbd8f5da117566b604b31fb446ce030ceb778b5ad4b5e012ec12c2a13cbd4c0",
+        "sha256": "c7eecde18910014aa0ade3cf08b4ff46a8323dd22736475f69113df7a530e1fa",
     },
 }
 
@@ -58,13 +58,14 @@ _SRC2 = [_CSRC + "stencil2d_wide.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hp
 _SRC3 = [_CSRC + "stencil3d.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 STEP_TRAFFIC = {
     ("2d5pt", "float64"): {"persistent": 11.5e6, "per_step": 174.3e6, "sources": _SRC2 + [_CSRC + "stencil2d_wide_f64.hip"],
-                           "sha256": "0a71b1a0543ebc2039c18b098c649fc32268b7e6b05941b2f56df643f68cd481"},
-    ("2d5pt", "float32"): {"persistent": 10.0e6, "per_step": 92.8e6, "sources": _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
-                           "sha256": "afddb6fcfb378bd24c0575ddf0acb6ec65fed5c67fcdab4ac1aea67cc9c11a53"},
-    ("3d7pt", "float64"): {"persistent": 189.8e6, "per_step": 407.3e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
-                           "sha256": "8dbd8f5da117566b604b31fb446ce030ceb778b5ad4b5e012ec12c2a13cbd4c0"},
-    ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.9e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
-                           "sha256": "d412ed25eacce61ab6f516ba29bd0e6bebe2667ca16c30b3cf5bdb480b81075c"},
+                           "sha256": "b2c994f5c3ef28535678fd1923c47c6ad8e7be55dcbfdd85cfb3547a7a17f282"},
+    ("2d5pt", "float32"): {"persistent": 14.7e6, "per_step": 92.9e6,
+                           "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
+                           "sha256": "a7b0afe60fcc8cd81378e00305bf85f54c5d70683d4baa9607e364fc4dd2cfaa"},
+    ("3d7pt", "float64"): {"persistent": 190.3e6, "per_step": 407.5e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
+                           "sha256": "c7eecde18910014aa0ade3cf08b4ff46a8323dd22736475f69113df7a530e1fa"},
+    ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
+                           "sha256": "e28cfc316e81d4aad6eafd72259a8b50fe539443d3c481617b9277a61ad146ef"},
 }
 
 
