@@ -170,9 +170,9 @@ int check_tuning(const perks_tuning *tu) {
 // library's choice below WIDE_FAMILY_MIN_CELLS interior cells (measured on
 // MI355X at 256^2 .. 1024^2 FP64 and FP32: 1.3-2.6 us per step against 3.1-4.8
 // for the point-to-point kernel and 3.4-5.1 for one launch per step), and
-// above it when its default plan keeps every tile in registers (3072^2 FP32:
-// 6.4 us per step against 7.3 for the radius-2..4 family; 3072^2 FP64 does
-// not fit and keeps that family).
+// above it when its default plan keeps every tile in registers (3072^2: 8.6
+// us per step FP64 and 6.1 FP32 against 10.5 and 7.4 for the radius-2..4
+// family).
 bool use_tb(Kind k, const perks_shape &s, perks_dtype dt, const perks_tuning *tu) {
     if (k != K_2D5 && k != K_2D9) return false;
     if (tu && tu->kernel == 3) return true;

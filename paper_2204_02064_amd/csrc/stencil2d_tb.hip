@@ -48,9 +48,7 @@ struct TB2DParams {
 // RB - 1 lack a neighbour row and lanes 0 and 63 a neighbour column: their
 // new values are not exact and are never used (they lie outside the region
 // that is still exact after this step).
-// PIN: each row is finished before the next one's shifts are issued (a
-// scheduling barrier per row), which bounds the registers a tall block needs.
-template <typename T, bool BOX, int RB, bool PIN = false>
+template <typename T, bool BOX, int RB>
 __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
     T pv = u[0], pw = from_west(pv, pv), pe = from_east(pv, pv);
     T cv = u[1], cw = from_west(cv, cv), ce = from_east(cv, cv);
@@ -84,13 +82,61 @@ __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_i
         cv = nv;
         cw = nw;
         ce = ne;
-        if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// The same step with every new row written into its own old row's register:
+// each old row is visited once, top to bottom, and adds its terms to the new
+// rows it touches (three rolling accumulators); new row i is complete, and
+// old row i dead, once old row i+1 has been visited.  tb_step instead holds
+// each old row in a copy while its new value takes another register, which
+// in a loop over steps makes the compiler rotate every row back (FP64 tall
+// blocks then need twice their registers).  Sums, rows updated and rows kept
+// are tb_step's, so the two give the same bits.
+template <typename T, bool BOX, int RB>
+__device__ __forceinline__ void tb_step_roll(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
+    T acc[3] = {T(0), T(0), T(0)};   // each starts with a product before use
+    static_for<0, RB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;   // old row visited
+        const T v = u[j];
+        const T vw = from_west(v, v), ve = from_east(v, v);
+        if constexpr (j + 1 <= RB - 2) {   // new row j+1: its dy = -1 terms, the first a product
+            T &a = acc[(j + 1) % 3];
+            if constexpr (BOX) {
+                a = w[0] * vw;
+                a = fma_t(w[1], v, a);
+                a = fma_t(w[2], ve, a);
+            } else {
+                a = w[1] * v;
+            }
+        }
+        if constexpr (j >= 1 && j <= RB - 2) {   // new row j: dy = 0
+            T &a = acc[j % 3];
+            a = fma_t(w[3], vw, a);
+            a = fma_t(w[4], v, a);
+            a = fma_t(w[5], ve, a);
+        }
+        if constexpr (j >= 2) {   // new row j-1: dy = +1, then it replaces old row j-1
+            T &a = acc[(j - 1) % 3];
+            if constexpr (BOX) {
+                a = fma_t(w[6], vw, a);
+                a = fma_t(w[7], v, a);
+                a = fma_t(w[8], ve, a);
+            } else {
+                a = fma_t(w[7], v, a);
+            }
+            const int y = y0 + j - 1;
+            u[j - 1] = (lane_in && y >= 1 && y <= ny - 2) ? a : u[j - 1];
+        }
+        settle(acc);   // this row's terms here (not sunk below later rows' shifts)
+    });
 }
 
 // One block of K (kk <= K) steps of tile t of a grid: load the tile and its
 // ghost ring from src, step, store the owned cells into dst.
-template <typename T, bool BOX, int K, int H>
+// ROLL: steps by tb_step_roll (fewer registers for 16-row FP64 blocks, more
+// waves: the batched kernel), else by tb_step (fewer for 8-row ones).
+template <typename T, bool BOX, int K, int H, bool ROLL = false>
 __device__ __forceinline__ void tb_tile(const gmem<T> *src, gmem<T> *dst, int nx, int ny, int ntx, int t, int kk,
                                         int lane, const T (&w)[9]) {
     constexpr int RB = H + 2 * K, OW = 64 - 2 * K;
@@ -105,7 +151,10 @@ __device__ __forceinline__ void tb_tile(const gmem<T> *src, gmem<T> *dst, int nx
         u[i] = ld_coh(src + (size_t)yc * nx + xc);
     }
     const bool lane_in = xg >= 1 && xg <= nx - 2;
-    for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB>(u, w, lane_in, y0, ny);
+    for (int j = 0; j < kk; ++j) {
+        if constexpr (ROLL) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, ny);
+        else tb_step<T, BOX, RB>(u, w, lane_in, y0, ny);
+    }
     const bool own = lane_in && lane >= K && lane < K + OW;
 #pragma unroll
     for (int i = K; i < K + H; ++i) {
@@ -208,7 +257,7 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
         const int kk = (int)std::min<int64_t>(K, p.steps - s0);
         const bool last = s0 + K >= p.steps;
         gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
-        for (int j = 0; j < kk; ++j) tb_step<T, BOX, RB, true>(u, w, lane_in, y0, p.ny);
+        for (int j = 0; j < kk; ++j) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, p.ny);
         // owned rows are K .. K+H-1: the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes
 #pragma unroll
         for (int i = K; i < K + H; ++i) {
@@ -309,7 +358,7 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tb_batched(TBBatchParams<T
             const TBGrid<T> g = p.grids[tb_locate(p.grids, p.count, t)];
             const gmem<T> *src = opaque((blk & 1) ? g.buf1 : g.buf0);
             gmem<T> *dst = opaque((blk & 1) ? g.buf0 : g.buf1);
-            tb_tile<T, BOX, K, H>(src, dst, g.nx, g.ny, g.ntx, t - g.tile_base, kk, lane, w);
+            tb_tile<T, BOX, K, H, true>(src, dst, g.nx, g.ny, g.ntx, t - g.tile_base, kk, lane, w);
         }
         gs.sync();
     }
@@ -370,11 +419,12 @@ template <typename T>
 int plan_tb(const perks_shape &s, bool box, const perks_tuning *tu, PlanTB *pl) {
     if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel is 2D");
     // defaults measured on MI355X (2d5pt and 2d9pt, FP64 and FP32, register
-    // resident): up to 2^18 interior cells K = 8 on 8-row tiles (256^2: 1.5 us
+    // resident): up to 2^18 interior cells K = 8 on 8-row tiles (256^2: 1.4 us
     // per step FP64), up to 2^20 K = 4 on 16-row tiles (1024^2: 2.6 us FP64,
     // 2.0 FP32), above that K = 4 on 56-row tiles, which only the resident
-    // kernel has (3072^2 FP32: 6.4 us per step; FP64 3072^2 does not fit and
-    // takes 8-row streamed tiles when asked for temporal blocking)
+    // kernel has (3072^2: 8.6 us per step FP64, 6.1 FP32); a grid whose 56-row
+    // tiles do not all fit takes 8-row streamed tiles when asked for temporal
+    // blocking
     const int64_t interior = (s.nx - 2) * (s.ny - 2);
     const bool hdef = !(tu && tu->rows_per_lane > 0);
     pl->k = (tu && tu->steps_per_sync > 0) ? tu->steps_per_sync : (interior <= (int64_t(1) << 18) ? 8 : 4);

@@ -197,9 +197,9 @@ def test_temporally_blocked_kernel_rejects_other_shapes(pk):
                {"kernel": 3, "rows_per_lane": 56, "max_cached_tiles": -1}):
         with pytest.raises(RuntimeError):
             pk.stencil_plan((256, 256), w, "float64", tuning=tu)
-    # 56-row tiles exist only register resident: FP64 3072^2 has too many
+    # 56-row tiles exist only register resident: FP64 4096^2 has too many
     with pytest.raises(RuntimeError):
-        pk.stencil_plan((3072, 3072), w, "float64", tuning={"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56})
+        pk.stencil_plan((4096, 4096), w, "float64", tuning={"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56})
 
 
 def test_repeated_launches_reuse_epochs_safely(pk):
@@ -236,11 +236,13 @@ def test_split_runs_compose_bitwise_and_zero_steps_is_identity(pk):
 # The plans the benchmark times at 3072^2 (the radius-2..4 kernel family at
 # radius 1: 48 register rows per lane in FP64, 24 in FP32, every tile cached;
 # also the untuned default there) and the radius-1 kernel family.
-BENCH_TUNING = {"float64": {"kernel": 2, "rows_per_lane": 48},
+BENCH_TUNING = {"float64": {"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56},
                 "float32": {"kernel": 3, "steps_per_sync": 4, "rows_per_lane": 56}}
+WIDE_TUNING = {"float64": {"kernel": 2, "rows_per_lane": 48}, "float32": {"kernel": 2, "rows_per_lane": 24}}
 EIGEN_CASES = [("2d5pt", (3072, 3072), "float64", {"kernel": 1}), ("2d9pt", (3072, 3072), "float32", {"kernel": 1}),
                ("3d7pt", (256, 256, 256), "float64", None)]
 EIGEN_CASES += [(k, (3072, 3072), dt, BENCH_TUNING[dt]) for k in ("2d5pt", "2d9pt") for dt in ("float64", "float32")]
+EIGEN_CASES += [(k, (3072, 3072), dt, WIDE_TUNING[dt]) for k in ("2d5pt", "2d9pt") for dt in ("float64", "float32")]
 
 
 @pytest.mark.parametrize("kind,shape,dtype,tuning", EIGEN_CASES)
@@ -315,7 +317,8 @@ def test_untuned_small_grids_take_temporal_blocking(pk):
     """Below 2^20 interior cells the untuned plan is the temporally blocked
     kernel (8 steps per exchange on 8-row tiles up to 2^18 cells, 4 steps on
     16-row tiles above), every tile in registers; above 2^20 it is too when 56-row
-    tiles all fit (FP32 3072^2), else the radius-2..4 family (FP64 3072^2).
+    tiles all fit (3072^2), else not (FP64 4096^2: the radius-2..4 family
+    when it caches every tile, else the radius-1 kernel).
     The 256^2 100-step configuration runs on it, and matches the oracle."""
     w = workloads.stencil_weights("2d5pt")
     pl = pk.stencil_plan((256, 256), w, "float64")
@@ -325,7 +328,8 @@ def test_untuned_small_grids_take_temporal_blocking(pk):
     pl = pk.stencil_plan((3072, 3072), w, "float32")
     assert pl["sync"] == 3 and pl["rows_per_lane"] == 56 and pl["cached_tiles"] == pl["tiles"]
     pl = pk.stencil_plan((3072, 3072), w, "float64")
-    assert pl["sync"] == 1 and pl["rows_per_lane"] == 48 and pl["cached_tiles"] == pl["tiles"]
+    assert pl["sync"] == 3 and pl["rows_per_lane"] == 56 and pl["cached_tiles"] == pl["tiles"]
+    assert pk.stencil_plan((4096, 4096), w, "float64")["sync"] != 3
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"sync": 2})["sync"] == 2
     assert pk.stencil_plan((256, 256), w, "float64", tuning={"kernel": 2})["sync"] == 1
     g = workloads.stencil_grid((256, 256), seed=0)
