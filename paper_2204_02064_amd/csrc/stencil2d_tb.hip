@@ -21,6 +21,7 @@
 // as the per-step baseline does, so the two agree bit for bit.  Ring cells
 // and clamped copies outside the grid are never updated.
 #include <algorithm>
+#include <type_traits>
 #include <new>
 #include <vector>
 
@@ -93,8 +94,12 @@ __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_i
 // in a loop over steps makes the compiler rotate every row back (FP64 tall
 // blocks then need twice their registers).  Sums, rows updated and rows kept
 // are tb_step's, so the two give the same bits.
-template <typename T, bool BOX, int RB>
-__device__ __forceinline__ void tb_step_roll(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
+// done(integral_constant<int, i>) is called once new row i is in u[i] (rows
+// 1 .. RB-2, in order), so that a caller can store it while later rows are
+// still being computed.
+template <typename T, bool BOX, int RB, class Done>
+__device__ __forceinline__ void tb_step_roll(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny,
+                                             Done &&done) {
     T acc[3] = {T(0), T(0), T(0)};   // each starts with a product before use
     static_for<0, RB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;   // old row visited
@@ -127,6 +132,7 @@ __device__ __forceinline__ void tb_step_roll(T (&u)[RB], const T (&w)[9], bool l
             }
             const int y = y0 + j - 1;
             u[j - 1] = (lane_in && y >= 1 && y <= ny - 2) ? a : u[j - 1];
+            done(std::integral_constant<int, j - 1>{});
         }
         settle(acc);   // this row's terms here (not sunk below later rows' shifts)
     });
@@ -152,7 +158,7 @@ __device__ __forceinline__ void tb_tile(const gmem<T> *src, gmem<T> *dst, int nx
     }
     const bool lane_in = xg >= 1 && xg <= nx - 2;
     for (int j = 0; j < kk; ++j) {
-        if constexpr (ROLL) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, ny);
+        if constexpr (ROLL) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, ny, [](auto) {});
         else tb_step<T, BOX, RB>(u, w, lane_in, y0, ny);
     }
     const bool own = lane_in && lane >= K && lane < K + OW;
@@ -257,14 +263,19 @@ __global__ __launch_bounds__(TBW * 64) void stencil2d_tbr(TB2DParams<T> p) {
         const int kk = (int)std::min<int64_t>(K, p.steps - s0);
         const bool last = s0 + K >= p.steps;
         gmem<T> *dst = opaque((blk & 1) ? p.buf0 : p.buf1);
-        for (int j = 0; j < kk; ++j) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, p.ny);
-        // owned rows are K .. K+H-1: the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes
-#pragma unroll
-        for (int i = K; i < K + H; ++i) {
-            const int y = y0 + i;
-            const bool band = last || side || i < 2 * K || i >= H;
-            if (own && band && y >= 1 && y <= p.ny - 2) st_coh(row_at(dst + (size_t)y * p.nx, xg), u[i]);
-        }
+        // the block's last step stores each owned row as soon as it is final
+        // (its band part; every owned cell in the last block), overlapping
+        // the writes with the rows still to come.  Owned rows are K .. K+H-1;
+        // the band is rows K .. 2K-1 and H .. H+K-1, and the side lanes.
+        for (int j = 0; j + 1 < kk; ++j) tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, p.ny, [](auto) {});
+        tb_step_roll<T, BOX, RB>(u, w, lane_in, y0, p.ny, [&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i >= K && i < K + H) {
+                const int y = y0 + i;
+                const bool band = last || side || i < 2 * K || i >= H;
+                if (own && band && y >= 1 && y <= p.ny - 2) st_coh(row_at(dst + (size_t)y * p.nx, xg), u[i]);
+            }
+        });
         gs.sync();
         // the ghost rows in every lane, then the ghost columns' owned rows in
         // their lanes only
