@@ -57,12 +57,12 @@ _CSRC = "paper_2204_02064_amd/csrc/"
 _SRC2 = [_CSRC + "stencil2d_wide.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 _SRC3 = [_CSRC + "stencil3d.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 STEP_TRAFFIC = {
-    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.6e6,
+    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.5e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f64.hip"],
-                           "sha256": "799e87c8333b021be9c5fd36f4ebedc3ee6588c8bac73ad43f37dffc6d68a7af"},
-    ("2d5pt", "float32"): {"persistent": 14.7e6, "per_step": 92.9e6,
+                           "sha256": "8936db222600b9ffad3fd28e86ab4ac24c7f55c4b8424c6eb0e23dbcdb5e832b"},
+    ("2d5pt", "float32"): {"persistent": 14.7e6, "per_step": 92.8e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
-                           "sha256": "d561a1c8414bf0c6c6bee19f2d922a00524367c4f4f2a7e3ded337b4c2bfd73a"},
+                           "sha256": "64feb085fb946ab44b9a50639210dba9fc9e113a3d32d71bf61eff4a57d724cf"},
     ("3d7pt", "float64"): {"persistent": 190.3e6, "per_step": 407.5e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
                            "sha256": "c7eecde18910014aa0ade3cf08b4ff46a8323dd22736475f69113df7a530e1fa"},
     ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
