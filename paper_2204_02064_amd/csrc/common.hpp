@@ -160,6 +160,25 @@ __device__ __forceinline__ T from_west(T v, T fill) { return dpp_move<DPP_WAVE_S
 template <typename T>
 __device__ __forceinline__ T from_east(T v, T fill) { return dpp_move<DPP_WAVE_SHL1>(v, fill); }
 
+// The same shifts where the edge lane's result is never used: it reads 0
+// (bound_ctrl), so the value need not be copied into the destination first
+// (one instruction per 32 bits instead of two).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move0(float src) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move0(double src) {
+    long long s = __double_as_longlong(src);
+    int lo = __builtin_amdgcn_mov_dpp((int)s, CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp((int)(s >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ T from_west0(T v) { return dpp_move0<DPP_WAVE_SHR1>(v); }
+template <typename T>
+__device__ __forceinline__ T from_east0(T v) { return dpp_move0<DPP_WAVE_SHL1>(v); }
+
 // a*b+c with one rounding in the operands' own precision (__builtin_fma
 // alone would widen float operands to double and round twice).
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }

@@ -48,15 +48,16 @@ struct TB2DParams {
 // One Jacobi step of a block of RB rows x 64 lanes, in place.  Rows 0 and
 // RB - 1 lack a neighbour row and lanes 0 and 63 a neighbour column: their
 // new values are not exact and are never used (they lie outside the region
-// that is still exact after this step).
+// that is still exact after this step), so the lane shifts give the edge
+// lane 0 for its missing neighbour.
 template <typename T, bool BOX, int RB>
 __device__ __forceinline__ void tb_step(T (&u)[RB], const T (&w)[9], bool lane_in, int y0, int ny) {
-    T pv = u[0], pw = from_west(pv, pv), pe = from_east(pv, pv);
-    T cv = u[1], cw = from_west(cv, cv), ce = from_east(cv, cv);
+    T pv = u[0], pw = from_west0(pv), pe = from_east0(pv);
+    T cv = u[1], cw = from_west0(cv), ce = from_east0(cv);
 #pragma unroll
     for (int i = 1; i < RB - 1; ++i) {
         const T nv = u[i + 1];
-        const T nw = from_west(nv, nv), ne = from_east(nv, nv);
+        const T nw = from_west0(nv), ne = from_east0(nv);
         T acc;
         if constexpr (BOX) {
             acc = w[0] * pw;
@@ -104,7 +105,7 @@ __device__ __forceinline__ void tb_step_roll(T (&u)[RB], const T (&w)[9], bool l
     static_for<0, RB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;   // old row visited
         const T v = u[j];
-        const T vw = from_west(v, v), ve = from_east(v, v);
+        const T vw = from_west0(v), ve = from_east0(v);
         if constexpr (j + 1 <= RB - 2) {   // new row j+1: its dy = -1 terms, the first a product
             T &a = acc[(j + 1) % 3];
             if constexpr (BOX) {
