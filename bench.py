@@ -44,7 +44,7 @@ MEASURED_TRAFFIC = {
         "bytes": 190.31e9,   # profiles/stencil3d_column_f64_256cubed.md
         "sources": ["paper_2204_02064_amd/csrc/stencil3d.hpp", "paper_2204_02064_amd/csrc/barrier.hpp",
                     "paper_2204_02064_amd/csrc/common.hpp", "paper_2204_02064_amd/csrc/stencil3d_f64.hip"],
-        "sha256": "c7eecde18910014aa0ade3cf08b4ff46a8323dd22736475f69113df7a530e1fa",
+        "sha256": "57bf5d50dba114748affa16306a451bdd0efd4c69033d4b4bf424a55a1a3c591",
     },
 }
 
@@ -57,16 +57,16 @@ _CSRC = "paper_2204_02064_amd/csrc/"
 _SRC2 = [_CSRC + "stencil2d_wide.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 _SRC3 = [_CSRC + "stencil3d.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 STEP_TRAFFIC = {
-    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.5e6,
+    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.3e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f64.hip"],
-                           "sha256": "8936db222600b9ffad3fd28e86ab4ac24c7f55c4b8424c6eb0e23dbcdb5e832b"},
+                           "sha256": "362868e6b757498d95f8fd57fd9d23c35f455ebd5702b6c76e869128bc315283"},
     ("2d5pt", "float32"): {"persistent": 14.7e6, "per_step": 92.8e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
-                           "sha256": "64feb085fb946ab44b9a50639210dba9fc9e113a3d32d71bf61eff4a57d724cf"},
+                           "sha256": "981685dfca44ce8f25ddd790eeca56730b40838ba06b487ebec6693718e551f7"},
     ("3d7pt", "float64"): {"persistent": 190.3e6, "per_step": 407.5e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
-                           "sha256": "c7eecde18910014aa0ade3cf08b4ff46a8323dd22736475f69113df7a530e1fa"},
+                           "sha256": "57bf5d50dba114748affa16306a451bdd0efd4c69033d4b4bf424a55a1a3c591"},
     ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
-                           "sha256": "e28cfc316e81d4aad6eafd72259a8b50fe539443d3c481617b9277a61ad146ef"},
+                           "sha256": "0710262a0734a41ba516abc125917221919a59ce7295c236d3155cb1b456f833"},
 }
 
 
