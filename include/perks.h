@@ -90,9 +90,9 @@ typedef struct perks_tuning {
                                  nonzero field selects kernel 1 unless kernel = 2
                                  or 3.                                                */
     int32_t steps_per_sync;   /* kernel 3: K, steps between exchanges (2, 4 or 8; 0
-                                 means 8 up to 2^18 interior cells, else 4); its
-                                 rows_per_lane 0 means 8, 16 (up to 2^20 cells) or
-                                 56                                                   */
+                                 means 8 below 2^20 interior cells, else 4); its
+                                 rows_per_lane 0 means 8 (up to 2^18 cells), 16
+                                 (below 2^20) or 56                                   */
 } perks_tuning;
 
 /* Plan a call would use (for reporting and for the performance model). */

@@ -431,15 +431,15 @@ template <typename T>
 int plan_tb(const perks_shape &s, bool box, const perks_tuning *tu, PlanTB *pl) {
     if (s.ndim != 2) return set_error(PERKS_E_UNSUPPORTED, "the temporally blocked kernel is 2D");
     // defaults measured on MI355X (2d5pt and 2d9pt, FP64 and FP32, register
-    // resident): up to 2^18 interior cells K = 8 on 8-row tiles (256^2: 1.4 us
-    // per step FP64), up to 2^20 K = 4 on 16-row tiles (1024^2: 2.6 us FP64,
-    // 2.0 FP32), above that K = 4 on 56-row tiles, which only the resident
-    // kernel has (3072^2: 8.6 us per step FP64, 6.1 FP32); a grid whose 56-row
-    // tiles do not all fit takes 8-row streamed tiles when asked for temporal
-    // blocking
+    // resident): up to 2^18 interior cells K = 8 on 8-row tiles (256^2: 1.25
+    // us per step FP64), up to 2^20 K = 8 on 16-row tiles (1024^2: 2.05 us
+    // FP64, 1.65 FP32), above that K = 4 on 56-row tiles, which only the
+    // resident kernel has (3072^2: 6.7 us per step FP64, 5.4 FP32); a grid
+    // whose 56-row tiles do not all fit takes 8-row streamed tiles when asked
+    // for temporal blocking
     const int64_t interior = (s.nx - 2) * (s.ny - 2);
     const bool hdef = !(tu && tu->rows_per_lane > 0);
-    pl->k = (tu && tu->steps_per_sync > 0) ? tu->steps_per_sync : (interior <= (int64_t(1) << 18) ? 8 : 4);
+    pl->k = (tu && tu->steps_per_sync > 0) ? tu->steps_per_sync : (interior < (int64_t(1) << 20) ? 8 : 4);
     pl->h = !hdef ? tu->rows_per_lane
                   : interior <= (int64_t(1) << 18) ? 8 : interior < (int64_t(1) << 20) ? 16 : 56;
     // max_cached_tiles < 0 keeps the grid in its buffers (streamed blocks);

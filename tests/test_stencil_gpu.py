@@ -315,8 +315,8 @@ def test_full_size_bench_plans_match_oracle(pk, kind, dtype):
 
 def test_untuned_small_grids_take_temporal_blocking(pk):
     """Below 2^20 interior cells the untuned plan is the temporally blocked
-    kernel (8 steps per exchange on 8-row tiles up to 2^18 cells, 4 steps on
-    16-row tiles above), every tile in registers; above 2^20 it is too when 56-row
+    kernel (8 steps per exchange on 8-row tiles up to 2^18 cells, on 16-row
+    tiles above), every tile in registers; above 2^20 it is too when 56-row
     tiles all fit (3072^2), else not (FP64 4096^2: the radius-2..4 family
     when it caches every tile, else the radius-1 kernel).
     The 256^2 100-step configuration runs on it, and matches the oracle."""
