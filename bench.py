@@ -57,12 +57,12 @@ _CSRC = "paper_2204_02064_amd/csrc/"
 _SRC2 = [_CSRC + "stencil2d_wide.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 _SRC3 = [_CSRC + "stencil3d.hpp", _CSRC + "barrier.hpp", _CSRC + "common.hpp"]
 STEP_TRAFFIC = {
-    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.3e6,
+    ("2d5pt", "float64"): {"persistent": 20.0e6, "per_step": 174.4e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f64.hip"],
-                           "sha256": "362868e6b757498d95f8fd57fd9d23c35f455ebd5702b6c76e869128bc315283"},
+                           "sha256": "91f7ef17091b0d3c5aee6f93a7e84c2da4fb0787205164a6c13dbde7369d6aa8"},
     ("2d5pt", "float32"): {"persistent": 14.7e6, "per_step": 92.8e6,
                            "sources": [_CSRC + "stencil2d_tb.hip"] + _SRC2 + [_CSRC + "stencil2d_wide_f32.hip"],
-                           "sha256": "981685dfca44ce8f25ddd790eeca56730b40838ba06b487ebec6693718e551f7"},
+                           "sha256": "4a9cc640085b58e073036b3431295137e76da1cb4781bfea188170d613ad0e36"},
     ("3d7pt", "float64"): {"persistent": 190.3e6, "per_step": 407.5e6, "sources": _SRC3 + [_CSRC + "stencil3d_f64.hip"],
                            "sha256": "57bf5d50dba114748affa16306a451bdd0efd4c69033d4b4bf424a55a1a3c591"},
     ("3d7pt", "float32"): {"persistent": 29.0e6, "per_step": 215.6e6, "sources": _SRC3 + [_CSRC + "stencil3d_f32.hip"],
